@@ -1,0 +1,237 @@
+"""Seeded synthetic inputs for the SSSP engine and its oracle.
+
+Inputs only: this package holds none of the shortest-path method's arithmetic.
+It draws undirected edge lists (R-MAT, G(n, m), road-like grid), cleans them
+into a symmetric CSR (self-loops dropped, parallel edges merged to their
+minimum weight, rows sorted by column) and picks sources uniformly among
+vertices of degree >= 1 (the paper's trial protocol, Section 4, draws 64 such
+sources per graph).
+
+The heavy lifting is in ``gen.cpp`` (``libgraphgen.so``), built by
+``graphgen/build.py``.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libgraphgen.so")
+_lib = None
+
+# Seeds: 20250619 + workload index, recorded in every result.
+SEED_BASE = 20250619
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        from . import build as _b
+        _b.build()
+    lib = ctypes.CDLL(_LIB_PATH)
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    u32p = ctypes.POINTER(ctypes.c_uint32)
+    i64 = ctypes.c_int64
+    lib.gg_rmat.argtypes = [ctypes.c_int32, i64, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                            ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32, i32p, i32p, u32p]
+    lib.gg_rmat.restype = ctypes.c_int
+    lib.gg_gnm.argtypes = [i64, i64, ctypes.c_uint32, ctypes.c_uint64, i32p, i32p, u32p]
+    lib.gg_gnm.restype = ctypes.c_int
+    lib.gg_grid.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                            ctypes.c_uint32, ctypes.c_uint64, i32p, i32p, u32p]
+    lib.gg_grid.restype = i64
+    lib.gg_csr_build.argtypes = [i64, i64, i32p, i32p, u32p, ctypes.POINTER(i64)]
+    lib.gg_csr_build.restype = ctypes.c_void_p
+    lib.gg_csr_copy.argtypes = [ctypes.c_void_p, i32p, i32p, u32p]
+    lib.gg_csr_copy.restype = None
+    lib.gg_csr_free.argtypes = [ctypes.c_void_p]
+    lib.gg_csr_free.restype = None
+    lib.gg_pick_sources.argtypes = [i64, i32p, ctypes.c_int32, ctypes.c_uint64, i32p]
+    lib.gg_pick_sources.restype = ctypes.c_int32
+    lib.gg_rmat_degrees.argtypes = [ctypes.c_int32, i64, ctypes.c_double, ctypes.c_double,
+                                    ctypes.c_double, ctypes.c_uint64, ctypes.c_int32,
+                                    ctypes.POINTER(ctypes.c_int64)]
+    lib.gg_rmat_degrees.restype = ctypes.c_int
+    lib.gg_permutation.argtypes = [i64, ctypes.c_uint64, i32p]
+    lib.gg_permutation.restype = None
+    _lib = lib
+    return lib
+
+
+def _p(a: np.ndarray, ct):
+    return a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+@dataclasses.dataclass
+class EdgeList:
+    """Raw undirected edge list: may hold self-loops and parallel edges."""
+    n: int
+    src: np.ndarray  # int32[m]
+    dst: np.ndarray  # int32[m]
+    w: np.ndarray    # uint32[m]
+
+    @property
+    def m(self) -> int:
+        return int(self.src.shape[0])
+
+
+@dataclasses.dataclass
+class CSR:
+    """Symmetric CSR: rowptr int32[n+1], col int32[nnz], w uint32[nnz]."""
+    n: int
+    rowptr: np.ndarray
+    col: np.ndarray
+    w: np.ndarray
+
+    @property
+    def nnz(self) -> int:
+        return int(self.rowptr[-1])
+
+    def degrees(self) -> np.ndarray:
+        return np.diff(self.rowptr.astype(np.int64))
+
+
+def rmat(scale: int, edge_factor: int = 16, a: float = 0.57, b: float = 0.19, c: float = 0.19,
+         wmax: int = 255, seed: int = SEED_BASE, relabel: bool = True) -> EdgeList:
+    lib = _load()
+    n = 1 << scale
+    m = edge_factor << scale
+    src = np.empty(m, np.int32)
+    dst = np.empty(m, np.int32)
+    w = np.empty(m, np.uint32)
+    rc = lib.gg_rmat(scale, edge_factor, a, b, c, wmax, seed, int(relabel),
+                     _p(src, ctypes.c_int32), _p(dst, ctypes.c_int32), _p(w, ctypes.c_uint32))
+    if rc != 0:
+        raise ValueError("gg_rmat: bad arguments")
+    return EdgeList(n, src, dst, w)
+
+
+def rmat_degrees(scale: int, edge_factor: int = 16, a: float = 0.57, b: float = 0.19,
+                 c: float = 0.19, seed: int = SEED_BASE, relabel: bool = True) -> np.ndarray:
+    """Degrees of the R-MAT multigraph (parallel edges counted, self-loops
+    dropped) without materialising the edge list."""
+    lib = _load()
+    deg = np.empty(1 << scale, np.int64)
+    rc = lib.gg_rmat_degrees(scale, edge_factor, a, b, c, seed, int(relabel),
+                             deg.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    if rc != 0:
+        raise ValueError("gg_rmat_degrees: bad arguments")
+    return deg
+
+
+def gnm(n: int, m: int, wmax: int = 255, seed: int = SEED_BASE) -> EdgeList:
+    lib = _load()
+    src = np.empty(m, np.int32)
+    dst = np.empty(m, np.int32)
+    w = np.empty(m, np.uint32)
+    rc = lib.gg_gnm(n, m, wmax, seed, _p(src, ctypes.c_int32), _p(dst, ctypes.c_int32),
+                    _p(w, ctypes.c_uint32))
+    if rc != 0:
+        raise ValueError("gg_gnm: bad arguments")
+    return EdgeList(n, src, dst, w)
+
+
+def grid(rows: int, cols: int, p_keep: float = 0.95, p_diag: float = 0.01, wmax: int = 1000,
+         seed: int = SEED_BASE) -> EdgeList:
+    lib = _load()
+    null = ctypes.POINTER(ctypes.c_int32)()
+    m = lib.gg_grid(rows, cols, p_keep, p_diag, wmax, seed, null, null,
+                    ctypes.POINTER(ctypes.c_uint32)())
+    if m < 0:
+        raise ValueError("gg_grid: bad arguments")
+    src = np.empty(m, np.int32)
+    dst = np.empty(m, np.int32)
+    w = np.empty(m, np.uint32)
+    m2 = lib.gg_grid(rows, cols, p_keep, p_diag, wmax, seed, _p(src, ctypes.c_int32),
+                     _p(dst, ctypes.c_int32), _p(w, ctypes.c_uint32))
+    assert m2 == m
+    return EdgeList(rows * cols, src, dst, w)
+
+
+def from_arrays(n: int, src, dst, w) -> EdgeList:
+    return EdgeList(int(n), np.ascontiguousarray(src, np.int32), np.ascontiguousarray(dst, np.int32),
+                    np.ascontiguousarray(w, np.uint32))
+
+
+def to_csr(el: EdgeList) -> CSR:
+    lib = _load()
+    src = np.ascontiguousarray(el.src, np.int32)
+    dst = np.ascontiguousarray(el.dst, np.int32)
+    w = np.ascontiguousarray(el.w, np.uint32)
+    nnz = ctypes.c_int64(0)
+    h = lib.gg_csr_build(el.n, src.shape[0], _p(src, ctypes.c_int32), _p(dst, ctypes.c_int32),
+                         _p(w, ctypes.c_uint32), ctypes.byref(nnz))
+    if not h:
+        raise ValueError("gg_csr_build failed (%d)" % nnz.value)
+    try:
+        rowptr = np.empty(el.n + 1, np.int32)
+        col = np.empty(nnz.value, np.int32)
+        wo = np.empty(nnz.value, np.uint32)
+        lib.gg_csr_copy(h, _p(rowptr, ctypes.c_int32), _p(col, ctypes.c_int32),
+                        _p(wo, ctypes.c_uint32))
+    finally:
+        lib.gg_csr_free(h)
+    return CSR(el.n, rowptr, col, wo)
+
+
+def pick_sources(csr: CSR, k: int, seed: int) -> np.ndarray:
+    lib = _load()
+    rowptr = np.ascontiguousarray(csr.rowptr, np.int32)
+    out = np.empty(max(k, 1), np.int32)
+    got = lib.gg_pick_sources(csr.n, _p(rowptr, ctypes.c_int32), k, seed, _p(out, ctypes.c_int32))
+    return out[:got].copy()
+
+
+def permutation(n: int, seed: int) -> np.ndarray:
+    lib = _load()
+    out = np.empty(n, np.int32)
+    lib.gg_permutation(n, seed, _p(out, ctypes.c_int32))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Named workloads (shapes of the paper's Section 4.2 graphs; sizes as stated).
+# Each returns (EdgeList, CSR).
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    edges: EdgeList
+    csr: CSR
+    seed: int
+
+    def sources(self, k: int) -> np.ndarray:
+        return pick_sources(self.csr, k, self.seed + 7919)
+
+
+def workload(name: str, scale: Optional[int] = None) -> Workload:
+    """Named synthetic workloads.
+
+    ``rmat14``  R-MAT scale 14, edge factor 16, (a,b,c)=(0.57,0.19,0.19), w in 1..255
+    ``er22``    G(n, m) with n = 2^22, m = 16 n (mean degree 32), w in 1..255
+    ``rmat24``  R-MAT scale 24, edge factor 16, w in 1..255
+    ``grid2048`` 2048 x 2048 grid, 5% of edges dropped, 1% diagonals, w in 1..1000
+    ``rmat<k>`` / ``er<k>`` / ``grid<k>`` the same recipes at other sizes
+    """
+    if name.startswith("rmat"):
+        s = int(name[4:]) if scale is None else scale
+        seed = SEED_BASE + {14: 1, 24: 3, 22: 5}.get(s, 100 + s)
+        el = rmat(s, 16, 0.57, 0.19, 0.19, 255, seed)
+    elif name.startswith("er"):
+        s = int(name[2:]) if scale is None else scale
+        seed = SEED_BASE + {22: 2}.get(s, 200 + s)
+        n = 1 << s
+        el = gnm(n, 16 * n, 255, seed)
+    elif name.startswith("grid"):
+        side = int(name[4:]) if scale is None else scale
+        seed = SEED_BASE + {2048: 4}.get(side, 300 + side)
+        el = grid(side, side, 0.95, 0.01, 1000, seed)
+    else:
+        raise ValueError("unknown workload %r" % name)
+    return Workload(name, el, to_csr(el), seed)

@@ -1,0 +1,306 @@
+/*
+ * ORACLE -- test infrastructure only. Nothing in the product path may call,
+ * link or load this file; only the tests, the smoke check and the benchmark's
+ * CPU-baseline leg do.
+ *
+ * Single-source shortest paths by its plain definition: dist[v] is the minimum
+ * over all s->v paths of the summed edge weights, dist[s] = 0, and a vertex
+ * with no path keeps +infinity (the paper's problem statement, Section 2).
+ * Computed with the textbook binary-heap Dijkstra (the exact sequential method
+ * the paper contrasts with, Section 2.2), lazy deletion, 64-bit accumulation.
+ *
+ * The input is the RAW undirected edge list (u, v, w): every edge is usable in
+ * both directions, self-loops and parallel edges are kept as given. The
+ * adjacency is built here from that list; nothing is shared with the GPU path.
+ *
+ * Output: uint32 distances, UINT32_MAX for unreachable vertices. A reachable
+ * vertex whose true distance does not fit below UINT32_MAX makes the call
+ * return ORACLE_OVERFLOW (its slot holds UINT32_MAX).
+ *
+ * Also here: an invariant checker over a CSR (dist[s] = 0; no edge can
+ * improve a distance; every finite vertex other than s has a tight incoming
+ * edge; every finite vertex is reached from s over tight edges; infinite
+ * vertices only have infinite neighbours), used as the any-size property check.
+ */
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORACLE_OK 0
+#define ORACLE_BAD_ARGS -1
+#define ORACLE_NOMEM -2
+#define ORACLE_OVERFLOW 1
+
+#define INF32 0xFFFFFFFFu
+
+typedef struct {
+  int64_t n;
+  int64_t *off; /* n + 1 */
+  int32_t *nbr; /* 2m */
+  uint32_t *wt; /* 2m */
+} oracle_adj;
+
+/* Build the undirected adjacency of a raw edge list (both directions). */
+void *oracle_adj_build(int64_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                       const uint32_t *w) {
+  if (n < 1 || m < 0) return NULL;
+  for (int64_t i = 0; i < m; ++i)
+    if (src[i] < 0 || src[i] >= n || dst[i] < 0 || dst[i] >= n) return NULL;
+  oracle_adj *a = (oracle_adj *)calloc(1, sizeof(oracle_adj));
+  if (!a) return NULL;
+  a->n = n;
+  a->off = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+  a->nbr = (int32_t *)malloc(sizeof(int32_t) * (size_t)(2 * m + 1));
+  a->wt = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(2 * m + 1));
+  int64_t *cur = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+  if (!a->off || !a->nbr || !a->wt || !cur) {
+    free(a->off); free(a->nbr); free(a->wt); free(a); free(cur);
+    return NULL;
+  }
+  for (int64_t i = 0; i < m; ++i) {
+    a->off[src[i] + 1]++;
+    a->off[dst[i] + 1]++;
+  }
+  for (int64_t v = 0; v < n; ++v) a->off[v + 1] += a->off[v];
+  memcpy(cur, a->off, sizeof(int64_t) * (size_t)n);
+  for (int64_t i = 0; i < m; ++i) {
+    int64_t p = cur[src[i]]++;
+    a->nbr[p] = dst[i];
+    a->wt[p] = w[i];
+    p = cur[dst[i]]++;
+    a->nbr[p] = src[i];
+    a->wt[p] = w[i];
+  }
+  free(cur);
+  return a;
+}
+
+void oracle_adj_free(void *h) {
+  oracle_adj *a = (oracle_adj *)h;
+  if (!a) return;
+  free(a->off);
+  free(a->nbr);
+  free(a->wt);
+  free(a);
+}
+
+typedef struct {
+  uint64_t d;
+  int32_t v;
+} heap_item;
+
+typedef struct {
+  heap_item *a;
+  int64_t size, cap;
+} heap;
+
+static int heap_push(heap *h, uint64_t d, int32_t v) {
+  if (h->size == h->cap) {
+    int64_t nc = h->cap ? h->cap * 2 : 1024;
+    heap_item *na = (heap_item *)realloc(h->a, sizeof(heap_item) * (size_t)nc);
+    if (!na) return -1;
+    h->a = na;
+    h->cap = nc;
+  }
+  int64_t i = h->size++;
+  while (i > 0) {
+    int64_t p = (i - 1) / 2;
+    if (h->a[p].d <= d) break;
+    h->a[i] = h->a[p];
+    i = p;
+  }
+  h->a[i].d = d;
+  h->a[i].v = v;
+  return 0;
+}
+
+static heap_item heap_pop(heap *h) {
+  heap_item top = h->a[0];
+  heap_item last = h->a[--h->size];
+  int64_t i = 0;
+  for (;;) {
+    int64_t c = 2 * i + 1;
+    if (c >= h->size) break;
+    if (c + 1 < h->size && h->a[c + 1].d < h->a[c].d) ++c;
+    if (h->a[c].d >= last.d) break;
+    h->a[i] = h->a[c];
+    i = c;
+  }
+  if (h->size > 0) h->a[i] = last;
+  return top;
+}
+
+/* Dijkstra from s on a built adjacency. Returns ORACLE_OK / ORACLE_OVERFLOW /
+ * an error code. dist_out has n entries. */
+int oracle_adj_dijkstra(const void *hv, int32_t s, uint32_t *dist_out) {
+  const oracle_adj *a = (const oracle_adj *)hv;
+  if (!a || s < 0 || s >= a->n) return ORACLE_BAD_ARGS;
+  const int64_t n = a->n;
+  uint64_t *d = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n);
+  unsigned char *done = (unsigned char *)calloc((size_t)n, 1);
+  heap h = {NULL, 0, 0};
+  if (!d || !done) {
+    free(d); free(done);
+    return ORACLE_NOMEM;
+  }
+  for (int64_t v = 0; v < n; ++v) d[v] = UINT64_MAX;
+  d[s] = 0;
+  int rc = ORACLE_OK;
+  if (heap_push(&h, 0, s)) rc = ORACLE_NOMEM;
+  while (rc == ORACLE_OK && h.size > 0) {
+    heap_item it = heap_pop(&h);
+    int32_t u = it.v;
+    if (done[u] || it.d != d[u]) continue; /* stale entry */
+    done[u] = 1;
+    for (int64_t e = a->off[u]; e < a->off[u + 1]; ++e) {
+      int32_t v = a->nbr[e];
+      uint64_t nd = d[u] + (uint64_t)a->wt[e];
+      if (nd < d[v]) {
+        d[v] = nd;
+        if (heap_push(&h, nd, v)) {
+          rc = ORACLE_NOMEM;
+          break;
+        }
+      }
+    }
+  }
+  if (rc == ORACLE_OK) {
+    for (int64_t v = 0; v < n; ++v) {
+      if (d[v] == UINT64_MAX) {
+        dist_out[v] = INF32;
+      } else if (d[v] >= (uint64_t)INF32) {
+        dist_out[v] = INF32;
+        rc = ORACLE_OVERFLOW;
+      } else {
+        dist_out[v] = (uint32_t)d[v];
+      }
+    }
+  }
+  free(h.a);
+  free(d);
+  free(done);
+  return rc;
+}
+
+/* One-shot: build the adjacency from the raw edge list, solve, free. */
+int oracle_dijkstra(int64_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                    const uint32_t *w, int32_t s, uint32_t *dist_out) {
+  void *a = oracle_adj_build(n, m, src, dst, w);
+  if (!a) return ORACLE_BAD_ARGS;
+  int rc = oracle_adj_dijkstra(a, s, dist_out);
+  oracle_adj_free(a);
+  return rc;
+}
+
+/* k sources over a shared adjacency on `threads` POSIX threads, one Dijkstra
+ * per query. Row i of dist_out (n entries) belongs to sources[i]. Returns the
+ * first nonzero per-query status, else 0. */
+typedef struct {
+  const oracle_adj *a;
+  const int32_t *sources;
+  uint32_t *out;
+  int32_t k;
+  volatile int32_t next;
+  volatile int rc;
+  pthread_mutex_t mu;
+} many_ctx;
+
+static void *many_worker(void *p) {
+  many_ctx *c = (many_ctx *)p;
+  for (;;) {
+    pthread_mutex_lock(&c->mu);
+    int32_t i = c->next++;
+    pthread_mutex_unlock(&c->mu);
+    if (i >= c->k) break;
+    int r = oracle_adj_dijkstra(c->a, c->sources[i], c->out + (size_t)i * (size_t)c->a->n);
+    if (r != ORACLE_OK) {
+      pthread_mutex_lock(&c->mu);
+      if (c->rc == ORACLE_OK) c->rc = r;
+      pthread_mutex_unlock(&c->mu);
+    }
+  }
+  return NULL;
+}
+
+int oracle_adj_dijkstra_many(const void *hv, int32_t k, const int32_t *sources, uint32_t *dist_out,
+                             int32_t threads) {
+  const oracle_adj *a = (const oracle_adj *)hv;
+  if (!a || k < 0 || threads < 1) return ORACLE_BAD_ARGS;
+  many_ctx c;
+  c.a = a;
+  c.sources = sources;
+  c.out = dist_out;
+  c.k = k;
+  c.next = 0;
+  c.rc = ORACLE_OK;
+  pthread_mutex_init(&c.mu, NULL);
+  pthread_t *tids = (pthread_t *)malloc(sizeof(pthread_t) * (size_t)threads);
+  int started = 0;
+  for (int t = 0; t < threads; ++t)
+    if (pthread_create(&tids[t], NULL, many_worker, &c) == 0) ++started;
+  if (started == 0) many_worker(&c);
+  for (int t = 0; t < started; ++t) pthread_join(tids[t], NULL);
+  free(tids);
+  pthread_mutex_destroy(&c.mu);
+  return c.rc;
+}
+
+/* Invariant checker on a CSR (rowptr[n+1], col[nnz], w[nnz]) for a candidate
+ * distance vector. counts[0..4] receive the number of violations of:
+ *   0  dist[s] != 0
+ *   1  an edge (u,v,w) with dist[u] finite and dist[u] + w < dist[v]
+ *   2  a finite vertex v != s with no tight incoming edge (dist[u]+w == dist[v])
+ *   3  a finite vertex not reached from s along tight edges
+ *   4  an infinite vertex adjacent to a finite one (subsumed by 1; kept apart)
+ * Returns the total. With every weight >= 1, zero violations of 0..2 pin the
+ * vector to the exact distances; check 3 closes the zero-weight loophole. */
+int64_t oracle_check_sssp(int64_t n, const int32_t *rowptr, const int32_t *col, const uint32_t *w,
+                          int32_t s, const uint32_t *dist, int64_t *counts) {
+  for (int i = 0; i < 5; ++i) counts[i] = 0;
+  if (n < 1 || s < 0 || s >= n) return -1;
+  if (dist[s] != 0) counts[0]++;
+  unsigned char *tight_in = (unsigned char *)calloc((size_t)n, 1);
+  unsigned char *seen = (unsigned char *)calloc((size_t)n, 1);
+  int32_t *queue = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+  if (!tight_in || !seen || !queue) {
+    free(tight_in); free(seen); free(queue);
+    return -2;
+  }
+  for (int64_t u = 0; u < n; ++u) {
+    for (int64_t e = rowptr[u]; e < rowptr[u + 1]; ++e) {
+      int32_t v = col[e];
+      if (dist[u] == INF32) {
+        if (dist[v] != INF32) counts[4]++;
+        continue;
+      }
+      uint64_t c = (uint64_t)dist[u] + (uint64_t)w[e];
+      if (c < (uint64_t)dist[v]) counts[1]++;
+      if (c == (uint64_t)dist[v]) tight_in[v] = 1;
+    }
+  }
+  for (int64_t v = 0; v < n; ++v)
+    if (v != s && dist[v] != INF32 && !tight_in[v]) counts[2]++;
+  /* BFS over tight edges from s */
+  int64_t head = 0, tail = 0;
+  if (dist[s] == 0) {
+    seen[s] = 1;
+    queue[tail++] = s;
+  }
+  while (head < tail) {
+    int32_t u = queue[head++];
+    for (int64_t e = rowptr[u]; e < rowptr[u + 1]; ++e) {
+      int32_t v = col[e];
+      if (!seen[v] && dist[v] != INF32 && (uint64_t)dist[u] + w[e] == (uint64_t)dist[v]) {
+        seen[v] = 1;
+        queue[tail++] = v;
+      }
+    }
+  }
+  for (int64_t v = 0; v < n; ++v)
+    if (dist[v] != INF32 && !seen[v]) counts[3]++;
+  free(tight_in);
+  free(seen);
+  free(queue);
+  return counts[0] + counts[1] + counts[2] + counts[3] + counts[4];
+}

@@ -1,0 +1,81 @@
+"""The seeded input generators: determinism, shapes, and the CSR cleaning rule."""
+import hashlib
+
+import numpy as np
+
+import graphgen
+from graphgen import small
+
+
+def _digest(*arrays):
+    h = hashlib.sha256()
+    for a in arrays:
+        h.update(np.ascontiguousarray(a).tobytes())
+    return h.hexdigest()[:16]
+
+
+def test_generators_are_deterministic_and_seeded():
+    for make in (lambda s: graphgen.rmat(10, 16, seed=s), lambda s: graphgen.gnm(1000, 8000, seed=s),
+                 lambda s: graphgen.grid(30, 40, seed=s)):
+        a, b, c = make(1), make(1), make(2)
+        assert _digest(a.src, a.dst, a.w) == _digest(b.src, b.dst, b.w)
+        assert _digest(a.src, a.dst, a.w) != _digest(c.src, c.dst, c.w)
+
+
+def test_rmat14_shape():
+    wl = graphgen.workload("rmat14")
+    el, c = wl.edges, wl.csr
+    assert el.n == 16384 and el.m == 16 * 16384
+    assert el.w.min() >= 1 and el.w.max() <= 255
+    deg = c.degrees()
+    # about 262K generated edges -> ~213K after cleaning; ~23% isolated
+    assert 200_000 < c.nnz // 2 < 230_000
+    assert 0.15 < (deg == 0).mean() < 0.3
+
+
+def test_weights_uniform():
+    el = graphgen.gnm(1 << 12, 1 << 18, wmax=255, seed=3)
+    counts = np.bincount(el.w, minlength=256)[1:]
+    assert counts.min() > 0.8 * counts.mean() and counts.max() < 1.2 * counts.mean()
+
+
+def test_csr_cleaning_rule():
+    """Self-loops dropped, both directions stored, one entry per neighbour
+    carrying the minimum weight of the parallel edges, rows sorted by column."""
+    el = small.tiny_random(50, 400, list(range(0, 30)), seed=4)
+    c = graphgen.to_csr(el)
+    best = {}
+    for u, v, w in zip(el.src.tolist(), el.dst.tolist(), el.w.tolist()):
+        if u == v:
+            continue
+        for a, b in ((u, v), (v, u)):
+            best[(a, b)] = min(best.get((a, b), 1 << 40), w)
+    got = {}
+    for u in range(c.n):
+        cols = c.col[c.rowptr[u]:c.rowptr[u + 1]]
+        assert np.all(np.diff(cols) > 0)
+        for v, w in zip(cols.tolist(), c.w[c.rowptr[u]:c.rowptr[u + 1]].tolist()):
+            got[(u, v)] = w
+    assert got == best
+
+
+def test_grid_structure():
+    el = graphgen.grid(64, 64, p_keep=0.95, p_diag=0.01, wmax=1000, seed=9)
+    c = graphgen.to_csr(el)
+    deg = c.degrees()
+    assert deg.max() <= 6
+    assert 0.93 < (c.nnz / 2) / (2 * 64 * 63) < 0.99 + 0.01
+    assert el.w.min() >= 1 and el.w.max() <= 1000
+    r, k = el.src // 64, el.src % 64
+    r2, k2 = el.dst // 64, el.dst % 64
+    dr, dk = r2 - r, k2 - k
+    assert set(zip(dr.tolist(), dk.tolist())) <= {(0, 1), (1, 0), (1, 1)}
+
+
+def test_sources_have_edges_and_are_distinct():
+    wl = graphgen.workload("rmat12")
+    srcs = wl.sources(64)
+    deg = wl.csr.degrees()
+    assert len(set(srcs.tolist())) == 64
+    assert np.all(deg[srcs] >= 1)
+    assert np.array_equal(srcs, wl.sources(64))
