@@ -1,0 +1,190 @@
+/*
+ * sssp.h -- C ABI of an MI355X (gfx950) engine for single-source shortest
+ * paths on undirected graphs with non-negative integer weights, following
+ * Yu, Wang and Luo, "A Heuristic Algorithm for Shortest Path Search"
+ * (arXiv 2506.19349).
+ *
+ * What is computed (the paper's problem statement, Section 2): for a source s,
+ * dist[v] is the length of the shortest s-v path, dist[s] = 0, and a vertex
+ * with no path to s keeps +infinity, written as UINT32_MAX. The engine reaches
+ * exactly these values; its heuristics (dynamic stepping, Section 3.1, and
+ * traversal optimisation, Section 3.2, driving the Algorithm of Section 3.3)
+ * only decide which relaxations run together. The predecessor array of
+ * Section 2 is not produced.
+ *
+ * Conventions for every call:
+ *  - Graphs are symmetric CSR: rowptr[n+1] (int32, rowptr[0] = 0,
+ *    non-decreasing, rowptr[n] = nnz <= INT32_MAX), colidx[nnz] (int32 in
+ *    [0, n)), weight[nnz] (uint32). Each undirected edge appears in both rows
+ *    with the same weight (as a multiset of (u, v, w) triples). Parallel edges
+ *    and self-loops are allowed and mean what they mean in a multigraph.
+ *  - "device" pointers are HIP device memory of the current device; "host"
+ *    pointers are ordinary (or pinned) host memory.
+ *  - Argument errors are detected on the host before anything is enqueued;
+ *    such a call writes nothing.
+ *  - Calls that take a stream enqueue their GPU work on it and return without
+ *    waiting (unless stated). Results are valid once the stream is
+ *    synchronised. A NULL stream is the null stream.
+ *  - Status codes are negative on failure; sssp_last_error() and
+ *    sssp_last_error_message() describe the most recent failure of the
+ *    calling thread.
+ */
+#ifndef SSSP_H
+#define SSSP_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SSSP_OK = 0,
+  SSSP_E_INVAL = -1,         /* bad argument (NULL pointer, n < 1, source out of range, bad CSR) */
+  SSSP_E_NOT_SYMMETRIC = -2, /* CSR is not symmetric as a multiset of (u, v, w) */
+  SSSP_E_RANGE = -3,         /* n, nnz or a size beyond the library's limits */
+  SSSP_E_DIST_OVERFLOW = -4, /* a reachable vertex's distance does not fit below UINT32_MAX */
+  SSSP_E_NOMEM = -5,         /* device or host allocation failed */
+  SSSP_E_DEVICE = -6,        /* a HIP call or a kernel failed */
+  SSSP_E_BUSY = -7           /* serving: no room to admit the request now */
+} sssp_status;
+
+typedef struct sssp_graph sssp_graph; /* opaque, library-owned, read-only after create */
+
+/* Solver options. Zero-initialise and set what you need; zero fields take the
+ * defaults given here (the paper's constants, Section 4.1). None of them
+ * changes a distance. */
+typedef struct {
+  int32_t traversal_opt; /* 0: default (on); 1: on; -1: off (st = lb in every step) */
+  int32_t alpha;         /* highD threshold of Eq. (3); 0 -> 3 */
+  double beta;           /* Eq. (1) trade-off in (0, 1); 0 -> 0.9 */
+  int32_t host_driven;   /* 1: one kernel launch per tick with a host sync (debug); 0: persistent */
+  int32_t blocks_per_cu; /* persistent grid size; 0 -> tuned / default */
+  int32_t heavy_split;   /* ranges longer than this are split across the grid; 0 -> default */
+  int32_t reserved[9];
+} sssp_options;
+
+/* Work counters of one solve (the paper's Section 4 measures). */
+typedef struct {
+  uint64_t expansions;      /* vertex expansions (paths extended), band and deferred */
+  uint64_t band_expansions; /* expansions of vertices at or above lb (nFrontier's count) */
+  uint64_t push_scanned;    /* CSR entries scanned by push (edges relaxed) */
+  uint64_t pull_vertices;   /* unsettled vertices scanned by the pull */
+  uint64_t pull_scanned;    /* CSR entries scanned by the pull (requests) */
+  uint64_t relax_success;   /* successful distance decreases */
+  uint64_t queue_entries;   /* frontier / touched / settled list entries written */
+  uint64_t rounds;          /* push rounds (synchronisations of the round loop) */
+  uint64_t pulls;           /* pull phases */
+  uint64_t steps;           /* scheduling-threshold pairs <lb, ub> */
+  uint64_t ticks;           /* device-wide phases executed (rounds + settle passes) */
+  uint32_t high_d0;         /* highD(0) */
+  uint32_t gap0;            /* gap(0) */
+  uint32_t flags;           /* nonzero: internal condition (see sssp_status_str of status) */
+  uint32_t reserved;
+} sssp_counters;
+
+/* One step of the schedule (Section 3.3): the band, the selection threshold,
+ * and the statistics taken at the step's end for the next pair. */
+typedef struct {
+  uint32_t lb, ub, st; /* this step's pair and selection threshold */
+  uint32_t rounds;     /* push rounds in this step */
+  uint32_t pulled;     /* 1 if the pull ran (st < lb) */
+  uint32_t L;          /* next lb (= this step's final ub) */
+  uint64_t S;          /* sumD(L) */
+  uint32_t h;          /* highD(L) */
+  uint32_t gap;        /* gap(L), Eq. (3) */
+  uint32_t st_next;    /* computeST for <L, L + gap(L)> (Function 2) */
+  uint32_t reserved;
+} sssp_step;
+
+typedef struct {
+  int32_t n;
+  int32_t nnz;
+  int32_t nonisolated;  /* vertices of degree >= 1 */
+  int32_t max_degree;
+  int32_t distinct_degrees;
+  uint32_t max_weight;  /* maxW(G, 1) */
+  uint32_t high_d0;     /* highD(0) over the whole vertex set */
+  uint32_t reserved;
+  uint64_t device_bytes; /* device memory held by the graph */
+} sssp_graph_info;
+
+/* ---- graphs ------------------------------------------------------------- */
+
+/* Build the device graph: validate the CSR, check symmetry, sort each row by
+ * (weight, column), and precompute the statistics inputs -- degrees, the
+ * degree histogram and highD(0), the weight quantiles RtoW[4096] (Section 4.1:
+ * RtoW[x] = maxW(G, x/4095)). This is the paper's preprocessing (Section 4.1,
+ * Section 4.6). rowptr/colidx/weight may be host or device pointers; they are
+ * copied, and the caller keeps ownership. Synchronous. Returns NULL on error
+ * (see sssp_last_error: SSSP_E_INVAL, SSSP_E_NOT_SYMMETRIC, SSSP_E_RANGE,
+ * SSSP_E_NOMEM, SSSP_E_DEVICE). */
+sssp_graph* sssp_graph_create(int32_t n, const int32_t* rowptr, const int32_t* colidx,
+                              const uint32_t* weight);
+
+#define SSSP_CREATE_SKIP_SYMMETRY_CHECK 1
+/* As sssp_graph_create, with flags (SSSP_CREATE_*). Skipping the symmetry
+ * check leaves correctness to the caller: the pull (Section 3.2) relies on it. */
+sssp_graph* sssp_graph_create_ex(int32_t n, const int32_t* rowptr, const int32_t* colidx,
+                                 const uint32_t* weight, int32_t flags);
+
+/* Free the graph. No solve on it may be in flight. NULL is accepted. */
+sssp_status sssp_graph_destroy(sssp_graph* g);
+
+/* Sizes and statistics of a graph (host struct). */
+sssp_status sssp_graph_info_get(const sssp_graph* g, sssp_graph_info* out);
+
+/* Copy the preprocessed rows to host arrays of nnz entries: columns and
+ * weights of each row in ascending (weight, column) order. Synchronous. */
+sssp_status sssp_graph_sorted_rows(const sssp_graph* g, int32_t* col_out, uint32_t* w_out);
+
+/* Copy RtoW[4096] (uint32, host). Synchronous. */
+sssp_status sssp_graph_rtow(const sssp_graph* g, uint32_t* rtow_out);
+
+/* ---- solves ------------------------------------------------------------- */
+
+/* Distances from `source` into dist_out (device, n uint32), enqueued on
+ * `stream`. dist_out[source] = 0; unreachable vertices get UINT32_MAX.
+ * Returns SSSP_E_DIST_OVERFLOW (after synchronising the stream) if a reachable
+ * vertex's distance is >= UINT32_MAX; the distances are then incomplete. */
+sssp_status sssp_solve(const sssp_graph* g, int32_t source, uint32_t* dist_out,
+                       hipStream_t stream);
+
+/* As sssp_solve with options (NULL = defaults). */
+sssp_status sssp_solve_ex(const sssp_graph* g, int32_t source, uint32_t* dist_out,
+                          const sssp_options* opt, hipStream_t stream);
+
+/* k sources on one graph in one persistent launch. sources: host array of k
+ * vertex ids; dist_out: device, k * n uint32, row i for sources[i]. */
+sssp_status sssp_solve_batch(const sssp_graph* g, const int32_t* sources, int32_t k,
+                             uint32_t* dist_out, hipStream_t stream);
+
+/* k independent (graph, source) pairs in one persistent launch; graphs may
+ * differ in size. gs, sources, dist_outs: host arrays of k entries;
+ * dist_outs[i] is device memory of gs[i]'s n uint32. */
+sssp_status sssp_solve_multi(const sssp_graph* const* gs, const int32_t* sources, int32_t k,
+                             uint32_t* const* dist_outs, const sssp_options* opt,
+                             hipStream_t stream);
+
+/* Counters of the last solve enqueued on `stream` (for a batch: summed over
+ * its instances). Synchronises the stream. */
+sssp_status sssp_get_counters(hipStream_t stream, sssp_counters* out);
+
+/* Schedule of the last single-source solve on `stream`: up to cap steps into
+ * out (host); *len receives the number of steps taken. Synchronises. */
+sssp_status sssp_get_schedule(hipStream_t stream, sssp_step* out, int32_t cap, int32_t* len);
+
+/* ---- errors ------------------------------------------------------------- */
+
+sssp_status sssp_last_error(void);
+const char* sssp_last_error_message(void);
+const char* sssp_status_str(sssp_status s);
+/* Library version string. */
+const char* sssp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SSSP_H */

@@ -1,0 +1,179 @@
+"""MI355X (gfx950) single-source shortest paths after Yu, Wang and Luo,
+"A Heuristic Algorithm for Shortest Path Search" (arXiv 2506.19349).
+
+Python face of the C ABI in include/sssp.h: graphs are prepared on the GPU
+(`Graph`), solves run as one persistent HIP launch on a torch stream and write
+uint32 distances (UINT32_MAX = unreachable) into torch device tensors.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Iterable, Optional, Sequence
+
+import numpy as np
+
+from . import _lib
+from ._lib import SSSPError
+
+INF = 0xFFFFFFFF
+
+__all__ = ["Graph", "solve_multi", "counters", "schedule", "SSSPError", "INF", "version"]
+
+
+def version() -> str:
+    return _lib.sssp_version().decode()
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream) -> int:
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(getattr(stream, "cuda_stream", stream) or 0)
+
+
+def _ptr(a):
+    """Device or host address of a torch tensor or numpy array (kept alive by the caller)."""
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return a.data_ptr()
+
+
+def _as_i32(a):
+    if isinstance(a, np.ndarray):
+        return np.ascontiguousarray(a, dtype=np.int32)
+    torch = _torch()
+    return a.to(torch.int32).contiguous()
+
+
+def _as_u32(a):
+    if isinstance(a, np.ndarray):
+        return np.ascontiguousarray(a, dtype=np.uint32)
+    torch = _torch()
+    if a.dtype == torch.uint32:
+        return a.contiguous()
+    return a.to(torch.int64).to(torch.uint32).contiguous()
+
+
+def _options(traversal_opt=True, alpha=None, beta=None, host_driven=False, blocks_per_cu=0,
+             heavy_split=0):
+    o = _lib.Options()
+    o.traversal_opt = 1 if traversal_opt else -1
+    o.alpha = int(alpha or 0)
+    o.beta = float(beta or 0.0)
+    o.host_driven = 1 if host_driven else 0
+    o.blocks_per_cu = int(blocks_per_cu)
+    o.heavy_split = int(heavy_split)
+    return o
+
+
+def _empty_dist(n: int, k: Optional[int] = None):
+    torch = _torch()
+    shape = (n,) if k is None else (k, n)
+    return torch.empty(shape, dtype=torch.uint32, device="cuda")
+
+
+class Graph:
+    """A symmetric CSR graph prepared on the current GPU (sssp_graph_create)."""
+
+    def __init__(self, rowptr, colidx, weight, check_symmetry: bool = True):
+        rp, ci, w = _as_i32(rowptr), _as_i32(colidx), _as_u32(weight)
+        n = int(rp.shape[0]) - 1
+        flags = 0 if check_symmetry else 1
+        h = _lib.sssp_graph_create_ex(n, _ptr(rp), _ptr(ci), _ptr(w), flags)
+        if not h:
+            _lib.check(_lib.sssp_last_error() or -6)
+        self._h = h
+        self.n = n
+        info = self.info()
+        self.nnz = info["nnz"]
+
+    @classmethod
+    def from_csr(cls, csr, check_symmetry: bool = True) -> "Graph":
+        return cls(csr.rowptr, csr.col, csr.w, check_symmetry)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.sssp_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        gi = _lib.GraphInfo()
+        _lib.check(_lib.sssp_graph_info_get(self._h, ctypes.byref(gi)))
+        return {f: getattr(gi, f) for f, _ in gi._fields_ if f != "reserved"}
+
+    def sorted_rows(self):
+        col = np.empty(self.nnz, np.int32)
+        w = np.empty(self.nnz, np.uint32)
+        _lib.check(_lib.sssp_graph_sorted_rows(self._h, col.ctypes.data, w.ctypes.data))
+        return col, w
+
+    def rtow(self) -> np.ndarray:
+        out = np.empty(4096, np.uint32)
+        _lib.check(_lib.sssp_graph_rtow(self._h, out.ctypes.data))
+        return out
+
+    def solve(self, source: int, out=None, stream=None, **opts):
+        """Distances from `source` as a uint32 cuda tensor of n entries."""
+        if out is None:
+            out = _empty_dist(self.n)
+        o = _options(**opts)
+        _lib.check(_lib.sssp_solve_ex(self._h, int(source), _ptr(out), ctypes.byref(o),
+                                      _stream_handle(stream)))
+        return out
+
+    def solve_batch(self, sources: Sequence[int], out=None, stream=None):
+        """k sources in one launch: a (k, n) uint32 cuda tensor, row i for sources[i]."""
+        srcs = np.ascontiguousarray(np.asarray(sources, dtype=np.int32))
+        k = int(srcs.shape[0])
+        if out is None:
+            out = _empty_dist(self.n, k)
+        _lib.check(_lib.sssp_solve_batch(self._h, srcs.ctypes.data, k, _ptr(out),
+                                         _stream_handle(stream)))
+        return out
+
+
+def solve_multi(graphs: Sequence[Graph], sources: Sequence[int], outs=None, stream=None, **opts):
+    """Independent (graph, source) pairs in one launch; returns the list of distance tensors."""
+    k = len(graphs)
+    if outs is None:
+        outs = [_empty_dist(g.n) for g in graphs]
+    hs = (ctypes.c_void_p * k)(*[g._h for g in graphs])
+    srcs = np.ascontiguousarray(np.asarray(sources, dtype=np.int32))
+    ptrs = (ctypes.c_void_p * k)(*[_ptr(o) for o in outs])
+    o = _options(**opts)
+    _lib.check(_lib.sssp_solve_multi(ctypes.cast(hs, ctypes.c_void_p), srcs.ctypes.data, k,
+                                     ctypes.cast(ptrs, ctypes.c_void_p), ctypes.byref(o),
+                                     _stream_handle(stream)))
+    return outs
+
+
+def counters(stream=None) -> dict:
+    """Work counters of the last solve on `stream` (synchronises it)."""
+    c = _lib.Counters()
+    st = _lib.sssp_get_counters(_stream_handle(stream), ctypes.byref(c))
+    d = {f: int(getattr(c, f)) for f, _ in c._fields_ if f != "reserved"}
+    _lib.check(st)
+    return d
+
+
+def schedule(stream=None, cap: int = 1 << 16) -> list:
+    """Per-step schedule of the last single-source solve on `stream`."""
+    buf = (_lib.Step * cap)()
+    n = ctypes.c_int32(0)
+    _lib.check(_lib.sssp_get_schedule(_stream_handle(stream), buf, cap, ctypes.byref(n)))
+    out = []
+    for i in range(min(cap, n.value)):
+        s = buf[i]
+        out.append({f: int(getattr(s, f)) for f, _ in s._fields_ if f != "reserved"})
+    return out

@@ -1,0 +1,619 @@
+// C ABI of the SSSP engine: argument checking, graph objects, per-stream
+// solver workspaces and the launch sequence of a solve.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/sssp.h"
+#include "engine.h"
+#include "prep.h"
+
+struct sssp_graph {
+  sssp::GraphHost gh;
+};
+
+namespace {
+
+using namespace sssp;
+
+thread_local sssp_status t_status = SSSP_OK;
+thread_local std::string t_msg;
+
+sssp_status fail(sssp_status s, const std::string& m) {
+  t_status = s;
+  t_msg = m;
+  return s;
+}
+
+sssp_status ok() {
+  t_status = SSSP_OK;
+  t_msg.clear();
+  return SSSP_OK;
+}
+
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t _e = (expr);                                                            \
+    if (_e != hipSuccess) return fail(SSSP_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+
+uint32_t pow2_at_least(uint64_t x) {
+  uint64_t p = 1;
+  while (p < x) p <<= 1;
+  return (uint32_t)p;
+}
+
+// ------------------------------------------------------------ workspaces --
+
+struct SlotBuf {
+  int32_t n_cap = 0, heavy_cap = 0, hist_cap = 0, trace_cap = 0;
+  uint32_t ring_cap = 0, steprec_cap = 0;
+  uint32_t* stamp = nullptr;
+  int32_t* q[2] = {nullptr, nullptr};
+  int32_t* touched = nullptr;
+  int32_t* settled = nullptr;
+  int32_t* plist[2] = {nullptr, nullptr};
+  int32_t* ulist[2] = {nullptr, nullptr};
+  HeavyItem* heavy[2] = {nullptr, nullptr};
+  uint64_t* ring_mass = nullptr;
+  uint32_t* ring_cnt = nullptr;
+  uint32_t* hist = nullptr;
+  StepRec* steprec = nullptr;
+  TraceRec* trace = nullptr;
+  uint32_t* rid = nullptr;
+  std::vector<void*> allocs;
+  void release() {
+    for (void* p : allocs) (void)hipFree(p);
+    allocs.clear();
+    n_cap = heavy_cap = hist_cap = trace_cap = 0;
+    ring_cap = steprec_cap = 0;
+  }
+};
+
+struct Needs {
+  int32_t n, heavy, hist, trace;
+  uint32_t ring, steprec;
+};
+
+Needs needs_for(const DevGraph& g) {
+  Needs r;
+  r.n = g.n;
+  r.heavy = g.nnz / 128 + 4096;
+  r.hist = std::max(g.num_deg, 1);
+  r.trace = 1 << 16;
+  if (g.max_w <= kRingMax) {
+    r.ring = pow2_at_least(std::max<uint64_t>(64, 2ull * g.max_w + 2));
+    r.steprec = pow2_at_least(std::max<uint64_t>(64, 2ull * g.max_w + 64));
+  } else {
+    r.ring = 1024;
+    r.steprec = 1u << 17;
+  }
+  return r;
+}
+
+template <typename T>
+hipError_t dev_alloc(T** p, size_t count, std::vector<void*>& list) {
+  void* v = nullptr;
+  hipError_t e = hipMalloc(&v, std::max<size_t>(count, 1) * sizeof(T));
+  if (e == hipSuccess) {
+    list.push_back(v);
+    *p = static_cast<T*>(v);
+  }
+  return e;
+}
+
+hipError_t ensure_slot(SlotBuf& s, const Needs& nd) {
+  if (s.n_cap >= nd.n && s.heavy_cap >= nd.heavy && s.hist_cap >= nd.hist && s.trace_cap >= nd.trace &&
+      s.ring_cap >= nd.ring && s.steprec_cap >= nd.steprec)
+    return hipSuccess;
+  Needs m;
+  m.n = std::max(s.n_cap, nd.n);
+  m.heavy = std::max(s.heavy_cap, nd.heavy);
+  m.hist = std::max(s.hist_cap, nd.hist);
+  m.trace = std::max(s.trace_cap, nd.trace);
+  m.ring = std::max(s.ring_cap, nd.ring);
+  m.steprec = std::max(s.steprec_cap, nd.steprec);
+  s.release();
+  hipError_t e = hipSuccess;
+  auto A = [&](auto** p, size_t c) {
+    if (e == hipSuccess) e = dev_alloc(p, c, s.allocs);
+  };
+  A(&s.stamp, m.n);
+  A(&s.q[0], m.n);
+  A(&s.q[1], m.n);
+  A(&s.touched, m.n);
+  A(&s.settled, m.n);
+  A(&s.plist[0], m.n);
+  A(&s.plist[1], m.n);
+  A(&s.ulist[0], m.n);
+  A(&s.ulist[1], m.n);
+  A(&s.heavy[0], m.heavy);
+  A(&s.heavy[1], m.heavy);
+  A(&s.ring_mass, m.ring);
+  A(&s.ring_cnt, m.ring);
+  A(&s.hist, m.hist);
+  A(&s.steprec, m.steprec);
+  A(&s.trace, m.trace);
+  A(&s.rid, 1);
+  if (e == hipSuccess) e = hipMemset(s.stamp, 0, sizeof(uint32_t) * (size_t)m.n);
+  if (e == hipSuccess) e = hipMemset(s.rid, 0, sizeof(uint32_t));
+  if (e != hipSuccess) {
+    s.release();
+    (void)hipGetLastError();
+    return e;
+  }
+  s.n_cap = m.n;
+  s.heavy_cap = m.heavy;
+  s.hist_cap = m.hist;
+  s.trace_cap = m.trace;
+  s.ring_cap = m.ring;
+  s.steprec_cap = m.steprec;
+  return hipSuccess;
+}
+
+struct Workspace {
+  hipStream_t stream = nullptr;
+  int device = 0;
+  std::vector<SlotBuf> slots;
+  int inst_cap = 0;
+  Globals* dG = nullptr;
+  Inst* dInst = nullptr;
+  int32_t* seg = nullptr;  // 5 arrays of (kMaxSegPerInst * inst_cap + 1)
+  std::vector<void*> allocs;
+  // pinned staging ring
+  static constexpr int kStages = 4;
+  void* stage[kStages] = {nullptr, nullptr, nullptr, nullptr};
+  size_t stage_cap[kStages] = {0, 0, 0, 0};
+  hipEvent_t stage_ev[kStages] = {nullptr, nullptr, nullptr, nullptr};
+  bool stage_used[kStages] = {false, false, false, false};
+  int next_stage = 0;
+  unsigned int* pinned_flag = nullptr;
+  int grid = 0;
+  int cus = 0;
+  int occ = 0;
+  // last solve
+  int last_k = 0;
+  bool persistent_failed = false;
+};
+
+std::mutex g_ws_mu;
+std::map<std::pair<int, hipStream_t>, Workspace*> g_ws;
+
+hipError_t ws_ensure_insts(Workspace& w, int k) {
+  if (w.inst_cap >= k) return hipSuccess;
+  if (w.stream) (void)hipStreamSynchronize(w.stream);
+  else (void)hipDeviceSynchronize();
+  for (void* p : w.allocs) (void)hipFree(p);
+  w.allocs.clear();
+  int cap = std::max(k, 1);
+  hipError_t e = dev_alloc(&w.dG, 1, w.allocs);
+  if (e == hipSuccess) e = dev_alloc(&w.dInst, (size_t)cap, w.allocs);
+  if (e == hipSuccess) e = dev_alloc(&w.seg, (size_t)5 * (kMaxSegPerInst * cap + 1), w.allocs);
+  if (e != hipSuccess) {
+    w.inst_cap = 0;
+    return e;
+  }
+  w.inst_cap = cap;
+  if ((int)w.slots.size() < cap) w.slots.resize((size_t)cap);
+  return hipSuccess;
+}
+
+Workspace* get_ws(hipStream_t stream, std::string* err) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    *err = "hipGetDevice failed";
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  auto key = std::make_pair(dev, stream);
+  auto it = g_ws.find(key);
+  if (it != g_ws.end()) return it->second;
+  Workspace* w = new Workspace;
+  w->stream = stream;
+  w->device = dev;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+    delete w;
+    *err = "hipGetDeviceProperties failed";
+    return nullptr;
+  }
+  w->cus = prop.multiProcessorCount;
+  w->occ = engine_blocks_per_cu();
+  w->grid = w->cus * w->occ;
+  for (int i = 0; i < Workspace::kStages; ++i) {
+    if (hipEventCreateWithFlags(&w->stage_ev[i], hipEventDisableTiming) != hipSuccess) {
+      *err = "hipEventCreate failed";
+      delete w;
+      return nullptr;
+    }
+  }
+  if (hipHostMalloc((void**)&w->pinned_flag, sizeof(unsigned int) * 4, hipHostMallocDefault) != hipSuccess) {
+    *err = "hipHostMalloc failed";
+    delete w;
+    return nullptr;
+  }
+  g_ws[key] = w;
+  return w;
+}
+
+// A pinned staging buffer of at least `bytes`, free of pending copies.
+void* ws_stage(Workspace& w, size_t bytes, int* idx) {
+  int i = w.next_stage;
+  w.next_stage = (i + 1) % Workspace::kStages;
+  if (w.stage_used[i]) (void)hipEventSynchronize(w.stage_ev[i]);
+  w.stage_used[i] = false;
+  if (w.stage_cap[i] < bytes) {
+    if (w.stage[i]) (void)hipHostFree(w.stage[i]);
+    w.stage[i] = nullptr;
+    w.stage_cap[i] = 0;
+    if (hipHostMalloc(&w.stage[i], bytes, hipHostMallocDefault) != hipSuccess) return nullptr;
+    w.stage_cap[i] = bytes;
+  }
+  *idx = i;
+  return w.stage[i];
+}
+
+struct Opts {
+  uint32_t alpha = 3;
+  double beta = 0.9;
+  uint32_t topt = 1;
+  bool host_driven = false;
+  int blocks_per_cu = 0;
+  int heavy = kDefaultHeavy;
+  unsigned long long tick_limit = 1ull << 22;
+};
+
+bool parse_opts(const sssp_options* o, Opts* r, std::string* err) {
+  if (!o) return true;
+  if (o->alpha < 0) { *err = "alpha must be >= 0"; return false; }
+  if (o->alpha > 0) r->alpha = (uint32_t)o->alpha;
+  if (o->beta != 0.0) {
+    if (!(o->beta > 0.0 && o->beta < 1.0)) { *err = "beta must be in (0, 1)"; return false; }
+    r->beta = o->beta;
+  }
+  if (o->traversal_opt < 0) r->topt = 0;
+  r->host_driven = o->host_driven != 0;
+  if (o->blocks_per_cu < 0) { *err = "blocks_per_cu must be >= 0"; return false; }
+  r->blocks_per_cu = o->blocks_per_cu;
+  if (o->heavy_split < 0) { *err = "heavy_split must be >= 0"; return false; }
+  if (o->heavy_split > 0) r->heavy = std::max(o->heavy_split, kWave);
+  return true;
+}
+
+// Enqueue k instances; every argument has been checked.
+sssp_status run_instances(const sssp_graph* const* gs, const int32_t* sources, int k,
+                          uint32_t* const* dists, const Opts& o, hipStream_t stream) {
+  std::string err;
+  Workspace* wp = get_ws(stream, &err);
+  if (!wp) return fail(SSSP_E_DEVICE, err);
+  Workspace& w = *wp;
+  HIP_TRY(ws_ensure_insts(w, k));
+  long long max_n = 0;
+  for (int i = 0; i < k; ++i) {
+    const DevGraph& g = gs[i]->gh.h;
+    max_n = std::max<long long>(max_n, g.n);
+    Needs nd = needs_for(g);
+    SlotBuf& s = w.slots[(size_t)i];
+    if (!(s.n_cap >= nd.n && s.heavy_cap >= nd.heavy && s.hist_cap >= nd.hist && s.ring_cap >= nd.ring &&
+          s.steprec_cap >= nd.steprec && s.trace_cap >= nd.trace)) {
+      (void)hipStreamSynchronize(stream);
+      hipError_t e = ensure_slot(s, nd);
+      if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+        return fail(SSSP_E_NOMEM, "workspace allocation failed");
+      HIP_TRY(e);
+    }
+  }
+  const size_t bytes = sizeof(Globals) + sizeof(Inst) * (size_t)k;
+  int si = 0;
+  void* st = ws_stage(w, bytes, &si);
+  if (!st) return fail(SSSP_E_NOMEM, "pinned staging allocation failed");
+  Globals* hG = static_cast<Globals*>(st);
+  Inst* hI = reinterpret_cast<Inst*>(static_cast<char*>(st) + sizeof(Globals));
+  std::memset(st, 0, bytes);
+  const int segcap = kMaxSegPerInst * w.inst_cap + 1;
+  hG->ninst = k;
+  hG->tick_limit = o.tick_limit;
+  hG->seg_inst = w.seg;
+  hG->seg_kind = w.seg + segcap;
+  hG->seg_count = w.seg + 2 * segcap;
+  hG->seg_per_batch = w.seg + 3 * segcap;
+  hG->seg_first_batch = w.seg + 4 * segcap;
+  hG->insts = w.dInst;
+  for (int i = 0; i < k; ++i) {
+    const SlotBuf& s = w.slots[(size_t)i];
+    Inst& I = hI[i];
+    I.g = gs[i]->gh.d;
+    I.dist = dists[i];
+    I.stamp = s.stamp;
+    I.q[0] = s.q[0];
+    I.q[1] = s.q[1];
+    I.touched = s.touched;
+    I.settled = s.settled;
+    I.plist[0] = s.plist[0];
+    I.plist[1] = s.plist[1];
+    I.ulist[0] = s.ulist[0];
+    I.ulist[1] = s.ulist[1];
+    I.heavy[0] = s.heavy[0];
+    I.heavy[1] = s.heavy[1];
+    I.ring_mass = s.ring_mass;
+    I.ring_cnt = s.ring_cnt;
+    I.hist_cnt = s.hist;
+    I.steprec = s.steprec;
+    I.trace = s.trace;
+    I.rid_slot = s.rid;
+    I.heavy_cap = s.heavy_cap;
+    Needs nd = needs_for(gs[i]->gh.h);
+    I.ring_mask = nd.ring - 1;
+    I.steprec_mask = nd.steprec - 1;
+    I.trace_cap = s.trace_cap;
+    I.source = sources[i];
+    I.n = gs[i]->gh.h.n;
+    I.alpha = o.alpha;
+    I.traversal_opt = o.topt;
+    I.beta = o.beta;
+    I.heavy_split = o.heavy;
+  }
+  HIP_TRY(hipMemcpyAsync(w.dG, hG, sizeof(Globals), hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipMemcpyAsync(w.dInst, hI, sizeof(Inst) * (size_t)k, hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipEventRecord(w.stage_ev[si], stream));
+  w.stage_used[si] = true;
+  HIP_TRY(launch_init(w.dG, max_n, stream));
+  bool host_driven = o.host_driven || w.persistent_failed;
+  if (!host_driven) {
+    int bpc = o.blocks_per_cu > 0 ? std::min(o.blocks_per_cu, w.occ) : w.occ;
+    hipError_t e = launch_engine(w.dG, w.cus * bpc, true, 0, stream);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      w.persistent_failed = true;
+      host_driven = true;
+    }
+  }
+  if (host_driven) {
+    // one tick per launch; the host polls the completion flag
+    const int grid = w.cus * std::max(1, std::min(w.occ, 8));
+    for (long long t = 0;; ++t) {
+      HIP_TRY(launch_engine(w.dG, grid, false, 0, stream));
+      HIP_TRY(hipMemcpyAsync(w.pinned_flag, &w.dG->all_done, sizeof(unsigned int) * 2,
+                             hipMemcpyDeviceToHost, stream));
+      HIP_TRY(hipStreamSynchronize(stream));
+      if (w.pinned_flag[0] || w.pinned_flag[1]) break;
+      if (t > (long long)o.tick_limit + 4) return fail(SSSP_E_DEVICE, "tick limit exceeded");
+    }
+  }
+  HIP_TRY(launch_overflow_check(w.dG, max_n, stream));
+  w.last_k = k;
+  return ok();
+}
+
+bool check_graph(const sssp_graph* g, std::string* err) {
+  if (!g) { *err = "graph is NULL"; return false; }
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev != g->gh.device) {
+    *err = "the graph lives on another device than the current one";
+    return false;
+  }
+  return true;
+}
+
+}  // namespace
+
+// ================================================================== C ABI
+
+extern "C" {
+
+sssp_graph* sssp_graph_create_ex(int32_t n, const int32_t* rowptr, const int32_t* colidx,
+                                 const uint32_t* weight, int32_t flags) {
+  if (n < 1 || rowptr == nullptr) {
+    fail(SSSP_E_INVAL, "n must be >= 1 and rowptr non-NULL");
+    return nullptr;
+  }
+  sssp_graph* g = new (std::nothrow) sssp_graph;
+  if (!g) {
+    fail(SSSP_E_NOMEM, "host allocation failed");
+    return nullptr;
+  }
+  std::string msg;
+  int rc = prep_graph(n, rowptr, colidx, weight, flags, &g->gh, &msg);
+  if (rc != 0) {
+    free_graph(&g->gh);
+    delete g;
+    (void)hipGetLastError();
+    fail((sssp_status)rc, msg);
+    return nullptr;
+  }
+  ok();
+  return g;
+}
+
+sssp_graph* sssp_graph_create(int32_t n, const int32_t* rowptr, const int32_t* colidx,
+                              const uint32_t* weight) {
+  return sssp_graph_create_ex(n, rowptr, colidx, weight, 0);
+}
+
+sssp_status sssp_graph_destroy(sssp_graph* g) {
+  if (!g) return ok();
+  (void)hipDeviceSynchronize();
+  free_graph(&g->gh);
+  delete g;
+  return ok();
+}
+
+sssp_status sssp_graph_info_get(const sssp_graph* g, sssp_graph_info* out) {
+  if (!g || !out) return fail(SSSP_E_INVAL, "NULL argument");
+  const DevGraph& h = g->gh.h;
+  std::memset(out, 0, sizeof(*out));
+  out->n = h.n;
+  out->nnz = h.nnz;
+  out->nonisolated = g->gh.nonisolated;
+  out->max_degree = g->gh.max_degree;
+  out->distinct_degrees = g->gh.distinct_degrees;
+  out->max_weight = h.max_w;
+  out->high_d0 = h.high_d0;
+  out->device_bytes = g->gh.bytes;
+  return ok();
+}
+
+sssp_status sssp_graph_sorted_rows(const sssp_graph* g, int32_t* col_out, uint32_t* w_out) {
+  std::string err;
+  if (!check_graph(g, &err)) return fail(SSSP_E_INVAL, err);
+  const DevGraph& h = g->gh.h;
+  if (h.nnz > 0 && (!col_out || !w_out)) return fail(SSSP_E_INVAL, "NULL output");
+  std::vector<uint64_t> tmp((size_t)h.nnz);
+  if (h.nnz > 0) HIP_TRY(hipMemcpy(tmp.data(), h.adj, sizeof(uint64_t) * (size_t)h.nnz, hipMemcpyDeviceToHost));
+  for (size_t e = 0; e < tmp.size(); ++e) {
+    col_out[e] = (int32_t)(uint32_t)(tmp[e] & 0xffffffffull);
+    w_out[e] = (uint32_t)(tmp[e] >> 32);
+  }
+  return ok();
+}
+
+sssp_status sssp_graph_rtow(const sssp_graph* g, uint32_t* rtow_out) {
+  std::string err;
+  if (!check_graph(g, &err)) return fail(SSSP_E_INVAL, err);
+  if (!rtow_out) return fail(SSSP_E_INVAL, "NULL output");
+  HIP_TRY(hipMemcpy(rtow_out, g->gh.h.rtow, sizeof(uint32_t) * kRatioNum, hipMemcpyDeviceToHost));
+  return ok();
+}
+
+sssp_status sssp_solve_ex(const sssp_graph* g, int32_t source, uint32_t* dist_out,
+                          const sssp_options* opt, hipStream_t stream) {
+  std::string err;
+  if (!check_graph(g, &err)) return fail(SSSP_E_INVAL, err);
+  if (source < 0 || source >= g->gh.h.n) return fail(SSSP_E_INVAL, "source out of range");
+  if (!dist_out) return fail(SSSP_E_INVAL, "dist_out is NULL");
+  Opts o;
+  if (!parse_opts(opt, &o, &err)) return fail(SSSP_E_INVAL, err);
+  const sssp_graph* gs[1] = {g};
+  int32_t src[1] = {source};
+  uint32_t* d[1] = {dist_out};
+  return run_instances(gs, src, 1, d, o, stream);
+}
+
+sssp_status sssp_solve(const sssp_graph* g, int32_t source, uint32_t* dist_out, hipStream_t stream) {
+  return sssp_solve_ex(g, source, dist_out, nullptr, stream);
+}
+
+sssp_status sssp_solve_batch(const sssp_graph* g, const int32_t* sources, int32_t k, uint32_t* dist_out,
+                             hipStream_t stream) {
+  std::string err;
+  if (!check_graph(g, &err)) return fail(SSSP_E_INVAL, err);
+  if (k < 1 || !sources || !dist_out) return fail(SSSP_E_INVAL, "k >= 1, sources and dist_out required");
+  for (int i = 0; i < k; ++i)
+    if (sources[i] < 0 || sources[i] >= g->gh.h.n) return fail(SSSP_E_INVAL, "source out of range");
+  std::vector<const sssp_graph*> gs((size_t)k, g);
+  std::vector<uint32_t*> d((size_t)k);
+  for (int i = 0; i < k; ++i) d[(size_t)i] = dist_out + (size_t)i * (size_t)g->gh.h.n;
+  Opts o;
+  return run_instances(gs.data(), sources, k, d.data(), o, stream);
+}
+
+sssp_status sssp_solve_multi(const sssp_graph* const* gs, const int32_t* sources, int32_t k,
+                             uint32_t* const* dist_outs, const sssp_options* opt, hipStream_t stream) {
+  std::string err;
+  if (k < 1 || !gs || !sources || !dist_outs) return fail(SSSP_E_INVAL, "k >= 1 and arrays required");
+  for (int i = 0; i < k; ++i) {
+    if (!check_graph(gs[i], &err)) return fail(SSSP_E_INVAL, err);
+    if (sources[i] < 0 || sources[i] >= gs[i]->gh.h.n) return fail(SSSP_E_INVAL, "source out of range");
+    if (!dist_outs[i]) return fail(SSSP_E_INVAL, "dist_outs entry is NULL");
+  }
+  Opts o;
+  if (!parse_opts(opt, &o, &err)) return fail(SSSP_E_INVAL, err);
+  return run_instances(gs, sources, k, dist_outs, o, stream);
+}
+
+sssp_status sssp_get_counters(hipStream_t stream, sssp_counters* out) {
+  if (!out) return fail(SSSP_E_INVAL, "NULL output");
+  std::string err;
+  Workspace* w = get_ws(stream, &err);
+  if (!w) return fail(SSSP_E_DEVICE, err);
+  std::memset(out, 0, sizeof(*out));
+  if (w->last_k == 0) return fail(SSSP_E_INVAL, "no solve on this stream");
+  HIP_TRY(hipStreamSynchronize(stream));
+  std::vector<Inst> hi((size_t)w->last_k);
+  HIP_TRY(hipMemcpy(hi.data(), w->dInst, sizeof(Inst) * (size_t)w->last_k, hipMemcpyDeviceToHost));
+  Globals hg;
+  HIP_TRY(hipMemcpy(&hg, w->dG, sizeof(Globals), hipMemcpyDeviceToHost));
+  uint32_t flags = 0;
+  for (const Inst& I : hi) {
+    out->expansions += I.c.expansions;
+    out->band_expansions += I.c.band_expansions;
+    out->push_scanned += I.c.push_scanned;
+    out->pull_vertices += I.c.pull_vertices;
+    out->pull_scanned += I.c.pull_scanned;
+    out->relax_success += I.c.relax_success;
+    out->queue_entries += I.c.queue_entries;
+    out->rounds += I.c.rounds;
+    out->pulls += I.c.pulls;
+    out->steps += I.c.steps;
+    out->ticks += I.c.ticks;
+    flags |= I.flags;
+  }
+  out->high_d0 = hi[0].high_d0;
+  out->gap0 = hi[0].gap0;
+  flags |= hg.error;
+  out->flags = flags;
+  if (flags & FLAG_OVERFLOW) return fail(SSSP_E_DIST_OVERFLOW, "a distance does not fit below UINT32_MAX");
+  if (flags & (FLAG_CAPACITY | FLAG_MASS | FLAG_TIMEOUT | FLAG_TICKS))
+    return fail(SSSP_E_DEVICE, "internal engine condition, flags = " + std::to_string(flags));
+  return ok();
+}
+
+sssp_status sssp_get_schedule(hipStream_t stream, sssp_step* out, int32_t cap, int32_t* len) {
+  if (!len || (cap > 0 && !out)) return fail(SSSP_E_INVAL, "NULL output");
+  std::string err;
+  Workspace* w = get_ws(stream, &err);
+  if (!w) return fail(SSSP_E_DEVICE, err);
+  if (w->last_k == 0) return fail(SSSP_E_INVAL, "no solve on this stream");
+  HIP_TRY(hipStreamSynchronize(stream));
+  Inst I;
+  HIP_TRY(hipMemcpy(&I, w->dInst, sizeof(Inst), hipMemcpyDeviceToHost));
+  *len = I.trace_len;
+  int m = std::min(std::min(cap, I.trace_len), I.trace_cap);
+  if (m > 0) {
+    std::vector<TraceRec> t((size_t)m);
+    HIP_TRY(hipMemcpy(t.data(), I.trace, sizeof(TraceRec) * (size_t)m, hipMemcpyDeviceToHost));
+    for (int i = 0; i < m; ++i) {
+      sssp_step& s = out[i];
+      std::memset(&s, 0, sizeof(s));
+      s.lb = t[(size_t)i].lb;
+      s.ub = t[(size_t)i].ub;
+      s.st = t[(size_t)i].st;
+      s.rounds = t[(size_t)i].rounds;
+      s.pulled = t[(size_t)i].pulled;
+      s.L = t[(size_t)i].L;
+      s.S = t[(size_t)i].S;
+      s.h = t[(size_t)i].h;
+      s.gap = t[(size_t)i].gap;
+      s.st_next = t[(size_t)i].st_next;
+    }
+  }
+  return ok();
+}
+
+sssp_status sssp_last_error(void) { return t_status; }
+
+const char* sssp_last_error_message(void) { return t_msg.c_str(); }
+
+const char* sssp_status_str(sssp_status s) {
+  switch (s) {
+    case SSSP_OK: return "ok";
+    case SSSP_E_INVAL: return "invalid argument";
+    case SSSP_E_NOT_SYMMETRIC: return "graph is not symmetric";
+    case SSSP_E_RANGE: return "size beyond limits";
+    case SSSP_E_DIST_OVERFLOW: return "distance overflow";
+    case SSSP_E_NOMEM: return "out of memory";
+    case SSSP_E_DEVICE: return "device error";
+    case SSSP_E_BUSY: return "busy";
+  }
+  return "unknown status";
+}
+
+const char* sssp_version(void) { return "paper_2506_19349_amd 0.1 (gfx950)"; }
+
+}  // extern "C"

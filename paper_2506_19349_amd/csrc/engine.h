@@ -1,0 +1,177 @@
+// Internal data layout shared by the graph preparation, the solver engine and
+// the C ABI. Device structures are plain structs of pointers and scalars that
+// live in device memory; the host fills them once and launches with pointers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sssp {
+
+constexpr uint32_t kInf = 0xFFFFFFFFu;   // +infinity: the single sentinel for dist and thresholds
+constexpr int kWave = 64;                // CDNA wavefront
+constexpr int kBlock = 256;              // threads per workgroup (4 waves)
+constexpr int kRatioNum = 4096;          // RATIO_NUM, Section 4.1
+constexpr uint32_t kRingMax = 65536;     // exact selection-threshold window up to this max weight
+constexpr int kLdsRing = 1024;           // settle: distance bins privatised in LDS
+constexpr int kLdsHist = 1024;           // settle: degree ranks privatised in LDS
+constexpr int kHeavyChunk = 256;         // edges per heavy chunk
+constexpr int kDefaultHeavy = 1024;      // ranges longer than this are split
+
+// ------------------------------------------------------------------ graph --
+struct DevGraph {
+  int32_t n;
+  int32_t nnz;
+  uint32_t max_w;        // maxW(G, 1)
+  uint32_t high_d0;      // highD(0)
+  int32_t num_deg;       // distinct degrees >= 1 (D)
+  int32_t n_nonisolated;
+  int32_t max_deg;
+  int32_t pad;
+  const int32_t* rowptr;     // n + 1
+  const uint64_t* adj;       // nnz entries, (weight << 32) | column, each row ascending
+  const uint32_t* wmin;      // n: smallest weight of the row (kInf for degree 0)
+  const int32_t* drank;      // n: index of deg(v) among the distinct degrees (-1 for 0)
+  const int32_t* deg_vals;   // D ascending distinct degrees
+  const uint32_t* deg_cnt0;  // D: vertices with that degree
+  const uint32_t* hub_bits;  // ceil(n/32) words: deg(v) >= highD(0)
+  const int32_t* nonisolated;  // n_nonisolated vertex ids, ascending
+  const uint32_t* rtow;      // 4096
+};
+
+// ------------------------------------------------------- solver instance --
+enum Phase : uint32_t { PH_ROUND = 0, PH_SETTLE = 1, PH_DONE = 2 };
+
+enum SegKind : int32_t {
+  SEG_W = 0,   // settled list range: deferred pushes of settled vertices in [lb0, st]
+  SEG_P = 1,   // pending list: first-step leftovers whose tentative dist fell into the band
+  SEG_U = 2,   // pull over the unsettled list
+  SEG_Q = 3,   // frontier queue
+  SEG_H = 4,   // heavy chunks split off the previous tick
+  SEG_ST = 5,  // settle: touched list
+  SEG_SP = 6,  // settle: pending list compaction
+};
+
+struct StepRec {
+  uint32_t lb, ub;
+  int32_t seg_begin, seg_end;  // settled-list positions of this step's vertices
+};
+
+struct HeavyItem {
+  int32_t u;
+  uint32_t d;       // dist[u] when split (push) / unused (pull)
+  int32_t lo;
+  int32_t hi_kind;  // hi | (kind << 31): kind 1 = pull chunk
+};
+
+struct TraceRec {
+  uint32_t lb, ub, st, rounds;
+  uint32_t pulled, L;
+  uint64_t S;
+  uint32_t h, gap, st_next, pad;
+};
+
+struct Counters {
+  unsigned long long expansions, band_expansions, push_scanned, pull_vertices, pull_scanned,
+      relax_success, queue_entries, rounds, pulls, steps, ticks;
+};
+
+struct Inst {
+  // ---- fixed for a solve ----
+  const DevGraph* g;
+  uint32_t* dist;
+  uint32_t* stamp;
+  int32_t* q[2];
+  int32_t* touched;
+  int32_t* settled;
+  int32_t* plist[2];
+  int32_t* ulist[2];
+  HeavyItem* heavy[2];
+  uint64_t* ring_mass;
+  uint32_t* ring_cnt;
+  uint32_t* hist_cnt;
+  StepRec* steprec;
+  TraceRec* trace;
+  uint32_t* rid_slot;      // persists the stamp counter of this workspace slot across solves
+  int32_t heavy_cap;
+  uint32_t ring_mask;
+  uint32_t steprec_mask;
+  int32_t trace_cap;
+  int32_t source;
+  int32_t n;
+  uint32_t alpha;
+  uint32_t traversal_opt;
+  double beta;
+  int32_t heavy_split;
+  int32_t pad0;
+  // ---- control (written by the epilogue / the heuristic) ----
+  uint32_t phase;
+  uint32_t tick_kind;      // PH_ROUND or PH_SETTLE: what the scheduled tick does
+  uint32_t init_round;     // current round is a step's first (W / P / U segments)
+  uint32_t pull_on;        // st < lb for this step
+  uint32_t lb, ub, st, lb0;
+  uint32_t first;          // first step (ub follows the nearest hub)
+  uint32_t gap_cur;        // gap(lb) of the current step
+  uint32_t M;
+  uint32_t rid;            // stamp value of the current round
+  uint32_t step_rid0;      // stamp marker of the current step (rounds use > step_rid0)
+  uint32_t step;
+  uint32_t rounds_in_step;
+  int32_t qsel, psel, usel, hsel;
+  int32_t nF, wBegin, wEnd, nP, nU, nT, nH;
+  int32_t settled_mark;
+  int32_t nsteprec;
+  int32_t trace_len;
+  // ---- append counters (reset by the epilogue) ----
+  int32_t q_next_cnt, touched_cnt, p_next_cnt, u_next_cnt, settled_cnt, h_next_cnt;
+  uint32_t ub_next;
+  uint32_t max_settled;
+  unsigned long long S;    // sumD(lb): degree mass of the unsettled set
+  int32_t settle_items;    // items (padded) of the settle tick
+  int32_t settle_done;
+  uint32_t flags;
+  uint32_t high_d0, gap0;
+  uint32_t pad1;
+  Counters c;
+};
+
+// flags
+constexpr uint32_t FLAG_MAYBE_OVERFLOW = 1u;  // an edge was cut by the +inf clamp
+constexpr uint32_t FLAG_CAPACITY = 2u;        // an internal list overflowed (bug guard)
+constexpr uint32_t FLAG_MASS = 4u;            // degree-mass bookkeeping mismatch (bug guard)
+constexpr uint32_t FLAG_TIMEOUT = 8u;         // a grid barrier wait gave up
+constexpr uint32_t FLAG_OVERFLOW = 16u;       // confirmed: a distance does not fit below kInf
+constexpr uint32_t FLAG_TICKS = 32u;          // the tick limit stopped the engine
+
+// ------------------------------------------------------------- tick table --
+constexpr int kMaxSegPerInst = 5;
+
+struct Globals {
+  // grid barrier
+  unsigned int bar_count;
+  unsigned int bar_gen;
+  unsigned int all_done;
+  unsigned int error;
+  // current tick layout
+  int32_t nseg;
+  int32_t total_batches;
+  int32_t ninst;
+  int32_t max_ticks_hit;
+  unsigned long long ticks;
+  unsigned long long tick_limit;  // safety stop for a schedule that fails to end
+  // per segment: instance, kind, item count, items per batch, first batch
+  int32_t* seg_inst;
+  int32_t* seg_kind;
+  int32_t* seg_count;
+  int32_t* seg_per_batch;
+  int32_t* seg_first_batch;  // nseg + 1 entries
+  Inst* insts;
+};
+
+// host launch wrappers (engine.hip)
+hipError_t launch_init(Globals* dG, long long max_n, hipStream_t stream);
+int engine_blocks_per_cu();
+hipError_t launch_engine(Globals* dG, int grid, bool persistent, int max_ticks, hipStream_t stream);
+hipError_t launch_overflow_check(Globals* dG, long long max_n, hipStream_t stream);
+
+}  // namespace sssp

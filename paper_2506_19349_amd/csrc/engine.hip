@@ -1,0 +1,1098 @@
+// Solver engine: the heuristic SSSP algorithm of Yu, Wang and Luo (Section 3.3,
+// the Algorithm with Function 1 initFrontiers and Function 2 computeST) on one
+// gfx950 GPU.
+//
+// Execution model. A solve (or a batch of independent solves, "instances") is
+// a sequence of device-wide ticks. A tick is either a push round of one or
+// more instances (Algorithm, the while loop) or a settle pass that closes a
+// step (statistics for the next pair). Ticks are separated by a grid barrier;
+// the last workgroup to arrive runs a short serial epilogue (phase
+// transitions and the next tick's work layout) before releasing the others.
+// The same tick body runs either inside one persistent cooperative launch or
+// as one launch per tick.
+//
+// Work of a tick is a list of segments (instance, kind, item count); items are
+// cut into fixed batches and batches are dealt to workgroups round-robin.
+//
+// Relaxations are asynchronous within a round (atomicMin on dist; every
+// relaxation's result is a real path length, so any interleaving reaches the
+// exact distances). The per-step schedule <lb, ub, st> depends only on the
+// settled set and is therefore deterministic.
+#include "engine.h"
+
+namespace sssp {
+
+// ------------------------------------------------------------ wave helpers --
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  return (1ull << lane_id()) - 1ull;
+}
+
+__device__ __forceinline__ int wave_incl_scan(int x) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    int y = __shfl_up(x, o, kWave);
+    if (lane >= o) x += y;
+  }
+  return x;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T x) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
+  return x;
+}
+
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t x) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    uint32_t y = __shfl_xor(x, o, kWave);
+    x = y < x ? y : x;
+  }
+  return x;
+}
+
+// Wave-aggregated append: one atomic per wave. Every lane of the wave must
+// call it (convergent). Returns the slot or -1.
+__device__ __forceinline__ int wave_append(int32_t* counter, bool want) {
+  uint64_t m = __ballot(want);
+  if (m == 0) return -1;
+  int leader = __ffsll((unsigned long long)m) - 1;
+  int base = 0;
+  if (lane_id() == leader) base = atomicAdd(counter, __popcll(m));
+  base = __shfl(base, leader, kWave);
+  return want ? base + __popcll(m & lanemask_lt()) : -1;
+}
+
+__device__ __forceinline__ int lower_bound_key(const uint64_t* __restrict__ adj, int lo, int hi,
+                                               uint64_t key) {
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (adj[mid] < key) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ bool is_hub(const DevGraph& g, int v) {
+  return (g.hub_bits[v >> 5] >> (v & 31)) & 1u;
+}
+
+// --------------------------------------------------------- block helpers --
+
+template <typename T>
+__device__ T block_excl_scan(T x, T* sh /* kBlock/kWave + 1 */, T* total) {
+  const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
+  T incl = x;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    T y = __shfl_up(incl, o, kWave);
+    if (lane >= o) incl += y;
+  }
+  if (lane == kWave - 1) sh[wid] = incl;
+  __syncthreads();
+  if (tid == 0) {
+    T run = 0;
+    for (int w = 0; w < kBlock / kWave; ++w) {
+      T t = sh[w];
+      sh[w] = run;
+      run += t;
+    }
+    sh[kBlock / kWave] = run;
+  }
+  __syncthreads();
+  T res = sh[wid] + incl - x;
+  *total = sh[kBlock / kWave];
+  __syncthreads();
+  return res;
+}
+
+// ---------------------------------------------------------- the heuristic --
+// Eq. (1)-(3) and Eq. (4)-(6) in IEEE double, operation order fixed, no fused
+// multiply-add (the file is compiled with -ffp-contract=off).
+
+__device__ uint32_t gap_of(unsigned long long S, uint32_t h, int32_t nnz, uint32_t M,
+                           const uint32_t* rtow, uint32_t alpha, double beta) {
+  uint32_t g;
+  if (h <= alpha) {
+    g = M;
+  } else {
+    unsigned long long other = (unsigned long long)nnz - S;
+    unsigned long long mx = S > other ? S : other;
+    double p = (double)mx / (double)nnz;          // Eq. (1)
+    if (beta < p) p = beta;
+    double ph = p * (double)h;
+    double r = 1.0 - pow(1.0 - p, 1.0 / ph);      // Eq. (2)
+    double xr = r * (double)(kRatioNum - 1);
+    long long idx = (long long)ceil(xr);
+    if (idx < 0) idx = 0;
+    if (idx > kRatioNum - 1) idx = kRatioNum - 1;
+    g = rtow[idx];                                // Eq. (3): maxW(G, ratio)
+  }
+  return g < 1u ? 1u : g;
+}
+
+__device__ __forceinline__ double profit_of(uint32_t x, uint32_t L, unsigned long long Y,
+                                            unsigned long long S, unsigned long long Sx,
+                                            uint32_t M, int32_t nnz) {
+  // x is within [L - M, L), so lb_0 = x (Section 3.2 clamps)
+  unsigned long long ub0 = (unsigned long long)L + M;
+  if (Y < ub0) ub0 = Y;
+  unsigned long long ub1 = (unsigned long long)x + M;
+  if (Y < ub1) ub1 = Y;
+  double pushed = (double)(ub0 - L) * (double)(Sx - S) / (double)M;  // Eq. (4)
+  double pulled = (double)(ub1 - x) * (double)S / (double)M;        // Eq. (5)
+  double lng = pulled * (double)(Sx - S) / (double)nnz;             // Eq. (6)
+  return (pushed - lng) - pulled;
+}
+
+struct HeurLds {
+  unsigned long long scan[kBlock / kWave + 1];
+  unsigned long long key[kBlock];
+  double pbest[kBlock];
+  uint32_t xbest[kBlock];
+};
+
+// highD over a degree histogram (distinct degrees deg_vals[0..D) ascending,
+// cnt[r] vertices each): the threshold h minimising |mass(deg < h) -
+// mass(deg >= h)|, smallest on ties, 0 if no mass. Whole workgroup.
+__device__ uint32_t block_high_d(const int32_t* deg_vals, const uint32_t* cnt, int32_t D,
+                                 unsigned long long* mass_total, HeurLds& L) {
+  const int tid = threadIdx.x;
+  const int chunk = (D + kBlock - 1) / kBlock;
+  const int r0 = min(D, tid * chunk), r1 = min(D, r0 + chunk);
+  unsigned long long local = 0;
+  for (int r = r0; r < r1; ++r) local += (unsigned long long)deg_vals[r] * cnt[r];
+  unsigned long long total;
+  unsigned long long low = block_excl_scan<unsigned long long>(local, L.scan, &total);
+  // best (diff, r) packed: diff < 2^33, r < 2^31 -> key = diff << 31 | r
+  unsigned long long best = ~0ull;
+  for (int r = r0; r < r1; ++r) {
+    uint32_t c = cnt[r];
+    if (c) {
+      long long dif = 2ll * (long long)low - (long long)total;
+      if (dif < 0) dif = -dif;
+      unsigned long long k = ((unsigned long long)dif << 31) | (unsigned long long)r;
+      if (k < best) best = k;
+      low += (unsigned long long)deg_vals[r] * c;
+    }
+  }
+  L.key[tid] = best;
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if (tid < s && L.key[tid + s] < L.key[tid]) L.key[tid] = L.key[tid + s];
+    __syncthreads();
+  }
+  unsigned long long b = L.key[0];
+  __syncthreads();
+  *mass_total = total;
+  if (b == ~0ull) return 0;
+  return (uint32_t)deg_vals[b & 0x7fffffffull];
+}
+
+// Function 2 (computeST) for the next pair <L, L + gap(L)>. Whole workgroup.
+__device__ uint32_t block_compute_st(const Inst& I, uint32_t L, uint32_t gapL, int32_t nnz,
+                                     HeurLds& lds) {
+  const uint32_t M = I.M;
+  const unsigned long long S = I.S;
+  if (!I.traversal_opt || M > kRingMax) return L;
+  if (2ull * S >= (unsigned long long)nnz || I.gap_cur == M) return L;
+  if (gapL == M) return L > M ? L - M : 0u;
+  const uint32_t wlo = L > M ? L - M : 0u;
+  const uint32_t W = L - wlo;
+  unsigned long long Y = (unsigned long long)L + gapL;
+  if (Y > kInf) Y = kInf;
+  const int tid = threadIdx.x;
+  const uint32_t chunk = (W + kBlock - 1) / kBlock;
+  // thread t owns x in [wlo + a, wlo + b), ascending
+  const uint32_t a = min(W, (uint32_t)tid * chunk), b = min(W, a + chunk);
+  unsigned long long local = 0;
+  for (uint32_t k = a; k < b; ++k) local += I.ring_mass[(wlo + k) & I.ring_mask];
+  unsigned long long total;
+  unsigned long long before = block_excl_scan<unsigned long long>(local, lds.scan, &total);
+  // mass at or above the end of my chunk: total - before - local
+  unsigned long long acc = total - before - local;
+  double bp = 0.0;
+  uint32_t bx = L;
+  for (uint32_t k = b; k > a; --k) {
+    uint32_t x = wlo + k - 1;
+    uint32_t slot = x & I.ring_mask;
+    acc += I.ring_mass[slot];
+    if (I.ring_cnt[slot]) {
+      double p = profit_of(x, L, Y, S, S + acc, M, nnz);
+      // ascending order, first strict maximum: prefer larger p, then smaller x
+      if (p > bp || (p == bp && p > 0.0 && x < bx)) {
+        bp = p;
+        bx = x;
+      }
+    }
+  }
+  lds.pbest[tid] = bp;
+  lds.xbest[tid] = bx;
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if (tid < s) {
+      double p2 = lds.pbest[tid + s];
+      uint32_t x2 = lds.xbest[tid + s];
+      if (p2 > lds.pbest[tid] || (p2 == lds.pbest[tid] && p2 > 0.0 && x2 < lds.xbest[tid])) {
+        lds.pbest[tid] = p2;
+        lds.xbest[tid] = x2;
+      }
+    }
+    __syncthreads();
+  }
+  uint32_t res = lds.pbest[0] > 0.0 ? lds.xbest[0] : L;
+  __syncthreads();
+  return res;
+}
+
+// The end-of-step heuristic for one instance: statistics at L = ub, gap(L),
+// computeST, step bookkeeping, termination test, and the next step's setup.
+// Runs on one workgroup, after every settle batch of the instance is done.
+__device__ void run_heuristic(Inst& I, HeurLds& lds) {
+  const DevGraph& g = *I.g;
+  const int tid = threadIdx.x;
+  const uint32_t L = I.ub;
+  unsigned long long mass;
+  uint32_t h = block_high_d(g.deg_vals, I.hist_cnt, g.num_deg, &mass, lds);
+  const unsigned long long S = I.S;
+  uint32_t gapL = gap_of(S, h, g.nnz, I.M, g.rtow, I.alpha, I.beta);
+  uint32_t stn = block_compute_st(I, L, gapL, g.nnz, lds);
+  if (tid == 0) {
+    if (mass != S) I.flags |= FLAG_MASS;
+    StepRec rec;
+    rec.lb = I.lb;
+    rec.ub = L;
+    rec.seg_begin = I.settled_mark;
+    rec.seg_end = min(I.settled_cnt, I.n);
+    I.steprec[(uint32_t)I.nsteprec & I.steprec_mask] = rec;
+    I.nsteprec += 1;
+    if (I.trace_len < I.trace_cap) {
+      TraceRec t;
+      t.lb = I.lb; t.ub = L; t.st = I.st; t.rounds = I.rounds_in_step;
+      t.pulled = I.pull_on; t.L = L; t.S = S; t.h = h; t.gap = gapL; t.st_next = stn; t.pad = 0;
+      I.trace[I.trace_len] = t;
+    }
+    I.trace_len += 1;
+    I.c.steps += 1;
+  }
+  const bool done = (L == kInf) ||
+                    (I.p_next_cnt == 0 && (unsigned long long)I.max_settled + I.M < L);
+  if (done) {
+    if (tid == 0) {
+      I.phase = PH_DONE;
+      *I.rid_slot = I.rid + 1;
+    }
+    __syncthreads();
+    return;
+  }
+  unsigned long long ubn = (unsigned long long)L + gapL;
+  if (ubn > kInf) ubn = kInf;
+  const uint32_t lb0 = L > I.M ? L - I.M : 0u;
+  // clear the ring slots of the next band [L, ubn) before its settle pass
+  const uint32_t width = (uint32_t)(ubn - L);
+  const uint32_t clr = width > I.ring_mask + 1 ? I.ring_mask + 1 : width;
+  for (uint32_t k = tid; k < clr; k += kBlock) {
+    uint32_t slot = (L + k) & I.ring_mask;
+    I.ring_mass[slot] = 0;
+    I.ring_cnt[slot] = 0;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    // settled-list range holding every vertex settled with dist in [lb0, st]
+    int32_t nrec = I.nsteprec;
+    int32_t avail = nrec < (int32_t)(I.steprec_mask + 1) ? nrec : (int32_t)(I.steprec_mask + 1);
+    int32_t first = nrec - avail;  // oldest record still held
+    // first record with ub > lb0
+    int32_t lo = first, hi = nrec;
+    while (lo < hi) {
+      int32_t mid = (lo + hi) >> 1;
+      if (I.steprec[(uint32_t)mid & I.steprec_mask].ub > lb0) hi = mid; else lo = mid + 1;
+    }
+    int32_t r0 = lo;
+    // last record with lb <= st  (records are ordered by band)
+    lo = first; hi = nrec;
+    while (lo < hi) {
+      int32_t mid = (lo + hi) >> 1;
+      if (I.steprec[(uint32_t)mid & I.steprec_mask].lb <= stn) lo = mid + 1; else hi = mid;
+    }
+    int32_t r1 = lo - 1;
+    int32_t wb = 0, we = 0;
+    if (r0 <= r1 && r0 < nrec && r1 >= first) {
+      wb = I.steprec[(uint32_t)r0 & I.steprec_mask].seg_begin;
+      we = I.steprec[(uint32_t)r1 & I.steprec_mask].seg_end;
+      if (r0 == first && first > 0) wb = 0;  // older records evicted: scan from the start
+    }
+    I.wBegin = wb;
+    I.wEnd = we;
+    I.lb = L;
+    I.ub = (uint32_t)ubn;
+    I.st = stn;
+    I.lb0 = lb0;
+    I.pull_on = stn < L ? 1u : 0u;
+    I.gap_cur = gapL;
+    I.first = 0;
+    I.step += 1;
+    I.rounds_in_step = 0;
+    I.step_rid0 = I.rid + 1;
+    I.rid = I.step_rid0 + 1;
+    I.phase = PH_ROUND;
+    if (I.pull_on) I.c.pulls += 1;
+  }
+  __syncthreads();
+}
+
+// ------------------------------------------------------------ tick: rounds --
+
+struct WaveAcc {
+  unsigned long long expansions, band, pscan, pvert, pullscan, success, qent;
+  uint32_t hubmin;
+};
+
+__device__ __forceinline__ void flush_acc(Inst& I, WaveAcc& a) {
+  unsigned long long e = wave_sum(a.expansions), b = wave_sum(a.band), ps = wave_sum(a.pscan),
+                     pv = wave_sum(a.pvert), pl = wave_sum(a.pullscan), su = wave_sum(a.success),
+                     qe = wave_sum(a.qent);
+  uint32_t hm = wave_min_u32(a.hubmin);
+  if (lane_id() == 0) {
+    if (e) atomicAdd(&I.c.expansions, e);
+    if (b) atomicAdd(&I.c.band_expansions, b);
+    if (ps) atomicAdd(&I.c.push_scanned, ps);
+    if (pv) atomicAdd(&I.c.pull_vertices, pv);
+    if (pl) atomicAdd(&I.c.pull_scanned, pl);
+    if (su) atomicAdd(&I.c.relax_success, su);
+    if (qe) atomicAdd(&I.c.queue_entries, qe);
+    if (hm != kInf) atomicMin(&I.ub_next, hm);
+  }
+}
+
+// A successful decrease of dist[t] to c during round `rid`: push t onto the
+// next frontier once per round (SAP) and onto the step's touched list once
+// per step. Convergent: every lane calls it.
+__device__ __forceinline__ void on_success(Inst& I, const DevGraph& g, bool ok, int t,
+                                           uint32_t c, WaveAcc& acc) {
+  bool wq = false, wt = false;
+  if (ok) {
+    uint32_t so = atomicMax(&I.stamp[t], I.rid);
+    wq = so < I.rid;
+    wt = so < I.step_rid0;
+    acc.success += 1;
+    if (I.first && is_hub(g, t) && c < acc.hubmin) acc.hubmin = c;
+  }
+  int nq = I.qsel ^ 1;
+  int p = wave_append(&I.q_next_cnt, wq);
+  if (wq) {
+    if (p < I.n) I.q[nq][p] = t; else atomicOr(&I.flags, FLAG_CAPACITY);
+    acc.qent += 1;
+  }
+  int p2 = wave_append(&I.touched_cnt, wt);
+  if (wt) {
+    if (p2 < I.n) I.touched[p2] = t; else atomicOr(&I.flags, FLAG_CAPACITY);
+    acc.qent += 1;
+  }
+}
+
+// Split a long range into heavy chunks for the next tick (grid-wide).
+__device__ void emit_heavy(Inst& I, int u, uint32_t d, int lo, int hi, bool pull) {
+  int nch = (hi - lo + kHeavyChunk - 1) / kHeavyChunk;
+  int base = atomicAdd(&I.h_next_cnt, nch);
+  HeavyItem* out = I.heavy[I.hsel ^ 1];
+  for (int k = 0; k < nch; ++k) {
+    int pos = base + k;
+    if (pos >= I.heavy_cap) {
+      atomicOr(&I.flags, FLAG_CAPACITY);
+      break;
+    }
+    int a = lo + k * kHeavyChunk;
+    int b = min(hi, a + kHeavyChunk);
+    HeavyItem it;
+    it.u = u;
+    it.d = d;
+    it.lo = a;
+    it.hi_kind = b | (pull ? (int)0x80000000 : 0);
+    out[pos] = it;
+  }
+}
+
+// One wave processes up to 64 items of a round segment.
+__device__ void wave_round(Inst& I, int kind, int item0, int nitems) {
+  const DevGraph& g = *I.g;
+  const int lane = lane_id();
+  const uint32_t lb = I.lb, ub = I.ub, st = I.st;
+  WaveAcc acc = {0, 0, 0, 0, 0, 0, 0, kInf};
+  int u = 0, lo = 0, size = 0;
+  uint32_t d = 0;
+  bool pull = false;
+  const int it = item0 + lane;
+  const bool have = (kind == SEG_H) ? (lane == 0 && item0 < nitems) : (it < nitems);
+
+  if (kind == SEG_U) {
+    pull = true;
+    bool keep = false, active = false;
+    if (have) {
+      u = (I.usel < 0) ? g.nonisolated[it] : I.ulist[I.usel][it];
+      d = I.dist[u];
+      keep = d >= lb;
+      active = d > lb && g.wmin[u] < ub - st;
+    }
+    int p = wave_append(&I.u_next_cnt, keep);
+    if (keep) I.ulist[I.usel < 0 ? 0 : (I.usel ^ 1)][p] = u;
+    if (active) {
+      int rs = g.rowptr[u], re = g.rowptr[u + 1];
+      lo = rs;
+      int hi = lower_bound_key(g.adj, rs, re, (uint64_t)(ub - st) << 32);
+      size = hi - lo;
+      acc.pvert += 1;
+      acc.pullscan += (unsigned long long)size;
+      if (size > I.heavy_split) {
+        emit_heavy(I, u, d, lo, hi, true);
+        size = 0;
+      }
+    }
+  } else if (kind == SEG_H) {
+    if (have) {
+      HeavyItem h = I.heavy[I.hsel][item0];
+      u = h.u;
+      lo = h.lo;
+      int hi = h.hi_kind & 0x7fffffff;
+      pull = (h.hi_kind & (int)0x80000000) != 0;
+      uint32_t du = I.dist[u];
+      if (pull) {
+        d = du;
+        size = du > lb ? hi - lo : 0;
+      } else {
+        d = h.d;
+        size = (du == d) ? hi - lo : 0;  // a newer, smaller dist[u] has its own expansion
+      }
+    }
+    pull = __shfl(pull ? 1 : 0, 0, kWave) != 0;
+  } else {
+    bool ok = false;
+    if (have) {
+      if (kind == SEG_W) {
+        u = I.settled[I.wBegin + it];
+        d = I.dist[u];
+        ok = d >= I.lb0 && d <= st;
+      } else if (kind == SEG_P) {
+        u = I.plist[I.psel][it];
+        d = I.dist[u];
+        ok = d >= lb && d < ub;
+      } else {  // SEG_Q
+        u = I.q[I.qsel][it];
+        d = I.dist[u];
+        ok = d < ub;
+      }
+    }
+    if (kind == SEG_P) {
+      // band members of the pending list join this step's touched list
+      bool wt = false;
+      if (ok) {
+        uint32_t so = atomicMax(&I.stamp[u], I.step_rid0);
+        wt = so < I.step_rid0;
+      }
+      int p = wave_append(&I.touched_cnt, wt);
+      if (wt) {
+        if (p < I.n) I.touched[p] = u; else atomicOr(&I.flags, FLAG_CAPACITY);
+        acc.qent += 1;
+      }
+    }
+    if (ok) {
+      int rs = g.rowptr[u], re = g.rowptr[u + 1];
+      if (re - rs == 1 && d > 0) ok = false;  // leaf pruning (Algorithm)
+      if (ok) {
+        uint32_t wl = lb > d ? lb - d : 0u;
+        uint32_t wh = ub - d;
+        lo = (wl <= g.wmin[u]) ? rs : lower_bound_key(g.adj, rs, re, (uint64_t)wl << 32);
+        int hi = lower_bound_key(g.adj, lo, re, (uint64_t)wh << 32);
+        if (ub == kInf && hi < re) atomicOr(&I.flags, FLAG_MAYBE_OVERFLOW);
+        size = hi - lo;
+        acc.expansions += 1;
+        acc.band += (d >= lb) ? 1 : 0;
+        acc.pscan += (unsigned long long)size;
+        if (size > I.heavy_split) {
+          emit_heavy(I, u, d, lo, hi, false);
+          size = 0;
+        }
+      }
+    }
+  }
+
+  // wave-level merge path over the ranges
+  const int incl = wave_incl_scan(size);
+  const int total = __shfl(incl, kWave - 1, kWave);
+  const int excl = incl - size;
+  for (int base = 0; base < total; base += kWave) {
+    const int e = base + lane;
+    // largest j with excl[j] <= e
+    int j = 0;
+#pragma unroll
+    for (int stp = 32; stp > 0; stp >>= 1) {
+      int cj = j + stp;
+      int ex = __shfl(excl, cj < kWave ? cj : kWave - 1, kWave);
+      if (cj < kWave && ex <= e) j = cj;
+    }
+    const int uj = __shfl(u, j, kWave);
+    const uint32_t dj = __shfl(d, j, kWave);
+    const int loj = __shfl(lo, j, kWave);
+    const int exj = __shfl(excl, j, kWave);
+    bool ok = false;
+    int t = 0;
+    uint32_t c = 0;
+    if (e < total) {
+      const uint64_t ent = g.adj[loj + (e - exj)];
+      const int v = (int)(uint32_t)(ent & 0xffffffffull);
+      const uint32_t w = (uint32_t)(ent >> 32);
+      if (!pull) {
+        c = dj + w;  // < ub by the range
+        t = v;
+        if (c < I.dist[v]) {
+          uint32_t old = atomicMin(&I.dist[v], c);
+          ok = c < old;
+        }
+      } else {
+        const uint32_t dv = I.dist[v];
+        if (dv >= st && dv < lb) {
+          unsigned long long cc = (unsigned long long)dv + w;
+          if (cc < ub && cc < dj) {
+            c = (uint32_t)cc;
+            t = uj;
+            uint32_t old = atomicMin(&I.dist[uj], c);
+            ok = c < old;
+          }
+        }
+      }
+    }
+    on_success(I, g, ok, t, c, acc);
+  }
+  flush_acc(I, acc);
+}
+
+// ------------------------------------------------------------ tick: settle --
+
+struct SettleLds {
+  uint32_t mass[kLdsRing];
+  uint32_t cnt[kLdsRing];
+  uint32_t hist[kLdsHist];
+  unsigned long long sdec[kBlock / kWave];
+  uint32_t maxd[kBlock / kWave];
+  int flag;
+};
+
+union BlockLds {
+  SettleLds s;
+  HeurLds h;
+};
+
+// One workgroup settles up to 256 items: the step's touched vertices (with
+// dist < ub they are final; in the first step the rest stay pending) and the
+// pending list's compaction. Degree mass moves from the unsettled histogram
+// to the per-distance ring; settled vertices are appended to the settled list.
+__device__ void block_settle(Inst& I, int kind, int item0, int nitems, SettleLds& L) {
+  const DevGraph& g = *I.g;
+  const int tid = threadIdx.x;
+  const uint32_t lb = I.lb, ub = I.ub;
+  const uint32_t band = ub - lb;
+  const uint32_t nb = band < (uint32_t)kLdsRing ? band : (uint32_t)kLdsRing;
+  const int nh = g.num_deg < kLdsHist ? g.num_deg : kLdsHist;
+  for (uint32_t k = tid; k < nb; k += kBlock) { L.mass[k] = 0; L.cnt[k] = 0; }
+  for (int k = tid; k < nh; k += kBlock) L.hist[k] = 0;
+  __syncthreads();
+  const int it = item0 + tid;
+  int v = -1;
+  uint32_t d = kInf;
+  if (it < nitems) {
+    v = (kind == SEG_ST) ? I.touched[it] : I.plist[I.psel][it];
+    d = I.dist[v];
+  }
+  bool settle = (kind == SEG_ST) && v >= 0 && d < ub;
+  bool pend = v >= 0 && d >= ub;
+  unsigned long long sdec = 0;
+  uint32_t maxd = 0;
+  if (settle) {
+    int deg = g.rowptr[v + 1] - g.rowptr[v];
+    uint32_t off = d - lb;
+    // only the window [ub - M, ub) is read by the next computeST; the first
+    // step's band may be wider, and older values would alias ring slots
+    if ((unsigned long long)d + I.M >= ub) {
+      if (off < nb) {
+        atomicAdd(&L.mass[off], (uint32_t)deg);
+        atomicAdd(&L.cnt[off], 1u);
+      } else {
+        atomicAdd(&I.ring_mass[d & I.ring_mask], (unsigned long long)deg);
+        atomicAdd(&I.ring_cnt[d & I.ring_mask], 1u);
+      }
+    }
+    int r = g.drank[v];
+    if (r >= 0) {
+      if (r < nh) atomicAdd(&L.hist[r], 1u); else atomicSub(&I.hist_cnt[r], 1u);
+    }
+    sdec = (unsigned long long)deg;
+    maxd = d;
+  }
+  int p = wave_append(&I.settled_cnt, settle);
+  if (settle) {
+    if (p < I.n) I.settled[p] = v; else atomicOr(&I.flags, FLAG_CAPACITY);
+  }
+  int q = wave_append(&I.p_next_cnt, pend);
+  if (pend) {
+    if (q < I.n) I.plist[I.psel ^ 1][q] = v; else atomicOr(&I.flags, FLAG_CAPACITY);
+  }
+  unsigned long long ws = wave_sum(sdec);
+  uint32_t wm = maxd;
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    uint32_t y = __shfl_xor(wm, o, kWave);
+    wm = y > wm ? y : wm;
+  }
+  unsigned long long qe = wave_sum((unsigned long long)(settle ? 1 : 0) + (pend ? 1 : 0));
+  if (lane_id() == 0) {
+    L.sdec[tid / kWave] = ws;
+    L.maxd[tid / kWave] = wm;
+    if (qe) atomicAdd(&I.c.queue_entries, qe);
+  }
+  __syncthreads();
+  for (uint32_t k = tid; k < nb; k += kBlock) {
+    uint32_t c = L.cnt[k];
+    if (c) {
+      uint32_t slot = (lb + k) & I.ring_mask;
+      atomicAdd(&I.ring_mass[slot], (unsigned long long)L.mass[k]);
+      atomicAdd(&I.ring_cnt[slot], c);
+    }
+  }
+  for (int k = tid; k < nh; k += kBlock) {
+    uint32_t c = L.hist[k];
+    if (c) atomicSub(&I.hist_cnt[k], c);
+  }
+  if (tid == 0) {
+    unsigned long long s = 0;
+    uint32_t m = 0;
+    for (int w = 0; w < kBlock / kWave; ++w) {
+      s += L.sdec[w];
+      m = L.maxd[w] > m ? L.maxd[w] : m;
+    }
+    if (s) atomicAdd(&I.S, (unsigned long long)(0ull - s));
+    if (m) atomicMax(&I.max_settled, m);
+  }
+  __syncthreads();
+}
+
+// ------------------------------------------------------------- scheduling --
+
+__device__ int find_segment(const Globals& G, int b) {
+  int lo = 0, hi = G.nseg;  // seg_first_batch has nseg + 1 entries
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (G.seg_first_batch[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ void run_tick(Globals& G, BlockLds& lds) {
+  const int wid = threadIdx.x / kWave;
+  __shared__ int s_last;
+  for (int b = blockIdx.x; b < G.total_batches; b += gridDim.x) {
+    const int sgi = find_segment(G, b);
+    Inst& I = G.insts[G.seg_inst[sgi]];
+    const int kind = G.seg_kind[sgi];
+    const int pb = G.seg_per_batch[sgi];
+    const int item0 = (b - G.seg_first_batch[sgi]) * pb;
+    const int cnt = G.seg_count[sgi];
+    if (kind == SEG_ST || kind == SEG_SP) {
+      block_settle(I, kind, item0, cnt, lds.s);
+      if (threadIdx.x == 0) {
+        __threadfence();
+        int done = atomicAdd(&I.settle_done, 1) + 1;
+        s_last = (done == I.settle_items);
+      }
+      __syncthreads();
+      if (s_last) {
+        __threadfence();
+        run_heuristic(I, lds.h);
+      }
+      __syncthreads();
+    } else if (kind == SEG_H) {
+      wave_round(I, kind, item0 + wid, cnt);
+    } else {
+      wave_round(I, kind, item0 + wid * kWave, cnt);
+    }
+  }
+}
+
+// Phase transition of one instance after a tick, and its segments for the
+// next tick. Serial per instance; called by one thread per instance.
+__device__ void transition(Inst& I, int32_t* cnt, int32_t* kinds, int32_t* pbs) {
+  for (int s = 0; s < kMaxSegPerInst; ++s) { cnt[s] = 0; kinds[s] = SEG_Q; pbs[s] = kBlock; }
+  if (I.phase == PH_DONE) return;
+  if (I.tick_kind == PH_ROUND) {
+    if (I.init_round && I.pull_on) {
+      I.usel = (I.usel < 0) ? 0 : (I.usel ^ 1);
+      I.nU = I.u_next_cnt;
+      I.u_next_cnt = 0;
+    }
+    I.init_round = 0;
+    if (I.first && I.ub_next < I.ub) I.ub = I.ub_next;
+    I.c.rounds += 1;
+    I.rounds_in_step += 1;
+    const int nq = min(I.q_next_cnt, I.n), nh = min(I.h_next_cnt, I.heavy_cap);
+    I.q_next_cnt = 0;
+    I.h_next_cnt = 0;
+    if (nq > 0 || nh > 0) {
+      I.qsel ^= 1;
+      I.hsel ^= 1;
+      I.nF = nq;
+      I.nH = nh;
+      I.rid += 1;
+      cnt[0] = nq; kinds[0] = SEG_Q;
+      cnt[1] = nh; kinds[1] = SEG_H; pbs[1] = kBlock / kWave;
+      return;
+    }
+    if (I.first && I.ub == kInf) {
+      I.phase = PH_DONE;
+      *I.rid_slot = I.rid + 1;
+      return;
+    }
+    I.tick_kind = PH_SETTLE;
+    I.phase = PH_SETTLE;
+    I.nT = min(I.touched_cnt, I.n);
+    I.settled_mark = min(I.settled_cnt, I.n);
+    I.settle_done = 0;
+    int bt = (I.nT + kBlock - 1) / kBlock;
+    if (bt < 1) bt = 1;
+    int bp = (I.nP + kBlock - 1) / kBlock;
+    I.settle_items = bt + bp;
+    // a settle tick always has at least one batch so that the heuristic runs:
+    // -1 marks one empty batch
+    cnt[0] = I.nT == 0 ? -1 : I.nT; kinds[0] = SEG_ST;
+    cnt[1] = I.nP; kinds[1] = SEG_SP;
+    return;
+  }
+  // a settle tick ran; the heuristic has set phase to ROUND or DONE
+  I.psel ^= 1;
+  I.nP = min(I.p_next_cnt, I.n);
+  I.p_next_cnt = 0;
+  I.touched_cnt = 0;
+  if (I.phase == PH_DONE) return;
+  I.tick_kind = PH_ROUND;
+  I.init_round = 1;
+  I.nF = 0;
+  cnt[0] = I.wEnd - I.wBegin; kinds[0] = SEG_W;
+  cnt[1] = I.nP; kinds[1] = SEG_P;
+  cnt[2] = I.pull_on ? I.nU : 0; kinds[2] = SEG_U;
+}
+
+// Build the tick table from every instance's transition. One workgroup.
+__device__ void build_table(Globals& G, bool do_transition) {
+  const int tid = threadIdx.x;
+  const int k = G.ninst;
+  __shared__ unsigned long long sh[kBlock / kWave + 1];
+  __shared__ int s_active;
+  if (tid == 0) s_active = 0;
+  __syncthreads();
+  // each thread handles a contiguous run of instances
+  const int per = (k + kBlock - 1) / kBlock;
+  const int i0 = min(k, tid * per), i1 = min(k, i0 + per);
+  int local_batches = 0;
+  for (int i = i0; i < i1; ++i) {
+    Inst& I = G.insts[i];
+    int32_t cnt[kMaxSegPerInst], kinds[kMaxSegPerInst], pbs[kMaxSegPerInst];
+    if (do_transition) {
+      transition(I, cnt, kinds, pbs);
+    } else {
+      // first tick of a solve: the source alone
+      for (int s = 0; s < kMaxSegPerInst; ++s) { cnt[s] = 0; kinds[s] = SEG_Q; pbs[s] = kBlock; }
+      if (I.phase != PH_DONE) { cnt[0] = I.nF; kinds[0] = SEG_Q; }
+    }
+    if (I.phase != PH_DONE) atomicAdd(&s_active, 1);
+    for (int s = 0; s < kMaxSegPerInst; ++s) {
+      int sg = i * kMaxSegPerInst + s;
+      int c = cnt[s];
+      int nb;
+      if (c < 0) { nb = 1; c = 0; }
+      else nb = (c + pbs[s] - 1) / pbs[s];
+      G.seg_inst[sg] = i;
+      G.seg_kind[sg] = kinds[s];
+      G.seg_count[sg] = c;
+      G.seg_per_batch[sg] = pbs[s];
+      G.seg_first_batch[sg] = nb;  // temporarily the batch count
+      local_batches += nb;
+    }
+  }
+  unsigned long long total;
+  unsigned long long before = block_excl_scan<unsigned long long>((unsigned long long)local_batches, sh, &total);
+  int run = (int)before;
+  for (int i = i0; i < i1; ++i) {
+    for (int s = 0; s < kMaxSegPerInst; ++s) {
+      int sg = i * kMaxSegPerInst + s;
+      int nb = G.seg_first_batch[sg];
+      G.seg_first_batch[sg] = run;
+      run += nb;
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    G.nseg = k * kMaxSegPerInst;
+    G.seg_first_batch[G.nseg] = (int)total;
+    G.total_batches = (int)total;
+    G.all_done = (s_active == 0) ? 1u : 0u;
+  }
+  __syncthreads();
+}
+
+// Ticks counted for the counters (every active instance).
+__device__ void count_ticks(Globals& G) {
+  for (int i = threadIdx.x; i < G.ninst; i += kBlock) {
+    Inst& I = G.insts[i];
+    if (I.phase != PH_DONE) I.c.ticks += 1;
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------- kernels --
+
+// Grid barrier whose last arriver runs the epilogue. Returns false if the
+// wait gave up (spin limit), after recording FLAG_TIMEOUT in G.error.
+__device__ bool barrier_epilogue(Globals& G, unsigned int& gen, bool persistent) {
+  __shared__ int s_last;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    unsigned int arrived = atomicAdd(&G.bar_count, 1u);
+    s_last = (arrived == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (s_last) {
+    __threadfence();
+    count_ticks(G);
+    build_table(G, true);
+    if (threadIdx.x == 0) {
+      G.ticks += 1;
+      if (G.ticks >= G.tick_limit) {
+        G.error |= FLAG_TICKS;
+        G.all_done = 1u;
+      }
+      __hip_atomic_store(&G.bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __threadfence();
+      __hip_atomic_fetch_add(&G.bar_gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    gen += 1;
+    return true;
+  }
+  if (!persistent) return true;
+  __shared__ int s_ok;
+  if (threadIdx.x == 0) {
+    unsigned long long spins = 0;
+    int ok = 1;
+    while (__hip_atomic_load(&G.bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+      __builtin_amdgcn_s_sleep(2);
+      if (++spins > (1ull << 26)) {
+        atomicOr(&G.error, FLAG_TIMEOUT);
+        ok = 0;
+        break;
+      }
+    }
+    s_ok = ok;
+  }
+  __syncthreads();
+  __threadfence();
+  gen += 1;
+  return s_ok != 0;
+}
+
+__global__ void __launch_bounds__(kBlock) k_engine(Globals* Gp, int persistent, int max_ticks) {
+  __shared__ BlockLds lds;
+  __shared__ unsigned int s_gen;
+  Globals& G = *Gp;
+  if (threadIdx.x == 0)
+    s_gen = __hip_atomic_load(&G.bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  unsigned int gen = s_gen;
+  for (int t = 0;; ++t) {
+    if (__hip_atomic_load(&G.all_done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+    if (__hip_atomic_load(&G.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+    run_tick(G, lds);
+    bool ok = barrier_epilogue(G, gen, persistent != 0);
+    if (!ok || !persistent) break;
+    if (max_ticks > 0 && t + 1 >= max_ticks) {
+      if (threadIdx.x == 0 && blockIdx.x == 0) G.max_ticks_hit = 1;
+      break;
+    }
+  }
+}
+
+// Per-solve state reset: distances, histogram, ring; stamps when their
+// counter is near wrapping. Grid-stride over every instance.
+__global__ void k_init_arrays(Globals* Gp) {
+  Globals& G = *Gp;
+  const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (int i = 0; i < G.ninst; ++i) {
+    Inst& I = G.insts[i];
+    const DevGraph& g = *I.g;
+    const bool reset_stamp = *I.rid_slot > 0x80000000u;
+    for (long long v = tid; v < I.n; v += stride) {
+      I.dist[v] = kInf;
+      if (reset_stamp) I.stamp[v] = 0;
+    }
+    for (long long r = tid; r < g.num_deg; r += stride) I.hist_cnt[r] = g.deg_cnt0[r];
+    for (long long r = tid; r <= (long long)I.ring_mask; r += stride) {
+      I.ring_mass[r] = 0;
+      I.ring_cnt[r] = 0;
+    }
+  }
+}
+
+// Per-solve control reset and the first tick's table. One workgroup.
+__global__ void __launch_bounds__(kBlock) k_init_ctl(Globals* Gp) {
+  Globals& G = *Gp;
+  for (int i = 0; i < G.ninst; ++i) {
+    Inst& I = G.insts[i];
+    const DevGraph& g = *I.g;
+    if (threadIdx.x == 0) {
+      I.rid = *I.rid_slot;
+      if (I.rid > 0x80000000u) I.rid = 0;
+      const int s = I.source;
+      const int deg_s = g.rowptr[s + 1] - g.rowptr[s];
+      I.dist[s] = 0;
+      I.M = g.max_w;
+      I.lb = 0; I.ub = kInf; I.st = 0; I.lb0 = 0;
+      I.first = 1;
+      I.step = 0;
+      I.rounds_in_step = 0;
+      I.qsel = 0; I.psel = 0; I.usel = -1; I.hsel = 0;
+      I.nP = 0; I.nU = g.n_nonisolated; I.nT = 0; I.nH = 0;
+      I.wBegin = 0; I.wEnd = 0;
+      I.q_next_cnt = 0; I.touched_cnt = 0; I.p_next_cnt = 0; I.u_next_cnt = 0;
+      I.settled_cnt = 0; I.h_next_cnt = 0;
+      I.settled_mark = 0;
+      I.nsteprec = 0;
+      I.trace_len = 0;
+      I.max_settled = 0;
+      I.S = (unsigned long long)g.nnz;
+      I.settle_items = 0; I.settle_done = 0;
+      I.flags = 0;
+      I.pull_on = 0;
+      I.init_round = 0;
+      I.tick_kind = PH_ROUND;
+      I.high_d0 = g.high_d0;
+      Counters z = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+      I.c = z;
+      I.step_rid0 = I.rid + 1;
+      I.stamp[s] = I.step_rid0;
+      I.rid = I.step_rid0 + 1;
+      I.touched[0] = s;
+      I.touched_cnt = 1;
+      I.q[0][0] = s;
+      I.nF = 1;
+      I.ub_next = is_hub(g, s) ? 0u : kInf;
+      I.phase = deg_s > 0 ? PH_ROUND : PH_DONE;
+      if (deg_s == 0) *I.rid_slot = I.rid + 1;
+    }
+    __syncthreads();
+    // gap(0) from whole-graph statistics: sumD(0) = nnz, highD(0)
+    uint32_t g0 = gap_of((unsigned long long)g.nnz, g.high_d0, g.nnz, g.max_w, g.rtow, I.alpha, I.beta);
+    if (threadIdx.x == 0) {
+      I.gap0 = g0;
+      I.gap_cur = g0;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    G.bar_count = 0;
+    G.error = 0;
+    G.max_ticks_hit = 0;
+    G.ticks = 0;
+  }
+  __syncthreads();
+  build_table(G, false);
+}
+
+// Overflow confirmation (only when a range was cut by the +inf clamp): a
+// vertex with a finite neighbour but no distance is reachable with a length
+// the uint32 range cannot hold.
+__global__ void k_overflow_check(Globals* Gp) {
+  Globals& G = *Gp;
+  for (int i = 0; i < G.ninst; ++i) {
+    Inst& I = G.insts[i];
+    if (!(I.flags & FLAG_MAYBE_OVERFLOW)) continue;
+    const DevGraph& g = *I.g;
+    bool found = false;
+    for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < g.n && !found;
+         v += (long long)gridDim.x * blockDim.x) {
+      if (I.dist[v] != kInf) continue;
+      for (int e = g.rowptr[v]; e < g.rowptr[v + 1]; ++e) {
+        int u = (int)(uint32_t)(g.adj[e] & 0xffffffffull);
+        if (I.dist[u] != kInf) {
+          found = true;
+          break;
+        }
+      }
+    }
+    if (found) atomicOr(&I.flags, FLAG_OVERFLOW);
+  }
+}
+
+// highD over a degree histogram, exported for the graph preparation.
+__global__ void __launch_bounds__(kBlock) k_high_d(const int32_t* deg_vals, const uint32_t* cnt,
+                                                   int32_t D, uint32_t* out_h,
+                                                   unsigned long long* out_mass) {
+  __shared__ HeurLds lds;
+  unsigned long long mass;
+  uint32_t h = block_high_d(deg_vals, cnt, D, &mass, lds);
+  if (threadIdx.x == 0) {
+    *out_h = h;
+    *out_mass = mass;
+  }
+}
+
+
+// ================================================================ host side
+
+hipError_t launch_high_d(const int32_t* deg_vals, const uint32_t* cnt, int32_t D, uint32_t* out_h,
+                         unsigned long long* out_mass, hipStream_t stream) {
+  k_high_d<<<1, kBlock, 0, stream>>>(deg_vals, cnt, D, out_h, out_mass);
+  return hipGetLastError();
+}
+
+hipError_t launch_init(Globals* dG, long long max_n, hipStream_t stream) {
+  long long blocks = (max_n + kBlock - 1) / kBlock;
+  if (blocks < 1) blocks = 1;
+  if (blocks > 16384) blocks = 16384;
+  k_init_arrays<<<(int)blocks, kBlock, 0, stream>>>(dG);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_init_ctl<<<1, kBlock, 0, stream>>>(dG);
+  return hipGetLastError();
+}
+
+int engine_blocks_per_cu() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(k_engine), kBlock,
+                                                   0) != hipSuccess)
+    return 1;
+  return nb < 1 ? 1 : nb;
+}
+
+hipError_t launch_engine(Globals* dG, int grid, bool persistent, int max_ticks, hipStream_t stream) {
+  if (!persistent) {
+    k_engine<<<grid, kBlock, 0, stream>>>(dG, 0, 0);
+    return hipGetLastError();
+  }
+  int pers = 1;
+  void* args[] = {(void*)&dG, (void*)&pers, (void*)&max_ticks};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_engine), dim3(grid), dim3(kBlock),
+                                    args, 0, stream);
+}
+
+hipError_t launch_overflow_check(Globals* dG, long long max_n, hipStream_t stream) {
+  long long blocks = (max_n + kBlock - 1) / kBlock;
+  if (blocks < 1) blocks = 1;
+  if (blocks > 4096) blocks = 4096;
+  k_overflow_check<<<(int)blocks, kBlock, 0, stream>>>(dG);
+  return hipGetLastError();
+}
+
+}  // namespace sssp
