@@ -70,7 +70,7 @@ typedef struct {
   uint64_t expansions;      /* vertex expansions (paths extended), band and deferred */
   uint64_t band_expansions; /* expansions of vertices at or above lb (nFrontier's count) */
   uint64_t push_scanned;    /* CSR entries scanned by push (edges relaxed) */
-  uint64_t pull_vertices;   /* unsettled vertices scanned by the pull */
+  uint64_t pull_vertices;   /* unsettled-list entries scanned by the pull */
   uint64_t pull_scanned;    /* CSR entries scanned by the pull (requests) */
   uint64_t relax_success;   /* successful distance decreases */
   uint64_t queue_entries;   /* frontier / touched / settled list entries written */
@@ -146,8 +146,9 @@ sssp_status sssp_graph_rtow(const sssp_graph* g, uint32_t* rtow_out);
 
 /* Distances from `source` into dist_out (device, n uint32), enqueued on
  * `stream`. dist_out[source] = 0; unreachable vertices get UINT32_MAX.
- * Returns SSSP_E_DIST_OVERFLOW (after synchronising the stream) if a reachable
- * vertex's distance is >= UINT32_MAX; the distances are then incomplete. */
+ * Asynchronous: a reachable vertex whose distance is >= UINT32_MAX (the
+ * distances are then incomplete) is reported by sssp_get_counters returning
+ * SSSP_E_DIST_OVERFLOW. */
 sssp_status sssp_solve(const sssp_graph* g, int32_t source, uint32_t* dist_out,
                        hipStream_t stream);
 
@@ -174,6 +175,27 @@ sssp_status sssp_get_counters(hipStream_t stream, sssp_counters* out);
 /* Schedule of the last single-source solve on `stream`: up to cap steps into
  * out (host); *len receives the number of steps taken. Synchronises. */
 sssp_status sssp_get_schedule(hipStream_t stream, sssp_step* out, int32_t cap, int32_t* len);
+
+/* Durations (microseconds, host array) of the engine kernel of the solves
+ * enqueued on `stream` since the previous call (at most the 256 most recent),
+ * oldest first, measured with HIP events recorded around the engine launch
+ * on that stream. *n receives the count. Synchronises the stream. */
+sssp_status sssp_engine_times(hipStream_t stream, float* us_out, int32_t cap, int32_t* n);
+
+/* ---- debugging ---------------------------------------------------------- */
+
+/* Enable (cap > 0) or disable (cap = 0) a per-tick log of the engine for the
+ * solves that follow on `stream`: for each device-wide tick, four uint64 --
+ * the 100 MHz wall clock when the tick's last workgroup arrived, the tick's
+ * work batches, bits of instance 0's state (tick kind | init round << 8 |
+ * pull << 9 | step << 16), and the wall clock when the next tick was released.
+ * Synchronises the stream. */
+sssp_status sssp_debug_tick_log(hipStream_t stream, int32_t cap);
+
+/* Copy the tick log of the last solve on `stream` (cap entries of four uint64
+ * into out); *len receives the tick count, *t_start the engine's start time. */
+sssp_status sssp_debug_get_tick_log(hipStream_t stream, uint64_t* out, int32_t cap, int32_t* len,
+                                    uint64_t* t_start);
 
 /* ---- errors ------------------------------------------------------------- */
 

@@ -17,7 +17,8 @@ from ._lib import SSSPError
 
 INF = 0xFFFFFFFF
 
-__all__ = ["Graph", "solve_multi", "counters", "schedule", "SSSPError", "INF", "version"]
+__all__ = ["Graph", "solve_multi", "counters", "schedule", "engine_times", "SSSPError", "INF",
+           "version"]
 
 
 def version() -> str:
@@ -165,6 +166,36 @@ def counters(stream=None) -> dict:
     d = {f: int(getattr(c, f)) for f, _ in c._fields_ if f != "reserved"}
     _lib.check(st)
     return d
+
+
+def engine_times(stream=None, cap: int = 256) -> list:
+    """Engine-kernel durations (microseconds) of the solves on `stream` since the last call."""
+    buf = (ctypes.c_float * cap)()
+    n = ctypes.c_int32(0)
+    _lib.check(_lib.sssp_engine_times(_stream_handle(stream), buf, cap, ctypes.byref(n)))
+    return [float(buf[i]) for i in range(n.value)]
+
+
+def debug_tick_log(enable_cap: int, stream=None) -> None:
+    """Enable (cap > 0) or disable the engine's per-tick log for later solves."""
+    _lib.check(_lib.sssp_debug_tick_log(_stream_handle(stream), int(enable_cap)))
+
+
+def debug_get_tick_log(stream=None, cap: int = 1 << 16):
+    """Per-tick log of the last solve: list of (t_end_us, batches, kind_bits, epilogue_us),
+    times in microseconds from the engine start (100 MHz clock)."""
+    buf = np.empty((cap, 4), np.uint64)
+    n = ctypes.c_int32(0)
+    t0 = ctypes.c_uint64(0)
+    _lib.check(_lib.sssp_debug_get_tick_log(_stream_handle(stream), buf.ctypes.data, cap,
+                                            ctypes.byref(n), ctypes.byref(t0)))
+    m = min(cap, n.value)
+    out = []
+    for i in range(m):
+        e = buf[i]
+        out.append(((int(e[0]) - t0.value) / 100.0, int(e[1]), int(e[2]),
+                    (int(e[3]) - int(e[0])) / 100.0))
+    return out
 
 
 def schedule(stream=None, cap: int = 1 << 16) -> list:

@@ -70,6 +70,10 @@ sssp_solve_batch = _sig("sssp_solve_batch", i32, vp, vp, i32, vp, vp)
 sssp_solve_multi = _sig("sssp_solve_multi", i32, vp, vp, i32, vp, ctypes.POINTER(Options), vp)
 sssp_get_counters = _sig("sssp_get_counters", i32, vp, ctypes.POINTER(Counters))
 sssp_get_schedule = _sig("sssp_get_schedule", i32, vp, ctypes.POINTER(Step), i32, i32p)
+sssp_engine_times = _sig("sssp_engine_times", i32, vp, ctypes.POINTER(ctypes.c_float), i32, i32p)
+sssp_debug_tick_log = _sig("sssp_debug_tick_log", i32, vp, i32)
+sssp_debug_get_tick_log = _sig("sssp_debug_get_tick_log", i32, vp, vp, i32, i32p,
+                               ctypes.POINTER(ctypes.c_uint64))
 sssp_last_error = _sig("sssp_last_error", i32)
 sssp_last_error_message = _sig("sssp_last_error_message", ctypes.c_char_p)
 sssp_status_str = _sig("sssp_status_str", ctypes.c_char_p, i32)

@@ -52,7 +52,7 @@ uint32_t pow2_at_least(uint64_t x) {
 // ------------------------------------------------------------ workspaces --
 
 struct SlotBuf {
-  int32_t n_cap = 0, heavy_cap = 0, hist_cap = 0, trace_cap = 0;
+  int32_t n_cap = 0, list_cap = 0, maxw = 0, heavy_cap = 0, hist_cap = 0, trace_cap = 0;
   uint32_t ring_cap = 0, steprec_cap = 0;
   uint32_t* stamp = nullptr;
   int32_t* q[2] = {nullptr, nullptr};
@@ -67,23 +67,27 @@ struct SlotBuf {
   StepRec* steprec = nullptr;
   TraceRec* trace = nullptr;
   uint32_t* rid = nullptr;
+  uint2* cstate = nullptr;
+  Counters* cslot = nullptr;
   std::vector<void*> allocs;
   void release() {
     for (void* p : allocs) (void)hipFree(p);
     allocs.clear();
-    n_cap = heavy_cap = hist_cap = trace_cap = 0;
+    n_cap = list_cap = maxw = heavy_cap = hist_cap = trace_cap = 0;
     ring_cap = steprec_cap = 0;
   }
 };
 
 struct Needs {
-  int32_t n, heavy, hist, trace;
+  int32_t n, list, maxw, heavy, hist, trace;
   uint32_t ring, steprec;
 };
 
-Needs needs_for(const DevGraph& g) {
+Needs needs_for(const DevGraph& g, int maxw) {
   Needs r;
   r.n = g.n;
+  r.maxw = maxw;
+  r.list = g.n + maxw * kChunk;
   r.heavy = g.nnz / 128 + 4096;
   r.hist = std::max(g.num_deg, 1);
   r.trace = 1 << 16;
@@ -108,12 +112,18 @@ hipError_t dev_alloc(T** p, size_t count, std::vector<void*>& list) {
   return e;
 }
 
+bool slot_fits(const SlotBuf& s, const Needs& nd) {
+  return s.n_cap >= nd.n && s.list_cap >= nd.list && s.maxw >= nd.maxw && s.heavy_cap >= nd.heavy &&
+         s.hist_cap >= nd.hist && s.trace_cap >= nd.trace && s.ring_cap >= nd.ring &&
+         s.steprec_cap >= nd.steprec;
+}
+
 hipError_t ensure_slot(SlotBuf& s, const Needs& nd) {
-  if (s.n_cap >= nd.n && s.heavy_cap >= nd.heavy && s.hist_cap >= nd.hist && s.trace_cap >= nd.trace &&
-      s.ring_cap >= nd.ring && s.steprec_cap >= nd.steprec)
-    return hipSuccess;
+  if (slot_fits(s, nd)) return hipSuccess;
   Needs m;
   m.n = std::max(s.n_cap, nd.n);
+  m.list = std::max(s.list_cap, nd.list);
+  m.maxw = std::max(s.maxw, nd.maxw);
   m.heavy = std::max(s.heavy_cap, nd.heavy);
   m.hist = std::max(s.hist_cap, nd.hist);
   m.trace = std::max(s.trace_cap, nd.trace);
@@ -125,14 +135,16 @@ hipError_t ensure_slot(SlotBuf& s, const Needs& nd) {
     if (e == hipSuccess) e = dev_alloc(p, c, s.allocs);
   };
   A(&s.stamp, m.n);
-  A(&s.q[0], m.n);
-  A(&s.q[1], m.n);
-  A(&s.touched, m.n);
+  A(&s.q[0], m.list);
+  A(&s.q[1], m.list);
+  A(&s.touched, m.list);
   A(&s.settled, m.n);
   A(&s.plist[0], m.n);
   A(&s.plist[1], m.n);
-  A(&s.ulist[0], m.n);
-  A(&s.ulist[1], m.n);
+  A(&s.ulist[0], m.list);
+  A(&s.ulist[1], m.list);
+  A(&s.cstate, 3 * (size_t)m.maxw);
+  A(&s.cslot, (size_t)m.maxw);
   A(&s.heavy[0], m.heavy);
   A(&s.heavy[1], m.heavy);
   A(&s.ring_mass, m.ring);
@@ -140,15 +152,20 @@ hipError_t ensure_slot(SlotBuf& s, const Needs& nd) {
   A(&s.hist, m.hist);
   A(&s.steprec, m.steprec);
   A(&s.trace, m.trace);
-  A(&s.rid, 1);
+  A(&s.rid, PW_COUNT);
   if (e == hipSuccess) e = hipMemset(s.stamp, 0, sizeof(uint32_t) * (size_t)m.n);
-  if (e == hipSuccess) e = hipMemset(s.rid, 0, sizeof(uint32_t));
+  if (e == hipSuccess) e = hipMemset(s.rid, 0, sizeof(uint32_t) * PW_COUNT);
+  // chunked lists start (and are kept) at -1 in every slot not holding an entry
+  for (int32_t* lp : {s.q[0], s.q[1], s.touched, s.ulist[0], s.ulist[1]})
+    if (e == hipSuccess) e = hipMemset(lp, 0xFF, sizeof(int32_t) * (size_t)m.list);
   if (e != hipSuccess) {
     s.release();
     (void)hipGetLastError();
     return e;
   }
   s.n_cap = m.n;
+  s.list_cap = m.list;
+  s.maxw = m.maxw;
   s.heavy_cap = m.heavy;
   s.hist_cap = m.hist;
   s.trace_cap = m.trace;
@@ -180,6 +197,13 @@ struct Workspace {
   // last solve
   int last_k = 0;
   bool persistent_failed = false;
+  // optional per-tick log of the engine (debug)
+  unsigned long long* d_tick_log = nullptr;
+  int tick_log_cap = 0;
+  // engine-kernel timing ring (HIP events around each engine launch)
+  static constexpr int kTimes = 256;
+  hipEvent_t tev[2][kTimes] = {};
+  long long t_rec = 0, t_read = 0;
 };
 
 std::mutex g_ws_mu;
@@ -233,6 +257,13 @@ Workspace* get_ws(hipStream_t stream, std::string* err) {
       return nullptr;
     }
   }
+  for (int a = 0; a < 2; ++a)
+    for (int i = 0; i < Workspace::kTimes; ++i)
+      if (hipEventCreate(&w->tev[a][i]) != hipSuccess) {
+        *err = "hipEventCreate failed";
+        delete w;
+        return nullptr;
+      }
   if (hipHostMalloc((void**)&w->pinned_flag, sizeof(unsigned int) * 4, hipHostMallocDefault) != hipSuccess) {
     *err = "hipHostMalloc failed";
     delete w;
@@ -298,10 +329,9 @@ sssp_status run_instances(const sssp_graph* const* gs, const int32_t* sources, i
   for (int i = 0; i < k; ++i) {
     const DevGraph& g = gs[i]->gh.h;
     max_n = std::max<long long>(max_n, g.n);
-    Needs nd = needs_for(g);
+    Needs nd = needs_for(g, w.cus * w.occ * (kBlock / kWave));
     SlotBuf& s = w.slots[(size_t)i];
-    if (!(s.n_cap >= nd.n && s.heavy_cap >= nd.heavy && s.hist_cap >= nd.hist && s.ring_cap >= nd.ring &&
-          s.steprec_cap >= nd.steprec && s.trace_cap >= nd.trace)) {
+    if (!slot_fits(s, nd)) {
       (void)hipStreamSynchronize(stream);
       hipError_t e = ensure_slot(s, nd);
       if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
@@ -319,6 +349,8 @@ sssp_status run_instances(const sssp_graph* const* gs, const int32_t* sources, i
   const int segcap = kMaxSegPerInst * w.inst_cap + 1;
   hG->ninst = k;
   hG->tick_limit = o.tick_limit;
+  hG->tick_log = w.d_tick_log;
+  hG->tick_log_cap = (unsigned long long)w.tick_log_cap;
   hG->seg_inst = w.seg;
   hG->seg_kind = w.seg + segcap;
   hG->seg_count = w.seg + 2 * segcap;
@@ -347,8 +379,12 @@ sssp_status run_instances(const sssp_graph* const* gs, const int32_t* sources, i
     I.steprec = s.steprec;
     I.trace = s.trace;
     I.rid_slot = s.rid;
+    I.cstate = s.cstate;
+    I.cslot = s.cslot;
+    I.maxw = s.maxw;
+    I.list_cap = s.list_cap;
     I.heavy_cap = s.heavy_cap;
-    Needs nd = needs_for(gs[i]->gh.h);
+    Needs nd = needs_for(gs[i]->gh.h, s.maxw);
     I.ring_mask = nd.ring - 1;
     I.steprec_mask = nd.steprec - 1;
     I.trace_cap = s.trace_cap;
@@ -364,6 +400,8 @@ sssp_status run_instances(const sssp_graph* const* gs, const int32_t* sources, i
   HIP_TRY(hipEventRecord(w.stage_ev[si], stream));
   w.stage_used[si] = true;
   HIP_TRY(launch_init(w.dG, max_n, stream));
+  const int tslot = (int)(w.t_rec % Workspace::kTimes);
+  HIP_TRY(hipEventRecord(w.tev[0][tslot], stream));
   bool host_driven = o.host_driven || w.persistent_failed;
   if (!host_driven) {
     int bpc = o.blocks_per_cu > 0 ? std::min(o.blocks_per_cu, w.occ) : w.occ;
@@ -386,6 +424,8 @@ sssp_status run_instances(const sssp_graph* const* gs, const int32_t* sources, i
       if (t > (long long)o.tick_limit + 4) return fail(SSSP_E_DEVICE, "tick limit exceeded");
     }
   }
+  HIP_TRY(hipEventRecord(w.tev[1][tslot], stream));
+  w.t_rec += 1;
   HIP_TRY(launch_overflow_check(w.dG, max_n, stream));
   w.last_k = k;
   return ok();
@@ -540,6 +580,19 @@ sssp_status sssp_get_counters(hipStream_t stream, sssp_counters* out) {
   Globals hg;
   HIP_TRY(hipMemcpy(&hg, w->dG, sizeof(Globals), hipMemcpyDeviceToHost));
   uint32_t flags = 0;
+  for (Inst& I : hi) {
+    std::vector<Counters> cs((size_t)I.maxw);
+    HIP_TRY(hipMemcpy(cs.data(), I.cslot, sizeof(Counters) * (size_t)I.maxw, hipMemcpyDeviceToHost));
+    for (const Counters& c : cs) {
+      I.c.expansions += c.expansions;
+      I.c.band_expansions += c.band_expansions;
+      I.c.push_scanned += c.push_scanned;
+      I.c.pull_vertices += c.pull_vertices;
+      I.c.pull_scanned += c.pull_scanned;
+      I.c.relax_success += c.relax_success;
+      I.c.queue_entries += c.queue_entries;
+    }
+  }
   for (const Inst& I : hi) {
     out->expansions += I.c.expansions;
     out->band_expansions += I.c.band_expansions;
@@ -593,6 +646,59 @@ sssp_status sssp_get_schedule(hipStream_t stream, sssp_step* out, int32_t cap, i
       s.st_next = t[(size_t)i].st_next;
     }
   }
+  return ok();
+}
+
+sssp_status sssp_engine_times(hipStream_t stream, float* us_out, int32_t cap, int32_t* n_out) {
+  if (!n_out || (cap > 0 && !us_out)) return fail(SSSP_E_INVAL, "NULL output");
+  std::string err;
+  Workspace* w = get_ws(stream, &err);
+  if (!w) return fail(SSSP_E_DEVICE, err);
+  HIP_TRY(hipStreamSynchronize(stream));
+  long long from = std::max(w->t_read, w->t_rec - Workspace::kTimes);
+  int m = 0;
+  for (long long i = from; i < w->t_rec && m < cap; ++i, ++m) {
+    int sl = (int)(i % Workspace::kTimes);
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, w->tev[0][sl], w->tev[1][sl]));
+    us_out[m] = ms * 1000.f;
+  }
+  *n_out = m;
+  w->t_read = w->t_rec;
+  return ok();
+}
+
+sssp_status sssp_debug_tick_log(hipStream_t stream, int32_t cap) {
+  if (cap < 0) return fail(SSSP_E_INVAL, "cap must be >= 0");
+  std::string err;
+  Workspace* w = get_ws(stream, &err);
+  if (!w) return fail(SSSP_E_DEVICE, err);
+  HIP_TRY(hipStreamSynchronize(stream));
+  if (w->d_tick_log) HIP_TRY(hipFree(w->d_tick_log));
+  w->d_tick_log = nullptr;
+  w->tick_log_cap = 0;
+  if (cap > 0) {
+    HIP_TRY(hipMalloc(&w->d_tick_log, sizeof(unsigned long long) * 4 * (size_t)cap));
+    w->tick_log_cap = cap;
+  }
+  return ok();
+}
+
+sssp_status sssp_debug_get_tick_log(hipStream_t stream, uint64_t* out, int32_t cap, int32_t* len,
+                                    uint64_t* t_start) {
+  if (!len || !t_start || (cap > 0 && !out)) return fail(SSSP_E_INVAL, "NULL output");
+  std::string err;
+  Workspace* w = get_ws(stream, &err);
+  if (!w) return fail(SSSP_E_DEVICE, err);
+  if (!w->d_tick_log || w->last_k == 0) return fail(SSSP_E_INVAL, "tick log not enabled or no solve");
+  HIP_TRY(hipStreamSynchronize(stream));
+  Globals hg;
+  HIP_TRY(hipMemcpy(&hg, w->dG, sizeof(Globals), hipMemcpyDeviceToHost));
+  int m = (int)std::min<unsigned long long>(hg.ticks, (unsigned long long)w->tick_log_cap);
+  *len = (int32_t)hg.ticks;
+  *t_start = hg.t_start;
+  m = std::min(m, cap);
+  if (m > 0) HIP_TRY(hipMemcpy(out, w->d_tick_log, sizeof(uint64_t) * 4 * (size_t)m, hipMemcpyDeviceToHost));
   return ok();
 }
 

@@ -17,6 +17,10 @@ constexpr int kLdsRing = 1024;           // settle: distance bins privatised in 
 constexpr int kLdsHist = 1024;           // settle: degree ranks privatised in LDS
 constexpr int kHeavyChunk = 256;         // edges per heavy chunk
 constexpr int kDefaultHeavy = 1024;      // ranges longer than this are split
+constexpr int kChunk = 64;               // slots a wave claims at a time in a chunked list
+// persistent per-slot words (rid_slot[]): stamp counter, then the extents of
+// list regions that may hold entries other than -1 (cleared at the next solve)
+enum PersistWord { PW_RID = 0, PW_TOUCHED = 1, PW_U0 = 2, PW_U1 = 3, PW_Q0 = 4, PW_Q1 = 5, PW_COUNT = 8 };
 
 // ------------------------------------------------------------------ graph --
 struct DevGraph {
@@ -92,7 +96,11 @@ struct Inst {
   uint32_t* hist_cnt;
   StepRec* steprec;
   TraceRec* trace;
-  uint32_t* rid_slot;      // persists the stamp counter of this workspace slot across solves
+  uint32_t* rid_slot;      // persists across solves: [0] stamp counter, [1..5] dirty list extents
+  uint2* cstate;           // per-wave chunk states of the chunked lists: [3][maxw]
+  Counters* cslot;         // per-wave work counters: [maxw]
+  int32_t maxw;            // waves the counter / chunk arrays can hold
+  int32_t list_cap;        // capacity of the chunked lists (q, touched, ulist)
   int32_t heavy_cap;
   uint32_t ring_mask;
   uint32_t steprec_mask;
@@ -159,6 +167,9 @@ struct Globals {
   int32_t max_ticks_hit;
   unsigned long long ticks;
   unsigned long long tick_limit;  // safety stop for a schedule that fails to end
+  unsigned long long* tick_log;   // optional: per tick {end time, batches, kind bits, epilogue end}
+  unsigned long long tick_log_cap;
+  unsigned long long t_start;     // wall clock when the engine started
   // per segment: instance, kind, item count, items per batch, first batch
   int32_t* seg_inst;
   int32_t* seg_kind;

@@ -56,16 +56,57 @@ __device__ __forceinline__ uint32_t wave_min_u32(uint32_t x) {
   return x;
 }
 
-// Wave-aggregated append: one atomic per wave. Every lane of the wave must
-// call it (convergent). Returns the slot or -1.
-__device__ __forceinline__ int wave_append(int32_t* counter, bool want) {
+// Chunked list append. A wave claims kChunk slots of a list with one atomic
+// and fills them over as many appends as it takes; its claim (base, used)
+// lives in memory between batches, tagged with an epoch so that a claim from
+// an earlier round or step reads as empty. Unfilled slots keep -1: every
+// consumer resets the slots it reads, and buffers start at -1.
+struct Chunk {
+  int base;
+  int used;
+};
+
+__device__ __forceinline__ uint32_t chunk_tag(uint32_t epoch, int used) {
+  return ((epoch & 0x1FFFFFFu) << 7) | (uint32_t)used;
+}
+
+__device__ __forceinline__ Chunk chunk_load(const uint2* st, uint32_t epoch) {
+  uint2 v = *st;
+  Chunk c;
+  if ((v.y >> 7) == (epoch & 0x1FFFFFFu)) {
+    c.base = (int)v.x;
+    c.used = (int)(v.y & 127u);
+  } else {
+    c.base = 0;
+    c.used = kChunk;  // nothing claimed
+  }
+  return c;
+}
+
+__device__ __forceinline__ void chunk_store(uint2* st, const Chunk& c, uint32_t epoch) {
+  if (lane_id() == 0) *st = make_uint2((uint32_t)c.base, chunk_tag(epoch, c.used));
+}
+
+// Convergent. Returns the slot for lanes with want, -1 otherwise.
+__device__ __forceinline__ int chunk_append(Chunk& c, int32_t* counter, bool want) {
   uint64_t m = __ballot(want);
   if (m == 0) return -1;
-  int leader = __ffsll((unsigned long long)m) - 1;
-  int base = 0;
-  if (lane_id() == leader) base = atomicAdd(counter, __popcll(m));
-  base = __shfl(base, leader, kWave);
-  return want ? base + __popcll(m & lanemask_lt()) : -1;
+  const int k = __popcll(m);
+  const int pre = __popcll(m & lanemask_lt());
+  const int rem = kChunk - c.used;
+  int pos;
+  if (k <= rem) {
+    pos = c.base + c.used + pre;
+    c.used += k;
+  } else {
+    int nb = 0;
+    if (lane_id() == 0) nb = atomicAdd(counter, kChunk);
+    nb = __shfl(nb, 0, kWave);
+    pos = pre < rem ? c.base + c.used + pre : nb + (pre - rem);
+    c.base = nb;
+    c.used = k - rem;
+  }
+  return want ? pos : -1;
 }
 
 __device__ __forceinline__ int lower_bound_key(const uint64_t* __restrict__ adj, int lo, int hi,
@@ -249,6 +290,20 @@ __device__ uint32_t block_compute_st(const Inst& I, uint32_t L, uint32_t gapL, i
   return res;
 }
 
+// A solve that ends normally leaves only these list regions holding entries
+// other than -1: the unconsumed survivors of the last pull and, when the
+// first step ends the search, its touched list. The next solve clears them.
+__device__ void record_clean_end(Inst& I, int touched_dirty) {
+  uint32_t* pw = I.rid_slot;
+  pw[PW_RID] = I.rid + 1;
+  pw[PW_TOUCHED] = (uint32_t)touched_dirty;
+  const int ucur = I.usel;
+  pw[PW_U0] = (ucur == 0) ? (uint32_t)I.nU : 0u;
+  pw[PW_U1] = (ucur == 1) ? (uint32_t)I.nU : 0u;
+  pw[PW_Q0] = 0u;
+  pw[PW_Q1] = 0u;
+}
+
 // The end-of-step heuristic for one instance: statistics at L = ub, gap(L),
 // computeST, step bookkeeping, termination test, and the next step's setup.
 // Runs on one workgroup, after every settle batch of the instance is done.
@@ -284,7 +339,7 @@ __device__ void run_heuristic(Inst& I, HeurLds& lds) {
   if (done) {
     if (tid == 0) {
       I.phase = PH_DONE;
-      *I.rid_slot = I.rid + 1;
+      record_clean_end(I, 0);
     }
     __syncthreads();
     return;
@@ -352,19 +407,27 @@ struct WaveAcc {
   uint32_t hubmin;
 };
 
+__device__ __forceinline__ int global_wave() { return (int)(blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave); }
+
+// Work counters go to this wave's own slot (plain read-modify-write: no
+// other wave touches it); only the step-1 hub bound is a shared atomic.
 __device__ __forceinline__ void flush_acc(Inst& I, WaveAcc& a) {
   unsigned long long e = wave_sum(a.expansions), b = wave_sum(a.band), ps = wave_sum(a.pscan),
                      pv = wave_sum(a.pvert), pl = wave_sum(a.pullscan), su = wave_sum(a.success),
                      qe = wave_sum(a.qent);
   uint32_t hm = wave_min_u32(a.hubmin);
   if (lane_id() == 0) {
-    if (e) atomicAdd(&I.c.expansions, e);
-    if (b) atomicAdd(&I.c.band_expansions, b);
-    if (ps) atomicAdd(&I.c.push_scanned, ps);
-    if (pv) atomicAdd(&I.c.pull_vertices, pv);
-    if (pl) atomicAdd(&I.c.pull_scanned, pl);
-    if (su) atomicAdd(&I.c.relax_success, su);
-    if (qe) atomicAdd(&I.c.queue_entries, qe);
+    const int gw = global_wave();
+    if (gw < I.maxw) {
+      Counters& c = I.cslot[gw];
+      c.expansions += e;
+      c.band_expansions += b;
+      c.push_scanned += ps;
+      c.pull_vertices += pv;
+      c.pull_scanned += pl;
+      c.relax_success += su;
+      c.queue_entries += qe;
+    }
     if (hm != kInf) atomicMin(&I.ub_next, hm);
   }
 }
@@ -373,7 +436,7 @@ __device__ __forceinline__ void flush_acc(Inst& I, WaveAcc& a) {
 // next frontier once per round (SAP) and onto the step's touched list once
 // per step. Convergent: every lane calls it.
 __device__ __forceinline__ void on_success(Inst& I, const DevGraph& g, bool ok, int t,
-                                           uint32_t c, WaveAcc& acc) {
+                                           uint32_t c, WaveAcc& acc, Chunk& cq, Chunk& ct) {
   bool wq = false, wt = false;
   if (ok) {
     uint32_t so = atomicMax(&I.stamp[t], I.rid);
@@ -382,15 +445,15 @@ __device__ __forceinline__ void on_success(Inst& I, const DevGraph& g, bool ok, 
     acc.success += 1;
     if (I.first && is_hub(g, t) && c < acc.hubmin) acc.hubmin = c;
   }
-  int nq = I.qsel ^ 1;
-  int p = wave_append(&I.q_next_cnt, wq);
+  const int nq = I.qsel ^ 1;
+  int p = chunk_append(cq, &I.q_next_cnt, wq);
   if (wq) {
-    if (p < I.n) I.q[nq][p] = t; else atomicOr(&I.flags, FLAG_CAPACITY);
+    if (p < I.list_cap) I.q[nq][p] = t; else atomicOr(&I.flags, FLAG_CAPACITY);
     acc.qent += 1;
   }
-  int p2 = wave_append(&I.touched_cnt, wt);
+  int p2 = chunk_append(ct, &I.touched_cnt, wt);
   if (wt) {
-    if (p2 < I.n) I.touched[p2] = t; else atomicOr(&I.flags, FLAG_CAPACITY);
+    if (p2 < I.list_cap) I.touched[p2] = t; else atomicOr(&I.flags, FLAG_CAPACITY);
     acc.qent += 1;
   }
 }
@@ -427,25 +490,44 @@ __device__ void wave_round(Inst& I, int kind, int item0, int nitems) {
   uint32_t d = 0;
   bool pull = false;
   const int it = item0 + lane;
-  const bool have = (kind == SEG_H) ? (lane == 0 && item0 < nitems) : (it < nitems);
+  bool have = (kind == SEG_H) ? (lane == 0 && item0 < nitems) : (it < nitems);
+  const int gw = global_wave();
+  uint2* st_q = I.cstate + 0 * I.maxw + gw;
+  uint2* st_t = I.cstate + 1 * I.maxw + gw;
+  uint2* st_u = I.cstate + 2 * I.maxw + gw;
+  Chunk cq = chunk_load(st_q, I.rid);
+  Chunk ct = chunk_load(st_t, I.step_rid0);
 
   if (kind == SEG_U) {
     pull = true;
     bool keep = false, active = false;
     if (have) {
-      u = (I.usel < 0) ? g.nonisolated[it] : I.ulist[I.usel][it];
+      if (I.usel < 0) {
+        u = g.nonisolated[it];
+      } else {
+        u = I.ulist[I.usel][it];
+        I.ulist[I.usel][it] = -1;
+      }
+      if (u < 0) have = false;
+    }
+    if (have) {
       d = I.dist[u];
       keep = d >= lb;
       active = d > lb && g.wmin[u] < ub - st;
+      acc.pvert += 1;
     }
-    int p = wave_append(&I.u_next_cnt, keep);
-    if (keep) I.ulist[I.usel < 0 ? 0 : (I.usel ^ 1)][p] = u;
+    Chunk cu = chunk_load(st_u, I.step_rid0);
+    int p = chunk_append(cu, &I.u_next_cnt, keep);
+    if (keep) {
+      if (p < I.list_cap) I.ulist[I.usel < 0 ? 0 : (I.usel ^ 1)][p] = u;
+      else atomicOr(&I.flags, FLAG_CAPACITY);
+    }
+    chunk_store(st_u, cu, I.step_rid0);
     if (active) {
       int rs = g.rowptr[u], re = g.rowptr[u + 1];
       lo = rs;
       int hi = lower_bound_key(g.adj, rs, re, (uint64_t)(ub - st) << 32);
       size = hi - lo;
-      acc.pvert += 1;
       acc.pullscan += (unsigned long long)size;
       if (size > I.heavy_split) {
         emit_heavy(I, u, d, lo, hi, true);
@@ -482,8 +564,11 @@ __device__ void wave_round(Inst& I, int kind, int item0, int nitems) {
         ok = d >= lb && d < ub;
       } else {  // SEG_Q
         u = I.q[I.qsel][it];
-        d = I.dist[u];
-        ok = d < ub;
+        I.q[I.qsel][it] = -1;
+        if (u >= 0) {
+          d = I.dist[u];
+          ok = d < ub;
+        }
       }
     }
     if (kind == SEG_P) {
@@ -493,9 +578,9 @@ __device__ void wave_round(Inst& I, int kind, int item0, int nitems) {
         uint32_t so = atomicMax(&I.stamp[u], I.step_rid0);
         wt = so < I.step_rid0;
       }
-      int p = wave_append(&I.touched_cnt, wt);
+      int p = chunk_append(ct, &I.touched_cnt, wt);
       if (wt) {
-        if (p < I.n) I.touched[p] = u; else atomicOr(&I.flags, FLAG_CAPACITY);
+        if (p < I.list_cap) I.touched[p] = u; else atomicOr(&I.flags, FLAG_CAPACITY);
         acc.qent += 1;
       }
     }
@@ -565,8 +650,10 @@ __device__ void wave_round(Inst& I, int kind, int item0, int nitems) {
         }
       }
     }
-    on_success(I, g, ok, t, c, acc);
+    on_success(I, g, ok, t, c, acc, cq, ct);
   }
+  chunk_store(st_q, cq, I.rid);
+  chunk_store(st_t, ct, I.step_rid0);
   flush_acc(I, acc);
 }
 
@@ -578,7 +665,8 @@ struct SettleLds {
   uint32_t hist[kLdsHist];
   unsigned long long sdec[kBlock / kWave];
   uint32_t maxd[kBlock / kWave];
-  int flag;
+  int iscan[kBlock / kWave + 1];
+  int base[2];
 };
 
 union BlockLds {
@@ -604,8 +692,13 @@ __device__ void block_settle(Inst& I, int kind, int item0, int nitems, SettleLds
   int v = -1;
   uint32_t d = kInf;
   if (it < nitems) {
-    v = (kind == SEG_ST) ? I.touched[it] : I.plist[I.psel][it];
-    d = I.dist[v];
+    if (kind == SEG_ST) {
+      v = I.touched[it];
+      I.touched[it] = -1;
+    } else {
+      v = I.plist[I.psel][it];
+    }
+    if (v >= 0) d = I.dist[v];
   }
   bool settle = (kind == SEG_ST) && v >= 0 && d < ub;
   bool pend = v >= 0 && d >= ub;
@@ -632,12 +725,21 @@ __device__ void block_settle(Inst& I, int kind, int item0, int nitems, SettleLds
     sdec = (unsigned long long)deg;
     maxd = d;
   }
-  int p = wave_append(&I.settled_cnt, settle);
+  // one atomic per workgroup and list
+  int tot_s, tot_p;
+  const int off_s = block_excl_scan<int>(settle ? 1 : 0, L.iscan, &tot_s);
+  const int off_p = block_excl_scan<int>(pend ? 1 : 0, L.iscan, &tot_p);
+  if (tid == 0) {
+    L.base[0] = tot_s ? atomicAdd(&I.settled_cnt, tot_s) : 0;
+    L.base[1] = tot_p ? atomicAdd(&I.p_next_cnt, tot_p) : 0;
+  }
+  __syncthreads();
   if (settle) {
+    int p = L.base[0] + off_s;
     if (p < I.n) I.settled[p] = v; else atomicOr(&I.flags, FLAG_CAPACITY);
   }
-  int q = wave_append(&I.p_next_cnt, pend);
   if (pend) {
+    int q = L.base[1] + off_p;
     if (q < I.n) I.plist[I.psel ^ 1][q] = v; else atomicOr(&I.flags, FLAG_CAPACITY);
   }
   unsigned long long ws = wave_sum(sdec);
@@ -651,7 +753,8 @@ __device__ void block_settle(Inst& I, int kind, int item0, int nitems, SettleLds
   if (lane_id() == 0) {
     L.sdec[tid / kWave] = ws;
     L.maxd[tid / kWave] = wm;
-    if (qe) atomicAdd(&I.c.queue_entries, qe);
+    const int gw = global_wave();
+    if (qe && gw < I.maxw) I.cslot[gw].queue_entries += qe;
   }
   __syncthreads();
   for (uint32_t k = tid; k < nb; k += kBlock) {
@@ -729,14 +832,14 @@ __device__ void transition(Inst& I, int32_t* cnt, int32_t* kinds, int32_t* pbs) 
   if (I.tick_kind == PH_ROUND) {
     if (I.init_round && I.pull_on) {
       I.usel = (I.usel < 0) ? 0 : (I.usel ^ 1);
-      I.nU = I.u_next_cnt;
+      I.nU = min(I.u_next_cnt, I.list_cap);
       I.u_next_cnt = 0;
     }
     I.init_round = 0;
     if (I.first && I.ub_next < I.ub) I.ub = I.ub_next;
     I.c.rounds += 1;
     I.rounds_in_step += 1;
-    const int nq = min(I.q_next_cnt, I.n), nh = min(I.h_next_cnt, I.heavy_cap);
+    const int nq = min(I.q_next_cnt, I.list_cap), nh = min(I.h_next_cnt, I.heavy_cap);
     I.q_next_cnt = 0;
     I.h_next_cnt = 0;
     if (nq > 0 || nh > 0) {
@@ -751,12 +854,12 @@ __device__ void transition(Inst& I, int32_t* cnt, int32_t* kinds, int32_t* pbs) 
     }
     if (I.first && I.ub == kInf) {
       I.phase = PH_DONE;
-      *I.rid_slot = I.rid + 1;
+      record_clean_end(I, min(I.touched_cnt, I.list_cap));
       return;
     }
     I.tick_kind = PH_SETTLE;
     I.phase = PH_SETTLE;
-    I.nT = min(I.touched_cnt, I.n);
+    I.nT = min(I.touched_cnt, I.list_cap);
     I.settled_mark = min(I.settled_cnt, I.n);
     I.settle_done = 0;
     int bt = (I.nT + kBlock - 1) / kBlock;
@@ -864,10 +967,22 @@ __device__ bool barrier_epilogue(Globals& G, unsigned int& gen, bool persistent)
   }
   __syncthreads();
   if (s_last) {
-    __threadfence();
+    if (threadIdx.x == 0) {
+      __threadfence();
+      if (G.tick_log && G.ticks < G.tick_log_cap) {
+        unsigned long long* e = G.tick_log + 4 * G.ticks;
+        e[0] = wall_clock64();
+        e[1] = (unsigned long long)G.total_batches;
+        const Inst& I0 = G.insts[0];
+        e[2] = (unsigned long long)I0.tick_kind | ((unsigned long long)I0.init_round << 8) |
+               ((unsigned long long)I0.pull_on << 9) | ((unsigned long long)I0.step << 16);
+      }
+    }
+    __syncthreads();
     count_ticks(G);
     build_table(G, true);
     if (threadIdx.x == 0) {
+      if (G.tick_log && G.ticks < G.tick_log_cap) G.tick_log[4 * G.ticks + 3] = wall_clock64();
       G.ticks += 1;
       if (G.ticks >= G.tick_limit) {
         G.error |= FLAG_TICKS;
@@ -884,20 +999,22 @@ __device__ bool barrier_epilogue(Globals& G, unsigned int& gen, bool persistent)
   if (!persistent) return true;
   __shared__ int s_ok;
   if (threadIdx.x == 0) {
+    // poll with relaxed loads (an acquire per poll would invalidate the
+    // cache on every iteration); one acquire fence once released
     unsigned long long spins = 0;
     int ok = 1;
-    while (__hip_atomic_load(&G.bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-      __builtin_amdgcn_s_sleep(2);
-      if (++spins > (1ull << 26)) {
+    while (__hip_atomic_load(&G.bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > (1ull << 27)) {
         atomicOr(&G.error, FLAG_TIMEOUT);
         ok = 0;
         break;
       }
     }
+    __threadfence();
     s_ok = ok;
   }
   __syncthreads();
-  __threadfence();
   gen += 1;
   return s_ok != 0;
 }
@@ -906,8 +1023,10 @@ __global__ void __launch_bounds__(kBlock) k_engine(Globals* Gp, int persistent, 
   __shared__ BlockLds lds;
   __shared__ unsigned int s_gen;
   Globals& G = *Gp;
-  if (threadIdx.x == 0)
+  if (threadIdx.x == 0) {
     s_gen = __hip_atomic_load(&G.bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    if (blockIdx.x == 0 && G.ticks == 0) G.t_start = wall_clock64();
+  }
   __syncthreads();
   unsigned int gen = s_gen;
   for (int t = 0;; ++t) {
@@ -932,10 +1051,27 @@ __global__ void k_init_arrays(Globals* Gp) {
   for (int i = 0; i < G.ninst; ++i) {
     Inst& I = G.insts[i];
     const DevGraph& g = *I.g;
-    const bool reset_stamp = *I.rid_slot > 0x80000000u;
+    const uint32_t* pw = I.rid_slot;
+    const bool reset_stamp = pw[PW_RID] > 0x80000000u;
     for (long long v = tid; v < I.n; v += stride) {
       I.dist[v] = kInf;
       if (reset_stamp) I.stamp[v] = 0;
+    }
+    // list regions a previous solve may have left holding entries
+    const long long dt = min((long long)pw[PW_TOUCHED], (long long)I.list_cap);
+    const long long du0 = min((long long)pw[PW_U0], (long long)I.list_cap);
+    const long long du1 = min((long long)pw[PW_U1], (long long)I.list_cap);
+    const long long dq0 = min((long long)pw[PW_Q0], (long long)I.list_cap);
+    const long long dq1 = min((long long)pw[PW_Q1], (long long)I.list_cap);
+    for (long long x = tid; x < dt; x += stride) I.touched[x] = -1;
+    for (long long x = tid; x < du0; x += stride) I.ulist[0][x] = -1;
+    for (long long x = tid; x < du1; x += stride) I.ulist[1][x] = -1;
+    for (long long x = tid; x < dq0; x += stride) I.q[0][x] = -1;
+    for (long long x = tid; x < dq1; x += stride) I.q[1][x] = -1;
+    for (long long x = tid; x < 3ll * I.maxw; x += stride) I.cstate[x] = make_uint2(0u, 0u);
+    for (long long x = tid; x < I.maxw; x += stride) {
+      Counters z = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+      I.cslot[x] = z;
     }
     for (long long r = tid; r < g.num_deg; r += stride) I.hist_cnt[r] = g.deg_cnt0[r];
     for (long long r = tid; r <= (long long)I.ring_mask; r += stride) {
@@ -952,8 +1088,12 @@ __global__ void __launch_bounds__(kBlock) k_init_ctl(Globals* Gp) {
     Inst& I = G.insts[i];
     const DevGraph& g = *I.g;
     if (threadIdx.x == 0) {
-      I.rid = *I.rid_slot;
+      uint32_t* pw = I.rid_slot;
+      I.rid = pw[PW_RID];
       if (I.rid > 0x80000000u) I.rid = 0;
+      // until this solve ends normally, assume every list may hold entries
+      pw[PW_RID] = I.rid + (1u << 24);
+      pw[PW_TOUCHED] = pw[PW_U0] = pw[PW_U1] = pw[PW_Q0] = pw[PW_Q1] = (uint32_t)I.list_cap;
       const int s = I.source;
       const int deg_s = g.rowptr[s + 1] - g.rowptr[s];
       I.dist[s] = 0;
@@ -989,7 +1129,7 @@ __global__ void __launch_bounds__(kBlock) k_init_ctl(Globals* Gp) {
       I.nF = 1;
       I.ub_next = is_hub(g, s) ? 0u : kInf;
       I.phase = deg_s > 0 ? PH_ROUND : PH_DONE;
-      if (deg_s == 0) *I.rid_slot = I.rid + 1;
+      if (deg_s == 0) record_clean_end(I, 1);
     }
     __syncthreads();
     // gap(0) from whole-graph statistics: sumD(0) = nnz, highD(0)

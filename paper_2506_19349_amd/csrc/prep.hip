@@ -50,14 +50,29 @@ __global__ void k_pack(const int32_t* col, const uint32_t* w, int32_t nnz, uint6
 // rows by length: 2..64 -> small, 65..kMedMax -> medium, longer -> large
 constexpr int kMedMax = 4096;
 
+// one atomic per wave and list (every lane of the wave calls it)
+__device__ __forceinline__ int wave_slot(int32_t* counter, bool want) {
+  uint64_t m = __ballot(want);
+  if (m == 0) return -1;
+  int leader = __ffsll((unsigned long long)m) - 1;
+  int base = 0;
+  if (__lane_id() == leader) base = atomicAdd(counter, __popcll(m));
+  base = __shfl(base, leader, kWave);
+  return want ? base + __popcll(m & ((1ull << __lane_id()) - 1ull)) : -1;
+}
+
 __global__ void k_classify(const int32_t* rowptr, int32_t n, int32_t* small, int32_t* nsmall,
                            int32_t* medium, int32_t* nmed, int32_t* large, int32_t* nlarge) {
-  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < n;
-       v += (long long)gridDim.x * blockDim.x) {
-    int len = rowptr[v + 1] - rowptr[v];
-    if (len >= 2 && len <= 64) small[atomicAdd(nsmall, 1)] = (int32_t)v;
-    else if (len > 64 && len <= kMedMax) medium[atomicAdd(nmed, 1)] = (int32_t)v;
-    else if (len > kMedMax) large[atomicAdd(nlarge, 1)] = (int32_t)v;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  const long long n_round = ((long long)n + stride - 1) / stride * stride;
+  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < n_round; v += stride) {
+    int len = v < n ? rowptr[v + 1] - rowptr[v] : 0;
+    int p0 = wave_slot(nsmall, len >= 2 && len <= 64);
+    int p1 = wave_slot(nmed, len > 64 && len <= kMedMax);
+    int p2 = wave_slot(nlarge, len > kMedMax);
+    if (p0 >= 0) small[p0] = (int32_t)v;
+    if (p1 >= 0) medium[p1] = (int32_t)v;
+    if (p2 >= 0) large[p2] = (int32_t)v;
   }
 }
 
