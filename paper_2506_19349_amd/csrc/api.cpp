@@ -605,7 +605,7 @@ sssp_status sssp_get_counters(hipStream_t stream, sssp_counters* out) {
     out->pulls += I.c.pulls;
     out->steps += I.c.steps;
     out->ticks += I.c.ticks;
-    flags |= I.flags;
+    flags |= I.flags.v;
   }
   out->high_d0 = hi[0].high_d0;
   out->gap0 = hi[0].gap0;

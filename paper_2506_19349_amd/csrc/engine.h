@@ -80,6 +80,19 @@ struct Counters {
       relax_success, queue_entries, rounds, pulls, steps, ticks;
 };
 
+struct alignas(128) HotI32 {
+  int32_t v;
+  int32_t pad[31];
+};
+struct alignas(128) HotU32 {
+  uint32_t v;
+  uint32_t pad[31];
+};
+struct alignas(128) HotU64 {
+  unsigned long long v;
+  unsigned long long pad[15];
+};
+
 struct Inst {
   // ---- fixed for a solve ----
   const DevGraph* g;
@@ -130,17 +143,15 @@ struct Inst {
   int32_t settled_mark;
   int32_t nsteprec;
   int32_t trace_len;
-  // ---- append counters (reset by the epilogue) ----
-  int32_t q_next_cnt, touched_cnt, p_next_cnt, u_next_cnt, settled_cnt, h_next_cnt;
-  uint32_t ub_next;
-  uint32_t max_settled;
-  unsigned long long S;    // sumD(lb): degree mass of the unsettled set
-  int32_t settle_items;    // items (padded) of the settle tick
-  int32_t settle_done;
-  uint32_t flags;
+  int32_t settle_items;    // batches of the settle tick
   uint32_t high_d0, gap0;
   uint32_t pad1;
   Counters c;
+  // ---- hot words: updated by device atomics from every CU, each on its own
+  // 128-byte line so that they never share a line with the fields above ----
+  HotI32 q_next_cnt, touched_cnt, p_next_cnt, u_next_cnt, settled_cnt, h_next_cnt, settle_done;
+  HotU32 ub_next, max_settled, flags;
+  HotU64 S;  // sumD(lb): degree mass of the unsettled set
 };
 
 // flags
@@ -154,10 +165,16 @@ constexpr uint32_t FLAG_TICKS = 32u;          // the tick limit stopped the engi
 // ------------------------------------------------------------- tick table --
 constexpr int kMaxSegPerInst = 5;
 
+constexpr int kMaxXcd = 8;  // XCDs (each with its own L2) on an MI355X
+
 struct Globals {
-  // grid barrier
-  unsigned int bar_count;
-  unsigned int bar_gen;
+  // grid barrier: arrival counter and release generation on lines of their own
+  HotU32 bar_count;
+  HotU32 bar_gen;
+  // per-XCD arrival counters, release generations and workgroup counts
+  HotU32 xcd_count[kMaxXcd];
+  HotU32 xcd_gen[kMaxXcd];
+  HotU32 xcd_members[kMaxXcd];
   unsigned int all_done;
   unsigned int error;
   // current tick layout

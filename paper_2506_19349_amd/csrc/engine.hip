@@ -238,7 +238,7 @@ __device__ uint32_t block_high_d(const int32_t* deg_vals, const uint32_t* cnt, i
 __device__ uint32_t block_compute_st(const Inst& I, uint32_t L, uint32_t gapL, int32_t nnz,
                                      HeurLds& lds) {
   const uint32_t M = I.M;
-  const unsigned long long S = I.S;
+  const unsigned long long S = I.S.v;
   if (!I.traversal_opt || M > kRingMax) return L;
   if (2ull * S >= (unsigned long long)nnz || I.gap_cur == M) return L;
   if (gapL == M) return L > M ? L - M : 0u;
@@ -313,16 +313,16 @@ __device__ void run_heuristic(Inst& I, HeurLds& lds) {
   const uint32_t L = I.ub;
   unsigned long long mass;
   uint32_t h = block_high_d(g.deg_vals, I.hist_cnt, g.num_deg, &mass, lds);
-  const unsigned long long S = I.S;
+  const unsigned long long S = I.S.v;
   uint32_t gapL = gap_of(S, h, g.nnz, I.M, g.rtow, I.alpha, I.beta);
   uint32_t stn = block_compute_st(I, L, gapL, g.nnz, lds);
   if (tid == 0) {
-    if (mass != S) I.flags |= FLAG_MASS;
+    if (mass != S) I.flags.v |= FLAG_MASS;
     StepRec rec;
     rec.lb = I.lb;
     rec.ub = L;
     rec.seg_begin = I.settled_mark;
-    rec.seg_end = min(I.settled_cnt, I.n);
+    rec.seg_end = min(I.settled_cnt.v, I.n);
     I.steprec[(uint32_t)I.nsteprec & I.steprec_mask] = rec;
     I.nsteprec += 1;
     if (I.trace_len < I.trace_cap) {
@@ -335,7 +335,7 @@ __device__ void run_heuristic(Inst& I, HeurLds& lds) {
     I.c.steps += 1;
   }
   const bool done = (L == kInf) ||
-                    (I.p_next_cnt == 0 && (unsigned long long)I.max_settled + I.M < L);
+                    (I.p_next_cnt.v == 0 && (unsigned long long)I.max_settled.v + I.M < L);
   if (done) {
     if (tid == 0) {
       I.phase = PH_DONE;
@@ -402,6 +402,49 @@ __device__ void run_heuristic(Inst& I, HeurLds& lds) {
 
 // ------------------------------------------------------------ tick: rounds --
 
+// Everything a batch needs from its instance, read once into registers: the
+// control words only change between ticks, and reading them through the
+// instance struct inside the loops would re-load them after every atomic.
+struct View {
+  const int32_t* rowptr;
+  const uint64_t* adj;
+  const uint32_t* wmin;
+  const uint32_t* hub_bits;
+  uint32_t* dist;
+  uint32_t* stamp;
+  int32_t* q_next;
+  int32_t* touched;
+  Inst* inst;
+  uint32_t lb, ub, st, lb0, rid, step_rid0;
+  int32_t list_cap, heavy_split, maxw;
+  uint32_t first;
+};
+
+__device__ __forceinline__ View make_view(Inst& I) {
+  View v;
+  const DevGraph& g = *I.g;
+  v.rowptr = g.rowptr;
+  v.adj = g.adj;
+  v.wmin = g.wmin;
+  v.hub_bits = g.hub_bits;
+  v.dist = I.dist;
+  v.stamp = I.stamp;
+  v.q_next = I.q[I.qsel ^ 1];
+  v.touched = I.touched;
+  v.inst = &I;
+  v.lb = I.lb;
+  v.ub = I.ub;
+  v.st = I.st;
+  v.lb0 = I.lb0;
+  v.rid = I.rid;
+  v.step_rid0 = I.step_rid0;
+  v.list_cap = I.list_cap;
+  v.heavy_split = I.heavy_split;
+  v.maxw = I.maxw;
+  v.first = I.first;
+  return v;
+}
+
 struct WaveAcc {
   unsigned long long expansions, band, pscan, pvert, pullscan, success, qent;
   uint32_t hubmin;
@@ -411,14 +454,14 @@ __device__ __forceinline__ int global_wave() { return (int)(blockIdx.x * (kBlock
 
 // Work counters go to this wave's own slot (plain read-modify-write: no
 // other wave touches it); only the step-1 hub bound is a shared atomic.
-__device__ __forceinline__ void flush_acc(Inst& I, WaveAcc& a) {
+__device__ __forceinline__ void flush_acc(Inst& I, int maxw, WaveAcc& a) {
   unsigned long long e = wave_sum(a.expansions), b = wave_sum(a.band), ps = wave_sum(a.pscan),
                      pv = wave_sum(a.pvert), pl = wave_sum(a.pullscan), su = wave_sum(a.success),
                      qe = wave_sum(a.qent);
   uint32_t hm = wave_min_u32(a.hubmin);
   if (lane_id() == 0) {
     const int gw = global_wave();
-    if (gw < I.maxw) {
+    if (gw < maxw) {
       Counters& c = I.cslot[gw];
       c.expansions += e;
       c.band_expansions += b;
@@ -428,32 +471,35 @@ __device__ __forceinline__ void flush_acc(Inst& I, WaveAcc& a) {
       c.relax_success += su;
       c.queue_entries += qe;
     }
-    if (hm != kInf) atomicMin(&I.ub_next, hm);
+    if (hm != kInf) atomicMin(&I.ub_next.v, hm);
   }
+}
+
+__device__ __forceinline__ bool hub_bit(const uint32_t* bits, int v) {
+  return (bits[v >> 5] >> (v & 31)) & 1u;
 }
 
 // A successful decrease of dist[t] to c during round `rid`: push t onto the
 // next frontier once per round (SAP) and onto the step's touched list once
 // per step. Convergent: every lane calls it.
-__device__ __forceinline__ void on_success(Inst& I, const DevGraph& g, bool ok, int t,
-                                           uint32_t c, WaveAcc& acc, Chunk& cq, Chunk& ct) {
+__device__ __forceinline__ void on_success(const View& V, bool ok, int t, uint32_t c, WaveAcc& acc,
+                                           Chunk& cq, Chunk& ct) {
   bool wq = false, wt = false;
   if (ok) {
-    uint32_t so = atomicMax(&I.stamp[t], I.rid);
-    wq = so < I.rid;
-    wt = so < I.step_rid0;
+    uint32_t so = atomicMax(&V.stamp[t], V.rid);
+    wq = so < V.rid;
+    wt = so < V.step_rid0;
     acc.success += 1;
-    if (I.first && is_hub(g, t) && c < acc.hubmin) acc.hubmin = c;
+    if (V.first && hub_bit(V.hub_bits, t) && c < acc.hubmin) acc.hubmin = c;
   }
-  const int nq = I.qsel ^ 1;
-  int p = chunk_append(cq, &I.q_next_cnt, wq);
+  int p = chunk_append(cq, &V.inst->q_next_cnt.v, wq);
   if (wq) {
-    if (p < I.list_cap) I.q[nq][p] = t; else atomicOr(&I.flags, FLAG_CAPACITY);
+    if (p < V.list_cap) V.q_next[p] = t; else atomicOr(&V.inst->flags.v, FLAG_CAPACITY);
     acc.qent += 1;
   }
-  int p2 = chunk_append(ct, &I.touched_cnt, wt);
+  int p2 = chunk_append(ct, &V.inst->touched_cnt.v, wt);
   if (wt) {
-    if (p2 < I.list_cap) I.touched[p2] = t; else atomicOr(&I.flags, FLAG_CAPACITY);
+    if (p2 < V.list_cap) V.touched[p2] = t; else atomicOr(&V.inst->flags.v, FLAG_CAPACITY);
     acc.qent += 1;
   }
 }
@@ -461,12 +507,13 @@ __device__ __forceinline__ void on_success(Inst& I, const DevGraph& g, bool ok, 
 // Split a long range into heavy chunks for the next tick (grid-wide).
 __device__ void emit_heavy(Inst& I, int u, uint32_t d, int lo, int hi, bool pull) {
   int nch = (hi - lo + kHeavyChunk - 1) / kHeavyChunk;
-  int base = atomicAdd(&I.h_next_cnt, nch);
+  int base = atomicAdd(&I.h_next_cnt.v, nch);
   HeavyItem* out = I.heavy[I.hsel ^ 1];
+  const int cap = I.heavy_cap;
   for (int k = 0; k < nch; ++k) {
     int pos = base + k;
-    if (pos >= I.heavy_cap) {
-      atomicOr(&I.flags, FLAG_CAPACITY);
+    if (pos >= cap) {
+      atomicOr(&I.flags.v, FLAG_CAPACITY);
       break;
     }
     int a = lo + k * kHeavyChunk;
@@ -482,9 +529,9 @@ __device__ void emit_heavy(Inst& I, int u, uint32_t d, int lo, int hi, bool pull
 
 // One wave processes up to 64 items of a round segment.
 __device__ void wave_round(Inst& I, int kind, int item0, int nitems) {
-  const DevGraph& g = *I.g;
+  const View V = make_view(I);
   const int lane = lane_id();
-  const uint32_t lb = I.lb, ub = I.ub, st = I.st;
+  const uint32_t lb = V.lb, ub = V.ub, st = V.st;
   WaveAcc acc = {0, 0, 0, 0, 0, 0, 0, kInf};
   int u = 0, lo = 0, size = 0;
   uint32_t d = 0;
@@ -492,44 +539,46 @@ __device__ void wave_round(Inst& I, int kind, int item0, int nitems) {
   const int it = item0 + lane;
   bool have = (kind == SEG_H) ? (lane == 0 && item0 < nitems) : (it < nitems);
   const int gw = global_wave();
-  uint2* st_q = I.cstate + 0 * I.maxw + gw;
-  uint2* st_t = I.cstate + 1 * I.maxw + gw;
-  uint2* st_u = I.cstate + 2 * I.maxw + gw;
-  Chunk cq = chunk_load(st_q, I.rid);
-  Chunk ct = chunk_load(st_t, I.step_rid0);
+  uint2* st_q = I.cstate + 0 * V.maxw + gw;
+  uint2* st_t = I.cstate + 1 * V.maxw + gw;
+  Chunk cq = chunk_load(st_q, V.rid);
+  Chunk ct = chunk_load(st_t, V.step_rid0);
 
   if (kind == SEG_U) {
     pull = true;
     bool keep = false, active = false;
+    const int usel = I.usel;
+    int32_t* ucur = usel < 0 ? nullptr : I.ulist[usel];
+    int32_t* unext = I.ulist[usel < 0 ? 0 : (usel ^ 1)];
     if (have) {
-      if (I.usel < 0) {
-        u = g.nonisolated[it];
+      if (ucur == nullptr) {
+        u = I.g->nonisolated[it];
       } else {
-        u = I.ulist[I.usel][it];
-        I.ulist[I.usel][it] = -1;
+        u = ucur[it];
+        ucur[it] = -1;
       }
       if (u < 0) have = false;
     }
     if (have) {
-      d = I.dist[u];
+      d = V.dist[u];
       keep = d >= lb;
-      active = d > lb && g.wmin[u] < ub - st;
+      active = d > lb && V.wmin[u] < ub - st;
       acc.pvert += 1;
     }
-    Chunk cu = chunk_load(st_u, I.step_rid0);
-    int p = chunk_append(cu, &I.u_next_cnt, keep);
+    uint2* st_u = I.cstate + 2 * V.maxw + gw;
+    Chunk cu = chunk_load(st_u, V.step_rid0);
+    int p = chunk_append(cu, &I.u_next_cnt.v, keep);
     if (keep) {
-      if (p < I.list_cap) I.ulist[I.usel < 0 ? 0 : (I.usel ^ 1)][p] = u;
-      else atomicOr(&I.flags, FLAG_CAPACITY);
+      if (p < V.list_cap) unext[p] = u; else atomicOr(&I.flags.v, FLAG_CAPACITY);
     }
-    chunk_store(st_u, cu, I.step_rid0);
+    chunk_store(st_u, cu, V.step_rid0);
     if (active) {
-      int rs = g.rowptr[u], re = g.rowptr[u + 1];
+      int rs = V.rowptr[u], re = V.rowptr[u + 1];
       lo = rs;
-      int hi = lower_bound_key(g.adj, rs, re, (uint64_t)(ub - st) << 32);
+      int hi = lower_bound_key(V.adj, rs, re, (uint64_t)(ub - st) << 32);
       size = hi - lo;
       acc.pullscan += (unsigned long long)size;
-      if (size > I.heavy_split) {
+      if (size > V.heavy_split) {
         emit_heavy(I, u, d, lo, hi, true);
         size = 0;
       }
@@ -541,7 +590,7 @@ __device__ void wave_round(Inst& I, int kind, int item0, int nitems) {
       lo = h.lo;
       int hi = h.hi_kind & 0x7fffffff;
       pull = (h.hi_kind & (int)0x80000000) != 0;
-      uint32_t du = I.dist[u];
+      uint32_t du = V.dist[u];
       if (pull) {
         d = du;
         size = du > lb ? hi - lo : 0;
@@ -556,17 +605,18 @@ __device__ void wave_round(Inst& I, int kind, int item0, int nitems) {
     if (have) {
       if (kind == SEG_W) {
         u = I.settled[I.wBegin + it];
-        d = I.dist[u];
-        ok = d >= I.lb0 && d <= st;
+        d = V.dist[u];
+        ok = d >= V.lb0 && d <= st;
       } else if (kind == SEG_P) {
         u = I.plist[I.psel][it];
-        d = I.dist[u];
+        d = V.dist[u];
         ok = d >= lb && d < ub;
       } else {  // SEG_Q
-        u = I.q[I.qsel][it];
-        I.q[I.qsel][it] = -1;
+        int32_t* qc = I.q[I.qsel];
+        u = qc[it];
+        qc[it] = -1;
         if (u >= 0) {
-          d = I.dist[u];
+          d = V.dist[u];
           ok = d < ub;
         }
       }
@@ -575,29 +625,29 @@ __device__ void wave_round(Inst& I, int kind, int item0, int nitems) {
       // band members of the pending list join this step's touched list
       bool wt = false;
       if (ok) {
-        uint32_t so = atomicMax(&I.stamp[u], I.step_rid0);
-        wt = so < I.step_rid0;
+        uint32_t so = atomicMax(&V.stamp[u], V.step_rid0);
+        wt = so < V.step_rid0;
       }
-      int p = chunk_append(ct, &I.touched_cnt, wt);
+      int p = chunk_append(ct, &I.touched_cnt.v, wt);
       if (wt) {
-        if (p < I.list_cap) I.touched[p] = u; else atomicOr(&I.flags, FLAG_CAPACITY);
+        if (p < V.list_cap) V.touched[p] = u; else atomicOr(&I.flags.v, FLAG_CAPACITY);
         acc.qent += 1;
       }
     }
     if (ok) {
-      int rs = g.rowptr[u], re = g.rowptr[u + 1];
+      int rs = V.rowptr[u], re = V.rowptr[u + 1];
       if (re - rs == 1 && d > 0) ok = false;  // leaf pruning (Algorithm)
       if (ok) {
         uint32_t wl = lb > d ? lb - d : 0u;
         uint32_t wh = ub - d;
-        lo = (wl <= g.wmin[u]) ? rs : lower_bound_key(g.adj, rs, re, (uint64_t)wl << 32);
-        int hi = lower_bound_key(g.adj, lo, re, (uint64_t)wh << 32);
-        if (ub == kInf && hi < re) atomicOr(&I.flags, FLAG_MAYBE_OVERFLOW);
+        lo = (wl <= V.wmin[u]) ? rs : lower_bound_key(V.adj, rs, re, (uint64_t)wl << 32);
+        int hi = lower_bound_key(V.adj, lo, re, (uint64_t)wh << 32);
+        if (ub == kInf && hi < re) atomicOr(&I.flags.v, FLAG_MAYBE_OVERFLOW);
         size = hi - lo;
         acc.expansions += 1;
         acc.band += (d >= lb) ? 1 : 0;
         acc.pscan += (unsigned long long)size;
-        if (size > I.heavy_split) {
+        if (size > V.heavy_split) {
           emit_heavy(I, u, d, lo, hi, false);
           size = 0;
         }
@@ -627,34 +677,34 @@ __device__ void wave_round(Inst& I, int kind, int item0, int nitems) {
     int t = 0;
     uint32_t c = 0;
     if (e < total) {
-      const uint64_t ent = g.adj[loj + (e - exj)];
+      const uint64_t ent = V.adj[loj + (e - exj)];
       const int v = (int)(uint32_t)(ent & 0xffffffffull);
       const uint32_t w = (uint32_t)(ent >> 32);
       if (!pull) {
         c = dj + w;  // < ub by the range
         t = v;
-        if (c < I.dist[v]) {
-          uint32_t old = atomicMin(&I.dist[v], c);
+        if (c < V.dist[v]) {
+          uint32_t old = atomicMin(&V.dist[v], c);
           ok = c < old;
         }
       } else {
-        const uint32_t dv = I.dist[v];
+        const uint32_t dv = V.dist[v];
         if (dv >= st && dv < lb) {
           unsigned long long cc = (unsigned long long)dv + w;
           if (cc < ub && cc < dj) {
             c = (uint32_t)cc;
             t = uj;
-            uint32_t old = atomicMin(&I.dist[uj], c);
+            uint32_t old = atomicMin(&V.dist[uj], c);
             ok = c < old;
           }
         }
       }
     }
-    on_success(I, g, ok, t, c, acc, cq, ct);
+    on_success(V, ok, t, c, acc, cq, ct);
   }
-  chunk_store(st_q, cq, I.rid);
-  chunk_store(st_t, ct, I.step_rid0);
-  flush_acc(I, acc);
+  chunk_store(st_q, cq, V.rid);
+  chunk_store(st_t, ct, V.step_rid0);
+  flush_acc(I, V.maxw, acc);
 }
 
 // ------------------------------------------------------------ tick: settle --
@@ -681,10 +731,23 @@ union BlockLds {
 __device__ void block_settle(Inst& I, int kind, int item0, int nitems, SettleLds& L) {
   const DevGraph& g = *I.g;
   const int tid = threadIdx.x;
-  const uint32_t lb = I.lb, ub = I.ub;
+  const uint32_t lb = I.lb, ub = I.ub, M = I.M;
   const uint32_t band = ub - lb;
   const uint32_t nb = band < (uint32_t)kLdsRing ? band : (uint32_t)kLdsRing;
   const int nh = g.num_deg < kLdsHist ? g.num_deg : kLdsHist;
+  const int32_t* rowptr = g.rowptr;
+  const int32_t* drank = g.drank;
+  uint32_t* dist = I.dist;
+  uint64_t* ring_mass = I.ring_mass;
+  uint32_t* ring_cnt = I.ring_cnt;
+  uint32_t* hist_cnt = I.hist_cnt;
+  const uint32_t ring_mask = I.ring_mask;
+  int32_t* touched = I.touched;
+  int32_t* pcur = I.plist[I.psel];
+  int32_t* pnext = I.plist[I.psel ^ 1];
+  int32_t* settled = I.settled;
+  const int n = I.n;
+  const int maxw = I.maxw;
   for (uint32_t k = tid; k < nb; k += kBlock) { L.mass[k] = 0; L.cnt[k] = 0; }
   for (int k = tid; k < nh; k += kBlock) L.hist[k] = 0;
   __syncthreads();
@@ -693,34 +756,34 @@ __device__ void block_settle(Inst& I, int kind, int item0, int nitems, SettleLds
   uint32_t d = kInf;
   if (it < nitems) {
     if (kind == SEG_ST) {
-      v = I.touched[it];
-      I.touched[it] = -1;
+      v = touched[it];
+      touched[it] = -1;
     } else {
-      v = I.plist[I.psel][it];
+      v = pcur[it];
     }
-    if (v >= 0) d = I.dist[v];
+    if (v >= 0) d = dist[v];
   }
   bool settle = (kind == SEG_ST) && v >= 0 && d < ub;
   bool pend = v >= 0 && d >= ub;
   unsigned long long sdec = 0;
   uint32_t maxd = 0;
   if (settle) {
-    int deg = g.rowptr[v + 1] - g.rowptr[v];
+    int deg = rowptr[v + 1] - rowptr[v];
     uint32_t off = d - lb;
     // only the window [ub - M, ub) is read by the next computeST; the first
     // step's band may be wider, and older values would alias ring slots
-    if ((unsigned long long)d + I.M >= ub) {
+    if ((unsigned long long)d + M >= ub) {
       if (off < nb) {
         atomicAdd(&L.mass[off], (uint32_t)deg);
         atomicAdd(&L.cnt[off], 1u);
       } else {
-        atomicAdd(&I.ring_mass[d & I.ring_mask], (unsigned long long)deg);
-        atomicAdd(&I.ring_cnt[d & I.ring_mask], 1u);
+        atomicAdd(&ring_mass[d & ring_mask], (unsigned long long)deg);
+        atomicAdd(&ring_cnt[d & ring_mask], 1u);
       }
     }
-    int r = g.drank[v];
+    int r = drank[v];
     if (r >= 0) {
-      if (r < nh) atomicAdd(&L.hist[r], 1u); else atomicSub(&I.hist_cnt[r], 1u);
+      if (r < nh) atomicAdd(&L.hist[r], 1u); else atomicSub(&hist_cnt[r], 1u);
     }
     sdec = (unsigned long long)deg;
     maxd = d;
@@ -730,17 +793,17 @@ __device__ void block_settle(Inst& I, int kind, int item0, int nitems, SettleLds
   const int off_s = block_excl_scan<int>(settle ? 1 : 0, L.iscan, &tot_s);
   const int off_p = block_excl_scan<int>(pend ? 1 : 0, L.iscan, &tot_p);
   if (tid == 0) {
-    L.base[0] = tot_s ? atomicAdd(&I.settled_cnt, tot_s) : 0;
-    L.base[1] = tot_p ? atomicAdd(&I.p_next_cnt, tot_p) : 0;
+    L.base[0] = tot_s ? atomicAdd(&I.settled_cnt.v, tot_s) : 0;
+    L.base[1] = tot_p ? atomicAdd(&I.p_next_cnt.v, tot_p) : 0;
   }
   __syncthreads();
   if (settle) {
     int p = L.base[0] + off_s;
-    if (p < I.n) I.settled[p] = v; else atomicOr(&I.flags, FLAG_CAPACITY);
+    if (p < n) settled[p] = v; else atomicOr(&I.flags.v, FLAG_CAPACITY);
   }
   if (pend) {
     int q = L.base[1] + off_p;
-    if (q < I.n) I.plist[I.psel ^ 1][q] = v; else atomicOr(&I.flags, FLAG_CAPACITY);
+    if (q < n) pnext[q] = v; else atomicOr(&I.flags.v, FLAG_CAPACITY);
   }
   unsigned long long ws = wave_sum(sdec);
   uint32_t wm = maxd;
@@ -754,20 +817,20 @@ __device__ void block_settle(Inst& I, int kind, int item0, int nitems, SettleLds
     L.sdec[tid / kWave] = ws;
     L.maxd[tid / kWave] = wm;
     const int gw = global_wave();
-    if (qe && gw < I.maxw) I.cslot[gw].queue_entries += qe;
+    if (qe && gw < maxw) I.cslot[gw].queue_entries += qe;
   }
   __syncthreads();
   for (uint32_t k = tid; k < nb; k += kBlock) {
     uint32_t c = L.cnt[k];
     if (c) {
-      uint32_t slot = (lb + k) & I.ring_mask;
-      atomicAdd(&I.ring_mass[slot], (unsigned long long)L.mass[k]);
-      atomicAdd(&I.ring_cnt[slot], c);
+      uint32_t slot = (lb + k) & ring_mask;
+      atomicAdd(&ring_mass[slot], (unsigned long long)L.mass[k]);
+      atomicAdd(&ring_cnt[slot], c);
     }
   }
   for (int k = tid; k < nh; k += kBlock) {
     uint32_t c = L.hist[k];
-    if (c) atomicSub(&I.hist_cnt[k], c);
+    if (c) atomicSub(&hist_cnt[k], c);
   }
   if (tid == 0) {
     unsigned long long s = 0;
@@ -776,8 +839,8 @@ __device__ void block_settle(Inst& I, int kind, int item0, int nitems, SettleLds
       s += L.sdec[w];
       m = L.maxd[w] > m ? L.maxd[w] : m;
     }
-    if (s) atomicAdd(&I.S, (unsigned long long)(0ull - s));
-    if (m) atomicMax(&I.max_settled, m);
+    if (s) atomicAdd(&I.S.v, (unsigned long long)(0ull - s));
+    if (m) atomicMax(&I.max_settled.v, m);
   }
   __syncthreads();
 }
@@ -796,7 +859,8 @@ __device__ int find_segment(const Globals& G, int b) {
 __device__ void run_tick(Globals& G, BlockLds& lds) {
   const int wid = threadIdx.x / kWave;
   __shared__ int s_last;
-  for (int b = blockIdx.x; b < G.total_batches; b += gridDim.x) {
+  const int total_batches = G.total_batches;
+  for (int b = blockIdx.x; b < total_batches; b += gridDim.x) {
     const int sgi = find_segment(G, b);
     Inst& I = G.insts[G.seg_inst[sgi]];
     const int kind = G.seg_kind[sgi];
@@ -805,15 +869,21 @@ __device__ void run_tick(Globals& G, BlockLds& lds) {
     const int cnt = G.seg_count[sgi];
     if (kind == SEG_ST || kind == SEG_SP) {
       block_settle(I, kind, item0, cnt, lds.s);
+      // the heuristic only reads words updated by device atomics: waiting for
+      // this batch's atomics to complete is enough before counting it done
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
       if (threadIdx.x == 0) {
-        __threadfence();
-        int done = atomicAdd(&I.settle_done, 1) + 1;
+        int done = atomicAdd(&I.settle_done.v, 1) + 1;
         s_last = (done == I.settle_items);
       }
       __syncthreads();
       if (s_last) {
-        __threadfence();
+        if (threadIdx.x == 0) __threadfence();
+        __syncthreads();
         run_heuristic(I, lds.h);
+        // its plain stores (next step's control words, ring clears) must be
+        // out of this XCD's L2 before other XCDs use them: done at the barrier
       }
       __syncthreads();
     } else if (kind == SEG_H) {
@@ -832,16 +902,16 @@ __device__ void transition(Inst& I, int32_t* cnt, int32_t* kinds, int32_t* pbs) 
   if (I.tick_kind == PH_ROUND) {
     if (I.init_round && I.pull_on) {
       I.usel = (I.usel < 0) ? 0 : (I.usel ^ 1);
-      I.nU = min(I.u_next_cnt, I.list_cap);
-      I.u_next_cnt = 0;
+      I.nU = min(I.u_next_cnt.v, I.list_cap);
+      I.u_next_cnt.v = 0;
     }
     I.init_round = 0;
-    if (I.first && I.ub_next < I.ub) I.ub = I.ub_next;
+    if (I.first && I.ub_next.v < I.ub) I.ub = I.ub_next.v;
     I.c.rounds += 1;
     I.rounds_in_step += 1;
-    const int nq = min(I.q_next_cnt, I.list_cap), nh = min(I.h_next_cnt, I.heavy_cap);
-    I.q_next_cnt = 0;
-    I.h_next_cnt = 0;
+    const int nq = min(I.q_next_cnt.v, I.list_cap), nh = min(I.h_next_cnt.v, I.heavy_cap);
+    I.q_next_cnt.v = 0;
+    I.h_next_cnt.v = 0;
     if (nq > 0 || nh > 0) {
       I.qsel ^= 1;
       I.hsel ^= 1;
@@ -854,14 +924,14 @@ __device__ void transition(Inst& I, int32_t* cnt, int32_t* kinds, int32_t* pbs) 
     }
     if (I.first && I.ub == kInf) {
       I.phase = PH_DONE;
-      record_clean_end(I, min(I.touched_cnt, I.list_cap));
+      record_clean_end(I, min(I.touched_cnt.v, I.list_cap));
       return;
     }
     I.tick_kind = PH_SETTLE;
     I.phase = PH_SETTLE;
-    I.nT = min(I.touched_cnt, I.list_cap);
-    I.settled_mark = min(I.settled_cnt, I.n);
-    I.settle_done = 0;
+    I.nT = min(I.touched_cnt.v, I.list_cap);
+    I.settled_mark = min(I.settled_cnt.v, I.n);
+    I.settle_done.v = 0;
     int bt = (I.nT + kBlock - 1) / kBlock;
     if (bt < 1) bt = 1;
     int bp = (I.nP + kBlock - 1) / kBlock;
@@ -874,9 +944,9 @@ __device__ void transition(Inst& I, int32_t* cnt, int32_t* kinds, int32_t* pbs) 
   }
   // a settle tick ran; the heuristic has set phase to ROUND or DONE
   I.psel ^= 1;
-  I.nP = min(I.p_next_cnt, I.n);
-  I.p_next_cnt = 0;
-  I.touched_cnt = 0;
+  I.nP = min(I.p_next_cnt.v, I.n);
+  I.p_next_cnt.v = 0;
+  I.touched_cnt.v = 0;
   if (I.phase == PH_DONE) return;
   I.tick_kind = PH_ROUND;
   I.init_round = 1;
@@ -955,86 +1025,201 @@ __device__ void count_ticks(Globals& G) {
 
 // ---------------------------------------------------------------- kernels --
 
-// Grid barrier whose last arriver runs the epilogue. Returns false if the
-// wait gave up (spin limit), after recording FLAG_TIMEOUT in G.error.
-__device__ bool barrier_epilogue(Globals& G, unsigned int& gen, bool persistent) {
+// ----------------------------------------------------------- grid barrier --
+// Workgroups are spread over the chip's XCDs (read from the XCC_ID hardware
+// register); each XCD has its own L2. Between ticks, data written by one XCD
+// must reach the others: the L2 of the writer is written back and the L2 of
+// the reader invalidated. Doing that from every workgroup serialises hundreds
+// of whole-cache operations per XCD per tick, so the barrier is two-level:
+// the last workgroup of an XCD to arrive writes back and invalidates that
+// XCD's L2 once, and arrives at the grid-wide counter; the last of those runs
+// the epilogue; on release every XCD leader invalidates its L2 and then
+// releases its own workgroups.
+
+__device__ __forceinline__ uint32_t xcd_of_this_wg() {
+  uint32_t r;
+  asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(r));
+  return r & (uint32_t)(kMaxXcd - 1);
+}
+
+// A workgroup released by its XCD leader must drop stale lines: an L1-only
+// invalidate (the cross-CU workgroup acquire) is not enough here -- measured:
+// stale data was read -- so it takes the agent-scope acquire.
+__device__ __forceinline__ void acquire_after_release() { __threadfence(); }
+
+__device__ bool spin_until_changed(unsigned int* word, unsigned int old, unsigned int* err) {
+  unsigned long long spins = 0;
+  while (__hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == old) {
+    __builtin_amdgcn_s_sleep(1);
+    if (++spins > (1ull << 27)) {
+      atomicOr(err, FLAG_TIMEOUT);
+      return false;
+    }
+  }
+  return true;
+}
+
+// The serial part between two ticks (one workgroup): tick log, phase
+// transitions and the next tick's work layout.
+__device__ void epilogue(Globals& G) {
+  if (threadIdx.x == 0) {
+    if (G.tick_log && G.ticks < G.tick_log_cap) {
+      unsigned long long* e = G.tick_log + 4 * G.ticks;
+      e[0] = wall_clock64();
+      e[1] = (unsigned long long)G.total_batches;
+      const Inst& I0 = G.insts[0];
+      e[2] = (unsigned long long)I0.tick_kind | ((unsigned long long)I0.init_round << 8) |
+             ((unsigned long long)I0.pull_on << 9) | ((unsigned long long)I0.step << 16);
+    }
+  }
+  __syncthreads();
+  count_ticks(G);
+  build_table(G, true);
+  if (threadIdx.x == 0) {
+    if (G.tick_log && G.ticks < G.tick_log_cap) G.tick_log[4 * G.ticks + 3] = wall_clock64();
+    G.ticks += 1;
+    if (G.ticks >= G.tick_limit) {
+      G.error |= FLAG_TICKS;
+      G.all_done = 1u;
+    }
+  }
+  __syncthreads();
+}
+
+struct BarrierState {
+  unsigned int gen;    // grid-wide release generation seen last
+  unsigned int xgen;   // this XCD's release generation seen last
+  uint32_t xcd;
+  uint32_t members;    // workgroups on this XCD
+  uint32_t nxcd;       // XCDs with at least one workgroup
+};
+
+// Flat barrier with full fences by every workgroup; used once per launch to
+// register the workgroups of each XCD, and as the whole barrier of the
+// one-launch-per-tick mode (where the kernel boundary does the waiting).
+__device__ bool barrier_flat(Globals& G, unsigned int& gen, bool wait, bool run_epilogue) {
   __shared__ int s_last;
+  __shared__ int s_ok;
   __syncthreads();
   if (threadIdx.x == 0) {
     __threadfence();
-    unsigned int arrived = atomicAdd(&G.bar_count, 1u);
+    unsigned int arrived = atomicAdd(&G.bar_count.v, 1u);
     s_last = (arrived == gridDim.x - 1);
+    s_ok = 1;
   }
   __syncthreads();
   if (s_last) {
-    if (threadIdx.x == 0) {
-      __threadfence();
-      if (G.tick_log && G.ticks < G.tick_log_cap) {
-        unsigned long long* e = G.tick_log + 4 * G.ticks;
-        e[0] = wall_clock64();
-        e[1] = (unsigned long long)G.total_batches;
-        const Inst& I0 = G.insts[0];
-        e[2] = (unsigned long long)I0.tick_kind | ((unsigned long long)I0.init_round << 8) |
-               ((unsigned long long)I0.pull_on << 9) | ((unsigned long long)I0.step << 16);
-      }
-    }
+    if (threadIdx.x == 0) __threadfence();
     __syncthreads();
-    count_ticks(G);
-    build_table(G, true);
+    if (run_epilogue) epilogue(G);
     if (threadIdx.x == 0) {
-      if (G.tick_log && G.ticks < G.tick_log_cap) G.tick_log[4 * G.ticks + 3] = wall_clock64();
-      G.ticks += 1;
-      if (G.ticks >= G.tick_limit) {
-        G.error |= FLAG_TICKS;
-        G.all_done = 1u;
-      }
-      __hip_atomic_store(&G.bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&G.bar_count.v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __threadfence();
-      __hip_atomic_fetch_add(&G.bar_gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      atomicAdd(&G.bar_gen.v, 1u);
     }
-    __syncthreads();
-    gen += 1;
-    return true;
-  }
-  if (!persistent) return true;
-  __shared__ int s_ok;
-  if (threadIdx.x == 0) {
-    // poll with relaxed loads (an acquire per poll would invalidate the
-    // cache on every iteration); one acquire fence once released
-    unsigned long long spins = 0;
-    int ok = 1;
-    while (__hip_atomic_load(&G.bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-      __builtin_amdgcn_s_sleep(1);
-      if (++spins > (1ull << 27)) {
-        atomicOr(&G.error, FLAG_TIMEOUT);
-        ok = 0;
-        break;
-      }
+  } else if (wait) {
+    if (threadIdx.x == 0) {
+      s_ok = spin_until_changed(&G.bar_gen.v, gen, &G.error) ? 1 : 0;
+      __threadfence();
     }
-    __threadfence();
-    s_ok = ok;
   }
   __syncthreads();
   gen += 1;
   return s_ok != 0;
 }
 
+// Two-level barrier of the persistent engine; the grid-wide last arriver runs
+// the epilogue. Returns false if a wait gave up.
+__device__ bool barrier_tick(Globals& G, BarrierState& B) {
+  __shared__ int s_role;  // 0 wait for the XCD leader, 1 XCD leader, 2 epilogue
+  __shared__ int s_ok;
+  // every wave's stores and atomics of this tick are complete before arriving
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    s_ok = 1;
+    unsigned int a = atomicAdd(&G.xcd_count[B.xcd].v, 1u);
+    if (a == B.members - 1) {
+      __hip_atomic_store(&G.xcd_count[B.xcd].v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __threadfence();  // this XCD's writes leave its L2
+      unsigned int b = atomicAdd(&G.bar_count.v, 1u);
+      if (b == B.nxcd - 1) {
+        __hip_atomic_store(&G.bar_count.v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();  // see every XCD's written-back data
+        s_role = 2;
+      } else {
+        s_ok = spin_until_changed(&G.bar_gen.v, B.gen, &G.error) ? 1 : 0;
+        __threadfence();  // drop stale lines from this XCD's L2
+        s_role = 1;
+      }
+    } else {
+      s_role = 0;
+    }
+  }
+  __syncthreads();
+  const int role = s_role;
+  if (role == 2) {
+    epilogue(G);
+    if (threadIdx.x == 0) {
+      __threadfence();
+      atomicAdd(&G.bar_gen.v, 1u);
+      atomicAdd(&G.xcd_gen[B.xcd].v, 1u);
+    }
+  } else if (role == 1) {
+    if (threadIdx.x == 0) atomicAdd(&G.xcd_gen[B.xcd].v, 1u);
+  } else {
+    if (threadIdx.x == 0) {
+      s_ok = spin_until_changed(&G.xcd_gen[B.xcd].v, B.xgen, &G.error) ? 1 : 0;
+      acquire_after_release();
+    }
+  }
+  __syncthreads();
+  B.gen += 1;
+  B.xgen += 1;
+  return s_ok != 0;
+}
+
 __global__ void __launch_bounds__(kBlock) k_engine(Globals* Gp, int persistent, int max_ticks) {
   __shared__ BlockLds lds;
-  __shared__ unsigned int s_gen;
+  __shared__ BarrierState s_b;
   Globals& G = *Gp;
   if (threadIdx.x == 0) {
-    s_gen = __hip_atomic_load(&G.bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    s_b.gen = __hip_atomic_load(&G.bar_gen.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (blockIdx.x == 0 && G.ticks == 0) G.t_start = wall_clock64();
   }
   __syncthreads();
-  unsigned int gen = s_gen;
+  if (!persistent) {
+    // one tick; the kernel boundary is the barrier
+    if (__hip_atomic_load(&G.all_done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+    run_tick(G, lds);
+    unsigned int gen = s_b.gen;
+    barrier_flat(G, gen, false, true);
+    return;
+  }
+  // register this workgroup with its XCD, then settle the counts grid-wide
+  if (threadIdx.x == 0) {
+    s_b.xcd = xcd_of_this_wg();
+    s_b.xgen = __hip_atomic_load(&G.xcd_gen[s_b.xcd].v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    atomicAdd(&G.xcd_members[s_b.xcd].v, 1u);
+  }
+  __syncthreads();
+  unsigned int gen = s_b.gen;
+  if (!barrier_flat(G, gen, true, false)) return;
+  if (threadIdx.x == 0) {
+    s_b.gen = gen;
+    s_b.members = __hip_atomic_load(&G.xcd_members[s_b.xcd].v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t nx = 0;
+    for (int x = 0; x < kMaxXcd; ++x)
+      nx += __hip_atomic_load(&G.xcd_members[x].v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ? 1u : 0u;
+    s_b.nxcd = nx;
+  }
+  __syncthreads();
+  BarrierState B = s_b;
   for (int t = 0;; ++t) {
     if (__hip_atomic_load(&G.all_done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
     if (__hip_atomic_load(&G.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
     run_tick(G, lds);
-    bool ok = barrier_epilogue(G, gen, persistent != 0);
-    if (!ok || !persistent) break;
+    if (!barrier_tick(G, B)) break;
     if (max_ticks > 0 && t + 1 >= max_ticks) {
       if (threadIdx.x == 0 && blockIdx.x == 0) G.max_ticks_hit = 1;
       break;
@@ -1105,15 +1290,15 @@ __global__ void __launch_bounds__(kBlock) k_init_ctl(Globals* Gp) {
       I.qsel = 0; I.psel = 0; I.usel = -1; I.hsel = 0;
       I.nP = 0; I.nU = g.n_nonisolated; I.nT = 0; I.nH = 0;
       I.wBegin = 0; I.wEnd = 0;
-      I.q_next_cnt = 0; I.touched_cnt = 0; I.p_next_cnt = 0; I.u_next_cnt = 0;
-      I.settled_cnt = 0; I.h_next_cnt = 0;
+      I.q_next_cnt.v = 0; I.touched_cnt.v = 0; I.p_next_cnt.v = 0; I.u_next_cnt.v = 0;
+      I.settled_cnt.v = 0; I.h_next_cnt.v = 0;
       I.settled_mark = 0;
       I.nsteprec = 0;
       I.trace_len = 0;
-      I.max_settled = 0;
-      I.S = (unsigned long long)g.nnz;
-      I.settle_items = 0; I.settle_done = 0;
-      I.flags = 0;
+      I.max_settled.v = 0;
+      I.S.v = (unsigned long long)g.nnz;
+      I.settle_items = 0; I.settle_done.v = 0;
+      I.flags.v = 0;
       I.pull_on = 0;
       I.init_round = 0;
       I.tick_kind = PH_ROUND;
@@ -1124,10 +1309,10 @@ __global__ void __launch_bounds__(kBlock) k_init_ctl(Globals* Gp) {
       I.stamp[s] = I.step_rid0;
       I.rid = I.step_rid0 + 1;
       I.touched[0] = s;
-      I.touched_cnt = 1;
+      I.touched_cnt.v = 1;
       I.q[0][0] = s;
       I.nF = 1;
-      I.ub_next = is_hub(g, s) ? 0u : kInf;
+      I.ub_next.v = is_hub(g, s) ? 0u : kInf;
       I.phase = deg_s > 0 ? PH_ROUND : PH_DONE;
       if (deg_s == 0) record_clean_end(I, 1);
     }
@@ -1141,7 +1326,11 @@ __global__ void __launch_bounds__(kBlock) k_init_ctl(Globals* Gp) {
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    G.bar_count = 0;
+    G.bar_count.v = 0;
+    for (int x = 0; x < kMaxXcd; ++x) {
+      G.xcd_count[x].v = 0;
+      G.xcd_members[x].v = 0;
+    }
     G.error = 0;
     G.max_ticks_hit = 0;
     G.ticks = 0;
@@ -1157,7 +1346,7 @@ __global__ void k_overflow_check(Globals* Gp) {
   Globals& G = *Gp;
   for (int i = 0; i < G.ninst; ++i) {
     Inst& I = G.insts[i];
-    if (!(I.flags & FLAG_MAYBE_OVERFLOW)) continue;
+    if (!(I.flags.v & FLAG_MAYBE_OVERFLOW)) continue;
     const DevGraph& g = *I.g;
     bool found = false;
     for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < g.n && !found;
@@ -1171,7 +1360,7 @@ __global__ void k_overflow_check(Globals* Gp) {
         }
       }
     }
-    if (found) atomicOr(&I.flags, FLAG_OVERFLOW);
+    if (found) atomicOr(&I.flags.v, FLAG_OVERFLOW);
   }
 }
 
