@@ -67,7 +67,6 @@ struct SlotBuf {
   StepRec* steprec = nullptr;
   TraceRec* trace = nullptr;
   uint32_t* rid = nullptr;
-  uint2* cstate = nullptr;
   Counters* cslot = nullptr;
   std::vector<void*> allocs;
   void release() {
@@ -87,7 +86,7 @@ Needs needs_for(const DevGraph& g, int maxw) {
   Needs r;
   r.n = g.n;
   r.maxw = maxw;
-  r.list = g.n + maxw * kChunk;
+  r.list = g.n;
   r.heavy = g.nnz / 128 + 4096;
   r.hist = std::max(g.num_deg, 1);
   r.trace = 1 << 16;
@@ -143,7 +142,6 @@ hipError_t ensure_slot(SlotBuf& s, const Needs& nd) {
   A(&s.plist[1], m.n);
   A(&s.ulist[0], m.list);
   A(&s.ulist[1], m.list);
-  A(&s.cstate, 3 * (size_t)m.maxw);
   A(&s.cslot, (size_t)m.maxw);
   A(&s.heavy[0], m.heavy);
   A(&s.heavy[1], m.heavy);
@@ -155,9 +153,6 @@ hipError_t ensure_slot(SlotBuf& s, const Needs& nd) {
   A(&s.rid, PW_COUNT);
   if (e == hipSuccess) e = hipMemset(s.stamp, 0, sizeof(uint32_t) * (size_t)m.n);
   if (e == hipSuccess) e = hipMemset(s.rid, 0, sizeof(uint32_t) * PW_COUNT);
-  // chunked lists start (and are kept) at -1 in every slot not holding an entry
-  for (int32_t* lp : {s.q[0], s.q[1], s.touched, s.ulist[0], s.ulist[1]})
-    if (e == hipSuccess) e = hipMemset(lp, 0xFF, sizeof(int32_t) * (size_t)m.list);
   if (e != hipSuccess) {
     s.release();
     (void)hipGetLastError();
@@ -379,10 +374,8 @@ sssp_status run_instances(const sssp_graph* const* gs, const int32_t* sources, i
     I.steprec = s.steprec;
     I.trace = s.trace;
     I.rid_slot = s.rid;
-    I.cstate = s.cstate;
     I.cslot = s.cslot;
     I.maxw = s.maxw;
-    I.list_cap = s.list_cap;
     I.heavy_cap = s.heavy_cap;
     Needs nd = needs_for(gs[i]->gh.h, s.maxw);
     I.ring_mask = nd.ring - 1;

@@ -17,10 +17,12 @@ constexpr int kLdsRing = 1024;           // settle: distance bins privatised in 
 constexpr int kLdsHist = 1024;           // settle: degree ranks privatised in LDS
 constexpr int kHeavyChunk = 256;         // edges per heavy chunk
 constexpr int kDefaultHeavy = 1024;      // ranges longer than this are split
-constexpr int kChunk = 64;               // slots a wave claims at a time in a chunked list
-// persistent per-slot words (rid_slot[]): stamp counter, then the extents of
-// list regions that may hold entries other than -1 (cleared at the next solve)
-enum PersistWord { PW_RID = 0, PW_TOUCHED = 1, PW_U0 = 2, PW_U1 = 3, PW_Q0 = 4, PW_Q1 = 5, PW_COUNT = 8 };
+constexpr int kStageCap = 1280;          // LDS staging of list appends per workgroup batch
+constexpr int kItemsPerThread = 4;       // round batches: items per thread
+constexpr int kRoundBatch = kBlock * kItemsPerThread;  // items per workgroup batch
+constexpr int kHeavyPerBatch = 16;       // heavy chunks per workgroup batch
+// persistent per-slot words (rid_slot[])
+enum PersistWord { PW_RID = 0, PW_COUNT = 8 };
 
 // ------------------------------------------------------------------ graph --
 struct DevGraph {
@@ -109,11 +111,10 @@ struct Inst {
   uint32_t* hist_cnt;
   StepRec* steprec;
   TraceRec* trace;
-  uint32_t* rid_slot;      // persists across solves: [0] stamp counter, [1..5] dirty list extents
-  uint2* cstate;           // per-wave chunk states of the chunked lists: [3][maxw]
+  uint32_t* rid_slot;      // persists across solves: [PW_RID] stamp counter
   Counters* cslot;         // per-wave work counters: [maxw]
-  int32_t maxw;            // waves the counter / chunk arrays can hold
-  int32_t list_cap;        // capacity of the chunked lists (q, touched, ulist)
+  int32_t maxw;            // waves the counter array can hold
+  int32_t pad2;
   int32_t heavy_cap;
   uint32_t ring_mask;
   uint32_t steprec_mask;

@@ -56,59 +56,6 @@ __device__ __forceinline__ uint32_t wave_min_u32(uint32_t x) {
   return x;
 }
 
-// Chunked list append. A wave claims kChunk slots of a list with one atomic
-// and fills them over as many appends as it takes; its claim (base, used)
-// lives in memory between batches, tagged with an epoch so that a claim from
-// an earlier round or step reads as empty. Unfilled slots keep -1: every
-// consumer resets the slots it reads, and buffers start at -1.
-struct Chunk {
-  int base;
-  int used;
-};
-
-__device__ __forceinline__ uint32_t chunk_tag(uint32_t epoch, int used) {
-  return ((epoch & 0x1FFFFFFu) << 7) | (uint32_t)used;
-}
-
-__device__ __forceinline__ Chunk chunk_load(const uint2* st, uint32_t epoch) {
-  uint2 v = *st;
-  Chunk c;
-  if ((v.y >> 7) == (epoch & 0x1FFFFFFu)) {
-    c.base = (int)v.x;
-    c.used = (int)(v.y & 127u);
-  } else {
-    c.base = 0;
-    c.used = kChunk;  // nothing claimed
-  }
-  return c;
-}
-
-__device__ __forceinline__ void chunk_store(uint2* st, const Chunk& c, uint32_t epoch) {
-  if (lane_id() == 0) *st = make_uint2((uint32_t)c.base, chunk_tag(epoch, c.used));
-}
-
-// Convergent. Returns the slot for lanes with want, -1 otherwise.
-__device__ __forceinline__ int chunk_append(Chunk& c, int32_t* counter, bool want) {
-  uint64_t m = __ballot(want);
-  if (m == 0) return -1;
-  const int k = __popcll(m);
-  const int pre = __popcll(m & lanemask_lt());
-  const int rem = kChunk - c.used;
-  int pos;
-  if (k <= rem) {
-    pos = c.base + c.used + pre;
-    c.used += k;
-  } else {
-    int nb = 0;
-    if (lane_id() == 0) nb = atomicAdd(counter, kChunk);
-    nb = __shfl(nb, 0, kWave);
-    pos = pre < rem ? c.base + c.used + pre : nb + (pre - rem);
-    c.base = nb;
-    c.used = k - rem;
-  }
-  return want ? pos : -1;
-}
-
 __device__ __forceinline__ int lower_bound_key(const uint64_t* __restrict__ adj, int lo, int hi,
                                                uint64_t key) {
   while (lo < hi) {
@@ -116,6 +63,19 @@ __device__ __forceinline__ int lower_bound_key(const uint64_t* __restrict__ adj,
     if (adj[mid] < key) lo = mid + 1; else hi = mid;
   }
   return lo;
+}
+
+// First index in [lo, re) whose key is >= key. The next kProbe entries (one
+// or two cache lines) are read at once first; a binary search handles the rest.
+constexpr int kProbe = 8;
+__device__ __forceinline__ int range_end(const uint64_t* __restrict__ adj, int lo, int re, uint64_t key) {
+  const int lim = min(re, lo + kProbe);
+  int cnt = 0;
+#pragma unroll
+  for (int i = 0; i < kProbe; ++i)
+    if (lo + i < lim) cnt += adj[lo + i] < key ? 1 : 0;
+  if (lo + cnt < lim || lim == re) return lo + cnt;
+  return lower_bound_key(adj, lim, re, key);
 }
 
 __device__ __forceinline__ bool is_hub(const DevGraph& g, int v) {
@@ -290,24 +250,14 @@ __device__ uint32_t block_compute_st(const Inst& I, uint32_t L, uint32_t gapL, i
   return res;
 }
 
-// A solve that ends normally leaves only these list regions holding entries
-// other than -1: the unconsumed survivors of the last pull and, when the
-// first step ends the search, its touched list. The next solve clears them.
-__device__ void record_clean_end(Inst& I, int touched_dirty) {
-  uint32_t* pw = I.rid_slot;
-  pw[PW_RID] = I.rid + 1;
-  pw[PW_TOUCHED] = (uint32_t)touched_dirty;
-  const int ucur = I.usel;
-  pw[PW_U0] = (ucur == 0) ? (uint32_t)I.nU : 0u;
-  pw[PW_U1] = (ucur == 1) ? (uint32_t)I.nU : 0u;
-  pw[PW_Q0] = 0u;
-  pw[PW_Q1] = 0u;
-}
+// A solve that ends normally hands the next solve on this slot a stamp
+// counter above every stamp it wrote.
+__device__ void record_clean_end(Inst& I) { I.rid_slot[PW_RID] = I.rid + 1; }
 
 // The end-of-step heuristic for one instance: statistics at L = ub, gap(L),
 // computeST, step bookkeeping, termination test, and the next step's setup.
 // Runs on one workgroup, after every settle batch of the instance is done.
-__device__ void run_heuristic(Inst& I, HeurLds& lds) {
+__device__ __noinline__ void run_heuristic(Inst& I, HeurLds& lds) {
   const DevGraph& g = *I.g;
   const int tid = threadIdx.x;
   const uint32_t L = I.ub;
@@ -339,7 +289,7 @@ __device__ void run_heuristic(Inst& I, HeurLds& lds) {
   if (done) {
     if (tid == 0) {
       I.phase = PH_DONE;
-      record_clean_end(I, 0);
+      record_clean_end(I);
     }
     __syncthreads();
     return;
@@ -402,6 +352,9 @@ __device__ void run_heuristic(Inst& I, HeurLds& lds) {
 
 // ------------------------------------------------------------ tick: rounds --
 
+// The phase bodies below are kept out of line: inlined together they need
+// more than twice the registers of the largest one, which halves occupancy.
+
 // Everything a batch needs from its instance, read once into registers: the
 // control words only change between ticks, and reading them through the
 // instance struct inside the loops would re-load them after every atomic.
@@ -416,7 +369,7 @@ struct View {
   int32_t* touched;
   Inst* inst;
   uint32_t lb, ub, st, lb0, rid, step_rid0;
-  int32_t list_cap, heavy_split, maxw;
+  int32_t n, heavy_split, maxw;
   uint32_t first;
 };
 
@@ -438,7 +391,7 @@ __device__ __forceinline__ View make_view(Inst& I) {
   v.lb0 = I.lb0;
   v.rid = I.rid;
   v.step_rid0 = I.step_rid0;
-  v.list_cap = I.list_cap;
+  v.n = I.n;
   v.heavy_split = I.heavy_split;
   v.maxw = I.maxw;
   v.first = I.first;
@@ -479,29 +432,67 @@ __device__ __forceinline__ bool hub_bit(const uint32_t* bits, int v) {
   return (bits[v >> 5] >> (v & 31)) & 1u;
 }
 
-// A successful decrease of dist[t] to c during round `rid`: push t onto the
-// next frontier once per round (SAP) and onto the step's touched list once
-// per step. Convergent: every lane calls it.
+// Appends of a workgroup batch are staged in LDS and written out with one
+// device atomic per list and flush: thousands of waves claiming list slots
+// on the same counter would otherwise queue behind each other.
+struct StageLds {
+  int32_t q[kStageCap];  // next frontier
+  int32_t t[kStageCap];  // touched list (and the surviving pull list in phase 1)
+  int32_t nq, nt;
+  int32_t base_q, base_t;
+};
+
+// Convergent within a wave.
+__device__ __forceinline__ void stage_append(int32_t* buf, int32_t* cnt, bool want, int32_t val) {
+  uint64_t m = __ballot(want);
+  if (m == 0) return;
+  int base = 0;
+  const int leader = __ffsll((unsigned long long)m) - 1;
+  if (lane_id() == leader) base = atomicAdd(cnt, __popcll(m));
+  base = __shfl(base, leader, kWave);
+  if (want) buf[base + __popcll(m & lanemask_lt())] = val;
+}
+
+// Whole workgroup: copy the staged entries to their lists.
+__device__ void stage_flush(StageLds& S, int32_t* qlist, int32_t* qcnt, int32_t* tlist, int32_t* tcnt,
+                            int cap, uint32_t* flags) {
+  __syncthreads();
+  const int nq = S.nq, nt = S.nt;
+  if (threadIdx.x == 0) {
+    S.base_q = nq ? atomicAdd(qcnt, nq) : 0;
+    S.base_t = nt ? atomicAdd(tcnt, nt) : 0;
+    if (S.base_q + nq > cap || S.base_t + nt > cap) atomicOr(flags, FLAG_CAPACITY);
+  }
+  __syncthreads();
+  const int bq = S.base_q, bt = S.base_t;
+  for (int i = threadIdx.x; i < nq; i += kBlock)
+    if (bq + i < cap) qlist[bq + i] = S.q[i];
+  for (int i = threadIdx.x; i < nt; i += kBlock)
+    if (bt + i < cap) tlist[bt + i] = S.t[i];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    S.nq = 0;
+    S.nt = 0;
+  }
+  __syncthreads();
+}
+
+// A successful decrease of dist[t] to c during round `rid`: t joins the next
+// frontier once per round (SAP) and the step's touched list once per step.
+// Convergent within a wave.
 __device__ __forceinline__ void on_success(const View& V, bool ok, int t, uint32_t c, WaveAcc& acc,
-                                           Chunk& cq, Chunk& ct) {
+                                           StageLds& S) {
   bool wq = false, wt = false;
   if (ok) {
     uint32_t so = atomicMax(&V.stamp[t], V.rid);
     wq = so < V.rid;
     wt = so < V.step_rid0;
     acc.success += 1;
+    acc.qent += (wq ? 1 : 0) + (wt ? 1 : 0);
     if (V.first && hub_bit(V.hub_bits, t) && c < acc.hubmin) acc.hubmin = c;
   }
-  int p = chunk_append(cq, &V.inst->q_next_cnt.v, wq);
-  if (wq) {
-    if (p < V.list_cap) V.q_next[p] = t; else atomicOr(&V.inst->flags.v, FLAG_CAPACITY);
-    acc.qent += 1;
-  }
-  int p2 = chunk_append(ct, &V.inst->touched_cnt.v, wt);
-  if (wt) {
-    if (p2 < V.list_cap) V.touched[p2] = t; else atomicOr(&V.inst->flags.v, FLAG_CAPACITY);
-    acc.qent += 1;
-  }
+  stage_append(S.q, &S.nq, wq, t);
+  stage_append(S.t, &S.nt, wt, t);
 }
 
 // Split a long range into heavy chunks for the next tick (grid-wide).
@@ -527,160 +518,214 @@ __device__ void emit_heavy(Inst& I, int u, uint32_t d, int lo, int hi, bool pull
   }
 }
 
-// One wave processes up to 64 items of a round segment.
-__device__ void wave_round(Inst& I, int kind, int item0, int nitems) {
+// One workgroup processes a batch of a round segment in two phases.
+// Phase 1 streams the items (kItemsPerThread per thread, their loads issued
+// together), applies the filters and the pending-list / pull-list
+// bookkeeping, and compacts the items that have edges to relax into LDS.
+// Phase 2 finds each compacted item's edge range -- the band filter
+// [lb - d, ub - d) on the weight-sorted row, or the pull prefix w < ub - st --
+// and relaxes all of the batch's edges with a workgroup-wide merge path.
+struct RoundLds {
+  int32_t u[kRoundBatch];
+  uint32_t d[kRoundBatch];
+  int32_t lo[kRoundBatch];
+  int32_t sz[kRoundBatch];  // size, -1 = range still to find; then exclusive offsets
+  uint8_t pull[kRoundBatch];
+  int32_t count;
+  int32_t iscan[kBlock / kWave + 1];
+  StageLds stage;
+};
+
+__device__ __forceinline__ void lds_push_item(RoundLds& L, bool want, int u, uint32_t d, int lo,
+                                              int sz, bool pull) {
+  uint64_t m = __ballot(want);
+  if (m == 0) return;
+  int base = 0;
+  const int leader = __ffsll((unsigned long long)m) - 1;
+  if (lane_id() == leader) base = atomicAdd(&L.count, __popcll(m));
+  base = __shfl(base, leader, kWave);
+  if (want) {
+    const int w = base + __popcll(m & lanemask_lt());
+    L.u[w] = u;
+    L.d[w] = d;
+    L.lo[w] = lo;
+    L.sz[w] = sz;
+    L.pull[w] = pull ? 1 : 0;
+  }
+}
+
+__device__ __noinline__ void block_round(Inst& I, int kind, int item0, int nitems, RoundLds& L) {
   const View V = make_view(I);
-  const int lane = lane_id();
+  const int tid = threadIdx.x;
   const uint32_t lb = V.lb, ub = V.ub, st = V.st;
   WaveAcc acc = {0, 0, 0, 0, 0, 0, 0, kInf};
-  int u = 0, lo = 0, size = 0;
-  uint32_t d = 0;
-  bool pull = false;
-  const int it = item0 + lane;
-  bool have = (kind == SEG_H) ? (lane == 0 && item0 < nitems) : (it < nitems);
-  const int gw = global_wave();
-  uint2* st_q = I.cstate + 0 * V.maxw + gw;
-  uint2* st_t = I.cstate + 1 * V.maxw + gw;
-  Chunk cq = chunk_load(st_q, V.rid);
-  Chunk ct = chunk_load(st_t, V.step_rid0);
+  StageLds& S = L.stage;
+  if (tid == 0) {
+    L.count = 0;
+    S.nq = 0;
+    S.nt = 0;
+  }
+  __syncthreads();
 
-  if (kind == SEG_U) {
-    pull = true;
-    bool keep = false, active = false;
-    const int usel = I.usel;
-    int32_t* ucur = usel < 0 ? nullptr : I.ulist[usel];
-    int32_t* unext = I.ulist[usel < 0 ? 0 : (usel ^ 1)];
-    if (have) {
-      if (ucur == nullptr) {
-        u = I.g->nonisolated[it];
-      } else {
-        u = ucur[it];
-        ucur[it] = -1;
-      }
-      if (u < 0) have = false;
-    }
-    if (have) {
-      d = V.dist[u];
-      keep = d >= lb;
-      active = d > lb && V.wmin[u] < ub - st;
-      acc.pvert += 1;
-    }
-    uint2* st_u = I.cstate + 2 * V.maxw + gw;
-    Chunk cu = chunk_load(st_u, V.step_rid0);
-    int p = chunk_append(cu, &I.u_next_cnt.v, keep);
-    if (keep) {
-      if (p < V.list_cap) unext[p] = u; else atomicOr(&I.flags.v, FLAG_CAPACITY);
-    }
-    chunk_store(st_u, cu, V.step_rid0);
-    if (active) {
-      int rs = V.rowptr[u], re = V.rowptr[u + 1];
-      lo = rs;
-      int hi = lower_bound_key(V.adj, rs, re, (uint64_t)(ub - st) << 32);
-      size = hi - lo;
-      acc.pullscan += (unsigned long long)size;
-      if (size > V.heavy_split) {
-        emit_heavy(I, u, d, lo, hi, true);
-        size = 0;
-      }
-    }
-  } else if (kind == SEG_H) {
-    if (have) {
-      HeavyItem h = I.heavy[I.hsel][item0];
+  // ---------------------------------------------------------- phase 1
+  if (kind == SEG_H) {
+    // heavy chunks: the range is known
+    const int it = item0 + tid;
+    bool want = false;
+    int u = 0, lo = 0, sz = 0;
+    uint32_t d = 0;
+    bool pull = false;
+    if (tid < kHeavyPerBatch && it < nitems) {
+      HeavyItem h = I.heavy[I.hsel][it];
       u = h.u;
       lo = h.lo;
-      int hi = h.hi_kind & 0x7fffffff;
+      sz = (h.hi_kind & 0x7fffffff) - lo;
       pull = (h.hi_kind & (int)0x80000000) != 0;
-      uint32_t du = V.dist[u];
+      const uint32_t du = V.dist[u];
       if (pull) {
         d = du;
-        size = du > lb ? hi - lo : 0;
+        want = du > lb;
       } else {
         d = h.d;
-        size = (du == d) ? hi - lo : 0;  // a newer, smaller dist[u] has its own expansion
+        want = (du == d);  // a newer, smaller dist[u] has its own expansion
       }
     }
-    pull = __shfl(pull ? 1 : 0, 0, kWave) != 0;
+    lds_push_item(L, want, u, d, lo, sz, pull);
+  } else if (kind == SEG_U) {
+    const int usel = I.usel;
+    const int32_t* ucur = usel < 0 ? I.g->nonisolated : I.ulist[usel];
+    int32_t* unext = I.ulist[usel < 0 ? 0 : (usel ^ 1)];
+    int uu[kItemsPerThread];
+#pragma unroll
+    for (int k = 0; k < kItemsPerThread; ++k) {
+      const int it = item0 + k * kBlock + tid;
+      uu[k] = it < nitems ? ucur[it] : -1;
+    }
+    uint32_t dd[kItemsPerThread], wm[kItemsPerThread];
+#pragma unroll
+    for (int k = 0; k < kItemsPerThread; ++k) {
+      dd[k] = uu[k] >= 0 ? V.dist[uu[k]] : 0u;
+      wm[k] = uu[k] >= 0 ? V.wmin[uu[k]] : kInf;
+    }
+#pragma unroll
+    for (int k = 0; k < kItemsPerThread; ++k) {
+      const int u = uu[k];
+      const bool keep = u >= 0 && dd[k] >= lb;
+      const bool active = u >= 0 && dd[k] > lb && wm[k] < ub - st;
+      acc.pvert += u >= 0 ? 1 : 0;
+      stage_append(S.t, &S.nt, keep, u);
+      lds_push_item(L, active, u, dd[k], 0, -1, true);
+    }
+    // the surviving pull list goes out now; the stage is free for phase 2
+    stage_flush(S, nullptr, &S.base_q, unext, &I.u_next_cnt.v, V.n, &I.flags.v);
   } else {
-    bool ok = false;
-    if (have) {
-      if (kind == SEG_W) {
-        u = I.settled[I.wBegin + it];
-        d = V.dist[u];
-        ok = d >= V.lb0 && d <= st;
-      } else if (kind == SEG_P) {
-        u = I.plist[I.psel][it];
-        d = V.dist[u];
-        ok = d >= lb && d < ub;
-      } else {  // SEG_Q
-        int32_t* qc = I.q[I.qsel];
-        u = qc[it];
-        qc[it] = -1;
-        if (u >= 0) {
-          d = V.dist[u];
-          ok = d < ub;
-        }
-      }
+    int uu[kItemsPerThread];
+    const int32_t* src = (kind == SEG_W) ? I.settled + I.wBegin
+                         : (kind == SEG_P) ? I.plist[I.psel] : I.q[I.qsel];
+#pragma unroll
+    for (int k = 0; k < kItemsPerThread; ++k) {
+      const int it = item0 + k * kBlock + tid;
+      uu[k] = it < nitems ? src[it] : -1;
     }
-    if (kind == SEG_P) {
-      // band members of the pending list join this step's touched list
-      bool wt = false;
-      if (ok) {
-        uint32_t so = atomicMax(&V.stamp[u], V.step_rid0);
-        wt = so < V.step_rid0;
-      }
-      int p = chunk_append(ct, &I.touched_cnt.v, wt);
-      if (wt) {
-        if (p < V.list_cap) V.touched[p] = u; else atomicOr(&I.flags.v, FLAG_CAPACITY);
-        acc.qent += 1;
-      }
-    }
-    if (ok) {
-      int rs = V.rowptr[u], re = V.rowptr[u + 1];
-      if (re - rs == 1 && d > 0) ok = false;  // leaf pruning (Algorithm)
-      if (ok) {
-        uint32_t wl = lb > d ? lb - d : 0u;
-        uint32_t wh = ub - d;
-        lo = (wl <= V.wmin[u]) ? rs : lower_bound_key(V.adj, rs, re, (uint64_t)wl << 32);
-        int hi = lower_bound_key(V.adj, lo, re, (uint64_t)wh << 32);
-        if (ub == kInf && hi < re) atomicOr(&I.flags.v, FLAG_MAYBE_OVERFLOW);
-        size = hi - lo;
-        acc.expansions += 1;
-        acc.band += (d >= lb) ? 1 : 0;
-        acc.pscan += (unsigned long long)size;
-        if (size > V.heavy_split) {
-          emit_heavy(I, u, d, lo, hi, false);
-          size = 0;
+    uint32_t dd[kItemsPerThread];
+#pragma unroll
+    for (int k = 0; k < kItemsPerThread; ++k) dd[k] = uu[k] >= 0 ? V.dist[uu[k]] : kInf;
+#pragma unroll
+    for (int k = 0; k < kItemsPerThread; ++k) {
+      const int u = uu[k];
+      const uint32_t d = dd[k];
+      bool ok;
+      if (kind == SEG_W) ok = u >= 0 && d >= V.lb0 && d <= st;
+      else ok = u >= 0 && d >= lb && d < ub;
+      if (kind == SEG_P) {
+        // band members of the pending list join this step's touched list
+        bool wt = false;
+        if (ok) {
+          uint32_t so = atomicMax(&V.stamp[u], V.step_rid0);
+          wt = so < V.step_rid0;
+          acc.qent += wt ? 1 : 0;
         }
+        stage_append(S.t, &S.nt, wt, u);
       }
+      lds_push_item(L, ok, u, d, 0, -1, false);
     }
   }
+  __syncthreads();
+  const int m = L.count;
 
-  // wave-level merge path over the ranges
-  const int incl = wave_incl_scan(size);
-  const int total = __shfl(incl, kWave - 1, kWave);
-  const int excl = incl - size;
-  for (int base = 0; base < total; base += kWave) {
-    const int e = base + lane;
-    // largest j with excl[j] <= e
-    int j = 0;
-#pragma unroll
-    for (int stp = 32; stp > 0; stp >>= 1) {
-      int cj = j + stp;
-      int ex = __shfl(excl, cj < kWave ? cj : kWave - 1, kWave);
-      if (cj < kWave && ex <= e) j = cj;
+  // ---------------------------------------------------------- phase 2a: ranges
+  for (int w = tid; w < m; w += kBlock) {
+    if (L.sz[w] >= 0) continue;  // heavy chunk: known
+    const int u = L.u[w];
+    const uint32_t d = L.d[w];
+    const bool pull = L.pull[w] != 0;
+    const int rs = V.rowptr[u], re = V.rowptr[u + 1];
+    int lo = rs, hi = rs;
+    if (pull) {
+      hi = range_end(V.adj, rs, re, (uint64_t)(ub - st) << 32);
+      acc.pullscan += (unsigned long long)(hi - lo);
+    } else if (!(re - rs == 1 && d > 0)) {  // leaf pruning (Algorithm)
+      const uint32_t wl = lb > d ? lb - d : 0u;
+      const uint32_t wh = ub - d;
+      lo = (wl <= V.wmin[u]) ? rs : lower_bound_key(V.adj, rs, re, (uint64_t)wl << 32);
+      hi = range_end(V.adj, lo, re, (uint64_t)wh << 32);
+      if (ub == kInf && hi < re) atomicOr(&I.flags.v, FLAG_MAYBE_OVERFLOW);
+      acc.expansions += 1;
+      acc.band += (d >= lb) ? 1 : 0;
+      acc.pscan += (unsigned long long)(hi - lo);
     }
-    const int uj = __shfl(u, j, kWave);
-    const uint32_t dj = __shfl(d, j, kWave);
-    const int loj = __shfl(lo, j, kWave);
-    const int exj = __shfl(excl, j, kWave);
+    int size = hi - lo;
+    if (size > V.heavy_split) {
+      emit_heavy(I, u, d, lo, hi, pull);
+      size = 0;
+    }
+    L.lo[w] = lo;
+    L.sz[w] = size;
+  }
+  __syncthreads();
+
+  // sizes -> exclusive offsets (each thread owns kItemsPerThread consecutive entries)
+  int loc[kItemsPerThread];
+  int run = 0;
+#pragma unroll
+  for (int k = 0; k < kItemsPerThread; ++k) {
+    const int w = tid * kItemsPerThread + k;
+    loc[k] = w < m ? L.sz[w] : 0;
+    run += loc[k];
+  }
+  int total;
+  int off = block_excl_scan<int>(run, L.iscan, &total);
+#pragma unroll
+  for (int k = 0; k < kItemsPerThread; ++k) {
+    const int w = tid * kItemsPerThread + k;
+    if (w < m) L.sz[w] = off;
+    off += loc[k];
+  }
+  __syncthreads();
+
+  // ---------------------------------------------------------- phase 2b: edges
+  const bool any_pull = (kind == SEG_U) || (kind == SEG_H);
+  int32_t* qnext = V.q_next;
+  for (int base = 0; base < total; base += kBlock) {
+    __syncthreads();
+    if (S.nq > kStageCap - kBlock || S.nt > kStageCap - kBlock)
+      stage_flush(S, qnext, &I.q_next_cnt.v, V.touched, &I.touched_cnt.v, V.n, &I.flags.v);
+    const int e = base + tid;
     bool ok = false;
     int t = 0;
     uint32_t c = 0;
     if (e < total) {
-      const uint64_t ent = V.adj[loj + (e - exj)];
+      int lo_j = 0, hi_j = m;  // largest j with offset[j] <= e
+      while (hi_j - lo_j > 1) {
+        const int mid = (lo_j + hi_j) >> 1;
+        if (L.sz[mid] <= e) lo_j = mid; else hi_j = mid;
+      }
+      const int j = lo_j;
+      const uint64_t ent = V.adj[L.lo[j] + (e - L.sz[j])];
       const int v = (int)(uint32_t)(ent & 0xffffffffull);
       const uint32_t w = (uint32_t)(ent >> 32);
-      if (!pull) {
+      const uint32_t dj = L.d[j];
+      if (!(any_pull && L.pull[j])) {
         c = dj + w;  // < ub by the range
         t = v;
         if (c < V.dist[v]) {
@@ -693,17 +738,16 @@ __device__ void wave_round(Inst& I, int kind, int item0, int nitems) {
           unsigned long long cc = (unsigned long long)dv + w;
           if (cc < ub && cc < dj) {
             c = (uint32_t)cc;
-            t = uj;
-            uint32_t old = atomicMin(&V.dist[uj], c);
+            t = L.u[j];
+            uint32_t old = atomicMin(&V.dist[t], c);
             ok = c < old;
           }
         }
       }
     }
-    on_success(V, ok, t, c, acc, cq, ct);
+    on_success(V, ok, t, c, acc, S);
   }
-  chunk_store(st_q, cq, V.rid);
-  chunk_store(st_t, ct, V.step_rid0);
+  stage_flush(S, qnext, &I.q_next_cnt.v, V.touched, &I.touched_cnt.v, V.n, &I.flags.v);
   flush_acc(I, V.maxw, acc);
 }
 
@@ -722,13 +766,14 @@ struct SettleLds {
 union BlockLds {
   SettleLds s;
   HeurLds h;
+  RoundLds r;
 };
 
 // One workgroup settles up to 256 items: the step's touched vertices (with
 // dist < ub they are final; in the first step the rest stay pending) and the
 // pending list's compaction. Degree mass moves from the unsettled histogram
 // to the per-distance ring; settled vertices are appended to the settled list.
-__device__ void block_settle(Inst& I, int kind, int item0, int nitems, SettleLds& L) {
+__device__ __noinline__ void block_settle(Inst& I, int kind, int item0, int nitems, SettleLds& L) {
   const DevGraph& g = *I.g;
   const int tid = threadIdx.x;
   const uint32_t lb = I.lb, ub = I.ub, M = I.M;
@@ -757,7 +802,6 @@ __device__ void block_settle(Inst& I, int kind, int item0, int nitems, SettleLds
   if (it < nitems) {
     if (kind == SEG_ST) {
       v = touched[it];
-      touched[it] = -1;
     } else {
       v = pcur[it];
     }
@@ -857,7 +901,6 @@ __device__ int find_segment(const Globals& G, int b) {
 }
 
 __device__ void run_tick(Globals& G, BlockLds& lds) {
-  const int wid = threadIdx.x / kWave;
   __shared__ int s_last;
   const int total_batches = G.total_batches;
   for (int b = blockIdx.x; b < total_batches; b += gridDim.x) {
@@ -886,10 +929,8 @@ __device__ void run_tick(Globals& G, BlockLds& lds) {
         // out of this XCD's L2 before other XCDs use them: done at the barrier
       }
       __syncthreads();
-    } else if (kind == SEG_H) {
-      wave_round(I, kind, item0 + wid, cnt);
     } else {
-      wave_round(I, kind, item0 + wid * kWave, cnt);
+      block_round(I, kind, item0, cnt, lds.r);
     }
   }
 }
@@ -902,14 +943,14 @@ __device__ void transition(Inst& I, int32_t* cnt, int32_t* kinds, int32_t* pbs) 
   if (I.tick_kind == PH_ROUND) {
     if (I.init_round && I.pull_on) {
       I.usel = (I.usel < 0) ? 0 : (I.usel ^ 1);
-      I.nU = min(I.u_next_cnt.v, I.list_cap);
+      I.nU = min(I.u_next_cnt.v, I.n);
       I.u_next_cnt.v = 0;
     }
     I.init_round = 0;
     if (I.first && I.ub_next.v < I.ub) I.ub = I.ub_next.v;
     I.c.rounds += 1;
     I.rounds_in_step += 1;
-    const int nq = min(I.q_next_cnt.v, I.list_cap), nh = min(I.h_next_cnt.v, I.heavy_cap);
+    const int nq = min(I.q_next_cnt.v, I.n), nh = min(I.h_next_cnt.v, I.heavy_cap);
     I.q_next_cnt.v = 0;
     I.h_next_cnt.v = 0;
     if (nq > 0 || nh > 0) {
@@ -918,18 +959,18 @@ __device__ void transition(Inst& I, int32_t* cnt, int32_t* kinds, int32_t* pbs) 
       I.nF = nq;
       I.nH = nh;
       I.rid += 1;
-      cnt[0] = nq; kinds[0] = SEG_Q;
-      cnt[1] = nh; kinds[1] = SEG_H; pbs[1] = kBlock / kWave;
+      cnt[0] = nq; kinds[0] = SEG_Q; pbs[0] = kRoundBatch;
+      cnt[1] = nh; kinds[1] = SEG_H; pbs[1] = kHeavyPerBatch;
       return;
     }
     if (I.first && I.ub == kInf) {
       I.phase = PH_DONE;
-      record_clean_end(I, min(I.touched_cnt.v, I.list_cap));
+      record_clean_end(I);
       return;
     }
     I.tick_kind = PH_SETTLE;
     I.phase = PH_SETTLE;
-    I.nT = min(I.touched_cnt.v, I.list_cap);
+    I.nT = min(I.touched_cnt.v, I.n);
     I.settled_mark = min(I.settled_cnt.v, I.n);
     I.settle_done.v = 0;
     int bt = (I.nT + kBlock - 1) / kBlock;
@@ -951,9 +992,9 @@ __device__ void transition(Inst& I, int32_t* cnt, int32_t* kinds, int32_t* pbs) 
   I.tick_kind = PH_ROUND;
   I.init_round = 1;
   I.nF = 0;
-  cnt[0] = I.wEnd - I.wBegin; kinds[0] = SEG_W;
-  cnt[1] = I.nP; kinds[1] = SEG_P;
-  cnt[2] = I.pull_on ? I.nU : 0; kinds[2] = SEG_U;
+  cnt[0] = I.wEnd - I.wBegin; kinds[0] = SEG_W; pbs[0] = kRoundBatch;
+  cnt[1] = I.nP; kinds[1] = SEG_P; pbs[1] = kRoundBatch;
+  cnt[2] = I.pull_on ? I.nU : 0; kinds[2] = SEG_U; pbs[2] = kRoundBatch;
 }
 
 // Build the tick table from every instance's transition. One workgroup.
@@ -976,7 +1017,7 @@ __device__ void build_table(Globals& G, bool do_transition) {
     } else {
       // first tick of a solve: the source alone
       for (int s = 0; s < kMaxSegPerInst; ++s) { cnt[s] = 0; kinds[s] = SEG_Q; pbs[s] = kBlock; }
-      if (I.phase != PH_DONE) { cnt[0] = I.nF; kinds[0] = SEG_Q; }
+      if (I.phase != PH_DONE) { cnt[0] = I.nF; kinds[0] = SEG_Q; pbs[0] = kRoundBatch; }
     }
     if (I.phase != PH_DONE) atomicAdd(&s_active, 1);
     for (int s = 0; s < kMaxSegPerInst; ++s) {
@@ -1061,7 +1102,7 @@ __device__ bool spin_until_changed(unsigned int* word, unsigned int old, unsigne
 
 // The serial part between two ticks (one workgroup): tick log, phase
 // transitions and the next tick's work layout.
-__device__ void epilogue(Globals& G) {
+__device__ __noinline__ void epilogue(Globals& G) {
   if (threadIdx.x == 0) {
     if (G.tick_log && G.ticks < G.tick_log_cap) {
       unsigned long long* e = G.tick_log + 4 * G.ticks;
@@ -1242,18 +1283,6 @@ __global__ void k_init_arrays(Globals* Gp) {
       I.dist[v] = kInf;
       if (reset_stamp) I.stamp[v] = 0;
     }
-    // list regions a previous solve may have left holding entries
-    const long long dt = min((long long)pw[PW_TOUCHED], (long long)I.list_cap);
-    const long long du0 = min((long long)pw[PW_U0], (long long)I.list_cap);
-    const long long du1 = min((long long)pw[PW_U1], (long long)I.list_cap);
-    const long long dq0 = min((long long)pw[PW_Q0], (long long)I.list_cap);
-    const long long dq1 = min((long long)pw[PW_Q1], (long long)I.list_cap);
-    for (long long x = tid; x < dt; x += stride) I.touched[x] = -1;
-    for (long long x = tid; x < du0; x += stride) I.ulist[0][x] = -1;
-    for (long long x = tid; x < du1; x += stride) I.ulist[1][x] = -1;
-    for (long long x = tid; x < dq0; x += stride) I.q[0][x] = -1;
-    for (long long x = tid; x < dq1; x += stride) I.q[1][x] = -1;
-    for (long long x = tid; x < 3ll * I.maxw; x += stride) I.cstate[x] = make_uint2(0u, 0u);
     for (long long x = tid; x < I.maxw; x += stride) {
       Counters z = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
       I.cslot[x] = z;
@@ -1276,9 +1305,8 @@ __global__ void __launch_bounds__(kBlock) k_init_ctl(Globals* Gp) {
       uint32_t* pw = I.rid_slot;
       I.rid = pw[PW_RID];
       if (I.rid > 0x80000000u) I.rid = 0;
-      // until this solve ends normally, assume every list may hold entries
+      // until this solve ends normally, the next one starts well above it
       pw[PW_RID] = I.rid + (1u << 24);
-      pw[PW_TOUCHED] = pw[PW_U0] = pw[PW_U1] = pw[PW_Q0] = pw[PW_Q1] = (uint32_t)I.list_cap;
       const int s = I.source;
       const int deg_s = g.rowptr[s + 1] - g.rowptr[s];
       I.dist[s] = 0;
@@ -1314,7 +1342,7 @@ __global__ void __launch_bounds__(kBlock) k_init_ctl(Globals* Gp) {
       I.nF = 1;
       I.ub_next.v = is_hub(g, s) ? 0u : kInf;
       I.phase = deg_s > 0 ? PH_ROUND : PH_DONE;
-      if (deg_s == 0) record_clean_end(I, 1);
+      if (deg_s == 0) record_clean_end(I);
     }
     __syncthreads();
     // gap(0) from whole-graph statistics: sumD(0) = nnz, highD(0)
