@@ -14,6 +14,7 @@ import argparse
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -40,6 +41,44 @@ def alg_bytes(c: dict) -> int:
             + 12 * c["pull_vertices"] + 12 * c["pull_scanned"] + 8 * c["queue_entries"])
 
 
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_engine_rmat24_counters.md")
+ENGINE_SOURCES = [os.path.join(ROOT, "paper_2506_19349_amd", "csrc", f)
+                  for f in ("engine.hip", "engine.h")]
+
+
+def engine_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ENGINE_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per engine launch from the committed counter summary: the
+    FETCH_SIZE and WRITE_SIZE readings (KiB per dispatch) of the engine kernel,
+    each scaled by what the same counter reads for a copy of known size. None
+    when there is no summary for this workload or the engine has changed since."""
+    if workload != "rmat24" or not os.path.exists(COUNTERS_FILE):
+        return None
+    vals = {}
+    with open(COUNTERS_FILE) as fh:
+        for line in fh:
+            m = re.match(r"^\s*-\s*([a-z0-9_]+):\s*([0-9a-f.]+)\s*$", line)
+            if m:
+                vals[m.group(1)] = m.group(2)
+    need = ("engine_source_sha256", "engine_fetch_kib", "engine_write_kib", "copy_bytes",
+            "copy_fetch_kib", "copy_write_kib")
+    if any(k not in vals for k in need) or vals["engine_source_sha256"] != engine_source_hash():
+        return None
+    cb = float(vals["copy_bytes"])
+    f_fetch = cb / (float(vals["copy_fetch_kib"]) * 1024.0)
+    f_write = cb / (float(vals["copy_write_kib"]) * 1024.0)
+    return (float(vals["engine_fetch_kib"]) * 1024.0 * f_fetch
+            + float(vals["engine_write_kib"]) * 1024.0 * f_write)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -47,6 +86,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="rmat24")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="end with three 1 GiB device-to-device copies (reference kernel for "
+                         "scaling the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs a single-GPU solver "
@@ -137,6 +179,27 @@ def main():
                          "RMAT-24 graph, %.1f s; GPU result for it bit-exact: %s" % (dt, parity)}
         log("oracle: %.2f s for one source -> %.4f GTEPS; GPU bit-exact: %s" % (dt, cpu["value"], parity))
 
+    if args.calibrate_copy:
+        nb = 1 << 30
+        a = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        log("calibration copies done (3 x 1 GiB)")
+
+    traffic = measured_traffic(wl.name)
+    config = {"workload": "rmat24-plain-sssp" if wl.name == "rmat24" else wl.name,
+              "n": csr.n, "nnz": csr.nnz, "sources": K, "seed": wl.seed,
+              "m_cc_mean": int(sum(m_cc) / len(m_cc)), "parallelism": "1 GPU"}
+    if wl.name.startswith("rmat"):
+        config.update({"edge_factor": 16, "weights": "U{1..255}", "rmat_abc": [0.57, 0.19, 0.19]})
+    elif wl.name.startswith("er"):
+        config.update({"mean_degree": 32, "weights": "U{1..255}"})
+    elif wl.name.startswith("grid"):
+        config.update({"edges_kept": 0.95, "diagonals": 0.01, "weights": "U{1..1000}"})
     line = {
         "metric": METRIC,
         "value": round(gteps, 3),
@@ -150,12 +213,10 @@ def main():
         "vs_baseline": None,
         "dtype": "u32",
         "data": "synthetic",
-        "config": {"workload": "rmat24-plain-sssp" if wl.name == "rmat24" else wl.name,
-                   "n": csr.n, "nnz": csr.nnz, "edge_factor": 16, "weights": "U{1..255}",
-                   "rmat_abc": [0.57, 0.19, 0.19], "sources": K, "seed": wl.seed,
-                   "m_cc_mean": int(sum(m_cc) / len(m_cc)), "parallelism": "1 GPU"},
+        "config": config,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
+                     "traffic": None if traffic is None else int(traffic),
                      "kernel": "k_engine", "kernel_us_mean": round(eng_mean_us, 2),
                      "alg_bytes_per_launch": int(sum(B) / len(B))},
         "cpu_baseline": cpu,
