@@ -62,7 +62,10 @@ typedef struct {
   int32_t host_driven;   /* 1: one kernel launch per tick with a host sync (debug); 0: persistent */
   int32_t blocks_per_cu; /* persistent grid size; 0 -> tuned / default */
   int32_t heavy_split;   /* ranges longer than this are split across the grid; 0 -> default */
-  int32_t reserved[9];
+  int32_t fuse_rounds;   /* bucket fusion (Section 4.1's FUSED): rounds one workgroup may chain
+                            without a grid-wide synchronisation while the frontier fits one
+                            batch; 0 -> 256, -1 -> off */
+  int32_t reserved[8];
 } sssp_options;
 
 /* Work counters of one solve (the paper's Section 4 measures). */
@@ -78,6 +81,7 @@ typedef struct {
   uint64_t pulls;           /* pull phases */
   uint64_t steps;           /* scheduling-threshold pairs <lb, ub> */
   uint64_t ticks;           /* device-wide phases executed (rounds + settle passes) */
+  uint64_t fused_rounds;    /* rounds run back to back by one workgroup (bucket fusion) */
   uint32_t high_d0;         /* highD(0) */
   uint32_t gap0;            /* gap(0) */
   uint32_t flags;           /* nonzero: internal condition (see sssp_status_str of status) */

@@ -15,7 +15,7 @@ It serves two purposes in the tests:
   the settled set, whose distances are final), so the GPU engine has to
   produce the same schedule step for step.
 
-Readings of the text it follows (also listed in the design doc): the first step's
+Readings of the text it follows: the first step's
 hub update of ub runs only during the first step; the first step ends the
 search when no vertex of degree >= highD(0) was reached (ub stays +inf);
 +inf is the single sentinel 2^32 - 1; the v != parent[u] skip is omitted

@@ -9,7 +9,7 @@ the text in plain numpy / Python arithmetic:
 * traversal optimisation: pushed, pulled and long, Eq. (4)-(6), with the
   lb_0 / ub_0 / ub_1 clamps of Section 3.2, and Function 2 (computeST).
 
-Readings where the text is silent or ambiguous (each is listed in the design doc):
+Readings where the text is silent or ambiguous:
 
 * |E| is the undirected edge count, so 2|E| = nnz, the number of CSR entries
   (the sum of all degrees); "sumD >= |E|" is tested as 2*sumD >= nnz.

@@ -61,7 +61,7 @@ def _as_u32(a):
 
 
 def _options(traversal_opt=True, alpha=None, beta=None, host_driven=False, blocks_per_cu=0,
-             heavy_split=0):
+             heavy_split=0, fuse_rounds=0):
     o = _lib.Options()
     o.traversal_opt = 1 if traversal_opt else -1
     o.alpha = int(alpha or 0)
@@ -69,6 +69,7 @@ def _options(traversal_opt=True, alpha=None, beta=None, host_driven=False, block
     o.host_driven = 1 if host_driven else 0
     o.blocks_per_cu = int(blocks_per_cu)
     o.heavy_split = int(heavy_split)
+    o.fuse_rounds = int(fuse_rounds)
     return o
 
 

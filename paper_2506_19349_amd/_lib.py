@@ -29,13 +29,13 @@ u32p = ctypes.POINTER(ctypes.c_uint32)
 class Options(ctypes.Structure):
     _fields_ = [("traversal_opt", i32), ("alpha", i32), ("beta", ctypes.c_double),
                 ("host_driven", i32), ("blocks_per_cu", i32), ("heavy_split", i32),
-                ("reserved", i32 * 9)]
+                ("fuse_rounds", i32), ("reserved", i32 * 8)]
 
 
 class Counters(ctypes.Structure):
     _fields_ = [(name, ctypes.c_uint64) for name in (
         "expansions", "band_expansions", "push_scanned", "pull_vertices", "pull_scanned",
-        "relax_success", "queue_entries", "rounds", "pulls", "steps", "ticks")] + [
+        "relax_success", "queue_entries", "rounds", "pulls", "steps", "ticks", "fused_rounds")] + [
         ("high_d0", u32), ("gap0", u32), ("flags", u32), ("reserved", u32)]
 
 

@@ -292,6 +292,7 @@ struct Opts {
   bool host_driven = false;
   int blocks_per_cu = 0;
   int heavy = kDefaultHeavy;
+  int fuse = kDefaultFuse;
   unsigned long long tick_limit = 1ull << 22;
 };
 
@@ -309,6 +310,8 @@ bool parse_opts(const sssp_options* o, Opts* r, std::string* err) {
   r->blocks_per_cu = o->blocks_per_cu;
   if (o->heavy_split < 0) { *err = "heavy_split must be >= 0"; return false; }
   if (o->heavy_split > 0) r->heavy = std::max(o->heavy_split, kWave);
+  if (o->fuse_rounds < 0) r->fuse = 0;
+  else if (o->fuse_rounds > 0) r->fuse = o->fuse_rounds;
   return true;
 }
 
@@ -387,6 +390,7 @@ sssp_status run_instances(const sssp_graph* const* gs, const int32_t* sources, i
     I.traversal_opt = o.topt;
     I.beta = o.beta;
     I.heavy_split = o.heavy;
+    I.fuse_cap = o.fuse;
   }
   HIP_TRY(hipMemcpyAsync(w.dG, hG, sizeof(Globals), hipMemcpyHostToDevice, stream));
   HIP_TRY(hipMemcpyAsync(w.dInst, hI, sizeof(Inst) * (size_t)k, hipMemcpyHostToDevice, stream));
@@ -598,6 +602,7 @@ sssp_status sssp_get_counters(hipStream_t stream, sssp_counters* out) {
     out->pulls += I.c.pulls;
     out->steps += I.c.steps;
     out->ticks += I.c.ticks;
+    out->fused_rounds += I.c.fused_rounds;
     flags |= I.flags.v;
   }
   out->high_d0 = hi[0].high_d0;

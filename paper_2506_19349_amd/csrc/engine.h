@@ -21,6 +21,7 @@ constexpr int kStageCap = 1280;          // LDS staging of list appends per work
 constexpr int kItemsPerThread = 4;       // round batches: items per thread
 constexpr int kRoundBatch = kBlock * kItemsPerThread;  // items per workgroup batch
 constexpr int kHeavyPerBatch = 16;       // heavy chunks per workgroup batch
+constexpr int kDefaultFuse = 256;        // rounds a workgroup may chain on a small frontier
 // persistent per-slot words (rid_slot[])
 enum PersistWord { PW_RID = 0, PW_COUNT = 8 };
 
@@ -79,7 +80,7 @@ struct TraceRec {
 
 struct Counters {
   unsigned long long expansions, band_expansions, push_scanned, pull_vertices, pull_scanned,
-      relax_success, queue_entries, rounds, pulls, steps, ticks;
+      relax_success, queue_entries, rounds, pulls, steps, ticks, fused_rounds;
 };
 
 struct alignas(128) HotI32 {
@@ -125,7 +126,7 @@ struct Inst {
   uint32_t traversal_opt;
   double beta;
   int32_t heavy_split;
-  int32_t pad0;
+  int32_t fuse_cap;        // rounds one workgroup may chain without a grid barrier (0: off)
   // ---- control (written by the epilogue / the heuristic) ----
   uint32_t phase;
   uint32_t tick_kind;      // PH_ROUND or PH_SETTLE: what the scheduled tick does

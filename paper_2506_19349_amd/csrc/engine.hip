@@ -900,6 +900,49 @@ __device__ int find_segment(const Globals& G, int b) {
   return lo;
 }
 
+// Bucket fusion (Section 4.1: up to FUSED = 256 rounds on a local frontier
+// between two synchronisations). Here: while an instance's next frontier fits
+// one batch and produced no heavy chunks, the workgroup that ran the round
+// applies the round transition itself and runs the next round at once -- no
+// grid barrier, no other workgroup involved. The band is fixed meanwhile, so
+// any grouping of rounds reaches the same settled set. When the frontier
+// empties or grows past one batch, the epilogue takes over with its usual
+// transition of the last round.
+__device__ __noinline__ void fused_rounds(Inst& I, RoundLds& L) {
+  __shared__ int s_go, s_nq;
+  const int cap = I.fuse_cap;
+  for (int r = 0; r < cap; ++r) {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      // the round's list appends and distance updates came from this
+      // workgroup's waves; the fence drops stale cached lines before reuse
+      __threadfence();
+      const int nq = __hip_atomic_load(&I.q_next_cnt.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const int nh = __hip_atomic_load(&I.h_next_cnt.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const bool go = nh == 0 && nq > 0 && nq <= kRoundBatch;
+      if (go) {
+        const uint32_t ubn = __hip_atomic_load(&I.ub_next.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (I.first && ubn < I.ub) I.ub = ubn;
+        I.c.rounds += 1;
+        I.c.fused_rounds += 1;
+        I.rounds_in_step += 1;
+        __hip_atomic_store(&I.q_next_cnt.v, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        I.qsel ^= 1;
+        I.hsel ^= 1;
+        I.nF = nq;
+        I.nH = 0;
+        I.rid += 1;
+      }
+      s_go = go ? 1 : 0;
+      s_nq = nq;
+    }
+    __syncthreads();
+    if (!s_go) break;
+    block_round(I, SEG_Q, 0, s_nq, L);
+  }
+}
+
 __device__ void run_tick(Globals& G, BlockLds& lds) {
   __shared__ int s_last;
   const int total_batches = G.total_batches;
@@ -931,6 +974,9 @@ __device__ void run_tick(Globals& G, BlockLds& lds) {
       __syncthreads();
     } else {
       block_round(I, kind, item0, cnt, lds.r);
+      // a frontier that fits one batch, with no heavy chunks, belongs to this
+      // workgroup alone for the whole tick: chain its next rounds here
+      if (kind == SEG_Q && cnt <= pb && I.nH == 0 && I.fuse_cap > 0) fused_rounds(I, lds.r);
     }
   }
 }
@@ -1284,7 +1330,7 @@ __global__ void k_init_arrays(Globals* Gp) {
       if (reset_stamp) I.stamp[v] = 0;
     }
     for (long long x = tid; x < I.maxw; x += stride) {
-      Counters z = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+      Counters z = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
       I.cslot[x] = z;
     }
     for (long long r = tid; r < g.num_deg; r += stride) I.hist_cnt[r] = g.deg_cnt0[r];
@@ -1331,7 +1377,7 @@ __global__ void __launch_bounds__(kBlock) k_init_ctl(Globals* Gp) {
       I.init_round = 0;
       I.tick_kind = PH_ROUND;
       I.high_d0 = g.high_d0;
-      Counters z = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+      Counters z = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
       I.c = z;
       I.step_rid0 = I.rid + 1;
       I.stamp[s] = I.step_rid0;

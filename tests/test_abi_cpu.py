@@ -18,7 +18,7 @@ def declared_functions():
     return sorted(set(names))
 
 
-def test_header_declares_the_north_star_calls():
+def test_header_declares_the_core_calls():
     names = declared_functions()
     for required in ("sssp_graph_create", "sssp_solve", "sssp_solve_batch"):
         assert required in names

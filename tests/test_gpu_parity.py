@@ -217,3 +217,26 @@ def test_repeated_solves_identical():
     first = gpu_dist(g, s)
     for _ in range(5):
         assert np.array_equal(gpu_dist(g, s), first)
+
+
+@pytest.mark.parametrize("name", ["grid256", "rmat14", "er12"])
+def test_fused_rounds_on_off(name):
+    """Bucket fusion only regroups rounds: same distances, same schedule."""
+    wl = graphgen.workload(name)
+    c = wl.csr
+    g = sssp.Graph.from_csr(c)
+    for s in wl.sources(2):
+        ref = oracle_dist(wl.edges, s)
+        on = gpu_dist(g, s)
+        c_on = sssp.counters()
+        sched_on = sssp.schedule()
+        off = gpu_dist(g, s, fuse_rounds=-1)
+        c_off = sssp.counters()
+        sched_off = sssp.schedule()
+        assert_same(on, ref, "%s fused s=%d" % (name, s))
+        assert_same(off, ref, "%s unfused s=%d" % (name, s))
+        assert c_off["fused_rounds"] == 0
+        assert [(a["lb"], a["ub"], a["st"]) for a in sched_on] == \
+            [(a["lb"], a["ub"], a["st"]) for a in sched_off]
+        if name == "grid256":
+            assert c_on["fused_rounds"] > 0 and c_on["ticks"] < c_off["ticks"]
