@@ -186,6 +186,129 @@ sssp_status sssp_get_schedule(hipStream_t stream, sssp_step* out, int32_t cap, i
  * on that stream. *n receives the count. Synchronises the stream. */
 sssp_status sssp_engine_times(hipStream_t stream, float* us_out, int32_t cap, int32_t* n);
 
+/* ---- batched plans (persistent launch captured in a HIP graph) ----------- */
+
+typedef struct sssp_plan sssp_plan; /* opaque */
+
+/* Capture the whole launch sequence of a k-instance solve -- instance set-up,
+ * the persistent engine (a cooperative graph node) and the overflow check --
+ * in a HIP graph, for k (graph, dist_out) pairs fixed here (graphs may repeat
+ * for several sources on one graph, or differ for a batch of small graphs).
+ * dist_outs[i]: device memory of gs[i]'s n uint32, written at every run.
+ * The plan owns its own workspace (device buffers sized for these graphs). A
+ * plan serves one run at a time and is used on the device it was created on.
+ * The graphs must outlive the plan. Returns NULL on error. */
+sssp_plan* sssp_plan_create(const sssp_graph* const* gs, int32_t k, uint32_t* const* dist_outs,
+                            const sssp_options* opt, hipStream_t stream);
+
+/* Replay the plan for k new sources (host array; sources[i] is a vertex of
+ * gs[i]) on `stream`. Waits for the plan's previous run to finish first (its
+ * instance images are re-staged). Asynchronous otherwise. */
+sssp_status sssp_plan_run(sssp_plan* p, const int32_t* sources, hipStream_t stream);
+
+/* Counters of the plan's last run, summed over its instances (waits for it). */
+sssp_status sssp_plan_counters(sssp_plan* p, sssp_counters* out);
+
+/* Free the plan (waits for its last run). NULL is accepted. */
+sssp_status sssp_plan_destroy(sssp_plan* p);
+
+/* ---- autotuner ----------------------------------------------------------- */
+
+typedef struct {
+  double default_us;    /* engine time of the workload under the options passed in */
+  double best_us;       /* engine time under the options returned */
+  int32_t evaluations;  /* option sets timed */
+  int32_t reserved[7];
+} sssp_tune_report;
+
+/* Time the workload -- k (graph, source) pairs, solved one at a time
+ * (batched = 0) or as one k-instance launch (batched = 1) -- under candidate
+ * launch knobs and return the fastest in *inout: workgroups per CU (grid
+ * size), the heavy-row split threshold (rows above it are spread over the
+ * grid in 256-entry chunks), bucket fusion on/off, and, when tune_beta is
+ * nonzero, beta of Eq. (1) (the step width; 0.9 is the paper's value). Knobs
+ * are tuned one at a time from the values passed in (coordinate descent), each
+ * candidate measured by HIP events around the engine launch after one untimed
+ * pass. No knob changes a distance. Synchronous; allocates scratch distance
+ * buffers for the trials. report may be NULL. */
+sssp_status sssp_autotune(const sssp_graph* const* gs, const int32_t* sources, int32_t k, int32_t batched,
+                          int32_t tune_beta, sssp_options* inout, sssp_tune_report* report,
+                          hipStream_t stream);
+
+/* ---- query server (continuous batching over resident graphs) ------------ */
+
+typedef struct sssp_server sssp_server; /* opaque */
+
+typedef struct {
+  uint64_t budget_bytes;    /* device memory the server may hold for queries in flight: solver
+                               workspaces it allocates plus the n * 4 bytes of each admitted
+                               query's output (graphs are resident already and not counted) */
+  int32_t max_batch;        /* solver slots, i.e. queries in flight at once; 0 -> 64 */
+  int32_t ticks_per_launch; /* device-wide ticks per engine launch between admissions; 0 -> 64 */
+  int32_t max_pending;      /* queued (not yet admitted) queries; 0 -> 65536 */
+  int32_t reserved[5];
+} sssp_server_config;
+
+typedef struct {
+  int32_t state;    /* 0 done, 1 queued, 2 running */
+  int32_t status;   /* final status once done (SSSP_OK, SSSP_E_DIST_OVERFLOW, ...) */
+  int32_t graph_id, source, slot;
+  uint32_t launches;  /* engine launches the query was part of */
+  double submit_us, admit_us, done_us;  /* server clock (microseconds since create); -1: not yet */
+} sssp_request_info;
+
+typedef struct {
+  uint64_t submitted, admitted, completed, launches;
+  double engine_us;   /* total engine-kernel time (HIP events) */
+  double now_us;      /* server clock */
+  uint64_t budget_bytes, allocated_bytes, peak_allocated_bytes, peak_in_use_bytes;
+  int32_t active, peak_active, queued, max_batch;
+} sssp_server_stats;
+
+/* Start a server on the current device, with its own stream and a pump
+ * thread. Queries are single-source solves (options as for sssp_solve_ex,
+ * NULL = defaults) on graphs registered with sssp_server_add_graph. The pump
+ * runs the persistent engine in launches of ticks_per_launch ticks; between
+ * launches it retires finished queries and admits queued ones (in arrival
+ * order) into free slots while the budget allows, so queries that arrive
+ * while others run join the next launch and share the device with them.
+ * Returns NULL on error. */
+sssp_server* sssp_server_create(const sssp_server_config* cfg, const sssp_options* opt);
+
+/* Register a resident graph (created on the same device; it must outlive the
+ * server). Returns its id (>= 0) or a negative status. */
+int32_t sssp_server_add_graph(sssp_server* s, const sssp_graph* g);
+
+/* Device bytes one query on graph `graph_id` is charged against the budget
+ * when it runs alone in a fresh slot (workspace + output), or a negative
+ * status. */
+int64_t sssp_server_query_bytes(sssp_server* s, int32_t graph_id);
+
+/* Queue a query: distances from `source` on graph `graph_id` into dist_out
+ * (device, n uint32, caller-owned; it must stay allocated until the query is
+ * done). *ticket identifies the query. SSSP_E_RANGE if the query alone
+ * exceeds the budget; SSSP_E_BUSY if the queue is full. Thread-safe. */
+sssp_status sssp_server_submit(sssp_server* s, int32_t graph_id, int32_t source, uint32_t* dist_out,
+                               int64_t* ticket);
+
+/* *done = 1 once the query is finished (its distances are then complete in
+ * device memory and visible to any stream). */
+sssp_status sssp_server_poll(sssp_server* s, int64_t ticket, int32_t* done);
+
+/* Block until the query is finished; returns its final status. */
+sssp_status sssp_server_wait(sssp_server* s, int64_t ticket);
+
+/* Timing and placement of one query (its record is kept until released). */
+sssp_status sssp_server_request_info(sssp_server* s, int64_t ticket, sssp_request_info* out);
+
+/* Forget a finished query's record. */
+sssp_status sssp_server_release(sssp_server* s, int64_t ticket);
+
+sssp_status sssp_server_get_stats(sssp_server* s, sssp_server_stats* out);
+
+/* Finish every submitted query, stop the pump and free the server. */
+sssp_status sssp_server_destroy(sssp_server* s);
+
 /* ---- debugging ---------------------------------------------------------- */
 
 /* Enable (cap > 0) or disable (cap = 0) a per-tick log of the engine for the

@@ -17,8 +17,8 @@ from ._lib import SSSPError
 
 INF = 0xFFFFFFFF
 
-__all__ = ["Graph", "solve_multi", "counters", "schedule", "engine_times", "SSSPError", "INF",
-           "version"]
+__all__ = ["Graph", "solve_multi", "counters", "schedule", "engine_times", "Plan", "autotune",
+           "Server", "SSSPError", "INF", "version"]
 
 
 def version() -> str:
@@ -158,6 +158,143 @@ def solve_multi(graphs: Sequence[Graph], sources: Sequence[int], outs=None, stre
                                      ctypes.cast(ptrs, ctypes.c_void_p), ctypes.byref(o),
                                      _stream_handle(stream)))
     return outs
+
+
+def _counters_dict(c) -> dict:
+    return {f: int(getattr(c, f)) for f, _ in c._fields_ if f != "reserved"}
+
+
+class Plan:
+    """A k-instance solve captured once as a HIP graph (sssp_plan_create) and
+    replayed with new sources: k sources on one graph, or one source on each
+    of k graphs. `outs` are the device tensors every run writes."""
+
+    def __init__(self, graphs: Sequence[Graph], outs, stream=None, **opts):
+        self.k = len(graphs)
+        self.graphs = list(graphs)
+        self.outs = list(outs)
+        hs = (ctypes.c_void_p * self.k)(*[g._h for g in graphs])
+        ptrs = (ctypes.c_void_p * self.k)(*[_ptr(o) for o in self.outs])
+        o = _options(**opts)
+        h = _lib.sssp_plan_create(ctypes.cast(hs, ctypes.c_void_p), self.k,
+                                  ctypes.cast(ptrs, ctypes.c_void_p), ctypes.byref(o),
+                                  _stream_handle(stream))
+        if not h:
+            _lib.check(_lib.sssp_last_error() or -6)
+        self._h = h
+
+    def run(self, sources: Sequence[int], stream=None):
+        srcs = np.ascontiguousarray(np.asarray(sources, dtype=np.int32))
+        if srcs.shape[0] != self.k:
+            raise ValueError("need %d sources" % self.k)
+        _lib.check(_lib.sssp_plan_run(self._h, srcs.ctypes.data, _stream_handle(stream)))
+        return self.outs
+
+    def counters(self) -> dict:
+        c = _lib.Counters()
+        st = _lib.sssp_plan_counters(self._h, ctypes.byref(c))
+        d = _counters_dict(c)
+        _lib.check(st)
+        return d
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.sssp_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune(graphs: Sequence[Graph], sources: Sequence[int], batched: bool = False,
+             tune_beta: bool = False, stream=None, **opts):
+    """Pick the fastest launch knobs for the workload (sssp_autotune).
+    Returns (options dict usable as solve(**opts), report dict)."""
+    k = len(graphs)
+    hs = (ctypes.c_void_p * k)(*[g._h for g in graphs])
+    srcs = np.ascontiguousarray(np.asarray(sources, dtype=np.int32))
+    o = _options(**opts)
+    rep = _lib.TuneReport()
+    _lib.check(_lib.sssp_autotune(ctypes.cast(hs, ctypes.c_void_p), srcs.ctypes.data, k,
+                                  1 if batched else 0, 1 if tune_beta else 0, ctypes.byref(o),
+                                  ctypes.byref(rep), _stream_handle(stream)))
+    tuned = {"traversal_opt": o.traversal_opt >= 0, "alpha": o.alpha, "beta": o.beta,
+             "blocks_per_cu": o.blocks_per_cu, "heavy_split": o.heavy_split,
+             "fuse_rounds": o.fuse_rounds}
+    report = {"default_us": rep.default_us, "best_us": rep.best_us, "evaluations": rep.evaluations}
+    return tuned, report
+
+
+class Server:
+    """Continuous-batching query server over resident graphs (sssp_server_*)."""
+
+    def __init__(self, budget_bytes: int, max_batch: int = 0, ticks_per_launch: int = 0,
+                 max_pending: int = 0, **opts):
+        cfg = _lib.ServerConfig()
+        cfg.budget_bytes = int(budget_bytes)
+        cfg.max_batch = int(max_batch)
+        cfg.ticks_per_launch = int(ticks_per_launch)
+        cfg.max_pending = int(max_pending)
+        o = _options(**opts)
+        h = _lib.sssp_server_create(ctypes.byref(cfg), ctypes.byref(o))
+        if not h:
+            _lib.check(_lib.sssp_last_error() or -6)
+        self._h = h
+        self._graphs = []
+
+    def add_graph(self, g: Graph) -> int:
+        gid = _lib.sssp_server_add_graph(self._h, g._h)
+        if gid < 0:
+            _lib.check(gid)
+        self._graphs.append(g)
+        return gid
+
+    def query_bytes(self, graph_id: int) -> int:
+        b = _lib.sssp_server_query_bytes(self._h, int(graph_id))
+        if b < 0:
+            _lib.check(int(b))
+        return int(b)
+
+    def submit(self, graph_id: int, source: int, out) -> int:
+        t = ctypes.c_int64(0)
+        _lib.check(_lib.sssp_server_submit(self._h, int(graph_id), int(source), _ptr(out),
+                                           ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int) -> bool:
+        d = ctypes.c_int32(0)
+        _lib.check(_lib.sssp_server_poll(self._h, ctypes.c_int64(ticket), ctypes.byref(d)))
+        return bool(d.value)
+
+    def wait(self, ticket: int) -> None:
+        _lib.check(_lib.sssp_server_wait(self._h, ctypes.c_int64(ticket)))
+
+    def info(self, ticket: int) -> dict:
+        r = _lib.RequestInfo()
+        _lib.check(_lib.sssp_server_request_info(self._h, ctypes.c_int64(ticket), ctypes.byref(r)))
+        return {f: getattr(r, f) for f, _ in r._fields_}
+
+    def release(self, ticket: int) -> None:
+        _lib.check(_lib.sssp_server_release(self._h, ctypes.c_int64(ticket)))
+
+    def stats(self) -> dict:
+        s = _lib.ServerStats()
+        _lib.check(_lib.sssp_server_get_stats(self._h, ctypes.byref(s)))
+        return {f: getattr(s, f) for f, _ in s._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.sssp_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def counters(stream=None) -> dict:

@@ -51,6 +51,31 @@ class GraphInfo(ctypes.Structure):
                 ("reserved", u32), ("device_bytes", ctypes.c_uint64)]
 
 
+class TuneReport(ctypes.Structure):
+    _fields_ = [("default_us", ctypes.c_double), ("best_us", ctypes.c_double),
+                ("evaluations", i32), ("reserved", i32 * 7)]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_uint64), ("max_batch", i32), ("ticks_per_launch", i32),
+                ("max_pending", i32), ("reserved", i32 * 5)]
+
+
+class RequestInfo(ctypes.Structure):
+    _fields_ = [("state", i32), ("status", i32), ("graph_id", i32), ("source", i32), ("slot", i32),
+                ("launches", u32), ("submit_us", ctypes.c_double), ("admit_us", ctypes.c_double),
+                ("done_us", ctypes.c_double)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("admitted", ctypes.c_uint64),
+                ("completed", ctypes.c_uint64), ("launches", ctypes.c_uint64),
+                ("engine_us", ctypes.c_double), ("now_us", ctypes.c_double),
+                ("budget_bytes", ctypes.c_uint64), ("allocated_bytes", ctypes.c_uint64),
+                ("peak_allocated_bytes", ctypes.c_uint64), ("peak_in_use_bytes", ctypes.c_uint64),
+                ("active", i32), ("peak_active", i32), ("queued", i32), ("max_batch", i32)]
+
+
 def _sig(name, res, *args):
     f = getattr(lib, name)
     f.restype = res
@@ -74,6 +99,23 @@ sssp_engine_times = _sig("sssp_engine_times", i32, vp, ctypes.POINTER(ctypes.c_f
 sssp_debug_tick_log = _sig("sssp_debug_tick_log", i32, vp, i32)
 sssp_debug_get_tick_log = _sig("sssp_debug_get_tick_log", i32, vp, vp, i32, i32p,
                                ctypes.POINTER(ctypes.c_uint64))
+sssp_plan_create = _sig("sssp_plan_create", vp, vp, i32, vp, ctypes.POINTER(Options), vp)
+sssp_plan_run = _sig("sssp_plan_run", i32, vp, vp, vp)
+sssp_plan_counters = _sig("sssp_plan_counters", i32, vp, ctypes.POINTER(Counters))
+sssp_plan_destroy = _sig("sssp_plan_destroy", i32, vp)
+sssp_autotune = _sig("sssp_autotune", i32, vp, vp, i32, i32, i32, ctypes.POINTER(Options),
+                     ctypes.POINTER(TuneReport), vp)
+sssp_server_create = _sig("sssp_server_create", vp, ctypes.POINTER(ServerConfig), ctypes.POINTER(Options))
+sssp_server_add_graph = _sig("sssp_server_add_graph", i32, vp, vp)
+sssp_server_query_bytes = _sig("sssp_server_query_bytes", ctypes.c_int64, vp, i32)
+sssp_server_submit = _sig("sssp_server_submit", i32, vp, i32, i32, vp, ctypes.POINTER(ctypes.c_int64))
+sssp_server_poll = _sig("sssp_server_poll", i32, vp, ctypes.c_int64, i32p)
+sssp_server_wait = _sig("sssp_server_wait", i32, vp, ctypes.c_int64)
+sssp_server_request_info = _sig("sssp_server_request_info", i32, vp, ctypes.c_int64,
+                                ctypes.POINTER(RequestInfo))
+sssp_server_release = _sig("sssp_server_release", i32, vp, ctypes.c_int64)
+sssp_server_get_stats = _sig("sssp_server_get_stats", i32, vp, ctypes.POINTER(ServerStats))
+sssp_server_destroy = _sig("sssp_server_destroy", i32, vp)
 sssp_last_error = _sig("sssp_last_error", i32)
 sssp_last_error_message = _sig("sssp_last_error_message", ctypes.c_char_p)
 sssp_status_str = _sig("sssp_status_str", ctypes.c_char_p, i32)

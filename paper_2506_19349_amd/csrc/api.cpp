@@ -1,5 +1,7 @@
 // C ABI of the SSSP engine: argument checking, graph objects, per-stream
-// solver workspaces and the launch sequence of a solve.
+// solver workspaces and the launch sequence of a solve. Batched plans,
+// the autotuner (plan.cpp) and the query server (server.cpp) build on the
+// runtime declared in runtime.h.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -10,17 +12,9 @@
 #include <utility>
 #include <vector>
 
-#include "../../include/sssp.h"
-#include "engine.h"
-#include "prep.h"
+#include "runtime.h"
 
-struct sssp_graph {
-  sssp::GraphHost gh;
-};
-
-namespace {
-
-using namespace sssp;
+namespace sssp {
 
 thread_local sssp_status t_status = SSSP_OK;
 thread_local std::string t_msg;
@@ -37,11 +31,6 @@ sssp_status ok() {
   return SSSP_OK;
 }
 
-#define HIP_TRY(expr)                                                                  \
-  do {                                                                                 \
-    hipError_t _e = (expr);                                                            \
-    if (_e != hipSuccess) return fail(SSSP_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(_e)); \
-  } while (0)
 
 uint32_t pow2_at_least(uint64_t x) {
   uint64_t p = 1;
@@ -51,36 +40,7 @@ uint32_t pow2_at_least(uint64_t x) {
 
 // ------------------------------------------------------------ workspaces --
 
-struct SlotBuf {
-  int32_t n_cap = 0, list_cap = 0, maxw = 0, heavy_cap = 0, hist_cap = 0, trace_cap = 0;
-  uint32_t ring_cap = 0, steprec_cap = 0;
-  uint32_t* stamp = nullptr;
-  int32_t* q[2] = {nullptr, nullptr};
-  int32_t* touched = nullptr;
-  int32_t* settled = nullptr;
-  int32_t* plist[2] = {nullptr, nullptr};
-  int32_t* ulist[2] = {nullptr, nullptr};
-  HeavyItem* heavy[2] = {nullptr, nullptr};
-  uint64_t* ring_mass = nullptr;
-  uint32_t* ring_cnt = nullptr;
-  uint32_t* hist = nullptr;
-  StepRec* steprec = nullptr;
-  TraceRec* trace = nullptr;
-  uint32_t* rid = nullptr;
-  Counters* cslot = nullptr;
-  std::vector<void*> allocs;
-  void release() {
-    for (void* p : allocs) (void)hipFree(p);
-    allocs.clear();
-    n_cap = list_cap = maxw = heavy_cap = hist_cap = trace_cap = 0;
-    ring_cap = steprec_cap = 0;
-  }
-};
 
-struct Needs {
-  int32_t n, list, maxw, heavy, hist, trace;
-  uint32_t ring, steprec;
-};
 
 Needs needs_for(const DevGraph& g, int maxw) {
   Needs r;
@@ -109,6 +69,21 @@ hipError_t dev_alloc(T** p, size_t count, std::vector<void*>& list) {
     *p = static_cast<T*>(v);
   }
   return e;
+}
+
+size_t needs_bytes(const Needs& m) {
+  size_t b = 0;
+  b += sizeof(uint32_t) * (size_t)m.n;             // stamp
+  b += sizeof(int32_t) * (size_t)m.list * 5;       // q[2], touched, ulist[2]
+  b += sizeof(int32_t) * (size_t)m.n * 3;          // settled, plist[2]
+  b += sizeof(Counters) * (size_t)m.maxw;
+  b += sizeof(HeavyItem) * (size_t)m.heavy * 2;
+  b += (sizeof(uint64_t) + sizeof(uint32_t)) * (size_t)m.ring;
+  b += sizeof(uint32_t) * (size_t)m.hist;
+  b += sizeof(StepRec) * (size_t)m.steprec;
+  b += sizeof(TraceRec) * (size_t)m.trace;
+  b += sizeof(uint32_t) * PW_COUNT;
+  return b;
 }
 
 bool slot_fits(const SlotBuf& s, const Needs& nd) {
@@ -169,37 +144,6 @@ hipError_t ensure_slot(SlotBuf& s, const Needs& nd) {
   return hipSuccess;
 }
 
-struct Workspace {
-  hipStream_t stream = nullptr;
-  int device = 0;
-  std::vector<SlotBuf> slots;
-  int inst_cap = 0;
-  Globals* dG = nullptr;
-  Inst* dInst = nullptr;
-  int32_t* seg = nullptr;  // 5 arrays of (kMaxSegPerInst * inst_cap + 1)
-  std::vector<void*> allocs;
-  // pinned staging ring
-  static constexpr int kStages = 4;
-  void* stage[kStages] = {nullptr, nullptr, nullptr, nullptr};
-  size_t stage_cap[kStages] = {0, 0, 0, 0};
-  hipEvent_t stage_ev[kStages] = {nullptr, nullptr, nullptr, nullptr};
-  bool stage_used[kStages] = {false, false, false, false};
-  int next_stage = 0;
-  unsigned int* pinned_flag = nullptr;
-  int grid = 0;
-  int cus = 0;
-  int occ = 0;
-  // last solve
-  int last_k = 0;
-  bool persistent_failed = false;
-  // optional per-tick log of the engine (debug)
-  unsigned long long* d_tick_log = nullptr;
-  int tick_log_cap = 0;
-  // engine-kernel timing ring (HIP events around each engine launch)
-  static constexpr int kTimes = 256;
-  hipEvent_t tev[2][kTimes] = {};
-  long long t_rec = 0, t_read = 0;
-};
 
 std::mutex g_ws_mu;
 std::map<std::pair<int, hipStream_t>, Workspace*> g_ws;
@@ -223,6 +167,65 @@ hipError_t ws_ensure_insts(Workspace& w, int k) {
   return hipSuccess;
 }
 
+bool ws_setup(Workspace& w, hipStream_t stream, std::string* err) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    *err = "hipGetDevice failed";
+    return false;
+  }
+  w.stream = stream;
+  w.device = dev;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+    *err = "hipGetDeviceProperties failed";
+    return false;
+  }
+  w.cus = prop.multiProcessorCount;
+  w.occ = engine_blocks_per_cu();
+  w.grid = w.cus * w.occ;
+  for (int i = 0; i < Workspace::kStages; ++i) {
+    if (hipEventCreateWithFlags(&w.stage_ev[i], hipEventDisableTiming) != hipSuccess) {
+      *err = "hipEventCreate failed";
+      return false;
+    }
+  }
+  for (int a = 0; a < 2; ++a)
+    for (int i = 0; i < Workspace::kTimes; ++i)
+      if (hipEventCreate(&w.tev[a][i]) != hipSuccess) {
+        *err = "hipEventCreate failed";
+        return false;
+      }
+  if (hipHostMalloc((void**)&w.pinned_flag, sizeof(unsigned int) * 4, hipHostMallocDefault) != hipSuccess) {
+    *err = "hipHostMalloc failed";
+    return false;
+  }
+  return true;
+}
+
+void ws_release(Workspace& w) {
+  for (SlotBuf& s : w.slots) s.release();
+  w.slots.clear();
+  for (void* p : w.allocs) (void)hipFree(p);
+  w.allocs.clear();
+  w.inst_cap = 0;
+  for (int i = 0; i < Workspace::kStages; ++i) {
+    if (w.stage[i]) (void)hipHostFree(w.stage[i]);
+    w.stage[i] = nullptr;
+    w.stage_cap[i] = 0;
+    if (w.stage_ev[i]) (void)hipEventDestroy(w.stage_ev[i]);
+    w.stage_ev[i] = nullptr;
+  }
+  for (int a = 0; a < 2; ++a)
+    for (int i = 0; i < Workspace::kTimes; ++i) {
+      if (w.tev[a][i]) (void)hipEventDestroy(w.tev[a][i]);
+      w.tev[a][i] = nullptr;
+    }
+  if (w.pinned_flag) (void)hipHostFree(w.pinned_flag);
+  w.pinned_flag = nullptr;
+  if (w.d_tick_log) (void)hipFree(w.d_tick_log);
+  w.d_tick_log = nullptr;
+}
+
 Workspace* get_ws(hipStream_t stream, std::string* err) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) {
@@ -234,33 +237,8 @@ Workspace* get_ws(hipStream_t stream, std::string* err) {
   auto it = g_ws.find(key);
   if (it != g_ws.end()) return it->second;
   Workspace* w = new Workspace;
-  w->stream = stream;
-  w->device = dev;
-  hipDeviceProp_t prop;
-  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) {
-    delete w;
-    *err = "hipGetDeviceProperties failed";
-    return nullptr;
-  }
-  w->cus = prop.multiProcessorCount;
-  w->occ = engine_blocks_per_cu();
-  w->grid = w->cus * w->occ;
-  for (int i = 0; i < Workspace::kStages; ++i) {
-    if (hipEventCreateWithFlags(&w->stage_ev[i], hipEventDisableTiming) != hipSuccess) {
-      *err = "hipEventCreate failed";
-      delete w;
-      return nullptr;
-    }
-  }
-  for (int a = 0; a < 2; ++a)
-    for (int i = 0; i < Workspace::kTimes; ++i)
-      if (hipEventCreate(&w->tev[a][i]) != hipSuccess) {
-        *err = "hipEventCreate failed";
-        delete w;
-        return nullptr;
-      }
-  if (hipHostMalloc((void**)&w->pinned_flag, sizeof(unsigned int) * 4, hipHostMallocDefault) != hipSuccess) {
-    *err = "hipHostMalloc failed";
+  if (!ws_setup(*w, stream, err)) {
+    ws_release(*w);
     delete w;
     return nullptr;
   }
@@ -285,16 +263,6 @@ void* ws_stage(Workspace& w, size_t bytes, int* idx) {
   return w.stage[i];
 }
 
-struct Opts {
-  uint32_t alpha = 3;
-  double beta = 0.9;
-  uint32_t topt = 1;
-  bool host_driven = false;
-  int blocks_per_cu = 0;
-  int heavy = kDefaultHeavy;
-  int fuse = kDefaultFuse;
-  unsigned long long tick_limit = 1ull << 22;
-};
 
 bool parse_opts(const sssp_options* o, Opts* r, std::string* err) {
   if (!o) return true;
@@ -315,13 +283,57 @@ bool parse_opts(const sssp_options* o, Opts* r, std::string* err) {
   return true;
 }
 
-// Enqueue k instances; every argument has been checked.
+// Host image of one solve instance (its control words are set on the device).
+void fill_inst(Inst& I, const SlotBuf& s, const sssp_graph* g, int32_t source, uint32_t* dist,
+               const Opts& o) {
+  std::memset(&I, 0, sizeof(Inst));
+  I.g = g->gh.d;
+  I.dist = dist;
+  I.stamp = s.stamp;
+  I.q[0] = s.q[0];
+  I.q[1] = s.q[1];
+  I.touched = s.touched;
+  I.settled = s.settled;
+  I.plist[0] = s.plist[0];
+  I.plist[1] = s.plist[1];
+  I.ulist[0] = s.ulist[0];
+  I.ulist[1] = s.ulist[1];
+  I.heavy[0] = s.heavy[0];
+  I.heavy[1] = s.heavy[1];
+  I.ring_mass = s.ring_mass;
+  I.ring_cnt = s.ring_cnt;
+  I.hist_cnt = s.hist;
+  I.steprec = s.steprec;
+  I.trace = s.trace;
+  I.rid_slot = s.rid;
+  I.cslot = s.cslot;
+  I.maxw = s.maxw;
+  I.heavy_cap = s.heavy_cap;
+  Needs nd = needs_for(g->gh.h, s.maxw);
+  I.ring_mask = nd.ring - 1;
+  I.steprec_mask = nd.steprec - 1;
+  I.trace_cap = s.trace_cap;
+  I.source = source;
+  I.n = g->gh.h.n;
+  I.alpha = o.alpha;
+  I.traversal_opt = o.topt;
+  I.beta = o.beta;
+  I.heavy_split = o.heavy;
+  I.fuse_cap = o.fuse;
+  I.phase = PH_DONE;
+}
+
 sssp_status run_instances(const sssp_graph* const* gs, const int32_t* sources, int k,
                           uint32_t* const* dists, const Opts& o, hipStream_t stream) {
   std::string err;
   Workspace* wp = get_ws(stream, &err);
   if (!wp) return fail(SSSP_E_DEVICE, err);
-  Workspace& w = *wp;
+  return run_instances_ws(*wp, gs, sources, k, dists, o, stream);
+}
+
+// Enqueue k instances on workspace w; every argument has been checked.
+sssp_status run_instances_ws(Workspace& w, const sssp_graph* const* gs, const int32_t* sources, int k,
+                             uint32_t* const* dists, const Opts& o, hipStream_t stream) {
   HIP_TRY(ws_ensure_insts(w, k));
   long long max_n = 0;
   for (int i = 0; i < k; ++i) {
@@ -355,43 +367,9 @@ sssp_status run_instances(const sssp_graph* const* gs, const int32_t* sources, i
   hG->seg_per_batch = w.seg + 3 * segcap;
   hG->seg_first_batch = w.seg + 4 * segcap;
   hG->insts = w.dInst;
-  for (int i = 0; i < k; ++i) {
-    const SlotBuf& s = w.slots[(size_t)i];
-    Inst& I = hI[i];
-    I.g = gs[i]->gh.d;
-    I.dist = dists[i];
-    I.stamp = s.stamp;
-    I.q[0] = s.q[0];
-    I.q[1] = s.q[1];
-    I.touched = s.touched;
-    I.settled = s.settled;
-    I.plist[0] = s.plist[0];
-    I.plist[1] = s.plist[1];
-    I.ulist[0] = s.ulist[0];
-    I.ulist[1] = s.ulist[1];
-    I.heavy[0] = s.heavy[0];
-    I.heavy[1] = s.heavy[1];
-    I.ring_mass = s.ring_mass;
-    I.ring_cnt = s.ring_cnt;
-    I.hist_cnt = s.hist;
-    I.steprec = s.steprec;
-    I.trace = s.trace;
-    I.rid_slot = s.rid;
-    I.cslot = s.cslot;
-    I.maxw = s.maxw;
-    I.heavy_cap = s.heavy_cap;
-    Needs nd = needs_for(gs[i]->gh.h, s.maxw);
-    I.ring_mask = nd.ring - 1;
-    I.steprec_mask = nd.steprec - 1;
-    I.trace_cap = s.trace_cap;
-    I.source = sources[i];
-    I.n = gs[i]->gh.h.n;
-    I.alpha = o.alpha;
-    I.traversal_opt = o.topt;
-    I.beta = o.beta;
-    I.heavy_split = o.heavy;
-    I.fuse_cap = o.fuse;
-  }
+  hG->sel_list = nullptr;
+  hG->n_sel = -1;
+  for (int i = 0; i < k; ++i) fill_inst(hI[i], w.slots[(size_t)i], gs[i], sources[i], dists[i], o);
   HIP_TRY(hipMemcpyAsync(w.dG, hG, sizeof(Globals), hipMemcpyHostToDevice, stream));
   HIP_TRY(hipMemcpyAsync(w.dInst, hI, sizeof(Inst) * (size_t)k, hipMemcpyHostToDevice, stream));
   HIP_TRY(hipEventRecord(w.stage_ev[si], stream));
@@ -438,7 +416,70 @@ bool check_graph(const sssp_graph* g, std::string* err) {
   return true;
 }
 
-}  // namespace
+// Counters of instances [i0, i0 + k) of the workspace's last launch (the
+// stream has been synchronised), summed; maps the engine's flags to a status.
+sssp_status collect_counters(Workspace& w, int i0, int k, sssp_counters* out) {
+  std::memset(out, 0, sizeof(*out));
+  std::vector<Inst> hi((size_t)k);
+  HIP_TRY(hipMemcpy(hi.data(), w.dInst + i0, sizeof(Inst) * (size_t)k, hipMemcpyDeviceToHost));
+  Globals hg;
+  HIP_TRY(hipMemcpy(&hg, w.dG, sizeof(Globals), hipMemcpyDeviceToHost));
+  uint32_t flags = 0;
+  for (Inst& I : hi) {
+    if (!I.cslot) continue;
+    std::vector<Counters> cs((size_t)I.maxw);
+    HIP_TRY(hipMemcpy(cs.data(), I.cslot, sizeof(Counters) * (size_t)I.maxw, hipMemcpyDeviceToHost));
+    for (const Counters& c : cs) {
+      I.c.expansions += c.expansions;
+      I.c.band_expansions += c.band_expansions;
+      I.c.push_scanned += c.push_scanned;
+      I.c.pull_vertices += c.pull_vertices;
+      I.c.pull_scanned += c.pull_scanned;
+      I.c.relax_success += c.relax_success;
+      I.c.queue_entries += c.queue_entries;
+    }
+  }
+  for (const Inst& I : hi) {
+    out->expansions += I.c.expansions;
+    out->band_expansions += I.c.band_expansions;
+    out->push_scanned += I.c.push_scanned;
+    out->pull_vertices += I.c.pull_vertices;
+    out->pull_scanned += I.c.pull_scanned;
+    out->relax_success += I.c.relax_success;
+    out->queue_entries += I.c.queue_entries;
+    out->rounds += I.c.rounds;
+    out->pulls += I.c.pulls;
+    out->steps += I.c.steps;
+    out->ticks += I.c.ticks;
+    out->fused_rounds += I.c.fused_rounds;
+    flags |= I.flags.v;
+  }
+  out->high_d0 = hi[0].high_d0;
+  out->gap0 = hi[0].gap0;
+  flags |= hg.error;
+  out->flags = flags;
+  if (flags & FLAG_OVERFLOW) return fail(SSSP_E_DIST_OVERFLOW, "a distance does not fit below UINT32_MAX");
+  if (flags & (FLAG_CAPACITY | FLAG_MASS | FLAG_TIMEOUT | FLAG_TICKS))
+    return fail(SSSP_E_DEVICE, "internal engine condition, flags = " + std::to_string(flags));
+  return ok();
+}
+
+// Engine durations recorded on the workspace since the last call (microseconds).
+sssp_status ws_take_times(Workspace& w, std::vector<float>* us) {
+  long long from = std::max(w.t_read, w.t_rec - Workspace::kTimes);
+  for (long long i = from; i < w.t_rec; ++i) {
+    int sl = (int)(i % Workspace::kTimes);
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, w.tev[0][sl], w.tev[1][sl]));
+    us->push_back(ms * 1000.f);
+  }
+  w.t_read = w.t_rec;
+  return ok();
+}
+
+}  // namespace sssp
+
+using namespace sssp;
 
 // ================================================================== C ABI
 
@@ -572,47 +613,7 @@ sssp_status sssp_get_counters(hipStream_t stream, sssp_counters* out) {
   std::memset(out, 0, sizeof(*out));
   if (w->last_k == 0) return fail(SSSP_E_INVAL, "no solve on this stream");
   HIP_TRY(hipStreamSynchronize(stream));
-  std::vector<Inst> hi((size_t)w->last_k);
-  HIP_TRY(hipMemcpy(hi.data(), w->dInst, sizeof(Inst) * (size_t)w->last_k, hipMemcpyDeviceToHost));
-  Globals hg;
-  HIP_TRY(hipMemcpy(&hg, w->dG, sizeof(Globals), hipMemcpyDeviceToHost));
-  uint32_t flags = 0;
-  for (Inst& I : hi) {
-    std::vector<Counters> cs((size_t)I.maxw);
-    HIP_TRY(hipMemcpy(cs.data(), I.cslot, sizeof(Counters) * (size_t)I.maxw, hipMemcpyDeviceToHost));
-    for (const Counters& c : cs) {
-      I.c.expansions += c.expansions;
-      I.c.band_expansions += c.band_expansions;
-      I.c.push_scanned += c.push_scanned;
-      I.c.pull_vertices += c.pull_vertices;
-      I.c.pull_scanned += c.pull_scanned;
-      I.c.relax_success += c.relax_success;
-      I.c.queue_entries += c.queue_entries;
-    }
-  }
-  for (const Inst& I : hi) {
-    out->expansions += I.c.expansions;
-    out->band_expansions += I.c.band_expansions;
-    out->push_scanned += I.c.push_scanned;
-    out->pull_vertices += I.c.pull_vertices;
-    out->pull_scanned += I.c.pull_scanned;
-    out->relax_success += I.c.relax_success;
-    out->queue_entries += I.c.queue_entries;
-    out->rounds += I.c.rounds;
-    out->pulls += I.c.pulls;
-    out->steps += I.c.steps;
-    out->ticks += I.c.ticks;
-    out->fused_rounds += I.c.fused_rounds;
-    flags |= I.flags.v;
-  }
-  out->high_d0 = hi[0].high_d0;
-  out->gap0 = hi[0].gap0;
-  flags |= hg.error;
-  out->flags = flags;
-  if (flags & FLAG_OVERFLOW) return fail(SSSP_E_DIST_OVERFLOW, "a distance does not fit below UINT32_MAX");
-  if (flags & (FLAG_CAPACITY | FLAG_MASS | FLAG_TIMEOUT | FLAG_TICKS))
-    return fail(SSSP_E_DEVICE, "internal engine condition, flags = " + std::to_string(flags));
-  return ok();
+  return collect_counters(*w, 0, w->last_k, out);
 }
 
 sssp_status sssp_get_schedule(hipStream_t stream, sssp_step* out, int32_t cap, int32_t* len) {

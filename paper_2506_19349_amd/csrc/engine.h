@@ -96,6 +96,8 @@ struct alignas(128) HotU64 {
   unsigned long long pad[15];
 };
 
+constexpr int kMaxSegPerInst = 5;  // segments one instance may have in a tick
+
 struct Inst {
   // ---- fixed for a solve ----
   const DevGraph* g;
@@ -148,6 +150,9 @@ struct Inst {
   int32_t settle_items;    // batches of the settle tick
   uint32_t high_d0, gap0;
   uint32_t pad1;
+  // this instance's segments of the next tick (written by its transition)
+  int32_t spec_cnt[kMaxSegPerInst], spec_kind[kMaxSegPerInst], spec_pb[kMaxSegPerInst];
+  int32_t pad3;
   Counters c;
   // ---- hot words: updated by device atomics from every CU, each on its own
   // 128-byte line so that they never share a line with the fields above ----
@@ -165,7 +170,6 @@ constexpr uint32_t FLAG_OVERFLOW = 16u;       // confirmed: a distance does not 
 constexpr uint32_t FLAG_TICKS = 32u;          // the tick limit stopped the engine
 
 // ------------------------------------------------------------- tick table --
-constexpr int kMaxSegPerInst = 5;
 
 constexpr int kMaxXcd = 8;  // XCDs (each with its own L2) on an MI355X
 
@@ -196,6 +200,10 @@ struct Globals {
   int32_t* seg_per_batch;
   int32_t* seg_first_batch;  // nseg + 1 entries
   Inst* insts;
+  // instances the set-up kernels act on: sel_list[0 .. n_sel), or all when n_sel < 0
+  const int32_t* sel_list;
+  int32_t n_sel;
+  int32_t pad_sel;
 };
 
 // host launch wrappers (engine.hip)
@@ -203,5 +211,11 @@ hipError_t launch_init(Globals* dG, long long max_n, hipStream_t stream);
 int engine_blocks_per_cu();
 hipError_t launch_engine(Globals* dG, int grid, bool persistent, int max_ticks, hipStream_t stream);
 hipError_t launch_overflow_check(Globals* dG, long long max_n, hipStream_t stream);
+// per-instance phase and flags (2 words each) into status[0 .. 2 * ninst)
+hipError_t launch_status(Globals* dG, int ninst, uint32_t* status, hipStream_t stream);
+// the set-up + engine + overflow-check sequence of one solve as graph nodes
+// after `dep` (may be null); the engine node is cooperative
+hipError_t add_solve_nodes(hipGraph_t graph, hipGraphNode_t dep, Globals* dG, long long max_n, int grid,
+                           hipGraphNode_t* last);
 
 }  // namespace sssp

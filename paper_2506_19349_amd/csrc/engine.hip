@@ -20,6 +20,8 @@
 // settled set and is therefore deterministic.
 #include "engine.h"
 
+#include <cstring>
+
 namespace sssp {
 
 // ------------------------------------------------------------ wave helpers --
@@ -1043,7 +1045,11 @@ __device__ void transition(Inst& I, int32_t* cnt, int32_t* kinds, int32_t* pbs) 
   cnt[2] = I.pull_on ? I.nU : 0; kinds[2] = SEG_U; pbs[2] = kRoundBatch;
 }
 
-// Build the tick table from every instance's transition. One workgroup.
+// Build the tick table. With do_transition, every instance first takes its
+// phase transition, which records its segments of the next tick in the
+// instance; otherwise the recorded segments are laid out as they are (a new
+// launch continuing earlier instances, or the first tick of new ones). One
+// workgroup.
 __device__ void build_table(Globals& G, bool do_transition) {
   const int tid = threadIdx.x;
   const int k = G.ninst;
@@ -1057,25 +1063,19 @@ __device__ void build_table(Globals& G, bool do_transition) {
   int local_batches = 0;
   for (int i = i0; i < i1; ++i) {
     Inst& I = G.insts[i];
-    int32_t cnt[kMaxSegPerInst], kinds[kMaxSegPerInst], pbs[kMaxSegPerInst];
-    if (do_transition) {
-      transition(I, cnt, kinds, pbs);
-    } else {
-      // first tick of a solve: the source alone
-      for (int s = 0; s < kMaxSegPerInst; ++s) { cnt[s] = 0; kinds[s] = SEG_Q; pbs[s] = kBlock; }
-      if (I.phase != PH_DONE) { cnt[0] = I.nF; kinds[0] = SEG_Q; pbs[0] = kRoundBatch; }
-    }
+    if (do_transition) transition(I, I.spec_cnt, I.spec_kind, I.spec_pb);
     if (I.phase != PH_DONE) atomicAdd(&s_active, 1);
     for (int s = 0; s < kMaxSegPerInst; ++s) {
       int sg = i * kMaxSegPerInst + s;
-      int c = cnt[s];
+      int c = I.phase == PH_DONE ? 0 : I.spec_cnt[s];
+      int pb = I.spec_pb[s] > 0 ? I.spec_pb[s] : kBlock;
       int nb;
       if (c < 0) { nb = 1; c = 0; }
-      else nb = (c + pbs[s] - 1) / pbs[s];
+      else nb = (c + pb - 1) / pb;
       G.seg_inst[sg] = i;
-      G.seg_kind[sg] = kinds[s];
+      G.seg_kind[sg] = I.spec_kind[s];
       G.seg_count[sg] = c;
-      G.seg_per_batch[sg] = pbs[s];
+      G.seg_per_batch[sg] = pb;
       G.seg_first_batch[sg] = nb;  // temporarily the batch count
       local_batches += nb;
     }
@@ -1320,8 +1320,9 @@ __global__ void k_init_arrays(Globals* Gp) {
   Globals& G = *Gp;
   const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long stride = (long long)gridDim.x * blockDim.x;
-  for (int i = 0; i < G.ninst; ++i) {
-    Inst& I = G.insts[i];
+  const int nsel = G.n_sel < 0 ? G.ninst : G.n_sel;
+  for (int j = 0; j < nsel; ++j) {
+    Inst& I = G.insts[G.n_sel < 0 ? j : G.sel_list[j]];
     const DevGraph& g = *I.g;
     const uint32_t* pw = I.rid_slot;
     const bool reset_stamp = pw[PW_RID] > 0x80000000u;
@@ -1344,8 +1345,9 @@ __global__ void k_init_arrays(Globals* Gp) {
 // Per-solve control reset and the first tick's table. One workgroup.
 __global__ void __launch_bounds__(kBlock) k_init_ctl(Globals* Gp) {
   Globals& G = *Gp;
-  for (int i = 0; i < G.ninst; ++i) {
-    Inst& I = G.insts[i];
+  const int nsel = G.n_sel < 0 ? G.ninst : G.n_sel;
+  for (int j = 0; j < nsel; ++j) {
+    Inst& I = G.insts[G.n_sel < 0 ? j : G.sel_list[j]];
     const DevGraph& g = *I.g;
     if (threadIdx.x == 0) {
       uint32_t* pw = I.rid_slot;
@@ -1389,6 +1391,13 @@ __global__ void __launch_bounds__(kBlock) k_init_ctl(Globals* Gp) {
       I.ub_next.v = is_hub(g, s) ? 0u : kInf;
       I.phase = deg_s > 0 ? PH_ROUND : PH_DONE;
       if (deg_s == 0) record_clean_end(I);
+      // first tick: the source alone
+      for (int sg = 0; sg < kMaxSegPerInst; ++sg) {
+        I.spec_cnt[sg] = 0;
+        I.spec_kind[sg] = SEG_Q;
+        I.spec_pb[sg] = kRoundBatch;
+      }
+      I.spec_cnt[0] = I.nF;
     }
     __syncthreads();
     // gap(0) from whole-graph statistics: sumD(0) = nnz, highD(0)
@@ -1418,8 +1427,9 @@ __global__ void __launch_bounds__(kBlock) k_init_ctl(Globals* Gp) {
 // the uint32 range cannot hold.
 __global__ void k_overflow_check(Globals* Gp) {
   Globals& G = *Gp;
-  for (int i = 0; i < G.ninst; ++i) {
-    Inst& I = G.insts[i];
+  const int nsel = G.n_sel < 0 ? G.ninst : G.n_sel;
+  for (int j = 0; j < nsel; ++j) {
+    Inst& I = G.insts[G.n_sel < 0 ? j : G.sel_list[j]];
     if (!(I.flags.v & FLAG_MAYBE_OVERFLOW)) continue;
     const DevGraph& g = *I.g;
     bool found = false;
@@ -1435,6 +1445,16 @@ __global__ void k_overflow_check(Globals* Gp) {
       }
     }
     if (found) atomicOr(&I.flags.v, FLAG_OVERFLOW);
+  }
+}
+
+// Phase and flags of every instance, for a host that polls completions.
+__global__ void k_status(Globals* Gp, uint32_t* status) {
+  Globals& G = *Gp;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < G.ninst; i += gridDim.x * blockDim.x) {
+    const Inst& I = G.insts[i];
+    status[2 * i] = I.phase;
+    status[2 * i + 1] = I.flags.v | G.error;
   }
 }
 
@@ -1488,6 +1508,55 @@ hipError_t launch_engine(Globals* dG, int grid, bool persistent, int max_ticks, 
   void* args[] = {(void*)&dG, (void*)&pers, (void*)&max_ticks};
   return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_engine), dim3(grid), dim3(kBlock),
                                     args, 0, stream);
+}
+
+hipError_t launch_status(Globals* dG, int ninst, uint32_t* status, hipStream_t stream) {
+  int blocks = (ninst + kBlock - 1) / kBlock;
+  if (blocks < 1) blocks = 1;
+  k_status<<<blocks, kBlock, 0, stream>>>(dG, status);
+  return hipGetLastError();
+}
+
+hipError_t add_solve_nodes(hipGraph_t graph, hipGraphNode_t dep, Globals* dG, long long max_n, int grid,
+                           hipGraphNode_t* last) {
+  long long ib = (max_n + kBlock - 1) / kBlock;
+  ib = ib < 1 ? 1 : (ib > 16384 ? 16384 : ib);
+  long long ob = (max_n + kBlock - 1) / kBlock;
+  ob = ob < 1 ? 1 : (ob > 4096 ? 4096 : ob);
+  int pers = 1, max_ticks = 0;
+  void* a_g[] = {(void*)&dG};
+  void* a_e[] = {(void*)&dG, (void*)&pers, (void*)&max_ticks};
+  hipKernelNodeParams p;
+  std::memset(&p, 0, sizeof(p));
+  p.blockDim = dim3(kBlock);
+  hipGraphNode_t n_arr, n_ctl, n_eng, n_ovf;
+  size_t nd = dep ? 1 : 0;
+  p.func = reinterpret_cast<void*>(k_init_arrays);
+  p.gridDim = dim3((unsigned)ib);
+  p.kernelParams = a_g;
+  hipError_t e = hipGraphAddKernelNode(&n_arr, graph, dep ? &dep : nullptr, nd, &p);
+  if (e != hipSuccess) return e;
+  p.func = reinterpret_cast<void*>(k_init_ctl);
+  p.gridDim = dim3(1);
+  e = hipGraphAddKernelNode(&n_ctl, graph, &n_arr, 1, &p);
+  if (e != hipSuccess) return e;
+  p.func = reinterpret_cast<void*>(k_engine);
+  p.gridDim = dim3((unsigned)grid);
+  p.kernelParams = a_e;
+  e = hipGraphAddKernelNode(&n_eng, graph, &n_ctl, 1, &p);
+  if (e != hipSuccess) return e;
+  hipKernelNodeAttrValue v;
+  std::memset(&v, 0, sizeof(v));
+  v.cooperative = 1;
+  e = hipGraphKernelNodeSetAttribute(n_eng, hipKernelNodeAttributeCooperative, &v);
+  if (e != hipSuccess) return e;
+  p.func = reinterpret_cast<void*>(k_overflow_check);
+  p.gridDim = dim3((unsigned)ob);
+  p.kernelParams = a_g;
+  e = hipGraphAddKernelNode(&n_ovf, graph, &n_eng, 1, &p);
+  if (e != hipSuccess) return e;
+  *last = n_ovf;
+  return hipSuccess;
 }
 
 hipError_t launch_overflow_check(Globals* dG, long long max_n, hipStream_t stream) {
