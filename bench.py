@@ -79,6 +79,173 @@ def measured_traffic(workload: str):
             + float(vals["engine_write_kib"]) * 1024.0 * f_write)
 
 
+def batched_section(args, sssp, torch, np, graphgen):
+    """64 sources on RMAT-22 in one graph-captured persistent launch, and 256
+    small R-MAT graphs (scales 10..16) in another; knobs picked by the
+    autotuner. Parity by the oracle's invariant checker (complete for w >= 1)."""
+    from oracle import native  # invariant checker and CPU baseline only
+    res = {}
+    wl = graphgen.workload("rmat22")
+    c = wl.csr
+    g = sssp.Graph.from_csr(c)
+    k = 64
+    srcs = [int(s) for s in wl.sources(4 * k)]
+    t = time.perf_counter()
+    tuned, rep = sssp.autotune([g] * k, srcs[:k], batched=True)
+    tune_s = time.perf_counter() - t
+    outs = [torch.empty(c.n, dtype=torch.uint32, device="cuda") for _ in range(k)]
+    plan = sssp.Plan([g] * k, outs, **tuned)
+    plan.run(srcs[:k])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in range(1, 4):
+        plan.run(srcs[r * k:(r + 1) * k])
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / 3
+    last = srcs[3 * k:4 * k]
+    ok = all(sum(native.check_sssp(c.n, c.rowptr, c.col, c.w, last[i], outs[i].cpu().numpy())) == 0
+             for i in (0, 21, 42, 63))
+    one = torch.empty(c.n, dtype=torch.uint32, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in last:
+        g.solve(s, out=one)
+    torch.cuda.synchronize()
+    dt1 = time.perf_counter() - t0
+    res["rmat22_64_sources"] = {
+        "queries_per_s": round(k / dt, 1), "ms_per_batch": round(dt * 1e3, 3),
+        "one_at_a_time_queries_per_s": round(k / dt1, 1), "speedup": round(dt1 / dt, 2),
+        "tuned": tuned, "tune_s": round(tune_s, 2), "tune_default_us": round(rep["default_us"], 1),
+        "tune_best_us": round(rep["best_us"], 1), "checked_rows_exact": bool(ok)}
+    log("batched RMAT-22 x64: %.1f q/s (one at a time %.1f q/s), tuned %s" % (k / dt, k / dt1, tuned))
+    if not args.no_cpu_baseline:
+        threads = max(1, min(16, os.cpu_count() or 1))
+        adj = native.Adjacency(wl.edges.n, wl.edges.src, wl.edges.dst, wl.edges.w)
+        sample = last[:16]
+        t0 = time.perf_counter()
+        ref = adj.dijkstra_many(sample, threads)
+        dtc = time.perf_counter() - t0
+        adj.close()
+        ok_c = bool(np.array_equal(ref[0], outs[0].cpu().numpy()))
+        res["rmat22_64_sources"]["cpu_baseline"] = {
+            "value": round(len(sample) / dtc, 3), "unit": "queries/s", "cores": threads, "kind": "oracle",
+            "sample": "binary-heap Dijkstra (the oracle), %d sources of the same graph on a %d-thread "
+                      "pool, %.1f s; first row equals the GPU's: %s" % (len(sample), threads, dtc, ok_c)}
+    del outs, plan, one
+    g.close()
+
+    batch = graphgen.small_rmat_batch()
+    gs = [sssp.Graph.from_csr(w.csr) for w in batch]
+    ss = [[int(x) for x in w.sources(4)] for w in batch]
+    tuned2, rep2 = sssp.autotune(gs, [s[0] for s in ss], batched=True)
+    outs = [torch.empty(w.csr.n, dtype=torch.uint32, device="cuda") for w in batch]
+    plan = sssp.Plan(gs, outs, **tuned2)
+    plan.run([s[0] for s in ss])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in range(1, 4):
+        plan.run([s[r] for s in ss])
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / 3
+    ok = all(sum(native.check_sssp(batch[i].csr.n, batch[i].csr.rowptr, batch[i].csr.col, batch[i].csr.w,
+                                   ss[i][3], outs[i].cpu().numpy())) == 0 for i in (0, 85, 170, 255))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for gg, s, o in zip(gs, ss, outs):
+        gg.solve(s[3], out=o)
+    torch.cuda.synchronize()
+    dt1 = time.perf_counter() - t0
+    res["rmat10to16_256_graphs"] = {
+        "queries_per_s": round(len(gs) / dt, 1), "ms_per_batch": round(dt * 1e3, 3),
+        "one_at_a_time_queries_per_s": round(len(gs) / dt1, 1), "speedup": round(dt1 / dt, 2),
+        "tuned": tuned2, "checked_rows_exact": bool(ok)}
+    log("batched 256 small graphs: %.1f q/s (one at a time %.1f q/s)" % (len(gs) / dt, len(gs) / dt1))
+    plan.close()
+    for gg in gs:
+        gg.close()
+    return res
+
+
+def served_section(args, sssp, torch, np, graphgen):
+    """Poisson stream of single-source queries over resident graphs (RMAT-20,
+    RMAT-22, RMAT-23 and the 2048 x 2048 road-like grid), graph uniform per
+    query, served with continuous batching; against plain one-at-a-time FIFO
+    solves of the same trace (service times measured solo, queueing applied)."""
+    names = ["rmat20", "rmat22", "rmat23", "grid2048"]
+    wls = [graphgen.workload(nm) for nm in names]
+    gs = [sssp.Graph.from_csr(w.csr) for w in wls]
+    N = args.serve_queries
+    pools = [[int(x) for x in w.sources(N)] for w in wls]
+    # capacity of one-at-a-time solves on this mix
+    one = [torch.empty(w.csr.n, dtype=torch.uint32, device="cuda") for w in wls]
+    cal = []
+    for gi, gg in enumerate(gs):
+        for s in pools[gi][-2:]:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            gg.solve(s, out=one[gi])
+            torch.cuda.synchronize()
+            cal.append(time.perf_counter() - t0)
+    mean_service = sum(cal) / len(cal)
+    rate = args.serve_load / mean_service
+    arrivals, which = graphgen.poisson_trace(N, rate, len(gs))
+    queries = [(int(which[q]), pools[int(which[q])][q]) for q in range(N)]
+    # plain: each query alone, in arrival order, one at a time
+    solo = []
+    service = []
+    for gi, s in queries:
+        o = torch.empty(wls[gi].csr.n, dtype=torch.uint32, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        gs[gi].solve(s, out=o)
+        torch.cuda.synchronize()
+        service.append(time.perf_counter() - t0)
+        solo.append(o)
+    fin = 0.0
+    fifo_lat = []
+    for a, sv in zip(arrivals, service):
+        fin = max(fin, a) + sv
+        fifo_lat.append(fin - a)
+    fifo_span = fin - arrivals[0]
+    # served
+    srv = sssp.Server(budget_bytes=args.serve_budget_gib << 30, max_batch=args.serve_slots,
+                      ticks_per_launch=args.serve_ticks)
+    ids = [srv.add_graph(gg) for gg in gs]
+    outs = [torch.empty(wls[gi].csr.n, dtype=torch.uint32, device="cuda") for gi, _ in queries]
+    tickets = []
+    t0 = time.perf_counter()
+    for q, (gi, s) in enumerate(queries):
+        delay = arrivals[q] - (time.perf_counter() - t0)
+        if delay > 0:
+            time.sleep(delay)
+        tickets.append(srv.submit(ids[gi], s, outs[q]))
+    for t in tickets:
+        srv.wait(t)
+    infos = [srv.info(t) for t in tickets]
+    st = srv.stats()
+    srv.close()
+    lat = [(i["done_us"] - i["submit_us"]) * 1e-6 for i in infos]
+    span = (max(i["done_us"] for i in infos) - min(i["submit_us"] for i in infos)) * 1e-6
+    same = all(bool(torch.equal(a, b)) for a, b in zip(outs, solo))
+    pct = lambda xs, p: float(np.percentile(np.asarray(xs), p) * 1e3)
+    res = {
+        "queries": N, "graphs": names, "arrival_rate_per_s": round(rate, 2),
+        "load_vs_one_at_a_time_capacity": args.serve_load,
+        "queries_per_s": round(N / span, 2), "p50_ms": round(pct(lat, 50), 2),
+        "p99_ms": round(pct(lat, 99), 2),
+        "plain_fifo": {"queries_per_s": round(N / fifo_span, 2), "p50_ms": round(pct(fifo_lat, 50), 2),
+                       "p99_ms": round(pct(fifo_lat, 99), 2)},
+        "peak_in_flight": st["peak_active"], "engine_launches": st["launches"],
+        "budget_bytes": st["budget_bytes"], "peak_in_use_bytes": st["peak_in_use_bytes"],
+        "results_equal_alone_and_in_mix": same}
+    log("served: %.2f q/s p50 %.1f ms p99 %.1f ms (plain FIFO %.2f q/s p50 %.1f p99 %.1f); equal: %s"
+        % (N / span, res["p50_ms"], res["p99_ms"], N / fifo_span, res["plain_fifo"]["p50_ms"],
+           res["plain_fifo"]["p99_ms"], same))
+    for gg in gs:
+        gg.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,6 +253,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="rmat24")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched measurements")
+    ap.add_argument("--no-served", action="store_true", help="skip the served measurements")
+    ap.add_argument("--serve-queries", type=int, default=128)
+    ap.add_argument("--serve-load", type=float, default=0.8,
+                    help="arrival rate as a fraction of the one-at-a-time capacity of the mix")
+    ap.add_argument("--serve-slots", type=int, default=64)
+    ap.add_argument("--serve-ticks", type=int, default=64)
+    ap.add_argument("--serve-budget-gib", type=int, default=64)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with three 1 GiB device-to-device copies (reference kernel for "
                          "scaling the FETCH_SIZE / WRITE_SIZE counters)")
@@ -190,6 +365,16 @@ def main():
         del a, b
         log("calibration copies done (3 x 1 GiB)")
 
+    batched = None
+    served = None
+    if wl.name == "rmat24":
+        del outs
+        g.close()
+        if not args.no_batched:
+            batched = batched_section(args, sssp, torch, np, graphgen)
+        if not args.no_served:
+            served = served_section(args, sssp, torch, np, graphgen)
+
     traffic = measured_traffic(wl.name)
     config = {"workload": "rmat24-plain-sssp" if wl.name == "rmat24" else wl.name,
               "n": csr.n, "nnz": csr.nnz, "sources": K, "seed": wl.seed,
@@ -220,6 +405,8 @@ def main():
                      "kernel": "k_engine", "kernel_us_mean": round(eng_mean_us, 2),
                      "alg_bytes_per_launch": int(sum(B) / len(B))},
         "cpu_baseline": cpu,
+        "batched": batched,
+        "served": served,
         "prep_s": round(prep_s, 4),
         "counters": counters,
     }

@@ -235,3 +235,27 @@ def workload(name: str, scale: Optional[int] = None) -> Workload:
     else:
         raise ValueError("unknown workload %r" % name)
     return Workload(name, el, to_csr(el), seed)
+
+
+def small_rmat_batch(count: int = 256, lo: int = 10, hi: int = 16) -> list:
+    """The batch of small graphs: `count` R-MAT graphs (edge factor 16, the same
+    (a, b, c), w in 1..255) with scales drawn uniformly from lo..hi, one source
+    each. Returns a list of Workload."""
+    rng = np.random.default_rng(SEED_BASE + 6)
+    scales = rng.integers(lo, hi + 1, size=count)
+    out = []
+    for i, sc in enumerate(scales):
+        seed = SEED_BASE + 1000 + i
+        el = rmat(int(sc), 16, 0.57, 0.19, 0.19, 255, seed)
+        out.append(Workload("rmat%d_b%d" % (int(sc), i), el, to_csr(el), seed))
+    return out
+
+
+def poisson_trace(count: int, rate: float, n_graphs: int, seed: int = SEED_BASE + 7) -> tuple:
+    """A query trace: arrival times (seconds, Poisson process of the given
+    rate) and the graph index of each query (uniform over n_graphs)."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate, size=count)
+    arrivals = np.cumsum(gaps) - gaps[0]
+    which = rng.integers(0, n_graphs, size=count)
+    return arrivals, which
