@@ -16,7 +16,7 @@ constexpr uint32_t kRingMax = 65536;     // exact selection-threshold window up 
 constexpr int kLdsRing = 1024;           // settle: distance bins privatised in LDS
 constexpr int kLdsHist = 1024;           // settle: degree ranks privatised in LDS
 constexpr int kHeavyChunk = 256;         // edges per heavy chunk
-constexpr int kDefaultHeavy = 1024;      // ranges longer than this are split
+constexpr int kDefaultHeavy = 64;        // ranges longer than this are split
 constexpr int kStageCap = 1280;          // LDS staging of list appends per workgroup batch
 constexpr int kItemsPerThread = 4;       // round batches: items per thread
 constexpr int kRoundBatch = kBlock * kItemsPerThread;  // items per workgroup batch
@@ -38,11 +38,11 @@ struct DevGraph {
   const int32_t* rowptr;     // n + 1
   const uint64_t* adj;       // nnz entries, (weight << 32) | column, each row ascending
   const uint32_t* wmin;      // n: smallest weight of the row (kInf for degree 0)
-  const int32_t* drank;      // n: index of deg(v) among the distinct degrees (-1 for 0)
+  const uint64_t* dinfo;     // n: (index of deg(v) among the distinct degrees, -1 for 0) << 32 | deg(v)
   const int32_t* deg_vals;   // D ascending distinct degrees
   const uint32_t* deg_cnt0;  // D: vertices with that degree
   const uint32_t* hub_bits;  // ceil(n/32) words: deg(v) >= highD(0)
-  const int32_t* nonisolated;  // n_nonisolated vertex ids, ascending
+  const uint64_t* nonisolated;  // n_nonisolated entries (wmin << 32) | id, ascending id
   const uint32_t* rtow;      // 4096
 };
 
@@ -107,7 +107,7 @@ struct Inst {
   int32_t* touched;
   int32_t* settled;
   int32_t* plist[2];
-  int32_t* ulist[2];
+  uint64_t* ulist[2];      // unsettled (pull) list entries (wmin << 32) | id
   HeavyItem* heavy[2];
   uint64_t* ring_mass;
   uint32_t* ring_cnt;

@@ -455,6 +455,39 @@ __device__ __forceinline__ void stage_append(int32_t* buf, int32_t* cnt, bool wa
   if (want) buf[base + __popcll(m & lanemask_lt())] = val;
 }
 
+// Convergent within a wave: a (lo, hi) pair takes one slot of q / t (the
+// pull phase stages its surviving unsettled-list entries this way).
+__device__ __forceinline__ void stage_append_pair(StageLds& S, bool want, int32_t lo, int32_t hi) {
+  uint64_t m = __ballot(want);
+  if (m == 0) return;
+  int base = 0;
+  const int leader = __ffsll((unsigned long long)m) - 1;
+  if (lane_id() == leader) base = atomicAdd(&S.nq, __popcll(m));
+  base = __shfl(base, leader, kWave);
+  if (want) {
+    const int pos = base + __popcll(m & lanemask_lt());
+    S.q[pos] = lo;
+    S.t[pos] = hi;
+  }
+}
+
+// Whole workgroup: write the staged pairs as (hi << 32) | lo entries.
+__device__ void stage_flush_pairs(StageLds& S, uint64_t* list, int32_t* cnt, int cap, uint32_t* flags) {
+  __syncthreads();
+  const int np = S.nq;
+  if (threadIdx.x == 0) {
+    S.base_q = np ? atomicAdd(cnt, np) : 0;
+    if (S.base_q + np > cap) atomicOr(flags, FLAG_CAPACITY);
+  }
+  __syncthreads();
+  const int b = S.base_q;
+  for (int i = threadIdx.x; i < np; i += kBlock)
+    if (b + i < cap) list[b + i] = ((uint64_t)(uint32_t)S.t[i] << 32) | (uint64_t)(uint32_t)S.q[i];
+  __syncthreads();
+  if (threadIdx.x == 0) S.nq = 0;
+  __syncthreads();
+}
+
 // Whole workgroup: copy the staged entries to their lists.
 __device__ void stage_flush(StageLds& S, int32_t* qlist, int32_t* qcnt, int32_t* tlist, int32_t* tcnt,
                             int cap, uint32_t* flags) {
@@ -530,6 +563,7 @@ __device__ void emit_heavy(Inst& I, int u, uint32_t d, int lo, int hi, bool pull
 struct RoundLds {
   int32_t u[kRoundBatch];
   uint32_t d[kRoundBatch];
+  uint32_t pmin[kRoundBatch];  // pull items: best candidate for dist[u] found in this batch
   int32_t lo[kRoundBatch];
   int32_t sz[kRoundBatch];  // size, -1 = range still to find; then exclusive offsets
   uint8_t pull[kRoundBatch];
@@ -594,32 +628,40 @@ __device__ __noinline__ void block_round(Inst& I, int kind, int item0, int nitem
     }
     lds_push_item(L, want, u, d, lo, sz, pull);
   } else if (kind == SEG_U) {
+    // unsettled-list entries carry the row's smallest weight: an entry whose
+    // lightest edge cannot reach below ub from a settled vertex (>= st) is
+    // kept without reading its distance
     const int usel = I.usel;
-    const int32_t* ucur = usel < 0 ? I.g->nonisolated : I.ulist[usel];
-    int32_t* unext = I.ulist[usel < 0 ? 0 : (usel ^ 1)];
-    int uu[kItemsPerThread];
+    const uint64_t* ucur = usel < 0 ? I.g->nonisolated : I.ulist[usel];
+    uint64_t* unext = I.ulist[usel < 0 ? 0 : (usel ^ 1)];
+    const uint32_t reach = ub - st;
+    uint64_t ee[kItemsPerThread];
 #pragma unroll
     for (int k = 0; k < kItemsPerThread; ++k) {
       const int it = item0 + k * kBlock + tid;
-      uu[k] = it < nitems ? ucur[it] : -1;
+      ee[k] = it < nitems ? ucur[it] : ~0ull;
     }
-    uint32_t dd[kItemsPerThread], wm[kItemsPerThread];
+    uint32_t dd[kItemsPerThread];
 #pragma unroll
     for (int k = 0; k < kItemsPerThread; ++k) {
-      dd[k] = uu[k] >= 0 ? V.dist[uu[k]] : 0u;
-      wm[k] = uu[k] >= 0 ? V.wmin[uu[k]] : kInf;
+      const bool valid = ee[k] != ~0ull;
+      const bool cand = valid && (uint32_t)(ee[k] >> 32) < reach;
+      dd[k] = cand ? V.dist[(int)(uint32_t)ee[k]] : 0u;
     }
 #pragma unroll
     for (int k = 0; k < kItemsPerThread; ++k) {
-      const int u = uu[k];
-      const bool keep = u >= 0 && dd[k] >= lb;
-      const bool active = u >= 0 && dd[k] > lb && wm[k] < ub - st;
-      acc.pvert += u >= 0 ? 1 : 0;
-      stage_append(S.t, &S.nt, keep, u);
+      const bool valid = ee[k] != ~0ull;
+      const int u = (int)(uint32_t)ee[k];
+      const uint32_t wm = (uint32_t)(ee[k] >> 32);
+      const bool cand = valid && wm < reach;
+      const bool keep = valid && (!cand || dd[k] >= lb);
+      const bool active = cand && dd[k] > lb;
+      acc.pvert += valid ? 1 : 0;
+      stage_append_pair(S, keep, u, (int32_t)wm);
       lds_push_item(L, active, u, dd[k], 0, -1, true);
     }
     // the surviving pull list goes out now; the stage is free for phase 2
-    stage_flush(S, nullptr, &S.base_q, unext, &I.u_next_cnt.v, V.n, &I.flags.v);
+    stage_flush_pairs(S, unext, &I.u_next_cnt.v, V.n, &I.flags.v);
   } else {
     int uu[kItemsPerThread];
     const int32_t* src = (kind == SEG_W) ? I.settled + I.wBegin
@@ -654,35 +696,136 @@ __device__ __noinline__ void block_round(Inst& I, int kind, int item0, int nitem
   }
   __syncthreads();
   const int m = L.count;
+  for (int w = tid; w < m; w += kBlock) L.pmin[w] = kInf;
 
   // ---------------------------------------------------------- phase 2a: ranges
-  for (int w = tid; w < m; w += kBlock) {
-    if (L.sz[w] >= 0) continue;  // heavy chunk: known
-    const int u = L.u[w];
-    const uint32_t d = L.d[w];
-    const bool pull = L.pull[w] != 0;
-    const int rs = V.rowptr[u], re = V.rowptr[u + 1];
-    int lo = rs, hi = rs;
-    if (pull) {
-      hi = range_end(V.adj, rs, re, (uint64_t)(ub - st) << 32);
-      acc.pullscan += (unsigned long long)(hi - lo);
-    } else if (!(re - rs == 1 && d > 0)) {  // leaf pruning (Algorithm)
+  // Each thread finds the ranges of its kItemsPerThread items together: the
+  // row bounds of all of them are loaded at once, and their binary searches
+  // advance in lockstep, so the loads of one step are in flight together.
+  {
+    int wi[kItemsPerThread], a[kItemsPerThread], b[kItemsPerThread], rs[kItemsPerThread],
+        re[kItemsPerThread];
+    uint32_t wmn[kItemsPerThread];
+    uint64_t key[kItemsPerThread];
+    bool need[kItemsPerThread];  // item whose range this thread has to find
+    bool leaf[kItemsPerThread];
+#pragma unroll
+    for (int k = 0; k < kItemsPerThread; ++k) {
+      wi[k] = tid + k * kBlock;
+      need[k] = wi[k] < m && L.sz[wi[k]] < 0;  // heavy chunks come with their range
+      rs[k] = re[k] = 0;
+      wmn[k] = 0;
+      if (need[k]) {
+        const int u = L.u[wi[k]];
+        rs[k] = V.rowptr[u];
+        re[k] = V.rowptr[u + 1];
+        wmn[k] = V.wmin[u];
+      }
+    }
+    // range start: the pull scans the row's prefix; a push starts at the
+    // first weight >= lb - d (binary search unless the row starts there)
+#pragma unroll
+    for (int k = 0; k < kItemsPerThread; ++k) {
+      a[k] = b[k] = rs[k];
+      key[k] = 0;
+      leaf[k] = false;
+      if (!need[k]) continue;
+      const uint32_t d = L.d[wi[k]];
+      if (L.pull[wi[k]]) continue;
+      leaf[k] = (re[k] - rs[k] == 1 && d > 0);  // leaf pruning (Algorithm)
       const uint32_t wl = lb > d ? lb - d : 0u;
-      const uint32_t wh = ub - d;
-      lo = (wl <= V.wmin[u]) ? rs : lower_bound_key(V.adj, rs, re, (uint64_t)wl << 32);
-      hi = range_end(V.adj, lo, re, (uint64_t)wh << 32);
-      if (ub == kInf && hi < re) atomicOr(&I.flags.v, FLAG_MAYBE_OVERFLOW);
-      acc.expansions += 1;
-      acc.band += (d >= lb) ? 1 : 0;
-      acc.pscan += (unsigned long long)(hi - lo);
+      if (!leaf[k] && wl > wmn[k]) {
+        b[k] = re[k];
+        key[k] = (uint64_t)wl << 32;
+      }
     }
-    int size = hi - lo;
-    if (size > V.heavy_split) {
-      emit_heavy(I, u, d, lo, hi, pull);
-      size = 0;
+    for (;;) {
+      int mid[kItemsPerThread];
+      uint64_t val[kItemsPerThread];
+      bool any = false;
+#pragma unroll
+      for (int k = 0; k < kItemsPerThread; ++k) {
+        if (a[k] < b[k]) {
+          mid[k] = (a[k] + b[k]) >> 1;
+          val[k] = V.adj[mid[k]];
+          any = true;
+        }
+      }
+      if (!any) break;
+#pragma unroll
+      for (int k = 0; k < kItemsPerThread; ++k) {
+        if (a[k] < b[k]) {
+          if (val[k] < key[k]) a[k] = mid[k] + 1; else b[k] = mid[k];
+        }
+      }
     }
-    L.lo[w] = lo;
-    L.sz[w] = size;
+    // range end: the first weight >= the bound (ub - st for a pull, ub - d
+    // for a push); the next kProbe entries are read at once, then bisection
+    int lo[kItemsPerThread], hi[kItemsPerThread];
+#pragma unroll
+    for (int k = 0; k < kItemsPerThread; ++k) {
+      lo[k] = a[k];
+      hi[k] = a[k];
+      key[k] = 0;
+      if (!need[k] || leaf[k]) continue;
+      const uint32_t bound = L.pull[wi[k]] ? ub - st : ub - L.d[wi[k]];
+      key[k] = (uint64_t)bound << 32;
+      const int lim = min(re[k], lo[k] + kProbe);
+      int cnt = 0;
+#pragma unroll
+      for (int i2 = 0; i2 < kProbe; ++i2)
+        if (lo[k] + i2 < lim) cnt += V.adj[lo[k] + i2] < key[k] ? 1 : 0;
+      hi[k] = lo[k] + cnt;
+      // a full probe that did not reach the row's end continues by bisection
+      a[k] = b[k] = 0;
+      if (!(lo[k] + cnt < lim || lim == re[k])) {
+        a[k] = lim;
+        b[k] = re[k];
+      }
+    }
+    for (;;) {
+      int mid[kItemsPerThread];
+      uint64_t val[kItemsPerThread];
+      bool any = false;
+#pragma unroll
+      for (int k = 0; k < kItemsPerThread; ++k) {
+        if (a[k] < b[k]) {
+          mid[k] = (a[k] + b[k]) >> 1;
+          val[k] = V.adj[mid[k]];
+          any = true;
+        }
+      }
+      if (!any) break;
+#pragma unroll
+      for (int k = 0; k < kItemsPerThread; ++k) {
+        if (a[k] < b[k]) {
+          if (val[k] < key[k]) a[k] = mid[k] + 1; else b[k] = mid[k];
+          if (a[k] >= b[k]) hi[k] = a[k];
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kItemsPerThread; ++k) {
+      if (!need[k]) continue;
+      const int w = wi[k];
+      const bool pull = L.pull[w] != 0;
+      const uint32_t d = L.d[w];
+      if (pull) {
+        acc.pullscan += (unsigned long long)(hi[k] - lo[k]);
+      } else if (!leaf[k]) {
+        if (ub == kInf && hi[k] < re[k]) atomicOr(&I.flags.v, FLAG_MAYBE_OVERFLOW);
+        acc.expansions += 1;
+        acc.band += (d >= lb) ? 1 : 0;
+        acc.pscan += (unsigned long long)(hi[k] - lo[k]);
+      }
+      int size = hi[k] - lo[k];
+      if (size > V.heavy_split) {
+        emit_heavy(I, L.u[w], d, lo[k], hi[k], pull);
+        size = 0;
+      }
+      L.lo[w] = lo[k];
+      L.sz[w] = size;
+    }
   }
   __syncthreads();
 
@@ -735,19 +878,36 @@ __device__ __noinline__ void block_round(Inst& I, int kind, int item0, int nitem
           ok = c < old;
         }
       } else {
+        // pull: the best candidate of u over this batch's edges, in LDS
         const uint32_t dv = V.dist[v];
         if (dv >= st && dv < lb) {
           unsigned long long cc = (unsigned long long)dv + w;
-          if (cc < ub && cc < dj) {
-            c = (uint32_t)cc;
-            t = L.u[j];
-            uint32_t old = atomicMin(&V.dist[t], c);
-            ok = c < old;
-          }
+          if (cc < ub && cc < dj) atomicMin(&L.pmin[j], (uint32_t)cc);
         }
       }
     }
     on_success(V, ok, t, c, acc, S);
+  }
+  if (any_pull) {
+    // one device atomic per pulled vertex
+    for (int base = 0; base < m; base += kBlock) {
+      __syncthreads();
+      if (S.nq > kStageCap - kBlock || S.nt > kStageCap - kBlock)
+        stage_flush(S, qnext, &I.q_next_cnt.v, V.touched, &I.touched_cnt.v, V.n, &I.flags.v);
+      const int w = base + tid;
+      bool ok = false;
+      int t = 0;
+      uint32_t c = 0;
+      if (w < m && L.pull[w]) {
+        c = L.pmin[w];
+        if (c < L.d[w]) {
+          t = L.u[w];
+          uint32_t old = atomicMin(&V.dist[t], c);
+          ok = c < old;
+        }
+      }
+      on_success(V, ok, t, c, acc, S);
+    }
   }
   stage_flush(S, qnext, &I.q_next_cnt.v, V.touched, &I.touched_cnt.v, V.n, &I.flags.v);
   flush_acc(I, V.maxw, acc);
@@ -782,8 +942,7 @@ __device__ __noinline__ void block_settle(Inst& I, int kind, int item0, int nite
   const uint32_t band = ub - lb;
   const uint32_t nb = band < (uint32_t)kLdsRing ? band : (uint32_t)kLdsRing;
   const int nh = g.num_deg < kLdsHist ? g.num_deg : kLdsHist;
-  const int32_t* rowptr = g.rowptr;
-  const int32_t* drank = g.drank;
+  const uint64_t* dinfo = g.dinfo;
   uint32_t* dist = I.dist;
   uint64_t* ring_mass = I.ring_mass;
   uint32_t* ring_cnt = I.ring_cnt;
@@ -801,20 +960,25 @@ __device__ __noinline__ void block_settle(Inst& I, int kind, int item0, int nite
   const int it = item0 + tid;
   int v = -1;
   uint32_t d = kInf;
+  uint64_t di = 0;
   if (it < nitems) {
     if (kind == SEG_ST) {
       v = touched[it];
     } else {
       v = pcur[it];
     }
-    if (v >= 0) d = dist[v];
+    if (v >= 0) {
+      // both loads in flight together: one round trip per vertex
+      d = dist[v];
+      di = dinfo[v];
+    }
   }
   bool settle = (kind == SEG_ST) && v >= 0 && d < ub;
   bool pend = v >= 0 && d >= ub;
   unsigned long long sdec = 0;
   uint32_t maxd = 0;
   if (settle) {
-    int deg = rowptr[v + 1] - rowptr[v];
+    const int deg = (int)(uint32_t)di;
     uint32_t off = d - lb;
     // only the window [ub - M, ub) is read by the next computeST; the first
     // step's band may be wider, and older values would alias ring slots
@@ -827,7 +991,7 @@ __device__ __noinline__ void block_settle(Inst& I, int kind, int item0, int nite
         atomicAdd(&ring_cnt[d & ring_mask], 1u);
       }
     }
-    int r = drank[v];
+    const int r = (int)(di >> 32);
     if (r >= 0) {
       if (r < nh) atomicAdd(&L.hist[r], 1u); else atomicSub(&hist_cnt[r], 1u);
     }
@@ -918,8 +1082,9 @@ __device__ __noinline__ void fused_rounds(Inst& I, RoundLds& L) {
     __syncthreads();
     if (threadIdx.x == 0) {
       // the round's list appends and distance updates came from this
-      // workgroup's waves; the fence drops stale cached lines before reuse
-      __threadfence();
+      // workgroup's waves and sit in this XCD's L2; the acquire drops stale
+      // lines from this CU's cache before the next round reads them
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       const int nq = __hip_atomic_load(&I.q_next_cnt.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       const int nh = __hip_atomic_load(&I.h_next_cnt.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       const bool go = nh == 0 && nq > 0 && nq <= kRoundBatch;
@@ -1129,10 +1294,12 @@ __device__ __forceinline__ uint32_t xcd_of_this_wg() {
   return r & (uint32_t)(kMaxXcd - 1);
 }
 
-// A workgroup released by its XCD leader must drop stale lines: an L1-only
-// invalidate (the cross-CU workgroup acquire) is not enough here -- measured:
-// stale data was read -- so it takes the agent-scope acquire.
-__device__ __forceinline__ void acquire_after_release() { __threadfence(); }
+// A workgroup released by its XCD leader must drop stale cached lines. The
+// leader's own fence already wrote this XCD's L2 back and the workgroup's
+// stores reached that L2 before it arrived, so an agent-scope acquire (no
+// write-back) completes the release/acquire chain. (A workgroup-scope
+// invalidate is not enough: measured, stale data was read.)
+__device__ __forceinline__ void acquire_after_release() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
 
 __device__ bool spin_until_changed(unsigned int* word, unsigned int old, unsigned int* err) {
   unsigned long long spins = 0;
@@ -1266,7 +1433,7 @@ __device__ bool barrier_tick(Globals& G, BarrierState& B) {
   return s_ok != 0;
 }
 
-__global__ void __launch_bounds__(kBlock) k_engine(Globals* Gp, int persistent, int max_ticks) {
+__global__ void __launch_bounds__(kBlock, 4) k_engine(Globals* Gp, int persistent, int max_ticks) {
   __shared__ BlockLds lds;
   __shared__ BarrierState s_b;
   Globals& G = *Gp;

@@ -256,7 +256,7 @@ __global__ void __launch_bounds__(kBlock) k_deg_count(const int32_t* rowptr, int
 }
 
 __global__ void k_deg_rank(const int32_t* rowptr, int32_t n, const int32_t* rank_small,
-                           const int32_t* deg_vals, int32_t D, int32_t* drank, uint32_t* wmin,
+                           const int32_t* deg_vals, int32_t D, uint64_t* dinfo, uint32_t* wmin,
                            const uint64_t* adj) {
   for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < n;
        v += (long long)gridDim.x * blockDim.x) {
@@ -273,7 +273,7 @@ __global__ void k_deg_rank(const int32_t* rowptr, int32_t n, const int32_t* rank
       }
       r = lo;
     }
-    drank[v] = r;
+    dinfo[v] = ((uint64_t)(uint32_t)r << 32) | (uint64_t)(uint32_t)d;
     wmin[v] = d > 0 ? (uint32_t)(adj[a] >> 32) : kInf;
   }
 }
@@ -292,8 +292,9 @@ __global__ void k_hub_bits(const int32_t* rowptr, int32_t n, uint32_t hd, uint32
   }
 }
 
-// Ordered compaction of the vertices with degree >= 1: per-block counts,
-// then per-block writes at the scanned offsets.
+// Ordered compaction of the vertices with degree >= 1, each packed with the
+// smallest weight of its row as (wmin << 32) | id: per-block counts, then
+// per-block writes at the scanned offsets.
 constexpr int kCompactPer = kBlock * 8;
 
 __global__ void __launch_bounds__(kBlock) k_noniso_count(const int32_t* rowptr, int32_t n, int32_t* bcnt) {
@@ -311,8 +312,8 @@ __global__ void __launch_bounds__(kBlock) k_noniso_count(const int32_t* rowptr, 
   if (threadIdx.x == 0) bcnt[blockIdx.x] = s;
 }
 
-__global__ void __launch_bounds__(kBlock) k_noniso_write(const int32_t* rowptr, int32_t n,
-                                                         const int32_t* boff, int32_t* out) {
+__global__ void __launch_bounds__(kBlock) k_noniso_write(const int32_t* rowptr, const uint32_t* wmin,
+                                                         int32_t n, const int32_t* boff, uint64_t* out) {
   __shared__ int wsum[kBlock / kWave];
   __shared__ int run;
   if (threadIdx.x == 0) run = boff[blockIdx.x];
@@ -328,7 +329,7 @@ __global__ void __launch_bounds__(kBlock) k_noniso_write(const int32_t* rowptr, 
     __syncthreads();
     int woff = 0;
     for (int w2 = 0; w2 < wid; ++w2) woff += wsum[w2];
-    if (f) out[run + woff + pre] = (int32_t)v;
+    if (f) out[run + woff + pre] = ((uint64_t)wmin[v] << 32) | (uint64_t)(uint32_t)v;
     __syncthreads();
     if (threadIdx.x == 0) {
       int t = 0;
@@ -485,7 +486,7 @@ int prep_graph(int32_t n, const int32_t* rowptr_in, const int32_t* col_in, const
   int32_t* rowptr = A.get<int32_t>((size_t)n + 1);
   uint64_t* adj = A.get<uint64_t>((size_t)nnz);
   uint32_t* wmin = A.get<uint32_t>((size_t)n);
-  int32_t* drank = A.get<int32_t>((size_t)n);
+  uint64_t* dinfo = A.get<uint64_t>((size_t)n);
   uint32_t* hub = A.get<uint32_t>(((size_t)n + 31) / 32);
   uint32_t* rtow = A.get<uint32_t>(kRatioNum);
   if (!A.ok) {
@@ -699,7 +700,7 @@ int prep_graph(int32_t n, const int32_t* rowptr_in, const int32_t* col_in, const
     PREP_CHECK(hipMemcpy(d_deg_cnt, deg_cnt.data(), sizeof(uint32_t) * (size_t)D, hipMemcpyHostToDevice));
   }
   PREP_CHECK(hipMemcpy(d_rank_small, rank_small.data(), sizeof(int32_t) * kDegDirect, hipMemcpyHostToDevice));
-  k_deg_rank<<<grid_for(n), kBlock>>>(rowptr, n, d_rank_small, d_deg_vals, D, drank, wmin, adj);
+  k_deg_rank<<<grid_for(n), kBlock>>>(rowptr, n, d_rank_small, d_deg_vals, D, dinfo, wmin, adj);
   PREP_CHECK(hipGetLastError());
   uint32_t* d_h = T.get<uint32_t>(1);
   unsigned long long* d_mass = T.get<unsigned long long>(1);
@@ -736,13 +737,13 @@ int prep_graph(int32_t n, const int32_t* rowptr_in, const int32_t* col_in, const
     run += c;
   }
   const int32_t nonisolated = run;
-  int32_t* noniso = A.get<int32_t>(std::max<int32_t>(nonisolated, 1));
+  uint64_t* noniso = A.get<uint64_t>(std::max<int32_t>(nonisolated, 1));
   if (!A.ok) {
     *msg = "device allocation failed";
     return -5;
   }
   PREP_CHECK(hipMemcpy(bcnt, hb.data(), sizeof(int32_t) * (size_t)nb, hipMemcpyHostToDevice));
-  k_noniso_write<<<nb, kBlock>>>(rowptr, n, bcnt, noniso);
+  k_noniso_write<<<nb, kBlock>>>(rowptr, wmin, n, bcnt, noniso);
   PREP_CHECK(hipGetLastError());
 
   // ---- RtoW[x] = maxW(G, x / 4095): the ceil(x * nnz / 4095)-th smallest weight
@@ -804,7 +805,7 @@ int prep_graph(int32_t n, const int32_t* rowptr_in, const int32_t* col_in, const
   h.rowptr = rowptr;
   h.adj = adj;
   h.wmin = wmin;
-  h.drank = drank;
+  h.dinfo = dinfo;
   h.deg_vals = d_deg_vals;
   h.deg_cnt0 = d_deg_cnt;
   h.hub_bits = hub;
