@@ -206,6 +206,60 @@ struct Globals {
   int32_t pad_sel;
 };
 
+// Every pointer in these structures points to global memory. Device code
+// reads them through pointers of the global address space: loads through a
+// generic pointer are flat instructions, which count against both the vector
+// and the LDS wait counters, so every LDS access would also wait for the
+// outstanding global loads.
+#define SSSP_GBL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ SSSP_GBL T* gbl(T* p) {
+  return (SSSP_GBL T*)p;
+}
+// whole-struct store into global memory (the implicit assignment operator
+// only takes generic objects)
+template <typename T>
+__device__ __forceinline__ void gstore(SSSP_GBL T* p, const T& v) {
+  *(T*)p = v;
+}
+// the HIP atomics on global-address-space pointers (the casts back to generic
+// pointers are folded: the instructions stay global atomics), beside HIP's own
+using ::atomicAdd;
+using ::atomicSub;
+using ::atomicMin;
+using ::atomicMax;
+using ::atomicOr;
+__device__ __forceinline__ int atomicAdd(SSSP_GBL int* p, int v) { return ::atomicAdd((int*)p, v); }
+__device__ __forceinline__ unsigned int atomicAdd(SSSP_GBL unsigned int* p, unsigned int v) {
+  return ::atomicAdd((unsigned int*)p, v);
+}
+__device__ __forceinline__ unsigned long long atomicAdd(SSSP_GBL unsigned long long* p, unsigned long long v) {
+  return ::atomicAdd((unsigned long long*)p, v);
+}
+__device__ __forceinline__ unsigned long atomicAdd(SSSP_GBL unsigned long* p, unsigned long v) {
+  return ::atomicAdd((unsigned long*)p, v);
+}
+__device__ __forceinline__ unsigned int atomicSub(SSSP_GBL unsigned int* p, unsigned int v) {
+  return ::atomicSub((unsigned int*)p, v);
+}
+__device__ __forceinline__ unsigned int atomicMin(SSSP_GBL unsigned int* p, unsigned int v) {
+  return ::atomicMin((unsigned int*)p, v);
+}
+__device__ __forceinline__ unsigned int atomicMax(SSSP_GBL unsigned int* p, unsigned int v) {
+  return ::atomicMax((unsigned int*)p, v);
+}
+__device__ __forceinline__ unsigned int atomicOr(SSSP_GBL unsigned int* p, unsigned int v) {
+  return ::atomicOr((unsigned int*)p, v);
+}
+// whole-struct load from global memory
+template <typename T>
+__device__ __forceinline__ T gload(const SSSP_GBL T* p) {
+  return *(const T*)p;
+}
+using GInst = SSSP_GBL Inst;
+using GGlobals = SSSP_GBL Globals;
+using GDevGraph = SSSP_GBL const DevGraph;
+
 // host launch wrappers (engine.hip)
 hipError_t launch_init(Globals* dG, long long max_n, hipStream_t stream);
 int engine_blocks_per_cu();

@@ -58,7 +58,7 @@ __device__ __forceinline__ uint32_t wave_min_u32(uint32_t x) {
   return x;
 }
 
-__device__ __forceinline__ int lower_bound_key(const uint64_t* __restrict__ adj, int lo, int hi,
+__device__ __forceinline__ int lower_bound_key(const SSSP_GBL uint64_t* __restrict__ adj, int lo, int hi,
                                                uint64_t key) {
   while (lo < hi) {
     int mid = (lo + hi) >> 1;
@@ -70,7 +70,7 @@ __device__ __forceinline__ int lower_bound_key(const uint64_t* __restrict__ adj,
 // First index in [lo, re) whose key is >= key. The next kProbe entries (one
 // or two cache lines) are read at once first; a binary search handles the rest.
 constexpr int kProbe = 8;
-__device__ __forceinline__ int range_end(const uint64_t* __restrict__ adj, int lo, int re, uint64_t key) {
+__device__ __forceinline__ int range_end(const SSSP_GBL uint64_t* __restrict__ adj, int lo, int re, uint64_t key) {
   const int lim = min(re, lo + kProbe);
   int cnt = 0;
 #pragma unroll
@@ -80,8 +80,8 @@ __device__ __forceinline__ int range_end(const uint64_t* __restrict__ adj, int l
   return lower_bound_key(adj, lim, re, key);
 }
 
-__device__ __forceinline__ bool is_hub(const DevGraph& g, int v) {
-  return (g.hub_bits[v >> 5] >> (v & 31)) & 1u;
+__device__ __forceinline__ bool is_hub(GDevGraph& g, int v) {
+  return (gbl(g.hub_bits)[v >> 5] >> (v & 31)) & 1u;
 }
 
 // --------------------------------------------------------- block helpers --
@@ -118,7 +118,7 @@ __device__ T block_excl_scan(T x, T* sh /* kBlock/kWave + 1 */, T* total) {
 // multiply-add (the file is compiled with -ffp-contract=off).
 
 __device__ uint32_t gap_of(unsigned long long S, uint32_t h, int32_t nnz, uint32_t M,
-                           const uint32_t* rtow, uint32_t alpha, double beta) {
+                           const SSSP_GBL uint32_t* rtow, uint32_t alpha, double beta) {
   uint32_t g;
   if (h <= alpha) {
     g = M;
@@ -162,7 +162,7 @@ struct HeurLds {
 // highD over a degree histogram (distinct degrees deg_vals[0..D) ascending,
 // cnt[r] vertices each): the threshold h minimising |mass(deg < h) -
 // mass(deg >= h)|, smallest on ties, 0 if no mass. Whole workgroup.
-__device__ uint32_t block_high_d(const int32_t* deg_vals, const uint32_t* cnt, int32_t D,
+__device__ uint32_t block_high_d(const SSSP_GBL int32_t* deg_vals, const SSSP_GBL uint32_t* cnt, int32_t D,
                                  unsigned long long* mass_total, HeurLds& L) {
   const int tid = threadIdx.x;
   const int chunk = (D + kBlock - 1) / kBlock;
@@ -197,7 +197,7 @@ __device__ uint32_t block_high_d(const int32_t* deg_vals, const uint32_t* cnt, i
 }
 
 // Function 2 (computeST) for the next pair <L, L + gap(L)>. Whole workgroup.
-__device__ uint32_t block_compute_st(const Inst& I, uint32_t L, uint32_t gapL, int32_t nnz,
+__device__ uint32_t block_compute_st(const GInst& I, uint32_t L, uint32_t gapL, int32_t nnz,
                                      HeurLds& lds) {
   const uint32_t M = I.M;
   const unsigned long long S = I.S.v;
@@ -213,7 +213,7 @@ __device__ uint32_t block_compute_st(const Inst& I, uint32_t L, uint32_t gapL, i
   // thread t owns x in [wlo + a, wlo + b), ascending
   const uint32_t a = min(W, (uint32_t)tid * chunk), b = min(W, a + chunk);
   unsigned long long local = 0;
-  for (uint32_t k = a; k < b; ++k) local += I.ring_mass[(wlo + k) & I.ring_mask];
+  for (uint32_t k = a; k < b; ++k) local += gbl(I.ring_mass)[(wlo + k) & I.ring_mask];
   unsigned long long total;
   unsigned long long before = block_excl_scan<unsigned long long>(local, lds.scan, &total);
   // mass at or above the end of my chunk: total - before - local
@@ -223,8 +223,8 @@ __device__ uint32_t block_compute_st(const Inst& I, uint32_t L, uint32_t gapL, i
   for (uint32_t k = b; k > a; --k) {
     uint32_t x = wlo + k - 1;
     uint32_t slot = x & I.ring_mask;
-    acc += I.ring_mass[slot];
-    if (I.ring_cnt[slot]) {
+    acc += gbl(I.ring_mass)[slot];
+    if (gbl(I.ring_cnt)[slot]) {
       double p = profit_of(x, L, Y, S, S + acc, M, nnz);
       // ascending order, first strict maximum: prefer larger p, then smaller x
       if (p > bp || (p == bp && p > 0.0 && x < bx)) {
@@ -254,19 +254,19 @@ __device__ uint32_t block_compute_st(const Inst& I, uint32_t L, uint32_t gapL, i
 
 // A solve that ends normally hands the next solve on this slot a stamp
 // counter above every stamp it wrote.
-__device__ void record_clean_end(Inst& I) { I.rid_slot[PW_RID] = I.rid + 1; }
+__device__ void record_clean_end(GInst& I) { gbl(I.rid_slot)[PW_RID] = I.rid + 1; }
 
 // The end-of-step heuristic for one instance: statistics at L = ub, gap(L),
 // computeST, step bookkeeping, termination test, and the next step's setup.
 // Runs on one workgroup, after every settle batch of the instance is done.
-__device__ __noinline__ void run_heuristic(Inst& I, HeurLds& lds) {
-  const DevGraph& g = *I.g;
+__device__ __noinline__ void run_heuristic(GInst& I, HeurLds& lds) {
+  GDevGraph& g = *gbl(I.g);
   const int tid = threadIdx.x;
   const uint32_t L = I.ub;
   unsigned long long mass;
-  uint32_t h = block_high_d(g.deg_vals, I.hist_cnt, g.num_deg, &mass, lds);
+  uint32_t h = block_high_d(gbl(g.deg_vals), gbl(I.hist_cnt), g.num_deg, &mass, lds);
   const unsigned long long S = I.S.v;
-  uint32_t gapL = gap_of(S, h, g.nnz, I.M, g.rtow, I.alpha, I.beta);
+  uint32_t gapL = gap_of(S, h, g.nnz, I.M, gbl(g.rtow), I.alpha, I.beta);
   uint32_t stn = block_compute_st(I, L, gapL, g.nnz, lds);
   if (tid == 0) {
     if (mass != S) I.flags.v |= FLAG_MASS;
@@ -275,13 +275,13 @@ __device__ __noinline__ void run_heuristic(Inst& I, HeurLds& lds) {
     rec.ub = L;
     rec.seg_begin = I.settled_mark;
     rec.seg_end = min(I.settled_cnt.v, I.n);
-    I.steprec[(uint32_t)I.nsteprec & I.steprec_mask] = rec;
+    gstore(gbl(I.steprec) + ((uint32_t)I.nsteprec & I.steprec_mask), rec);
     I.nsteprec += 1;
     if (I.trace_len < I.trace_cap) {
       TraceRec t;
       t.lb = I.lb; t.ub = L; t.st = I.st; t.rounds = I.rounds_in_step;
       t.pulled = I.pull_on; t.L = L; t.S = S; t.h = h; t.gap = gapL; t.st_next = stn; t.pad = 0;
-      I.trace[I.trace_len] = t;
+      gstore(gbl(I.trace) + I.trace_len, t);
     }
     I.trace_len += 1;
     I.c.steps += 1;
@@ -304,8 +304,8 @@ __device__ __noinline__ void run_heuristic(Inst& I, HeurLds& lds) {
   const uint32_t clr = width > I.ring_mask + 1 ? I.ring_mask + 1 : width;
   for (uint32_t k = tid; k < clr; k += kBlock) {
     uint32_t slot = (L + k) & I.ring_mask;
-    I.ring_mass[slot] = 0;
-    I.ring_cnt[slot] = 0;
+    gbl(I.ring_mass)[slot] = 0;
+    gbl(I.ring_cnt)[slot] = 0;
   }
   __syncthreads();
   if (tid == 0) {
@@ -317,20 +317,20 @@ __device__ __noinline__ void run_heuristic(Inst& I, HeurLds& lds) {
     int32_t lo = first, hi = nrec;
     while (lo < hi) {
       int32_t mid = (lo + hi) >> 1;
-      if (I.steprec[(uint32_t)mid & I.steprec_mask].ub > lb0) hi = mid; else lo = mid + 1;
+      if (gbl(I.steprec)[(uint32_t)mid & I.steprec_mask].ub > lb0) hi = mid; else lo = mid + 1;
     }
     int32_t r0 = lo;
     // last record with lb <= st  (records are ordered by band)
     lo = first; hi = nrec;
     while (lo < hi) {
       int32_t mid = (lo + hi) >> 1;
-      if (I.steprec[(uint32_t)mid & I.steprec_mask].lb <= stn) lo = mid + 1; else hi = mid;
+      if (gbl(I.steprec)[(uint32_t)mid & I.steprec_mask].lb <= stn) lo = mid + 1; else hi = mid;
     }
     int32_t r1 = lo - 1;
     int32_t wb = 0, we = 0;
     if (r0 <= r1 && r0 < nrec && r1 >= first) {
-      wb = I.steprec[(uint32_t)r0 & I.steprec_mask].seg_begin;
-      we = I.steprec[(uint32_t)r1 & I.steprec_mask].seg_end;
+      wb = gbl(I.steprec)[(uint32_t)r0 & I.steprec_mask].seg_begin;
+      we = gbl(I.steprec)[(uint32_t)r1 & I.steprec_mask].seg_end;
       if (r0 == first && first > 0) wb = 0;  // older records evicted: scan from the start
     }
     I.wBegin = wb;
@@ -361,31 +361,31 @@ __device__ __noinline__ void run_heuristic(Inst& I, HeurLds& lds) {
 // control words only change between ticks, and reading them through the
 // instance struct inside the loops would re-load them after every atomic.
 struct View {
-  const int32_t* rowptr;
-  const uint64_t* adj;
-  const uint32_t* wmin;
-  const uint32_t* hub_bits;
-  uint32_t* dist;
-  uint32_t* stamp;
-  int32_t* q_next;
-  int32_t* touched;
-  Inst* inst;
+  const SSSP_GBL int32_t* rowptr;
+  const SSSP_GBL uint64_t* adj;
+  const SSSP_GBL uint32_t* wmin;
+  const SSSP_GBL uint32_t* hub_bits;
+  SSSP_GBL uint32_t* dist;
+  SSSP_GBL uint32_t* stamp;
+  SSSP_GBL int32_t* q_next;
+  SSSP_GBL int32_t* touched;
+  GInst* inst;
   uint32_t lb, ub, st, lb0, rid, step_rid0;
   int32_t n, heavy_split, maxw;
   uint32_t first;
 };
 
-__device__ __forceinline__ View make_view(Inst& I) {
+__device__ __forceinline__ View make_view(GInst& I) {
   View v;
-  const DevGraph& g = *I.g;
-  v.rowptr = g.rowptr;
-  v.adj = g.adj;
-  v.wmin = g.wmin;
-  v.hub_bits = g.hub_bits;
-  v.dist = I.dist;
-  v.stamp = I.stamp;
-  v.q_next = I.q[I.qsel ^ 1];
-  v.touched = I.touched;
+  GDevGraph& g = *gbl(I.g);
+  v.rowptr = gbl(g.rowptr);
+  v.adj = gbl(g.adj);
+  v.wmin = gbl(g.wmin);
+  v.hub_bits = gbl(g.hub_bits);
+  v.dist = gbl(I.dist);
+  v.stamp = gbl(I.stamp);
+  v.q_next = gbl(I.q[I.qsel ^ 1]);
+  v.touched = gbl(I.touched);
   v.inst = &I;
   v.lb = I.lb;
   v.ub = I.ub;
@@ -409,7 +409,7 @@ __device__ __forceinline__ int global_wave() { return (int)(blockIdx.x * (kBlock
 
 // Work counters go to this wave's own slot (plain read-modify-write: no
 // other wave touches it); only the step-1 hub bound is a shared atomic.
-__device__ __forceinline__ void flush_acc(Inst& I, int maxw, WaveAcc& a) {
+__device__ __forceinline__ void flush_acc(GInst& I, int maxw, WaveAcc& a) {
   unsigned long long e = wave_sum(a.expansions), b = wave_sum(a.band), ps = wave_sum(a.pscan),
                      pv = wave_sum(a.pvert), pl = wave_sum(a.pullscan), su = wave_sum(a.success),
                      qe = wave_sum(a.qent);
@@ -417,7 +417,7 @@ __device__ __forceinline__ void flush_acc(Inst& I, int maxw, WaveAcc& a) {
   if (lane_id() == 0) {
     const int gw = global_wave();
     if (gw < maxw) {
-      Counters& c = I.cslot[gw];
+      SSSP_GBL Counters& c = gbl(I.cslot)[gw];
       c.expansions += e;
       c.band_expansions += b;
       c.push_scanned += ps;
@@ -430,7 +430,7 @@ __device__ __forceinline__ void flush_acc(Inst& I, int maxw, WaveAcc& a) {
   }
 }
 
-__device__ __forceinline__ bool hub_bit(const uint32_t* bits, int v) {
+__device__ __forceinline__ bool hub_bit(const SSSP_GBL uint32_t* bits, int v) {
   return (bits[v >> 5] >> (v & 31)) & 1u;
 }
 
@@ -472,7 +472,8 @@ __device__ __forceinline__ void stage_append_pair(StageLds& S, bool want, int32_
 }
 
 // Whole workgroup: write the staged pairs as (hi << 32) | lo entries.
-__device__ void stage_flush_pairs(StageLds& S, uint64_t* list, int32_t* cnt, int cap, uint32_t* flags) {
+__device__ void stage_flush_pairs(StageLds& S, SSSP_GBL uint64_t* list, SSSP_GBL int32_t* cnt, int cap,
+                                  SSSP_GBL uint32_t* flags) {
   __syncthreads();
   const int np = S.nq;
   if (threadIdx.x == 0) {
@@ -489,8 +490,9 @@ __device__ void stage_flush_pairs(StageLds& S, uint64_t* list, int32_t* cnt, int
 }
 
 // Whole workgroup: copy the staged entries to their lists.
-__device__ void stage_flush(StageLds& S, int32_t* qlist, int32_t* qcnt, int32_t* tlist, int32_t* tcnt,
-                            int cap, uint32_t* flags) {
+__device__ void stage_flush(StageLds& S, SSSP_GBL int32_t* qlist, SSSP_GBL int32_t* qcnt, SSSP_GBL int32_t* tlist,
+                            SSSP_GBL int32_t* tcnt,
+                            int cap, SSSP_GBL uint32_t* flags) {
   __syncthreads();
   const int nq = S.nq, nt = S.nt;
   if (threadIdx.x == 0) {
@@ -531,10 +533,10 @@ __device__ __forceinline__ void on_success(const View& V, bool ok, int t, uint32
 }
 
 // Split a long range into heavy chunks for the next tick (grid-wide).
-__device__ void emit_heavy(Inst& I, int u, uint32_t d, int lo, int hi, bool pull) {
+__device__ void emit_heavy(GInst& I, int u, uint32_t d, int lo, int hi, bool pull) {
   int nch = (hi - lo + kHeavyChunk - 1) / kHeavyChunk;
   int base = atomicAdd(&I.h_next_cnt.v, nch);
-  HeavyItem* out = I.heavy[I.hsel ^ 1];
+  auto out = gbl(I.heavy[I.hsel ^ 1]);
   const int cap = I.heavy_cap;
   for (int k = 0; k < nch; ++k) {
     int pos = base + k;
@@ -549,7 +551,7 @@ __device__ void emit_heavy(Inst& I, int u, uint32_t d, int lo, int hi, bool pull
     it.d = d;
     it.lo = a;
     it.hi_kind = b | (pull ? (int)0x80000000 : 0);
-    out[pos] = it;
+    gstore(out + pos, it);
   }
 }
 
@@ -590,7 +592,7 @@ __device__ __forceinline__ void lds_push_item(RoundLds& L, bool want, int u, uin
   }
 }
 
-__device__ __noinline__ void block_round(Inst& I, int kind, int item0, int nitems, RoundLds& L) {
+__device__ __noinline__ void block_round(GInst& I, int kind, int item0, int nitems, RoundLds& L) {
   const View V = make_view(I);
   const int tid = threadIdx.x;
   const uint32_t lb = V.lb, ub = V.ub, st = V.st;
@@ -612,7 +614,7 @@ __device__ __noinline__ void block_round(Inst& I, int kind, int item0, int nitem
     uint32_t d = 0;
     bool pull = false;
     if (tid < kHeavyPerBatch && it < nitems) {
-      HeavyItem h = I.heavy[I.hsel][it];
+      HeavyItem h = gload(gbl(I.heavy[I.hsel]) + it);
       u = h.u;
       lo = h.lo;
       sz = (h.hi_kind & 0x7fffffff) - lo;
@@ -632,8 +634,8 @@ __device__ __noinline__ void block_round(Inst& I, int kind, int item0, int nitem
     // lightest edge cannot reach below ub from a settled vertex (>= st) is
     // kept without reading its distance
     const int usel = I.usel;
-    const uint64_t* ucur = usel < 0 ? I.g->nonisolated : I.ulist[usel];
-    uint64_t* unext = I.ulist[usel < 0 ? 0 : (usel ^ 1)];
+    const SSSP_GBL uint64_t* ucur = usel < 0 ? gbl(gbl(I.g)->nonisolated) : gbl(I.ulist[usel]);
+    auto unext = gbl(I.ulist[usel < 0 ? 0 : (usel ^ 1)]);
     const uint32_t reach = ub - st;
     uint64_t ee[kItemsPerThread];
 #pragma unroll
@@ -664,8 +666,8 @@ __device__ __noinline__ void block_round(Inst& I, int kind, int item0, int nitem
     stage_flush_pairs(S, unext, &I.u_next_cnt.v, V.n, &I.flags.v);
   } else {
     int uu[kItemsPerThread];
-    const int32_t* src = (kind == SEG_W) ? I.settled + I.wBegin
-                         : (kind == SEG_P) ? I.plist[I.psel] : I.q[I.qsel];
+    const SSSP_GBL int32_t* src = (kind == SEG_W) ? gbl(I.settled) + I.wBegin
+                         : (kind == SEG_P) ? gbl(I.plist[I.psel]) : gbl(I.q[I.qsel]);
 #pragma unroll
     for (int k = 0; k < kItemsPerThread; ++k) {
       const int it = item0 + k * kBlock + tid;
@@ -850,7 +852,7 @@ __device__ __noinline__ void block_round(Inst& I, int kind, int item0, int nitem
 
   // ---------------------------------------------------------- phase 2b: edges
   const bool any_pull = (kind == SEG_U) || (kind == SEG_H);
-  int32_t* qnext = V.q_next;
+  SSSP_GBL int32_t* qnext = V.q_next;
   for (int base = 0; base < total; base += kBlock) {
     __syncthreads();
     if (S.nq > kStageCap - kBlock || S.nt > kStageCap - kBlock)
@@ -935,23 +937,23 @@ union BlockLds {
 // dist < ub they are final; in the first step the rest stay pending) and the
 // pending list's compaction. Degree mass moves from the unsettled histogram
 // to the per-distance ring; settled vertices are appended to the settled list.
-__device__ __noinline__ void block_settle(Inst& I, int kind, int item0, int nitems, SettleLds& L) {
-  const DevGraph& g = *I.g;
+__device__ __noinline__ void block_settle(GInst& I, int kind, int item0, int nitems, SettleLds& L) {
+  GDevGraph& g = *gbl(I.g);
   const int tid = threadIdx.x;
   const uint32_t lb = I.lb, ub = I.ub, M = I.M;
   const uint32_t band = ub - lb;
   const uint32_t nb = band < (uint32_t)kLdsRing ? band : (uint32_t)kLdsRing;
   const int nh = g.num_deg < kLdsHist ? g.num_deg : kLdsHist;
-  const uint64_t* dinfo = g.dinfo;
-  uint32_t* dist = I.dist;
-  uint64_t* ring_mass = I.ring_mass;
-  uint32_t* ring_cnt = I.ring_cnt;
-  uint32_t* hist_cnt = I.hist_cnt;
+  auto dinfo = gbl(g.dinfo);
+  auto dist = gbl(I.dist);
+  auto ring_mass = gbl(I.ring_mass);
+  auto ring_cnt = gbl(I.ring_cnt);
+  auto hist_cnt = gbl(I.hist_cnt);
   const uint32_t ring_mask = I.ring_mask;
-  int32_t* touched = I.touched;
-  int32_t* pcur = I.plist[I.psel];
-  int32_t* pnext = I.plist[I.psel ^ 1];
-  int32_t* settled = I.settled;
+  auto touched = gbl(I.touched);
+  auto pcur = gbl(I.plist[I.psel]);
+  auto pnext = gbl(I.plist[I.psel ^ 1]);
+  auto settled = gbl(I.settled);
   const int n = I.n;
   const int maxw = I.maxw;
   for (uint32_t k = tid; k < nb; k += kBlock) { L.mass[k] = 0; L.cnt[k] = 0; }
@@ -1027,7 +1029,7 @@ __device__ __noinline__ void block_settle(Inst& I, int kind, int item0, int nite
     L.sdec[tid / kWave] = ws;
     L.maxd[tid / kWave] = wm;
     const int gw = global_wave();
-    if (qe && gw < maxw) I.cslot[gw].queue_entries += qe;
+    if (qe && gw < maxw) gbl(I.cslot)[gw].queue_entries += qe;
   }
   __syncthreads();
   for (uint32_t k = tid; k < nb; k += kBlock) {
@@ -1057,11 +1059,11 @@ __device__ __noinline__ void block_settle(Inst& I, int kind, int item0, int nite
 
 // ------------------------------------------------------------- scheduling --
 
-__device__ int find_segment(const Globals& G, int b) {
+__device__ int find_segment(const GGlobals& G, int b) {
   int lo = 0, hi = G.nseg;  // seg_first_batch has nseg + 1 entries
   while (lo < hi) {
     int mid = (lo + hi + 1) >> 1;
-    if (G.seg_first_batch[mid] <= b) lo = mid; else hi = mid - 1;
+    if (gbl(G.seg_first_batch)[mid] <= b) lo = mid; else hi = mid - 1;
   }
   return lo;
 }
@@ -1074,7 +1076,7 @@ __device__ int find_segment(const Globals& G, int b) {
 // any grouping of rounds reaches the same settled set. When the frontier
 // empties or grows past one batch, the epilogue takes over with its usual
 // transition of the last round.
-__device__ __noinline__ void fused_rounds(Inst& I, RoundLds& L) {
+__device__ __noinline__ void fused_rounds(GInst& I, RoundLds& L) {
   __shared__ int s_go, s_nq;
   const int cap = I.fuse_cap;
   for (int r = 0; r < cap; ++r) {
@@ -1110,16 +1112,16 @@ __device__ __noinline__ void fused_rounds(Inst& I, RoundLds& L) {
   }
 }
 
-__device__ void run_tick(Globals& G, BlockLds& lds) {
+__device__ void run_tick(GGlobals& G, BlockLds& lds) {
   __shared__ int s_last;
   const int total_batches = G.total_batches;
   for (int b = blockIdx.x; b < total_batches; b += gridDim.x) {
     const int sgi = find_segment(G, b);
-    Inst& I = G.insts[G.seg_inst[sgi]];
-    const int kind = G.seg_kind[sgi];
-    const int pb = G.seg_per_batch[sgi];
-    const int item0 = (b - G.seg_first_batch[sgi]) * pb;
-    const int cnt = G.seg_count[sgi];
+    GInst& I = gbl(G.insts)[gbl(G.seg_inst)[sgi]];
+    const int kind = gbl(G.seg_kind)[sgi];
+    const int pb = gbl(G.seg_per_batch)[sgi];
+    const int item0 = (b - gbl(G.seg_first_batch)[sgi]) * pb;
+    const int cnt = gbl(G.seg_count)[sgi];
     if (kind == SEG_ST || kind == SEG_SP) {
       block_settle(I, kind, item0, cnt, lds.s);
       // the heuristic only reads words updated by device atomics: waiting for
@@ -1150,7 +1152,7 @@ __device__ void run_tick(Globals& G, BlockLds& lds) {
 
 // Phase transition of one instance after a tick, and its segments for the
 // next tick. Serial per instance; called by one thread per instance.
-__device__ void transition(Inst& I, int32_t* cnt, int32_t* kinds, int32_t* pbs) {
+__device__ void transition(GInst& I, SSSP_GBL int32_t* cnt, SSSP_GBL int32_t* kinds, SSSP_GBL int32_t* pbs) {
   for (int s = 0; s < kMaxSegPerInst; ++s) { cnt[s] = 0; kinds[s] = SEG_Q; pbs[s] = kBlock; }
   if (I.phase == PH_DONE) return;
   if (I.tick_kind == PH_ROUND) {
@@ -1215,7 +1217,7 @@ __device__ void transition(Inst& I, int32_t* cnt, int32_t* kinds, int32_t* pbs) 
 // instance; otherwise the recorded segments are laid out as they are (a new
 // launch continuing earlier instances, or the first tick of new ones). One
 // workgroup.
-__device__ void build_table(Globals& G, bool do_transition) {
+__device__ void build_table(GGlobals& G, bool do_transition) {
   const int tid = threadIdx.x;
   const int k = G.ninst;
   __shared__ unsigned long long sh[kBlock / kWave + 1];
@@ -1227,7 +1229,7 @@ __device__ void build_table(Globals& G, bool do_transition) {
   const int i0 = min(k, tid * per), i1 = min(k, i0 + per);
   int local_batches = 0;
   for (int i = i0; i < i1; ++i) {
-    Inst& I = G.insts[i];
+    GInst& I = gbl(G.insts)[i];
     if (do_transition) transition(I, I.spec_cnt, I.spec_kind, I.spec_pb);
     if (I.phase != PH_DONE) atomicAdd(&s_active, 1);
     for (int s = 0; s < kMaxSegPerInst; ++s) {
@@ -1237,11 +1239,11 @@ __device__ void build_table(Globals& G, bool do_transition) {
       int nb;
       if (c < 0) { nb = 1; c = 0; }
       else nb = (c + pb - 1) / pb;
-      G.seg_inst[sg] = i;
-      G.seg_kind[sg] = I.spec_kind[s];
-      G.seg_count[sg] = c;
-      G.seg_per_batch[sg] = pb;
-      G.seg_first_batch[sg] = nb;  // temporarily the batch count
+      gbl(G.seg_inst)[sg] = i;
+      gbl(G.seg_kind)[sg] = I.spec_kind[s];
+      gbl(G.seg_count)[sg] = c;
+      gbl(G.seg_per_batch)[sg] = pb;
+      gbl(G.seg_first_batch)[sg] = nb;  // temporarily the batch count
       local_batches += nb;
     }
   }
@@ -1251,15 +1253,15 @@ __device__ void build_table(Globals& G, bool do_transition) {
   for (int i = i0; i < i1; ++i) {
     for (int s = 0; s < kMaxSegPerInst; ++s) {
       int sg = i * kMaxSegPerInst + s;
-      int nb = G.seg_first_batch[sg];
-      G.seg_first_batch[sg] = run;
+      int nb = gbl(G.seg_first_batch)[sg];
+      gbl(G.seg_first_batch)[sg] = run;
       run += nb;
     }
   }
   __syncthreads();
   if (tid == 0) {
     G.nseg = k * kMaxSegPerInst;
-    G.seg_first_batch[G.nseg] = (int)total;
+    gbl(G.seg_first_batch)[G.nseg] = (int)total;
     G.total_batches = (int)total;
     G.all_done = (s_active == 0) ? 1u : 0u;
   }
@@ -1267,9 +1269,9 @@ __device__ void build_table(Globals& G, bool do_transition) {
 }
 
 // Ticks counted for the counters (every active instance).
-__device__ void count_ticks(Globals& G) {
+__device__ void count_ticks(GGlobals& G) {
   for (int i = threadIdx.x; i < G.ninst; i += kBlock) {
-    Inst& I = G.insts[i];
+    GInst& I = gbl(G.insts)[i];
     if (I.phase != PH_DONE) I.c.ticks += 1;
   }
   __syncthreads();
@@ -1301,7 +1303,7 @@ __device__ __forceinline__ uint32_t xcd_of_this_wg() {
 // invalidate is not enough: measured, stale data was read.)
 __device__ __forceinline__ void acquire_after_release() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
 
-__device__ bool spin_until_changed(unsigned int* word, unsigned int old, unsigned int* err) {
+__device__ bool spin_until_changed(SSSP_GBL unsigned int* word, unsigned int old, SSSP_GBL unsigned int* err) {
   unsigned long long spins = 0;
   while (__hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == old) {
     __builtin_amdgcn_s_sleep(1);
@@ -1315,13 +1317,13 @@ __device__ bool spin_until_changed(unsigned int* word, unsigned int old, unsigne
 
 // The serial part between two ticks (one workgroup): tick log, phase
 // transitions and the next tick's work layout.
-__device__ __noinline__ void epilogue(Globals& G) {
+__device__ __noinline__ void epilogue(GGlobals& G) {
   if (threadIdx.x == 0) {
-    if (G.tick_log && G.ticks < G.tick_log_cap) {
-      unsigned long long* e = G.tick_log + 4 * G.ticks;
+    if (gbl(G.tick_log) && G.ticks < G.tick_log_cap) {
+      auto e = gbl(G.tick_log) + 4 * G.ticks;
       e[0] = wall_clock64();
       e[1] = (unsigned long long)G.total_batches;
-      const Inst& I0 = G.insts[0];
+      const GInst& I0 = gbl(G.insts)[0];
       e[2] = (unsigned long long)I0.tick_kind | ((unsigned long long)I0.init_round << 8) |
              ((unsigned long long)I0.pull_on << 9) | ((unsigned long long)I0.step << 16);
     }
@@ -1330,7 +1332,7 @@ __device__ __noinline__ void epilogue(Globals& G) {
   count_ticks(G);
   build_table(G, true);
   if (threadIdx.x == 0) {
-    if (G.tick_log && G.ticks < G.tick_log_cap) G.tick_log[4 * G.ticks + 3] = wall_clock64();
+    if (gbl(G.tick_log) && G.ticks < G.tick_log_cap) gbl(G.tick_log)[4 * G.ticks + 3] = wall_clock64();
     G.ticks += 1;
     if (G.ticks >= G.tick_limit) {
       G.error |= FLAG_TICKS;
@@ -1351,7 +1353,7 @@ struct BarrierState {
 // Flat barrier with full fences by every workgroup; used once per launch to
 // register the workgroups of each XCD, and as the whole barrier of the
 // one-launch-per-tick mode (where the kernel boundary does the waiting).
-__device__ bool barrier_flat(Globals& G, unsigned int& gen, bool wait, bool run_epilogue) {
+__device__ bool barrier_flat(GGlobals& G, unsigned int& gen, bool wait, bool run_epilogue) {
   __shared__ int s_last;
   __shared__ int s_ok;
   __syncthreads();
@@ -1384,7 +1386,7 @@ __device__ bool barrier_flat(Globals& G, unsigned int& gen, bool wait, bool run_
 
 // Two-level barrier of the persistent engine; the grid-wide last arriver runs
 // the epilogue. Returns false if a wait gave up.
-__device__ bool barrier_tick(Globals& G, BarrierState& B) {
+__device__ bool barrier_tick(GGlobals& G, BarrierState& B) {
   __shared__ int s_role;  // 0 wait for the XCD leader, 1 XCD leader, 2 epilogue
   __shared__ int s_ok;
   // every wave's stores and atomics of this tick are complete before arriving
@@ -1436,7 +1438,7 @@ __device__ bool barrier_tick(Globals& G, BarrierState& B) {
 __global__ void __launch_bounds__(kBlock, 4) k_engine(Globals* Gp, int persistent, int max_ticks) {
   __shared__ BlockLds lds;
   __shared__ BarrierState s_b;
-  Globals& G = *Gp;
+  GGlobals& G = *gbl(Gp);
   if (threadIdx.x == 0) {
     s_b.gen = __hip_atomic_load(&G.bar_gen.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (blockIdx.x == 0 && G.ticks == 0) G.t_start = wall_clock64();
@@ -1484,47 +1486,47 @@ __global__ void __launch_bounds__(kBlock, 4) k_engine(Globals* Gp, int persisten
 // Per-solve state reset: distances, histogram, ring; stamps when their
 // counter is near wrapping. Grid-stride over every instance.
 __global__ void k_init_arrays(Globals* Gp) {
-  Globals& G = *Gp;
+  GGlobals& G = *gbl(Gp);
   const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long stride = (long long)gridDim.x * blockDim.x;
   const int nsel = G.n_sel < 0 ? G.ninst : G.n_sel;
   for (int j = 0; j < nsel; ++j) {
-    Inst& I = G.insts[G.n_sel < 0 ? j : G.sel_list[j]];
-    const DevGraph& g = *I.g;
-    const uint32_t* pw = I.rid_slot;
+    GInst& I = gbl(G.insts)[G.n_sel < 0 ? j : gbl(G.sel_list)[j]];
+    GDevGraph& g = *gbl(I.g);
+    auto pw = gbl(I.rid_slot);
     const bool reset_stamp = pw[PW_RID] > 0x80000000u;
     for (long long v = tid; v < I.n; v += stride) {
-      I.dist[v] = kInf;
-      if (reset_stamp) I.stamp[v] = 0;
+      gbl(I.dist)[v] = kInf;
+      if (reset_stamp) gbl(I.stamp)[v] = 0;
     }
     for (long long x = tid; x < I.maxw; x += stride) {
       Counters z = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-      I.cslot[x] = z;
+      gstore(gbl(I.cslot) + x, z);
     }
-    for (long long r = tid; r < g.num_deg; r += stride) I.hist_cnt[r] = g.deg_cnt0[r];
+    for (long long r = tid; r < g.num_deg; r += stride) gbl(I.hist_cnt)[r] = gbl(g.deg_cnt0)[r];
     for (long long r = tid; r <= (long long)I.ring_mask; r += stride) {
-      I.ring_mass[r] = 0;
-      I.ring_cnt[r] = 0;
+      gbl(I.ring_mass)[r] = 0;
+      gbl(I.ring_cnt)[r] = 0;
     }
   }
 }
 
 // Per-solve control reset and the first tick's table. One workgroup.
 __global__ void __launch_bounds__(kBlock) k_init_ctl(Globals* Gp) {
-  Globals& G = *Gp;
+  GGlobals& G = *gbl(Gp);
   const int nsel = G.n_sel < 0 ? G.ninst : G.n_sel;
   for (int j = 0; j < nsel; ++j) {
-    Inst& I = G.insts[G.n_sel < 0 ? j : G.sel_list[j]];
-    const DevGraph& g = *I.g;
+    GInst& I = gbl(G.insts)[G.n_sel < 0 ? j : gbl(G.sel_list)[j]];
+    GDevGraph& g = *gbl(I.g);
     if (threadIdx.x == 0) {
-      uint32_t* pw = I.rid_slot;
+      auto pw = gbl(I.rid_slot);
       I.rid = pw[PW_RID];
       if (I.rid > 0x80000000u) I.rid = 0;
       // until this solve ends normally, the next one starts well above it
       pw[PW_RID] = I.rid + (1u << 24);
       const int s = I.source;
-      const int deg_s = g.rowptr[s + 1] - g.rowptr[s];
-      I.dist[s] = 0;
+      const int deg_s = gbl(g.rowptr)[s + 1] - gbl(g.rowptr)[s];
+      gbl(I.dist)[s] = 0;
       I.M = g.max_w;
       I.lb = 0; I.ub = kInf; I.st = 0; I.lb0 = 0;
       I.first = 1;
@@ -1547,13 +1549,13 @@ __global__ void __launch_bounds__(kBlock) k_init_ctl(Globals* Gp) {
       I.tick_kind = PH_ROUND;
       I.high_d0 = g.high_d0;
       Counters z = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-      I.c = z;
+      gstore(&I.c, z);
       I.step_rid0 = I.rid + 1;
-      I.stamp[s] = I.step_rid0;
+      gbl(I.stamp)[s] = I.step_rid0;
       I.rid = I.step_rid0 + 1;
-      I.touched[0] = s;
+      gbl(I.touched)[0] = s;
       I.touched_cnt.v = 1;
-      I.q[0][0] = s;
+      gbl(I.q[0])[0] = s;
       I.nF = 1;
       I.ub_next.v = is_hub(g, s) ? 0u : kInf;
       I.phase = deg_s > 0 ? PH_ROUND : PH_DONE;
@@ -1568,7 +1570,7 @@ __global__ void __launch_bounds__(kBlock) k_init_ctl(Globals* Gp) {
     }
     __syncthreads();
     // gap(0) from whole-graph statistics: sumD(0) = nnz, highD(0)
-    uint32_t g0 = gap_of((unsigned long long)g.nnz, g.high_d0, g.nnz, g.max_w, g.rtow, I.alpha, I.beta);
+    uint32_t g0 = gap_of((unsigned long long)g.nnz, g.high_d0, g.nnz, g.max_w, gbl(g.rtow), I.alpha, I.beta);
     if (threadIdx.x == 0) {
       I.gap0 = g0;
       I.gap_cur = g0;
@@ -1593,19 +1595,19 @@ __global__ void __launch_bounds__(kBlock) k_init_ctl(Globals* Gp) {
 // vertex with a finite neighbour but no distance is reachable with a length
 // the uint32 range cannot hold.
 __global__ void k_overflow_check(Globals* Gp) {
-  Globals& G = *Gp;
+  GGlobals& G = *gbl(Gp);
   const int nsel = G.n_sel < 0 ? G.ninst : G.n_sel;
   for (int j = 0; j < nsel; ++j) {
-    Inst& I = G.insts[G.n_sel < 0 ? j : G.sel_list[j]];
+    GInst& I = gbl(G.insts)[G.n_sel < 0 ? j : gbl(G.sel_list)[j]];
     if (!(I.flags.v & FLAG_MAYBE_OVERFLOW)) continue;
-    const DevGraph& g = *I.g;
+    GDevGraph& g = *gbl(I.g);
     bool found = false;
     for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < g.n && !found;
          v += (long long)gridDim.x * blockDim.x) {
-      if (I.dist[v] != kInf) continue;
-      for (int e = g.rowptr[v]; e < g.rowptr[v + 1]; ++e) {
-        int u = (int)(uint32_t)(g.adj[e] & 0xffffffffull);
-        if (I.dist[u] != kInf) {
+      if (gbl(I.dist)[v] != kInf) continue;
+      for (int e = gbl(g.rowptr)[v]; e < gbl(g.rowptr)[v + 1]; ++e) {
+        int u = (int)(uint32_t)(gbl(g.adj)[e] & 0xffffffffull);
+        if (gbl(I.dist)[u] != kInf) {
           found = true;
           break;
         }
@@ -1617,9 +1619,9 @@ __global__ void k_overflow_check(Globals* Gp) {
 
 // Phase and flags of every instance, for a host that polls completions.
 __global__ void k_status(Globals* Gp, uint32_t* status) {
-  Globals& G = *Gp;
+  GGlobals& G = *gbl(Gp);
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < G.ninst; i += gridDim.x * blockDim.x) {
-    const Inst& I = G.insts[i];
+    const GInst& I = gbl(G.insts)[i];
     status[2 * i] = I.phase;
     status[2 * i + 1] = I.flags.v | G.error;
   }
@@ -1631,7 +1633,7 @@ __global__ void __launch_bounds__(kBlock) k_high_d(const int32_t* deg_vals, cons
                                                    unsigned long long* out_mass) {
   __shared__ HeurLds lds;
   unsigned long long mass;
-  uint32_t h = block_high_d(deg_vals, cnt, D, &mass, lds);
+  uint32_t h = block_high_d(gbl(deg_vals), gbl(cnt), D, &mass, lds);
   if (threadIdx.x == 0) {
     *out_h = h;
     *out_mass = mass;
