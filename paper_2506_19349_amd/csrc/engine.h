@@ -183,6 +183,9 @@ struct Globals {
   HotU32 xcd_members[kMaxXcd];
   unsigned int all_done;
   unsigned int error;
+  // workgroups per XCD that take part in a tick (the rest wait aside), for
+  // the tick that starts at release generation g in quota[g % 8]
+  unsigned int quota[8];
   // current tick layout
   int32_t nseg;
   int32_t total_batches;

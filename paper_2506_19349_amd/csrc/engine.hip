@@ -1112,10 +1112,12 @@ __device__ __noinline__ void fused_rounds(GInst& I, RoundLds& L) {
   }
 }
 
-__device__ void run_tick(GGlobals& G, BlockLds& lds) {
+// One tick's batches, taken round-robin by the P participating workgroups
+// (this one is number pid).
+__device__ void run_tick(GGlobals& G, BlockLds& lds, int pid, int P) {
   __shared__ int s_last;
   const int total_batches = G.total_batches;
-  for (int b = blockIdx.x; b < total_batches; b += gridDim.x) {
+  for (int b = pid; b < total_batches; b += P) {
     const int sgi = find_segment(G, b);
     GInst& I = gbl(G.insts)[gbl(G.seg_inst)[sgi]];
     const int kind = gbl(G.seg_kind)[sgi];
@@ -1315,9 +1317,24 @@ __device__ bool spin_until_changed(SSSP_GBL unsigned int* word, unsigned int old
   return true;
 }
 
+// Workgroups per XCD for the next tick: one batch each as far as there are
+// batches, at least one per XCD. The others sit the tick out, so a tick with
+// little work synchronises few workgroups (the barrier's cost grows with the
+// number of workgroups that write back and invalidate caches).
+__device__ __forceinline__ unsigned int quota_for(int total_batches, unsigned int nxcd,
+                                                  unsigned int min_members) {
+  const unsigned int nx = nxcd ? nxcd : 1u;
+  unsigned int q = ((unsigned int)total_batches + nx - 1) / nx;
+  if (q < 1u) q = 1u;
+  if (q > min_members) q = min_members;
+  return q;
+}
+
+
 // The serial part between two ticks (one workgroup): tick log, phase
 // transitions and the next tick's work layout.
-__device__ __noinline__ void epilogue(GGlobals& G) {
+__device__ __noinline__ void epilogue(GGlobals& G, unsigned int gen, unsigned int nxcd,
+                                     unsigned int min_members) {
   if (threadIdx.x == 0) {
     if (gbl(G.tick_log) && G.ticks < G.tick_log_cap) {
       auto e = gbl(G.tick_log) + 4 * G.ticks;
@@ -1332,6 +1349,9 @@ __device__ __noinline__ void epilogue(GGlobals& G) {
   count_ticks(G);
   build_table(G, true);
   if (threadIdx.x == 0) {
+    // the next tick starts at generation gen + 1
+    __hip_atomic_store(&G.quota[(gen + 1u) & 7u], quota_for(G.total_batches, nxcd, min_members),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (gbl(G.tick_log) && G.ticks < G.tick_log_cap) gbl(G.tick_log)[4 * G.ticks + 3] = wall_clock64();
     G.ticks += 1;
     if (G.ticks >= G.tick_limit) {
@@ -1348,6 +1368,10 @@ struct BarrierState {
   uint32_t xcd;
   uint32_t members;    // workgroups on this XCD
   uint32_t nxcd;       // XCDs with at least one workgroup
+  uint32_t rank;       // this workgroup's rank among its XCD's workgroups
+  uint32_t xidx;       // this XCD's index among the populated XCDs
+  uint32_t q0;         // workgroups per XCD in the launch's first tick
+  uint32_t min_members;  // workgroups on the least populated XCD
 };
 
 // Flat barrier with full fences by every workgroup; used once per launch to
@@ -1367,7 +1391,7 @@ __device__ bool barrier_flat(GGlobals& G, unsigned int& gen, bool wait, bool run
   if (s_last) {
     if (threadIdx.x == 0) __threadfence();
     __syncthreads();
-    if (run_epilogue) epilogue(G);
+    if (run_epilogue) epilogue(G, gen, 1u, 1u);
     if (threadIdx.x == 0) {
       __hip_atomic_store(&G.bar_count.v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __threadfence();
@@ -1384,9 +1408,29 @@ __device__ bool barrier_flat(GGlobals& G, unsigned int& gen, bool wait, bool run
   return s_ok != 0;
 }
 
-// Two-level barrier of the persistent engine; the grid-wide last arriver runs
-// the epilogue. Returns false if a wait gave up.
-__device__ bool barrier_tick(GGlobals& G, BarrierState& B) {
+// A workgroup outside the current tick waits for the tick's release (longer
+// sleeps: it is not on the tick's critical path) and returns the new release
+// generation, or gen if the engine is done or a wait gave up.
+__device__ unsigned int park_until_released(GGlobals& G, unsigned int gen) {
+  unsigned long long spins = 0;
+  unsigned int g;
+  while ((g = __hip_atomic_load(&G.bar_gen.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == gen) {
+    if (__hip_atomic_load(&G.all_done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
+        __hip_atomic_load(&G.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      return gen;
+    __builtin_amdgcn_s_sleep(16);
+    if (++spins > (1ull << 23)) {
+      atomicOr(&G.error, FLAG_TIMEOUT);
+      return gen;
+    }
+  }
+  return g;
+}
+
+// Two-level barrier of the persistent engine among the tick's participants
+// (quota per XCD); the grid-wide last arriver runs the epilogue. Returns false
+// if a wait gave up.
+__device__ bool barrier_tick(GGlobals& G, BarrierState& B, unsigned int quota) {
   __shared__ int s_role;  // 0 wait for the XCD leader, 1 XCD leader, 2 epilogue
   __shared__ int s_ok;
   // every wave's stores and atomics of this tick are complete before arriving
@@ -1395,7 +1439,7 @@ __device__ bool barrier_tick(GGlobals& G, BarrierState& B) {
   if (threadIdx.x == 0) {
     s_ok = 1;
     unsigned int a = atomicAdd(&G.xcd_count[B.xcd].v, 1u);
-    if (a == B.members - 1) {
+    if (a == quota - 1) {
       __hip_atomic_store(&G.xcd_count[B.xcd].v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __threadfence();  // this XCD's writes leave its L2
       unsigned int b = atomicAdd(&G.bar_count.v, 1u);
@@ -1415,7 +1459,7 @@ __device__ bool barrier_tick(GGlobals& G, BarrierState& B) {
   __syncthreads();
   const int role = s_role;
   if (role == 2) {
-    epilogue(G);
+    epilogue(G, B.gen, B.nxcd, B.min_members);
     if (threadIdx.x == 0) {
       __threadfence();
       atomicAdd(&G.bar_gen.v, 1u);
@@ -1447,16 +1491,17 @@ __global__ void __launch_bounds__(kBlock, 4) k_engine(Globals* Gp, int persisten
   if (!persistent) {
     // one tick; the kernel boundary is the barrier
     if (__hip_atomic_load(&G.all_done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
-    run_tick(G, lds);
+    run_tick(G, lds, blockIdx.x, gridDim.x);
     unsigned int gen = s_b.gen;
     barrier_flat(G, gen, false, true);
     return;
   }
-  // register this workgroup with its XCD, then settle the counts grid-wide
+  // register this workgroup with its XCD (and take a rank there), then
+  // settle the counts grid-wide
   if (threadIdx.x == 0) {
     s_b.xcd = xcd_of_this_wg();
     s_b.xgen = __hip_atomic_load(&G.xcd_gen[s_b.xcd].v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    atomicAdd(&G.xcd_members[s_b.xcd].v, 1u);
+    s_b.rank = atomicAdd(&G.xcd_members[s_b.xcd].v, 1u);
   }
   __syncthreads();
   unsigned int gen = s_b.gen;
@@ -1464,19 +1509,57 @@ __global__ void __launch_bounds__(kBlock, 4) k_engine(Globals* Gp, int persisten
   if (threadIdx.x == 0) {
     s_b.gen = gen;
     s_b.members = __hip_atomic_load(&G.xcd_members[s_b.xcd].v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    uint32_t nx = 0;
-    for (int x = 0; x < kMaxXcd; ++x)
-      nx += __hip_atomic_load(&G.xcd_members[x].v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ? 1u : 0u;
+    uint32_t nx = 0, xi = 0, mn = 0xffffffffu;
+    for (int x = 0; x < kMaxXcd; ++x) {
+      const uint32_t m = __hip_atomic_load(&G.xcd_members[x].v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (m == 0) continue;
+      if ((uint32_t)x < s_b.xcd) ++xi;
+      ++nx;
+      mn = m < mn ? m : mn;
+    }
     s_b.nxcd = nx;
+    s_b.xidx = xi;
+    // every workgroup computes the same values, the first tick's quota
+    // included (from the table the set-up kernel built); the epilogue
+    // publishes the later ones
+    s_b.q0 = quota_for(G.total_batches, nx, mn);
+    s_b.min_members = mn;
   }
   __syncthreads();
   BarrierState B = s_b;
-  for (int t = 0;; ++t) {
+  __shared__ unsigned int s_quota;
+  bool stale = false;  // parked since the last acquire
+  for (int t = 0;;) {
     if (__hip_atomic_load(&G.all_done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
     if (__hip_atomic_load(&G.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
-    run_tick(G, lds);
-    if (!barrier_tick(G, B)) break;
-    if (max_ticks > 0 && t + 1 >= max_ticks) {
+    if (threadIdx.x == 0)
+      s_quota = t == 0 ? B.q0
+                       : __hip_atomic_load(&G.quota[B.gen & 7u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const unsigned int q = s_quota;
+    if (B.rank < q) {
+      if (stale) {
+        // back from waiting aside: drop cached lines before reading the tick's data
+        if (threadIdx.x == 0) acquire_after_release();
+        __syncthreads();
+        stale = false;
+      }
+      run_tick(G, lds, (int)(B.rank * B.nxcd + B.xidx), (int)(q * B.nxcd));
+      if (!barrier_tick(G, B, q)) break;
+      t += 1;
+    } else {
+      // not needed in this tick: wait for its release
+      __shared__ unsigned int s_gen;
+      if (threadIdx.x == 0) s_gen = park_until_released(G, B.gen);
+      __syncthreads();
+      const unsigned int g = s_gen;
+      if (g == B.gen) break;  // done, error or timeout
+      t += (int)(g - B.gen);
+      B.xgen += g - B.gen;
+      B.gen = g;
+      stale = true;
+    }
+    if (max_ticks > 0 && t >= max_ticks) {
       if (threadIdx.x == 0 && blockIdx.x == 0) G.max_ticks_hit = 1;
       break;
     }
