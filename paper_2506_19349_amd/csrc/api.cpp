@@ -73,7 +73,7 @@ hipError_t dev_alloc(T** p, size_t count, std::vector<void*>& list) {
 
 size_t needs_bytes(const Needs& m) {
   size_t b = 0;
-  b += sizeof(uint32_t) * (size_t)m.n;             // stamp
+  b += sizeof(uint64_t) * (size_t)m.n;             // state
   b += sizeof(int32_t) * (size_t)m.list * 3;       // q[2], touched
   b += sizeof(uint64_t) * (size_t)m.list * 2;      // ulist[2]
   b += sizeof(int32_t) * (size_t)m.n * 3;          // settled, plist[2]
@@ -83,7 +83,6 @@ size_t needs_bytes(const Needs& m) {
   b += sizeof(uint32_t) * (size_t)m.hist;
   b += sizeof(StepRec) * (size_t)m.steprec;
   b += sizeof(TraceRec) * (size_t)m.trace;
-  b += sizeof(uint32_t) * PW_COUNT;
   return b;
 }
 
@@ -109,7 +108,7 @@ hipError_t ensure_slot(SlotBuf& s, const Needs& nd) {
   auto A = [&](auto** p, size_t c) {
     if (e == hipSuccess) e = dev_alloc(p, c, s.allocs);
   };
-  A(&s.stamp, m.n);
+  A(&s.state, m.n);
   A(&s.q[0], m.list);
   A(&s.q[1], m.list);
   A(&s.touched, m.list);
@@ -126,9 +125,6 @@ hipError_t ensure_slot(SlotBuf& s, const Needs& nd) {
   A(&s.hist, m.hist);
   A(&s.steprec, m.steprec);
   A(&s.trace, m.trace);
-  A(&s.rid, PW_COUNT);
-  if (e == hipSuccess) e = hipMemset(s.stamp, 0, sizeof(uint32_t) * (size_t)m.n);
-  if (e == hipSuccess) e = hipMemset(s.rid, 0, sizeof(uint32_t) * PW_COUNT);
   if (e != hipSuccess) {
     s.release();
     (void)hipGetLastError();
@@ -290,7 +286,7 @@ void fill_inst(Inst& I, const SlotBuf& s, const sssp_graph* g, int32_t source, u
   std::memset(&I, 0, sizeof(Inst));
   I.g = g->gh.d;
   I.dist = dist;
-  I.stamp = s.stamp;
+  I.state = s.state;
   I.q[0] = s.q[0];
   I.q[1] = s.q[1];
   I.touched = s.touched;
@@ -306,7 +302,6 @@ void fill_inst(Inst& I, const SlotBuf& s, const sssp_graph* g, int32_t source, u
   I.hist_cnt = s.hist;
   I.steprec = s.steprec;
   I.trace = s.trace;
-  I.rid_slot = s.rid;
   I.cslot = s.cslot;
   I.maxw = s.maxw;
   I.heavy_cap = s.heavy_cap;
@@ -403,6 +398,7 @@ sssp_status run_instances_ws(Workspace& w, const sssp_graph* const* gs, const in
   HIP_TRY(hipEventRecord(w.tev[1][tslot], stream));
   w.t_rec += 1;
   HIP_TRY(launch_overflow_check(w.dG, max_n, stream));
+  HIP_TRY(launch_finish(w.dG, max_n, stream));
   w.last_k = k;
   return ok();
 }

@@ -22,8 +22,6 @@ constexpr int kItemsPerThread = 4;       // round batches: items per thread
 constexpr int kRoundBatch = kBlock * kItemsPerThread;  // items per workgroup batch
 constexpr int kHeavyPerBatch = 16;       // heavy chunks per workgroup batch
 constexpr int kDefaultFuse = 256;        // rounds a workgroup may chain on a small frontier
-// persistent per-slot words (rid_slot[])
-enum PersistWord { PW_RID = 0, PW_COUNT = 8 };
 
 // ------------------------------------------------------------------ graph --
 struct DevGraph {
@@ -101,8 +99,12 @@ constexpr int kMaxSegPerInst = 5;  // segments one instance may have in a tick
 struct Inst {
   // ---- fixed for a solve ----
   const DevGraph* g;
-  uint32_t* dist;
-  uint32_t* stamp;
+  uint32_t* dist;          // the caller's output, written once the solve ends
+  // per vertex: (tentative distance << 32) | round id of its last decrease
+  // (0: never decreased). One 64-bit atomicMin both lowers the distance and
+  // returns the round of the previous decrease, which de-duplicates the next
+  // frontier (once per round) and the step's touched list (once per step).
+  uint64_t* state;
   int32_t* q[2];
   int32_t* touched;
   int32_t* settled;
@@ -114,7 +116,6 @@ struct Inst {
   uint32_t* hist_cnt;
   StepRec* steprec;
   TraceRec* trace;
-  uint32_t* rid_slot;      // persists across solves: [PW_RID] stamp counter
   Counters* cslot;         // per-wave work counters: [maxw]
   int32_t maxw;            // waves the counter array can hold
   int32_t pad2;
@@ -138,8 +139,8 @@ struct Inst {
   uint32_t first;          // first step (ub follows the nearest hub)
   uint32_t gap_cur;        // gap(lb) of the current step
   uint32_t M;
-  uint32_t rid;            // stamp value of the current round
-  uint32_t step_rid0;      // stamp marker of the current step (rounds use > step_rid0)
+  uint32_t rid;            // round id of the current round
+  uint32_t step_rid0;      // round-id marker of the current step (its rounds use > step_rid0)
   uint32_t step;
   uint32_t rounds_in_step;
   int32_t qsel, psel, usel, hsel;
@@ -248,6 +249,9 @@ __device__ __forceinline__ unsigned int atomicSub(SSSP_GBL unsigned int* p, unsi
 __device__ __forceinline__ unsigned int atomicMin(SSSP_GBL unsigned int* p, unsigned int v) {
   return ::atomicMin((unsigned int*)p, v);
 }
+__device__ __forceinline__ unsigned long long atomicMin(SSSP_GBL unsigned long long* p, unsigned long long v) {
+  return ::atomicMin((unsigned long long*)p, v);
+}
 __device__ __forceinline__ unsigned int atomicMax(SSSP_GBL unsigned int* p, unsigned int v) {
   return ::atomicMax((unsigned int*)p, v);
 }
@@ -268,6 +272,8 @@ hipError_t launch_init(Globals* dG, long long max_n, hipStream_t stream);
 int engine_blocks_per_cu();
 hipError_t launch_engine(Globals* dG, int grid, bool persistent, int max_ticks, hipStream_t stream);
 hipError_t launch_overflow_check(Globals* dG, long long max_n, hipStream_t stream);
+// distances of the selected instances from their state into the outputs
+hipError_t launch_finish(Globals* dG, long long max_n, hipStream_t stream);
 // per-instance phase and flags (2 words each) into status[0 .. 2 * ninst)
 hipError_t launch_status(Globals* dG, int ninst, uint32_t* status, hipStream_t stream);
 // the set-up + engine + overflow-check sequence of one solve as graph nodes

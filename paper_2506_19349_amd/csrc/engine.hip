@@ -252,10 +252,6 @@ __device__ uint32_t block_compute_st(const GInst& I, uint32_t L, uint32_t gapL, 
   return res;
 }
 
-// A solve that ends normally hands the next solve on this slot a stamp
-// counter above every stamp it wrote.
-__device__ void record_clean_end(GInst& I) { gbl(I.rid_slot)[PW_RID] = I.rid + 1; }
-
 // The end-of-step heuristic for one instance: statistics at L = ub, gap(L),
 // computeST, step bookkeeping, termination test, and the next step's setup.
 // Runs on one workgroup, after every settle batch of the instance is done.
@@ -289,10 +285,7 @@ __device__ __noinline__ void run_heuristic(GInst& I, HeurLds& lds) {
   const bool done = (L == kInf) ||
                     (I.p_next_cnt.v == 0 && (unsigned long long)I.max_settled.v + I.M < L);
   if (done) {
-    if (tid == 0) {
-      I.phase = PH_DONE;
-      record_clean_end(I);
-    }
+    if (tid == 0) I.phase = PH_DONE;
     __syncthreads();
     return;
   }
@@ -365,8 +358,7 @@ struct View {
   const SSSP_GBL uint64_t* adj;
   const SSSP_GBL uint32_t* wmin;
   const SSSP_GBL uint32_t* hub_bits;
-  SSSP_GBL uint32_t* dist;
-  SSSP_GBL uint32_t* stamp;
+  SSSP_GBL uint64_t* state;
   SSSP_GBL int32_t* q_next;
   SSSP_GBL int32_t* touched;
   GInst* inst;
@@ -382,8 +374,7 @@ __device__ __forceinline__ View make_view(GInst& I) {
   v.adj = gbl(g.adj);
   v.wmin = gbl(g.wmin);
   v.hub_bits = gbl(g.hub_bits);
-  v.dist = gbl(I.dist);
-  v.stamp = gbl(I.stamp);
+  v.state = gbl(I.state);
   v.q_next = gbl(I.q[I.qsel ^ 1]);
   v.touched = gbl(I.touched);
   v.inst = &I;
@@ -398,6 +389,18 @@ __device__ __forceinline__ View make_view(GInst& I) {
   v.maxw = I.maxw;
   v.first = I.first;
   return v;
+}
+
+// The tentative distance of v (the high half of its state word).
+__device__ __forceinline__ uint32_t dist_of(const SSSP_GBL uint64_t* state, int v) {
+  return ((const SSSP_GBL uint32_t*)state)[2 * v + 1];
+}
+
+// Lower v's distance to c in round rid. Returns the previous state word; the
+// decrease happened iff c is below its distance.
+__device__ __forceinline__ uint64_t relax_state(SSSP_GBL uint64_t* state, int v, uint32_t c, uint32_t rid) {
+  return atomicMin(reinterpret_cast<SSSP_GBL unsigned long long*>(state + v),
+                   ((unsigned long long)c << 32) | (unsigned long long)rid);
 }
 
 struct WaveAcc {
@@ -514,16 +517,15 @@ __device__ void stage_flush(StageLds& S, SSSP_GBL int32_t* qlist, SSSP_GBL int32
   __syncthreads();
 }
 
-// A successful decrease of dist[t] to c during round `rid`: t joins the next
-// frontier once per round (SAP) and the step's touched list once per step.
-// Convergent within a wave.
-__device__ __forceinline__ void on_success(const View& V, bool ok, int t, uint32_t c, WaveAcc& acc,
-                                           StageLds& S) {
+// A successful decrease of dist[t] to c during round `rid`, whose previous
+// decrease was in round `prev`: t joins the next frontier once per round
+// (SAP) and the step's touched list once per step. Convergent within a wave.
+__device__ __forceinline__ void on_success(const View& V, bool ok, int t, uint32_t c, uint32_t prev,
+                                           WaveAcc& acc, StageLds& S) {
   bool wq = false, wt = false;
   if (ok) {
-    uint32_t so = atomicMax(&V.stamp[t], V.rid);
-    wq = so < V.rid;
-    wt = so < V.step_rid0;
+    wq = prev != V.rid;
+    wt = prev < V.step_rid0;
     acc.success += 1;
     acc.qent += (wq ? 1 : 0) + (wt ? 1 : 0);
     if (V.first && hub_bit(V.hub_bits, t) && c < acc.hubmin) acc.hubmin = c;
@@ -619,7 +621,7 @@ __device__ __noinline__ void block_round(GInst& I, int kind, int item0, int nite
       lo = h.lo;
       sz = (h.hi_kind & 0x7fffffff) - lo;
       pull = (h.hi_kind & (int)0x80000000) != 0;
-      const uint32_t du = V.dist[u];
+      const uint32_t du = dist_of(V.state, u);
       if (pull) {
         d = du;
         want = du > lb;
@@ -648,7 +650,7 @@ __device__ __noinline__ void block_round(GInst& I, int kind, int item0, int nite
     for (int k = 0; k < kItemsPerThread; ++k) {
       const bool valid = ee[k] != ~0ull;
       const bool cand = valid && (uint32_t)(ee[k] >> 32) < reach;
-      dd[k] = cand ? V.dist[(int)(uint32_t)ee[k]] : 0u;
+      dd[k] = cand ? dist_of(V.state, (int)(uint32_t)ee[k]) : 0u;
     }
 #pragma unroll
     for (int k = 0; k < kItemsPerThread; ++k) {
@@ -675,7 +677,7 @@ __device__ __noinline__ void block_round(GInst& I, int kind, int item0, int nite
     }
     uint32_t dd[kItemsPerThread];
 #pragma unroll
-    for (int k = 0; k < kItemsPerThread; ++k) dd[k] = uu[k] >= 0 ? V.dist[uu[k]] : kInf;
+    for (int k = 0; k < kItemsPerThread; ++k) dd[k] = uu[k] >= 0 ? dist_of(V.state, uu[k]) : kInf;
 #pragma unroll
     for (int k = 0; k < kItemsPerThread; ++k) {
       const int u = uu[k];
@@ -687,7 +689,8 @@ __device__ __noinline__ void block_round(GInst& I, int kind, int item0, int nite
         // band members of the pending list join this step's touched list
         bool wt = false;
         if (ok) {
-          uint32_t so = atomicMax(&V.stamp[u], V.step_rid0);
+          // raise the round id (low half of the state word) to the step's marker
+          uint32_t so = atomicMax(&((SSSP_GBL uint32_t*)V.state)[2 * u], V.step_rid0);
           wt = so < V.step_rid0;
           acc.qent += wt ? 1 : 0;
         }
@@ -860,7 +863,7 @@ __device__ __noinline__ void block_round(GInst& I, int kind, int item0, int nite
     const int e = base + tid;
     bool ok = false;
     int t = 0;
-    uint32_t c = 0;
+    uint32_t c = 0, prev = 0;
     if (e < total) {
       int lo_j = 0, hi_j = m;  // largest j with offset[j] <= e
       while (hi_j - lo_j > 1) {
@@ -875,20 +878,21 @@ __device__ __noinline__ void block_round(GInst& I, int kind, int item0, int nite
       if (!(any_pull && L.pull[j])) {
         c = dj + w;  // < ub by the range
         t = v;
-        if (c < V.dist[v]) {
-          uint32_t old = atomicMin(&V.dist[v], c);
-          ok = c < old;
+        if (c < dist_of(V.state, v)) {
+          const uint64_t old = relax_state(V.state, v, c, V.rid);
+          ok = c < (uint32_t)(old >> 32);
+          prev = (uint32_t)old;
         }
       } else {
         // pull: the best candidate of u over this batch's edges, in LDS
-        const uint32_t dv = V.dist[v];
+        const uint32_t dv = dist_of(V.state, v);
         if (dv >= st && dv < lb) {
           unsigned long long cc = (unsigned long long)dv + w;
           if (cc < ub && cc < dj) atomicMin(&L.pmin[j], (uint32_t)cc);
         }
       }
     }
-    on_success(V, ok, t, c, acc, S);
+    on_success(V, ok, t, c, prev, acc, S);
   }
   if (any_pull) {
     // one device atomic per pulled vertex
@@ -899,16 +903,17 @@ __device__ __noinline__ void block_round(GInst& I, int kind, int item0, int nite
       const int w = base + tid;
       bool ok = false;
       int t = 0;
-      uint32_t c = 0;
+      uint32_t c = 0, prev = 0;
       if (w < m && L.pull[w]) {
         c = L.pmin[w];
         if (c < L.d[w]) {
           t = L.u[w];
-          uint32_t old = atomicMin(&V.dist[t], c);
-          ok = c < old;
+          const uint64_t old = relax_state(V.state, t, c, V.rid);
+          ok = c < (uint32_t)(old >> 32);
+          prev = (uint32_t)old;
         }
       }
-      on_success(V, ok, t, c, acc, S);
+      on_success(V, ok, t, c, prev, acc, S);
     }
   }
   stage_flush(S, qnext, &I.q_next_cnt.v, V.touched, &I.touched_cnt.v, V.n, &I.flags.v);
@@ -945,7 +950,7 @@ __device__ __noinline__ void block_settle(GInst& I, int kind, int item0, int nit
   const uint32_t nb = band < (uint32_t)kLdsRing ? band : (uint32_t)kLdsRing;
   const int nh = g.num_deg < kLdsHist ? g.num_deg : kLdsHist;
   auto dinfo = gbl(g.dinfo);
-  auto dist = gbl(I.dist);
+  auto state = gbl(I.state);
   auto ring_mass = gbl(I.ring_mass);
   auto ring_cnt = gbl(I.ring_cnt);
   auto hist_cnt = gbl(I.hist_cnt);
@@ -971,7 +976,7 @@ __device__ __noinline__ void block_settle(GInst& I, int kind, int item0, int nit
     }
     if (v >= 0) {
       // both loads in flight together: one round trip per vertex
-      d = dist[v];
+      d = dist_of(state, v);
       di = dinfo[v];
     }
   }
@@ -1182,7 +1187,6 @@ __device__ void transition(GInst& I, SSSP_GBL int32_t* cnt, SSSP_GBL int32_t* ki
     }
     if (I.first && I.ub == kInf) {
       I.phase = PH_DONE;
-      record_clean_end(I);
       return;
     }
     I.tick_kind = PH_SETTLE;
@@ -1566,8 +1570,8 @@ __global__ void __launch_bounds__(kBlock, 4) k_engine(Globals* Gp, int persisten
   }
 }
 
-// Per-solve state reset: distances, histogram, ring; stamps when their
-// counter is near wrapping. Grid-stride over every instance.
+// Per-solve state reset: state words, histogram, ring, counters. Grid-stride
+// over every selected instance.
 __global__ void k_init_arrays(Globals* Gp) {
   GGlobals& G = *gbl(Gp);
   const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1576,12 +1580,8 @@ __global__ void k_init_arrays(Globals* Gp) {
   for (int j = 0; j < nsel; ++j) {
     GInst& I = gbl(G.insts)[G.n_sel < 0 ? j : gbl(G.sel_list)[j]];
     GDevGraph& g = *gbl(I.g);
-    auto pw = gbl(I.rid_slot);
-    const bool reset_stamp = pw[PW_RID] > 0x80000000u;
-    for (long long v = tid; v < I.n; v += stride) {
-      gbl(I.dist)[v] = kInf;
-      if (reset_stamp) gbl(I.stamp)[v] = 0;
-    }
+    auto state = gbl(I.state);
+    for (long long v = tid; v < I.n; v += stride) state[v] = (unsigned long long)kInf << 32;
     for (long long x = tid; x < I.maxw; x += stride) {
       Counters z = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
       gstore(gbl(I.cslot) + x, z);
@@ -1602,14 +1602,8 @@ __global__ void __launch_bounds__(kBlock) k_init_ctl(Globals* Gp) {
     GInst& I = gbl(G.insts)[G.n_sel < 0 ? j : gbl(G.sel_list)[j]];
     GDevGraph& g = *gbl(I.g);
     if (threadIdx.x == 0) {
-      auto pw = gbl(I.rid_slot);
-      I.rid = pw[PW_RID];
-      if (I.rid > 0x80000000u) I.rid = 0;
-      // until this solve ends normally, the next one starts well above it
-      pw[PW_RID] = I.rid + (1u << 24);
       const int s = I.source;
       const int deg_s = gbl(g.rowptr)[s + 1] - gbl(g.rowptr)[s];
-      gbl(I.dist)[s] = 0;
       I.M = g.max_w;
       I.lb = 0; I.ub = kInf; I.st = 0; I.lb0 = 0;
       I.first = 1;
@@ -1633,8 +1627,9 @@ __global__ void __launch_bounds__(kBlock) k_init_ctl(Globals* Gp) {
       I.high_d0 = g.high_d0;
       Counters z = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
       gstore(&I.c, z);
-      I.step_rid0 = I.rid + 1;
-      gbl(I.stamp)[s] = I.step_rid0;
+      // round ids restart with every solve (the state words are reset)
+      I.step_rid0 = 1;
+      gbl(I.state)[s] = (unsigned long long)I.step_rid0;  // distance 0, touched in step 1
       I.rid = I.step_rid0 + 1;
       gbl(I.touched)[0] = s;
       I.touched_cnt.v = 1;
@@ -1642,7 +1637,6 @@ __global__ void __launch_bounds__(kBlock) k_init_ctl(Globals* Gp) {
       I.nF = 1;
       I.ub_next.v = is_hub(g, s) ? 0u : kInf;
       I.phase = deg_s > 0 ? PH_ROUND : PH_DONE;
-      if (deg_s == 0) record_clean_end(I);
       // first tick: the source alone
       for (int sg = 0; sg < kMaxSegPerInst; ++sg) {
         I.spec_cnt[sg] = 0;
@@ -1687,16 +1681,30 @@ __global__ void k_overflow_check(Globals* Gp) {
     bool found = false;
     for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < g.n && !found;
          v += (long long)gridDim.x * blockDim.x) {
-      if (gbl(I.dist)[v] != kInf) continue;
+      if (dist_of(gbl(I.state), (int)v) != kInf) continue;
       for (int e = gbl(g.rowptr)[v]; e < gbl(g.rowptr)[v + 1]; ++e) {
         int u = (int)(uint32_t)(gbl(g.adj)[e] & 0xffffffffull);
-        if (gbl(I.dist)[u] != kInf) {
+        if (dist_of(gbl(I.state), u) != kInf) {
           found = true;
           break;
         }
       }
     }
     if (found) atomicOr(&I.flags.v, FLAG_OVERFLOW);
+  }
+}
+
+// The distances of the selected instances into their outputs.
+__global__ void k_finish(Globals* Gp) {
+  GGlobals& G = *gbl(Gp);
+  const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  const int nsel = G.n_sel < 0 ? G.ninst : G.n_sel;
+  for (int j = 0; j < nsel; ++j) {
+    GInst& I = gbl(G.insts)[G.n_sel < 0 ? j : gbl(G.sel_list)[j]];
+    auto state = gbl(I.state);
+    auto dist = gbl(I.dist);
+    for (long long v = tid; v < I.n; v += stride) dist[v] = (uint32_t)(state[v] >> 32);
   }
 }
 
@@ -1807,8 +1815,23 @@ hipError_t add_solve_nodes(hipGraph_t graph, hipGraphNode_t dep, Globals* dG, lo
   p.kernelParams = a_g;
   e = hipGraphAddKernelNode(&n_ovf, graph, &n_eng, 1, &p);
   if (e != hipSuccess) return e;
-  *last = n_ovf;
+  hipGraphNode_t n_fin;
+  long long fb = (max_n + kBlock - 1) / kBlock;
+  fb = fb < 1 ? 1 : (fb > 8192 ? 8192 : fb);
+  p.func = reinterpret_cast<void*>(k_finish);
+  p.gridDim = dim3((unsigned)fb);
+  e = hipGraphAddKernelNode(&n_fin, graph, &n_ovf, 1, &p);
+  if (e != hipSuccess) return e;
+  *last = n_fin;
   return hipSuccess;
+}
+
+hipError_t launch_finish(Globals* dG, long long max_n, hipStream_t stream) {
+  long long blocks = (max_n + kBlock - 1) / kBlock;
+  if (blocks < 1) blocks = 1;
+  if (blocks > 8192) blocks = 8192;
+  k_finish<<<(int)blocks, kBlock, 0, stream>>>(dG);
+  return hipGetLastError();
 }
 
 hipError_t launch_overflow_check(Globals* dG, long long max_n, hipStream_t stream) {

@@ -36,7 +36,7 @@ uint32_t pow2_at_least(uint64_t x);
 struct SlotBuf {
   int32_t n_cap = 0, list_cap = 0, maxw = 0, heavy_cap = 0, hist_cap = 0, trace_cap = 0;
   uint32_t ring_cap = 0, steprec_cap = 0;
-  uint32_t* stamp = nullptr;
+  uint64_t* state = nullptr;
   int32_t* q[2] = {nullptr, nullptr};
   int32_t* touched = nullptr;
   int32_t* settled = nullptr;
@@ -48,7 +48,6 @@ struct SlotBuf {
   uint32_t* hist = nullptr;
   StepRec* steprec = nullptr;
   TraceRec* trace = nullptr;
-  uint32_t* rid = nullptr;
   Counters* cslot = nullptr;
   std::vector<void*> allocs;
   void release() {

@@ -243,6 +243,20 @@ sssp_status cycle(sssp_server* S, const std::vector<int>& fresh, std::vector<int
     HIP_TRY(hipEventRecord(S->ev, st));
     HIP_TRY(hipEventSynchronize(S->ev));
   }
+  if (!finished->empty()) {
+    // the finished queries' distances into their outputs
+    long long fn = 1;
+    for (size_t j = 0; j < finished->size(); ++j) {
+      S->h_sel[j] = (*finished)[j];
+      fn = std::max<long long>(fn, S->slot_graph[(size_t)(*finished)[j]]->gh.h.n);
+    }
+    *S->h_nsel = (int32_t)finished->size();
+    HIP_TRY(hipMemcpyAsync(S->d_sel, S->h_sel, sizeof(int32_t) * finished->size(), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(&w.dG->n_sel, S->h_nsel, sizeof(int32_t), hipMemcpyHostToDevice, st));
+    HIP_TRY(launch_finish(w.dG, fn, st));
+    HIP_TRY(hipEventRecord(S->ev, st));
+    HIP_TRY(hipEventSynchronize(S->ev));
+  }
   return ok();
 }
 
