@@ -21,6 +21,8 @@ constexpr int kStageCap = 1280;          // LDS staging of list appends per work
 constexpr int kItemsPerThread = 4;       // round batches: items per thread
 constexpr int kRoundBatch = kBlock * kItemsPerThread;  // items per workgroup batch
 constexpr int kHeavyPerBatch = 16;       // heavy chunks per workgroup batch
+constexpr int kSettlePer = 4;            // settle batches: items per thread
+constexpr int kSettleBatch = kBlock * kSettlePer;
 constexpr int kDefaultFuse = 256;        // rounds a workgroup may chain on a small frontier
 
 // ------------------------------------------------------------------ graph --

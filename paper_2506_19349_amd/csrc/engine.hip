@@ -964,29 +964,38 @@ __device__ __noinline__ void block_settle(GInst& I, int kind, int item0, int nit
   for (uint32_t k = tid; k < nb; k += kBlock) { L.mass[k] = 0; L.cnt[k] = 0; }
   for (int k = tid; k < nh; k += kBlock) L.hist[k] = 0;
   __syncthreads();
-  const int it = item0 + tid;
-  int v = -1;
-  uint32_t d = kInf;
-  uint64_t di = 0;
-  if (it < nitems) {
-    if (kind == SEG_ST) {
-      v = touched[it];
-    } else {
-      v = pcur[it];
-    }
-    if (v >= 0) {
-      // both loads in flight together: one round trip per vertex
-      d = dist_of(state, v);
-      di = dinfo[v];
+  // kSettlePer items per thread, their loads in flight together
+  int vv[kSettlePer];
+  uint32_t dd[kSettlePer];
+  uint64_t di[kSettlePer];
+#pragma unroll
+  for (int k = 0; k < kSettlePer; ++k) {
+    const int it = item0 + k * kBlock + tid;
+    vv[k] = it < nitems ? (kind == SEG_ST ? touched[it] : pcur[it]) : -1;
+  }
+#pragma unroll
+  for (int k = 0; k < kSettlePer; ++k) {
+    dd[k] = kInf;
+    di[k] = 0;
+    if (vv[k] >= 0) {
+      dd[k] = dist_of(state, vv[k]);
+      di[k] = dinfo[vv[k]];
     }
   }
-  bool settle = (kind == SEG_ST) && v >= 0 && d < ub;
-  bool pend = v >= 0 && d >= ub;
   unsigned long long sdec = 0;
   uint32_t maxd = 0;
-  if (settle) {
-    const int deg = (int)(uint32_t)di;
-    uint32_t off = d - lb;
+  int ns = 0, np = 0;
+#pragma unroll
+  for (int k = 0; k < kSettlePer; ++k) {
+    const int v = vv[k];
+    const uint32_t d = dd[k];
+    const bool settle = (kind == SEG_ST) && v >= 0 && d < ub;
+    const bool pend = v >= 0 && d >= ub;
+    ns += settle ? 1 : 0;
+    np += pend ? 1 : 0;
+    if (!settle) continue;
+    const int deg = (int)(uint32_t)di[k];
+    const uint32_t off = d - lb;
     // only the window [ub - M, ub) is read by the next computeST; the first
     // step's band may be wider, and older values would alias ring slots
     if ((unsigned long long)d + M >= ub) {
@@ -998,29 +1007,33 @@ __device__ __noinline__ void block_settle(GInst& I, int kind, int item0, int nit
         atomicAdd(&ring_cnt[d & ring_mask], 1u);
       }
     }
-    const int r = (int)(di >> 32);
+    const int r = (int)(di[k] >> 32);
     if (r >= 0) {
       if (r < nh) atomicAdd(&L.hist[r], 1u); else atomicSub(&hist_cnt[r], 1u);
     }
-    sdec = (unsigned long long)deg;
-    maxd = d;
+    sdec += (unsigned long long)deg;
+    maxd = d > maxd ? d : maxd;
   }
   // one atomic per workgroup and list
   int tot_s, tot_p;
-  const int off_s = block_excl_scan<int>(settle ? 1 : 0, L.iscan, &tot_s);
-  const int off_p = block_excl_scan<int>(pend ? 1 : 0, L.iscan, &tot_p);
+  int off_s = block_excl_scan<int>(ns, L.iscan, &tot_s);
+  int off_p = block_excl_scan<int>(np, L.iscan, &tot_p);
   if (tid == 0) {
     L.base[0] = tot_s ? atomicAdd(&I.settled_cnt.v, tot_s) : 0;
     L.base[1] = tot_p ? atomicAdd(&I.p_next_cnt.v, tot_p) : 0;
   }
   __syncthreads();
-  if (settle) {
-    int p = L.base[0] + off_s;
-    if (p < n) settled[p] = v; else atomicOr(&I.flags.v, FLAG_CAPACITY);
-  }
-  if (pend) {
-    int q = L.base[1] + off_p;
-    if (q < n) pnext[q] = v; else atomicOr(&I.flags.v, FLAG_CAPACITY);
+#pragma unroll
+  for (int k = 0; k < kSettlePer; ++k) {
+    const int v = vv[k];
+    if (v < 0) continue;
+    if (kind == SEG_ST && dd[k] < ub) {
+      const int p = L.base[0] + off_s++;
+      if (p < n) settled[p] = v; else atomicOr(&I.flags.v, FLAG_CAPACITY);
+    } else if (dd[k] >= ub) {
+      const int q = L.base[1] + off_p++;
+      if (q < n) pnext[q] = v; else atomicOr(&I.flags.v, FLAG_CAPACITY);
+    }
   }
   unsigned long long ws = wave_sum(sdec);
   uint32_t wm = maxd;
@@ -1029,7 +1042,7 @@ __device__ __noinline__ void block_settle(GInst& I, int kind, int item0, int nit
     uint32_t y = __shfl_xor(wm, o, kWave);
     wm = y > wm ? y : wm;
   }
-  unsigned long long qe = wave_sum((unsigned long long)(settle ? 1 : 0) + (pend ? 1 : 0));
+  unsigned long long qe = wave_sum((unsigned long long)(ns + np));
   if (lane_id() == 0) {
     L.sdec[tid / kWave] = ws;
     L.maxd[tid / kWave] = wm;
@@ -1194,14 +1207,14 @@ __device__ void transition(GInst& I, SSSP_GBL int32_t* cnt, SSSP_GBL int32_t* ki
     I.nT = min(I.touched_cnt.v, I.n);
     I.settled_mark = min(I.settled_cnt.v, I.n);
     I.settle_done.v = 0;
-    int bt = (I.nT + kBlock - 1) / kBlock;
+    int bt = (I.nT + kSettleBatch - 1) / kSettleBatch;
     if (bt < 1) bt = 1;
-    int bp = (I.nP + kBlock - 1) / kBlock;
+    int bp = (I.nP + kSettleBatch - 1) / kSettleBatch;
     I.settle_items = bt + bp;
     // a settle tick always has at least one batch so that the heuristic runs:
     // -1 marks one empty batch
-    cnt[0] = I.nT == 0 ? -1 : I.nT; kinds[0] = SEG_ST;
-    cnt[1] = I.nP; kinds[1] = SEG_SP;
+    cnt[0] = I.nT == 0 ? -1 : I.nT; kinds[0] = SEG_ST; pbs[0] = kSettleBatch;
+    cnt[1] = I.nP; kinds[1] = SEG_SP; pbs[1] = kSettleBatch;
     return;
   }
   // a settle tick ran; the heuristic has set phase to ROUND or DONE
