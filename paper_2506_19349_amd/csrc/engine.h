@@ -34,7 +34,7 @@ struct DevGraph {
   int32_t num_deg;       // distinct degrees >= 1 (D)
   int32_t n_nonisolated;
   int32_t max_deg;
-  int32_t pad;
+  uint32_t rwi_width;        // weight width of the row-index buckets: ceil((maxW + 1) / 16)
   const int32_t* rowptr;     // n + 1
   const uint64_t* adj;       // nnz entries, (weight << 32) | column, each row ascending
   const uint32_t* wmin;      // n: smallest weight of the row (kInf for degree 0)
@@ -44,7 +44,12 @@ struct DevGraph {
   const uint32_t* hub_bits;  // ceil(n/32) words: deg(v) >= highD(0)
   const uint64_t* nonisolated;  // n_nonisolated entries (wmin << 32) | id, ascending id
   const uint32_t* rtow;      // 4096
+  // per row, 16 int32: entry b - 1 (b = 1..15) is the first position of the
+  // row whose weight is >= b * rwi_width (entry 15 unused). Written for rows
+  // longer than kRowIndexMin only.
+  const int32_t* rwi;
 };
+constexpr int kRowIndexMin = 8;
 
 // ------------------------------------------------------- solver instance --
 enum Phase : uint32_t { PH_ROUND = 0, PH_SETTLE = 1, PH_DONE = 2 };

@@ -358,6 +358,7 @@ struct View {
   const SSSP_GBL uint64_t* adj;
   const SSSP_GBL uint32_t* wmin;
   const SSSP_GBL uint32_t* hub_bits;
+  const SSSP_GBL int32_t* rwi;
   SSSP_GBL uint64_t* state;
   SSSP_GBL int32_t* q_next;
   SSSP_GBL int32_t* touched;
@@ -365,6 +366,7 @@ struct View {
   uint32_t lb, ub, st, lb0, rid, step_rid0;
   int32_t n, heavy_split, maxw;
   uint32_t first;
+  uint32_t rwi_width;
 };
 
 __device__ __forceinline__ View make_view(GInst& I) {
@@ -374,6 +376,8 @@ __device__ __forceinline__ View make_view(GInst& I) {
   v.adj = gbl(g.adj);
   v.wmin = gbl(g.wmin);
   v.hub_bits = gbl(g.hub_bits);
+  v.rwi = gbl(g.rwi);
+  v.rwi_width = g.rwi_width;
   v.state = gbl(I.state);
   v.q_next = gbl(I.q[I.qsel ^ 1]);
   v.touched = gbl(I.touched);
@@ -704,108 +708,88 @@ __device__ __noinline__ void block_round(GInst& I, int kind, int item0, int nite
   for (int w = tid; w < m; w += kBlock) L.pmin[w] = kInf;
 
   // ---------------------------------------------------------- phase 2a: ranges
-  // Each thread finds the ranges of its kItemsPerThread items together: the
-  // row bounds of all of them are loaded at once, and their binary searches
-  // advance in lockstep, so the loads of one step are in flight together.
+  // An item's range is [first weight >= lo key, first weight >= hi key) of
+  // its weight-sorted row (lo key lb - d for a push, 0 for a pull; hi key
+  // ub - d for a push, ub - st for a pull). The row index narrows each of the
+  // two searches to one weight bucket (about deg/16 entries); the bounds of
+  // those buckets are loaded together with the row bounds. Then a thread's
+  // eight searches (two per item) bisect in lockstep, so the loads of one step
+  // are in flight together.
   {
-    int wi[kItemsPerThread], a[kItemsPerThread], b[kItemsPerThread], rs[kItemsPerThread],
-        re[kItemsPerThread];
-    uint32_t wmn[kItemsPerThread];
-    uint64_t key[kItemsPerThread];
-    bool need[kItemsPerThread];  // item whose range this thread has to find
-    bool leaf[kItemsPerThread];
+    constexpr int K2 = 2 * kItemsPerThread;
+    int wi[kItemsPerThread], rs[kItemsPerThread], re[kItemsPerThread];
+    int pb[K2][2];  // bucket bounds (positions) of each search
+    uint32_t key[K2];
+    bool need[kItemsPerThread], leaf[kItemsPerThread];
+    const uint32_t W = V.rwi_width;
 #pragma unroll
     for (int k = 0; k < kItemsPerThread; ++k) {
       wi[k] = tid + k * kBlock;
       need[k] = wi[k] < m && L.sz[wi[k]] < 0;  // heavy chunks come with their range
       rs[k] = re[k] = 0;
-      wmn[k] = 0;
-      if (need[k]) {
-        const int u = L.u[wi[k]];
-        rs[k] = V.rowptr[u];
-        re[k] = V.rowptr[u + 1];
-        wmn[k] = V.wmin[u];
-      }
-    }
-    // range start: the pull scans the row's prefix; a push starts at the
-    // first weight >= lb - d (binary search unless the row starts there)
-#pragma unroll
-    for (int k = 0; k < kItemsPerThread; ++k) {
-      a[k] = b[k] = rs[k];
-      key[k] = 0;
-      leaf[k] = false;
+      key[2 * k] = key[2 * k + 1] = 0;
+      pb[2 * k][0] = pb[2 * k][1] = pb[2 * k + 1][0] = pb[2 * k + 1][1] = 0;
       if (!need[k]) continue;
+      const int u = L.u[wi[k]];
       const uint32_t d = L.d[wi[k]];
-      if (L.pull[wi[k]]) continue;
-      leaf[k] = (re[k] - rs[k] == 1 && d > 0);  // leaf pruning (Algorithm)
-      const uint32_t wl = lb > d ? lb - d : 0u;
-      if (!leaf[k] && wl > wmn[k]) {
-        b[k] = re[k];
-        key[k] = (uint64_t)wl << 32;
+      const bool pull = L.pull[wi[k]] != 0;
+      key[2 * k] = pull ? 0u : (lb > d ? lb - d : 0u);
+      key[2 * k + 1] = pull ? ub - st : ub - d;
+      rs[k] = V.rowptr[u];
+      re[k] = V.rowptr[u + 1];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        // bucket b (clamped to 16: past the last boundary) spans
+        // [P[b], P[b + 1]], P[b] at rwi[16 u + b - 1] for b in 1..15 (P[0] and
+        // P[16] are the row ends; -1 marks "use the row end")
+        const uint32_t b = min(key[2 * k + h] / W, 16u);
+        const SSSP_GBL int32_t* P = V.rwi + 16ll * u;
+        pb[2 * k + h][0] = (b >= 1u && b <= 15u) ? P[b - 1u] : -1;
+        pb[2 * k + h][1] = (b <= 14u) ? P[b] : -1;
       }
     }
-    for (;;) {
-      int mid[kItemsPerThread];
-      uint64_t val[kItemsPerThread];
-      bool any = false;
-#pragma unroll
-      for (int k = 0; k < kItemsPerThread; ++k) {
-        if (a[k] < b[k]) {
-          mid[k] = (a[k] + b[k]) >> 1;
-          val[k] = V.adj[mid[k]];
-          any = true;
-        }
-      }
-      if (!any) break;
-#pragma unroll
-      for (int k = 0; k < kItemsPerThread; ++k) {
-        if (a[k] < b[k]) {
-          if (val[k] < key[k]) a[k] = mid[k] + 1; else b[k] = mid[k];
-        }
-      }
-    }
-    // range end: the first weight >= the bound (ub - st for a pull, ub - d
-    // for a push); the next kProbe entries are read at once, then bisection
-    int lo[kItemsPerThread], hi[kItemsPerThread];
+    int a[K2], c[K2];
 #pragma unroll
     for (int k = 0; k < kItemsPerThread; ++k) {
-      lo[k] = a[k];
-      hi[k] = a[k];
-      key[k] = 0;
-      if (!need[k] || leaf[k]) continue;
-      const uint32_t bound = L.pull[wi[k]] ? ub - st : ub - L.d[wi[k]];
-      key[k] = (uint64_t)bound << 32;
-      const int lim = min(re[k], lo[k] + kProbe);
-      int cnt = 0;
+      leaf[k] = false;
 #pragma unroll
-      for (int i2 = 0; i2 < kProbe; ++i2)
-        if (lo[k] + i2 < lim) cnt += V.adj[lo[k] + i2] < key[k] ? 1 : 0;
-      hi[k] = lo[k] + cnt;
-      // a full probe that did not reach the row's end continues by bisection
-      a[k] = b[k] = 0;
-      if (!(lo[k] + cnt < lim || lim == re[k])) {
-        a[k] = lim;
-        b[k] = re[k];
+      for (int h = 0; h < 2; ++h) {
+        a[2 * k + h] = c[2 * k + h] = rs[k];
+        if (!need[k]) continue;
+        const uint32_t kk = key[2 * k + h];
+        const uint32_t b = min(kk / W, 16u);
+        if (re[k] - rs[k] <= kRowIndexMin) {
+          a[2 * k + h] = rs[k];
+          c[2 * k + h] = re[k];
+        } else {
+          a[2 * k + h] = b == 0u ? rs[k] : (b >= 16u ? re[k] : pb[2 * k + h][0]);
+          c[2 * k + h] = b >= 15u ? re[k] : pb[2 * k + h][1];
+        }
+        if (h == 0 && kk == 0) c[2 * k] = a[2 * k] = rs[k];  // starts at the row start
+      }
+      if (need[k] && !L.pull[wi[k]]) {
+        leaf[k] = (re[k] - rs[k] == 1 && L.d[wi[k]] > 0);  // leaf pruning (Algorithm)
+        if (leaf[k]) a[2 * k] = c[2 * k] = a[2 * k + 1] = c[2 * k + 1] = rs[k];
       }
     }
+    const SSSP_GBL uint32_t* wts = (const SSSP_GBL uint32_t*)V.adj;  // weight: high half of an entry
     for (;;) {
-      int mid[kItemsPerThread];
-      uint64_t val[kItemsPerThread];
+      int mid[K2];
+      uint32_t val[K2];
       bool any = false;
 #pragma unroll
-      for (int k = 0; k < kItemsPerThread; ++k) {
-        if (a[k] < b[k]) {
-          mid[k] = (a[k] + b[k]) >> 1;
-          val[k] = V.adj[mid[k]];
+      for (int x = 0; x < K2; ++x) {
+        if (a[x] < c[x]) {
+          mid[x] = (a[x] + c[x]) >> 1;
+          val[x] = wts[2ll * mid[x] + 1];
           any = true;
         }
       }
       if (!any) break;
 #pragma unroll
-      for (int k = 0; k < kItemsPerThread; ++k) {
-        if (a[k] < b[k]) {
-          if (val[k] < key[k]) a[k] = mid[k] + 1; else b[k] = mid[k];
-          if (a[k] >= b[k]) hi[k] = a[k];
+      for (int x = 0; x < K2; ++x) {
+        if (a[x] < c[x]) {
+          if (val[x] < key[x]) a[x] = mid[x] + 1; else c[x] = mid[x];
         }
       }
     }
@@ -815,20 +799,22 @@ __device__ __noinline__ void block_round(GInst& I, int kind, int item0, int nite
       const int w = wi[k];
       const bool pull = L.pull[w] != 0;
       const uint32_t d = L.d[w];
+      const int lo = a[2 * k];
+      const int hi = leaf[k] ? lo : max(lo, a[2 * k + 1]);
       if (pull) {
-        acc.pullscan += (unsigned long long)(hi[k] - lo[k]);
+        acc.pullscan += (unsigned long long)(hi - lo);
       } else if (!leaf[k]) {
-        if (ub == kInf && hi[k] < re[k]) atomicOr(&I.flags.v, FLAG_MAYBE_OVERFLOW);
+        if (ub == kInf && hi < re[k]) atomicOr(&I.flags.v, FLAG_MAYBE_OVERFLOW);
         acc.expansions += 1;
         acc.band += (d >= lb) ? 1 : 0;
-        acc.pscan += (unsigned long long)(hi[k] - lo[k]);
+        acc.pscan += (unsigned long long)(hi - lo);
       }
-      int size = hi[k] - lo[k];
+      int size = hi - lo;
       if (size > V.heavy_split) {
-        emit_heavy(I, L.u[w], d, lo[k], hi[k], pull);
+        emit_heavy(I, L.u[w], d, lo, hi, pull);
         size = 0;
       }
-      L.lo[w] = lo[k];
+      L.lo[w] = lo;
       L.sz[w] = size;
     }
   }

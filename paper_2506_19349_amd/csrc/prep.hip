@@ -278,6 +278,34 @@ __global__ void k_deg_rank(const int32_t* rowptr, int32_t n, const int32_t* rank
   }
 }
 
+// Row index: per row, the first position of each weight bucket boundary, so
+// that a weight range search starts inside a bucket of about deg/16 entries.
+__global__ void k_row_index(const int32_t* rowptr, const uint64_t* adj, int32_t n, uint32_t width,
+                            int32_t* rwi) {
+  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+       v += (long long)gridDim.x * blockDim.x) {
+    const int rs = rowptr[v], re = rowptr[v + 1];
+    if (re - rs <= kRowIndexMin) continue;
+    int lo = rs;
+    for (int b = 1; b < 16; ++b) {
+      const unsigned long long t = (unsigned long long)b * width;
+      int pos = re;
+      if (t <= 0xffffffffull) {
+        const uint64_t key = t << 32;
+        int a = lo, c = re;  // positions only grow with b
+        while (a < c) {
+          const int mid = (a + c) >> 1;
+          if (adj[mid] < key) a = mid + 1; else c = mid;
+        }
+        pos = a;
+      }
+      rwi[v * 16 + (b - 1)] = pos;
+      lo = pos;
+    }
+    rwi[v * 16 + 15] = re;
+  }
+}
+
 __global__ void k_hub_bits(const int32_t* rowptr, int32_t n, uint32_t hd, uint32_t* bits) {
   const int nw = (n + 31) / 32;
   const int thr = hd < 1u ? 1 : (int)hd;
@@ -489,6 +517,7 @@ int prep_graph(int32_t n, const int32_t* rowptr_in, const int32_t* col_in, const
   uint64_t* dinfo = A.get<uint64_t>((size_t)n);
   uint32_t* hub = A.get<uint32_t>(((size_t)n + 31) / 32);
   uint32_t* rtow = A.get<uint32_t>(kRatioNum);
+  int32_t* rwi = A.get<int32_t>((size_t)n * 16);
   if (!A.ok) {
     *msg = "device allocation failed";
     return -5;
@@ -719,6 +748,9 @@ int prep_graph(int32_t n, const int32_t* rowptr_in, const int32_t* col_in, const
   }
   k_hub_bits<<<grid_for((n + 31) / 32), kBlock>>>(rowptr, n, high_d0, hub);
   PREP_CHECK(hipGetLastError());
+  const uint32_t rwi_width = (uint32_t)(((unsigned long long)maxw + 16ull) / 16ull);
+  k_row_index<<<grid_for(n), kBlock>>>(rowptr, adj, n, rwi_width, rwi);
+  PREP_CHECK(hipGetLastError());
   // non-isolated vertices in ascending order
   const int nb = (int)(((long long)n + kCompactPer - 1) / kCompactPer);
   int32_t* bcnt = T.get<int32_t>((size_t)nb);
@@ -811,6 +843,8 @@ int prep_graph(int32_t n, const int32_t* rowptr_in, const int32_t* col_in, const
   h.hub_bits = hub;
   h.nonisolated = noniso;
   h.rtow = rtow;
+  h.rwi = rwi;
+  h.rwi_width = rwi_width;
   out->d = A.get<DevGraph>(1);
   if (!A.ok) {
     *msg = "device allocation failed";
