@@ -773,6 +773,33 @@ __device__ __noinline__ void block_round(GInst& I, int kind, int item0, int nite
       }
     }
     const SSSP_GBL uint32_t* wts = (const SSSP_GBL uint32_t*)V.adj;  // weight: high half of an entry
+    // rows of at most kRowIndexMin entries: one probe of the whole row answers
+    // both searches
+#pragma unroll
+    for (int k0 = 0; k0 < kItemsPerThread; k0 += 2) {  // two items at a time (registers)
+      uint32_t pw[2][kRowIndexMin];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int k = k0 + j;
+        const bool small = need[k] && re[k] - rs[k] <= kRowIndexMin;
+#pragma unroll
+        for (int i = 0; i < kRowIndexMin; ++i)
+          pw[j][i] = (small && rs[k] + i < re[k]) ? wts[2ll * (rs[k] + i) + 1] : 0xffffffffu;
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int k = k0 + j;
+        if (!(need[k] && re[k] - rs[k] <= kRowIndexMin) || leaf[k]) continue;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          if (a[2 * k + h] >= c[2 * k + h]) continue;  // already decided (row start)
+          int cnt = 0;
+#pragma unroll
+          for (int i = 0; i < kRowIndexMin; ++i) cnt += pw[j][i] < key[2 * k + h] ? 1 : 0;
+          a[2 * k + h] = c[2 * k + h] = rs[k] + cnt;
+        }
+      }
+    }
     for (;;) {
       int mid[K2];
       uint32_t val[K2];
