@@ -351,7 +351,7 @@ def main():
         parity = bool(np.array_equal(ref, outs[0].cpu().numpy()))
         cpu = {"value": round(m_cc[-1] / dt / 1e9, 6), "unit": "GTEPS", "cores": 1, "kind": "oracle",
                "sample": "binary-heap Dijkstra (the oracle), 1 thread, one source of the same "
-                         "RMAT-24 graph, %.1f s; GPU result for it bit-exact: %s" % (dt, parity)}
+                         "%s graph, %.1f s; GPU result for it bit-exact: %s" % (wl.name, dt, parity)}
         log("oracle: %.2f s for one source -> %.4f GTEPS; GPU bit-exact: %s" % (dt, cpu["value"], parity))
 
     if args.calibrate_copy:
