@@ -338,6 +338,26 @@ def main():
     log("GTEPS %.2f, engine %.1f us/solve, alg bytes %.1f MB/solve -> %.1f GB/s"
         % (gteps, eng_mean_us, sum(B) / len(B) / 1e6, achieved))
 
+    # ablation: the traversal-optimisation filter off (st = lb in every step;
+    # same distances, more edges traversed)
+    ab_src = timed[:4]
+    ab_out = torch.empty(csr.n, dtype=torch.uint32, device="cuda")
+    g.solve(ab_src[0], out=ab_out, traversal_opt=False)
+    torch.cuda.synchronize()
+    t0a = time.perf_counter()
+    for s in ab_src:
+        g.solve(s, out=ab_out, traversal_opt=False)
+    torch.cuda.synchronize()
+    dt_off = (time.perf_counter() - t0a) / len(ab_src)
+    c_off = sssp.counters()
+    n_reach_off = int((ab_out.cpu().numpy() != INF).sum())
+    del ab_out
+    ablation = {"traversal_opt": False, "gteps": round(sum(m_cc[:len(ab_src)]) / len(ab_src) / dt_off / 1e9, 3),
+                "ms_per_step": round(dt_off * 1e3, 4),
+                "nTrav": round((c_off["push_scanned"] + c_off["pull_scanned"]) / max(n_reach_off, 1), 3)}
+    sssp.engine_times()
+    log("filter off: %.2f GTEPS, nTrav %.2f" % (ablation["gteps"], ablation["nTrav"]))
+
     cpu = None
     if not args.no_cpu_baseline:
         from oracle import native  # CPU baseline leg only
@@ -405,6 +425,7 @@ def main():
                      "kernel": "k_engine", "kernel_us_mean": round(eng_mean_us, 2),
                      "alg_bytes_per_launch": int(sum(B) / len(B))},
         "cpu_baseline": cpu,
+        "ablation_filter_off": ablation,
         "batched": batched,
         "served": served,
         "prep_s": round(prep_s, 4),
