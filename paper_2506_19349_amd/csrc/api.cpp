@@ -75,7 +75,7 @@ size_t needs_bytes(const Needs& m) {
   size_t b = 0;
   b += sizeof(uint64_t) * (size_t)m.n;             // state
   b += sizeof(int32_t) * (size_t)m.list * 3;       // q[2], touched
-  b += sizeof(uint64_t) * (size_t)m.list * 2;      // ulist[2]
+  b += sizeof(UEntry) * (size_t)m.list * 2;        // ulist[2]
   b += sizeof(int32_t) * (size_t)m.n * 3;          // settled, plist[2]
   b += sizeof(Counters) * (size_t)m.maxw;
   b += sizeof(HeavyItem) * (size_t)m.heavy * 2;

@@ -26,6 +26,15 @@ constexpr int kSettleBatch = kBlock * kSettlePer;
 constexpr int kDefaultFuse = 256;        // rounds a workgroup may chain on a small frontier
 
 // ------------------------------------------------------------------ graph --
+// An unsettled-list (pull-list) entry: the vertex, the smallest weight of its
+// row and the row's bounds, so that the pull reads no per-vertex array before
+// deciding and searching.
+struct alignas(16) UEntry {
+  int32_t id;
+  uint32_t wmin;
+  int32_t rs, re;
+};
+
 struct DevGraph {
   int32_t n;
   int32_t nnz;
@@ -42,7 +51,7 @@ struct DevGraph {
   const int32_t* deg_vals;   // D ascending distinct degrees
   const uint32_t* deg_cnt0;  // D: vertices with that degree
   const uint32_t* hub_bits;  // ceil(n/32) words: deg(v) >= highD(0)
-  const uint64_t* nonisolated;  // n_nonisolated entries (wmin << 32) | id, ascending id
+  const UEntry* nonisolated;  // n_nonisolated entries, ascending id
   const uint32_t* rtow;      // 4096
   // per row, 16 int32: entry b - 1 (b = 1..15) is the first position of the
   // row whose weight is >= b * rwi_width (entry 15 unused). Written for rows
@@ -116,7 +125,7 @@ struct Inst {
   int32_t* touched;
   int32_t* settled;
   int32_t* plist[2];
-  uint64_t* ulist[2];      // unsettled (pull) list entries (wmin << 32) | id
+  UEntry* ulist[2];        // unsettled (pull) lists
   HeavyItem* heavy[2];
   uint64_t* ring_mass;
   uint32_t* ring_cnt;

@@ -462,25 +462,10 @@ __device__ __forceinline__ void stage_append(int32_t* buf, int32_t* cnt, bool wa
   if (want) buf[base + __popcll(m & lanemask_lt())] = val;
 }
 
-// Convergent within a wave: a (lo, hi) pair takes one slot of q / t (the
-// pull phase stages its surviving unsettled-list entries this way).
-__device__ __forceinline__ void stage_append_pair(StageLds& S, bool want, int32_t lo, int32_t hi) {
-  uint64_t m = __ballot(want);
-  if (m == 0) return;
-  int base = 0;
-  const int leader = __ffsll((unsigned long long)m) - 1;
-  if (lane_id() == leader) base = atomicAdd(&S.nq, __popcll(m));
-  base = __shfl(base, leader, kWave);
-  if (want) {
-    const int pos = base + __popcll(m & lanemask_lt());
-    S.q[pos] = lo;
-    S.t[pos] = hi;
-  }
-}
-
-// Whole workgroup: write the staged pairs as (hi << 32) | lo entries.
-__device__ void stage_flush_pairs(StageLds& S, SSSP_GBL uint64_t* list, SSSP_GBL int32_t* cnt, int cap,
-                                  SSSP_GBL uint32_t* flags) {
+// Whole workgroup: copy the pull-list entries whose positions in `src` were
+// staged in q to `dst`.
+__device__ void stage_flush_entries(StageLds& S, const SSSP_GBL UEntry* src, SSSP_GBL UEntry* dst,
+                                    SSSP_GBL int32_t* cnt, int cap, SSSP_GBL uint32_t* flags) {
   __syncthreads();
   const int np = S.nq;
   if (threadIdx.x == 0) {
@@ -490,7 +475,7 @@ __device__ void stage_flush_pairs(StageLds& S, SSSP_GBL uint64_t* list, SSSP_GBL
   __syncthreads();
   const int b = S.base_q;
   for (int i = threadIdx.x; i < np; i += kBlock)
-    if (b + i < cap) list[b + i] = ((uint64_t)(uint32_t)S.t[i] << 32) | (uint64_t)(uint32_t)S.q[i];
+    if (b + i < cap) gstore(dst + b + i, gload(src + S.q[i]));
   __syncthreads();
   if (threadIdx.x == 0) S.nq = 0;
   __syncthreads();
@@ -573,6 +558,7 @@ struct RoundLds {
   uint32_t d[kRoundBatch];
   uint32_t pmin[kRoundBatch];  // pull items: best candidate for dist[u] found in this batch
   int32_t lo[kRoundBatch];
+  int32_t re[kRoundBatch];  // row end when the row is known (pull-list items), else -1
   int32_t sz[kRoundBatch];  // size, -1 = range still to find; then exclusive offsets
   uint8_t pull[kRoundBatch];
   int32_t count;
@@ -581,7 +567,7 @@ struct RoundLds {
 };
 
 __device__ __forceinline__ void lds_push_item(RoundLds& L, bool want, int u, uint32_t d, int lo,
-                                              int sz, bool pull) {
+                                              int sz, bool pull, int re = -1) {
   uint64_t m = __ballot(want);
   if (m == 0) return;
   int base = 0;
@@ -593,6 +579,7 @@ __device__ __forceinline__ void lds_push_item(RoundLds& L, bool want, int u, uin
     L.u[w] = u;
     L.d[w] = d;
     L.lo[w] = lo;
+    L.re[w] = re;
     L.sz[w] = sz;
     L.pull[w] = pull ? 1 : 0;
   }
@@ -636,40 +623,40 @@ __device__ __noinline__ void block_round(GInst& I, int kind, int item0, int nite
     }
     lds_push_item(L, want, u, d, lo, sz, pull);
   } else if (kind == SEG_U) {
-    // unsettled-list entries carry the row's smallest weight: an entry whose
-    // lightest edge cannot reach below ub from a settled vertex (>= st) is
-    // kept without reading its distance
+    // unsettled-list entries carry the row's smallest weight and bounds: an
+    // entry whose lightest edge cannot reach below ub from a settled vertex
+    // (>= st) is kept without reading its distance
     const int usel = I.usel;
-    const SSSP_GBL uint64_t* ucur = usel < 0 ? gbl(gbl(I.g)->nonisolated) : gbl(I.ulist[usel]);
+    const SSSP_GBL UEntry* ucur = usel < 0 ? gbl(gbl(I.g)->nonisolated) : gbl(I.ulist[usel]);
     auto unext = gbl(I.ulist[usel < 0 ? 0 : (usel ^ 1)]);
     const uint32_t reach = ub - st;
-    uint64_t ee[kItemsPerThread];
+    UEntry ee[kItemsPerThread];
+    bool valid[kItemsPerThread];
 #pragma unroll
     for (int k = 0; k < kItemsPerThread; ++k) {
       const int it = item0 + k * kBlock + tid;
-      ee[k] = it < nitems ? ucur[it] : ~0ull;
+      valid[k] = it < nitems;
+      if (valid[k]) ee[k] = gload(ucur + it);
     }
     uint32_t dd[kItemsPerThread];
 #pragma unroll
     for (int k = 0; k < kItemsPerThread; ++k) {
-      const bool valid = ee[k] != ~0ull;
-      const bool cand = valid && (uint32_t)(ee[k] >> 32) < reach;
-      dd[k] = cand ? dist_of(V.state, (int)(uint32_t)ee[k]) : 0u;
+      const bool cand = valid[k] && ee[k].wmin < reach;
+      dd[k] = cand ? dist_of(V.state, ee[k].id) : 0u;
     }
 #pragma unroll
     for (int k = 0; k < kItemsPerThread; ++k) {
-      const bool valid = ee[k] != ~0ull;
-      const int u = (int)(uint32_t)ee[k];
-      const uint32_t wm = (uint32_t)(ee[k] >> 32);
-      const bool cand = valid && wm < reach;
-      const bool keep = valid && (!cand || dd[k] >= lb);
+      const int it = item0 + k * kBlock + tid;
+      const bool cand = valid[k] && ee[k].wmin < reach;
+      const bool keep = valid[k] && (!cand || dd[k] >= lb);
       const bool active = cand && dd[k] > lb;
-      acc.pvert += valid ? 1 : 0;
-      stage_append_pair(S, keep, u, (int32_t)wm);
-      lds_push_item(L, active, u, dd[k], 0, -1, true);
+      acc.pvert += valid[k] ? 1 : 0;
+      stage_append(S.q, &S.nq, keep, it);
+      lds_push_item(L, active, valid[k] ? ee[k].id : 0, dd[k], valid[k] ? ee[k].rs : 0, -1, true,
+                    valid[k] ? ee[k].re : -1);
     }
     // the surviving pull list goes out now; the stage is free for phase 2
-    stage_flush_pairs(S, unext, &I.u_next_cnt.v, V.n, &I.flags.v);
+    stage_flush_entries(S, ucur, unext, &I.u_next_cnt.v, V.n, &I.flags.v);
   } else {
     int uu[kItemsPerThread];
     const SSSP_GBL int32_t* src = (kind == SEG_W) ? gbl(I.settled) + I.wBegin
@@ -735,8 +722,14 @@ __device__ __noinline__ void block_round(GInst& I, int kind, int item0, int nite
       const bool pull = L.pull[wi[k]] != 0;
       key[2 * k] = pull ? 0u : (lb > d ? lb - d : 0u);
       key[2 * k + 1] = pull ? ub - st : ub - d;
-      rs[k] = V.rowptr[u];
-      re[k] = V.rowptr[u + 1];
+      // row bounds: carried by pull-list items, else loaded
+      const int kre = L.re[wi[k]];
+      const bool known = kre >= 0;
+      rs[k] = known ? L.lo[wi[k]] : V.rowptr[u];
+      re[k] = known ? kre : V.rowptr[u + 1];
+      // the bucket bounds are loaded with the row bounds (a known short row
+      // needs none)
+      const bool idx = !known || kre - L.lo[wi[k]] > kRowIndexMin;
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         // bucket b (clamped to 16: past the last boundary) spans
@@ -744,8 +737,8 @@ __device__ __noinline__ void block_round(GInst& I, int kind, int item0, int nite
         // P[16] are the row ends; -1 marks "use the row end")
         const uint32_t b = min(key[2 * k + h] / W, 16u);
         const SSSP_GBL int32_t* P = V.rwi + 16ll * u;
-        pb[2 * k + h][0] = (b >= 1u && b <= 15u) ? P[b - 1u] : -1;
-        pb[2 * k + h][1] = (b <= 14u) ? P[b] : -1;
+        pb[2 * k + h][0] = (idx && b >= 1u && b <= 15u) ? P[b - 1u] : -1;
+        pb[2 * k + h][1] = (idx && b <= 14u) ? P[b] : -1;
       }
     }
     int a[K2], c[K2];

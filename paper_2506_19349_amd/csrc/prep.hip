@@ -320,9 +320,9 @@ __global__ void k_hub_bits(const int32_t* rowptr, int32_t n, uint32_t hd, uint32
   }
 }
 
-// Ordered compaction of the vertices with degree >= 1, each packed with the
-// smallest weight of its row as (wmin << 32) | id: per-block counts, then
-// per-block writes at the scanned offsets.
+// Ordered compaction of the vertices with degree >= 1 into pull-list entries
+// (id, smallest weight, row bounds): per-block counts, then per-block writes
+// at the scanned offsets.
 constexpr int kCompactPer = kBlock * 8;
 
 __global__ void __launch_bounds__(kBlock) k_noniso_count(const int32_t* rowptr, int32_t n, int32_t* bcnt) {
@@ -341,7 +341,7 @@ __global__ void __launch_bounds__(kBlock) k_noniso_count(const int32_t* rowptr, 
 }
 
 __global__ void __launch_bounds__(kBlock) k_noniso_write(const int32_t* rowptr, const uint32_t* wmin,
-                                                         int32_t n, const int32_t* boff, uint64_t* out) {
+                                                         int32_t n, const int32_t* boff, UEntry* out) {
   __shared__ int wsum[kBlock / kWave];
   __shared__ int run;
   if (threadIdx.x == 0) run = boff[blockIdx.x];
@@ -357,7 +357,14 @@ __global__ void __launch_bounds__(kBlock) k_noniso_write(const int32_t* rowptr, 
     __syncthreads();
     int woff = 0;
     for (int w2 = 0; w2 < wid; ++w2) woff += wsum[w2];
-    if (f) out[run + woff + pre] = ((uint64_t)wmin[v] << 32) | (uint64_t)(uint32_t)v;
+    if (f) {
+      UEntry e;
+      e.id = (int32_t)v;
+      e.wmin = wmin[v];
+      e.rs = rowptr[v];
+      e.re = rowptr[v + 1];
+      out[run + woff + pre] = e;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
       int t = 0;
@@ -769,7 +776,7 @@ int prep_graph(int32_t n, const int32_t* rowptr_in, const int32_t* col_in, const
     run += c;
   }
   const int32_t nonisolated = run;
-  uint64_t* noniso = A.get<uint64_t>(std::max<int32_t>(nonisolated, 1));
+  UEntry* noniso = A.get<UEntry>(std::max<int32_t>(nonisolated, 1));
   if (!A.ok) {
     *msg = "device allocation failed";
     return -5;

@@ -41,7 +41,7 @@ struct SlotBuf {
   int32_t* touched = nullptr;
   int32_t* settled = nullptr;
   int32_t* plist[2] = {nullptr, nullptr};
-  uint64_t* ulist[2] = {nullptr, nullptr};
+  UEntry* ulist[2] = {nullptr, nullptr};
   HeavyItem* heavy[2] = {nullptr, nullptr};
   uint64_t* ring_mass = nullptr;
   uint32_t* ring_cnt = nullptr;
