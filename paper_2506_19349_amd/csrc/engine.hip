@@ -666,9 +666,16 @@ __device__ __noinline__ void block_round(GInst& I, int kind, int item0, int nite
       const int it = item0 + k * kBlock + tid;
       uu[k] = it < nitems ? src[it] : -1;
     }
+    // the distance and the row bounds of each item in one round trip (the
+    // bounds are needed by almost every item that passes the filter)
     uint32_t dd[kItemsPerThread];
+    int rsk[kItemsPerThread], rek[kItemsPerThread];
 #pragma unroll
-    for (int k = 0; k < kItemsPerThread; ++k) dd[k] = uu[k] >= 0 ? dist_of(V.state, uu[k]) : kInf;
+    for (int k = 0; k < kItemsPerThread; ++k) {
+      dd[k] = uu[k] >= 0 ? dist_of(V.state, uu[k]) : kInf;
+      rsk[k] = uu[k] >= 0 ? V.rowptr[uu[k]] : 0;
+      rek[k] = uu[k] >= 0 ? V.rowptr[uu[k] + 1] : 0;
+    }
 #pragma unroll
     for (int k = 0; k < kItemsPerThread; ++k) {
       const int u = uu[k];
@@ -687,7 +694,7 @@ __device__ __noinline__ void block_round(GInst& I, int kind, int item0, int nite
         }
         stage_append(S.t, &S.nt, wt, u);
       }
-      lds_push_item(L, ok, u, d, 0, -1, false);
+      lds_push_item(L, ok, u, d, rsk[k], -1, false, rek[k]);
     }
   }
   __syncthreads();
