@@ -414,8 +414,8 @@ struct WaveAcc {
 
 __device__ __forceinline__ int global_wave() { return (int)(blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave); }
 
-// Work counters go to this wave's own slot (plain read-modify-write: no
-// other wave touches it); only the step-1 hub bound is a shared atomic.
+// Work counters go to this wave's own slot (no other wave adds to it, so the
+// atomics never contend); the step-1 hub bound is a shared atomic.
 __device__ __forceinline__ void flush_acc(GInst& I, int maxw, WaveAcc& a) {
   unsigned long long e = wave_sum(a.expansions), b = wave_sum(a.band), ps = wave_sum(a.pscan),
                      pv = wave_sum(a.pvert), pl = wave_sum(a.pullscan), su = wave_sum(a.success),
@@ -424,14 +424,15 @@ __device__ __forceinline__ void flush_acc(GInst& I, int maxw, WaveAcc& a) {
   if (lane_id() == 0) {
     const int gw = global_wave();
     if (gw < maxw) {
+      // atomics without a returned value: nothing waits for them
       SSSP_GBL Counters& c = gbl(I.cslot)[gw];
-      c.expansions += e;
-      c.band_expansions += b;
-      c.push_scanned += ps;
-      c.pull_vertices += pv;
-      c.pull_scanned += pl;
-      c.relax_success += su;
-      c.queue_entries += qe;
+      if (e) atomicAdd(&c.expansions, e);
+      if (b) atomicAdd(&c.band_expansions, b);
+      if (ps) atomicAdd(&c.push_scanned, ps);
+      if (pv) atomicAdd(&c.pull_vertices, pv);
+      if (pl) atomicAdd(&c.pull_scanned, pl);
+      if (su) atomicAdd(&c.relax_success, su);
+      if (qe) atomicAdd(&c.queue_entries, qe);
     }
     if (hm != kInf) atomicMin(&I.ub_next.v, hm);
   }
@@ -1060,7 +1061,7 @@ __device__ __noinline__ void block_settle(GInst& I, int kind, int item0, int nit
     L.sdec[tid / kWave] = ws;
     L.maxd[tid / kWave] = wm;
     const int gw = global_wave();
-    if (qe && gw < maxw) gbl(I.cslot)[gw].queue_entries += qe;
+    if (qe && gw < maxw) atomicAdd(&gbl(I.cslot)[gw].queue_entries, qe);
   }
   __syncthreads();
   for (uint32_t k = tid; k < nb; k += kBlock) {
