@@ -375,8 +375,9 @@ sssp_status run_instances_ws(Workspace& w, const sssp_graph* const* gs, const in
   HIP_TRY(hipEventRecord(w.tev[0][tslot], stream));
   bool host_driven = o.host_driven || w.persistent_failed;
   if (!host_driven) {
-    int bpc = o.blocks_per_cu > 0 ? std::min(o.blocks_per_cu, w.occ) : w.occ;
-    hipError_t e = launch_engine(w.dG, w.cus * bpc, true, 0, stream);
+    long long total_n = 0;
+    for (int i = 0; i < k; ++i) total_n += gs[i]->gh.h.n;
+    hipError_t e = launch_engine(w.dG, engine_grid(w, o, total_n), true, 0, stream);
     if (e != hipSuccess) {
       (void)hipGetLastError();
       w.persistent_failed = true;
@@ -401,6 +402,18 @@ sssp_status run_instances_ws(Workspace& w, const sssp_graph* const* gs, const in
   HIP_TRY(launch_finish(w.dG, max_n, stream));
   w.last_k = k;
   return ok();
+}
+
+int engine_grid(const Workspace& w, const Opts& o, long long total_n) {
+  const int bpc = o.blocks_per_cu > 0 ? std::min(o.blocks_per_cu, w.occ) : w.occ;
+  const int full = w.cus * bpc;
+  if (o.blocks_per_cu > 0) return full;  // an explicit choice is honoured
+  // no tick has more batches than the vertices fill: small graphs take a
+  // smaller grid (cheaper barriers), a multiple of the XCD count
+  long long need = (total_n + kRoundBatch - 1) / kRoundBatch;
+  need = ((need + kMaxXcd - 1) / kMaxXcd) * kMaxXcd;
+  if (need < kMaxXcd) need = kMaxXcd;
+  return (int)std::min<long long>(full, need);
 }
 
 bool check_graph(const sssp_graph* g, std::string* err) {

@@ -75,14 +75,16 @@ sssp_status plan_build(sssp_plan* p, uint32_t* const* dist_outs, hipStream_t str
   hG->n_sel = -1;
   for (int i = 0; i < k; ++i) fill_inst(p->hI[i], w.slots[(size_t)i], p->gs[(size_t)i], 0, dist_outs[i], p->o);
 
-  const int bpc = p->o.blocks_per_cu > 0 ? std::min(p->o.blocks_per_cu, w.occ) : w.occ;
+  long long total_n = 0;
+  for (int i = 0; i < k; ++i) total_n += p->gs[(size_t)i]->gh.h.n;
+  const int grid = engine_grid(w, p->o, total_n);
   HIP_TRY(hipGraphCreate(&p->graph, 0));
   hipGraphNode_t n_g, n_i, last;
   HIP_TRY(hipGraphAddMemcpyNode1D(&n_g, p->graph, nullptr, 0, w.dG, p->hG, sizeof(Globals),
                                   hipMemcpyHostToDevice));
   HIP_TRY(hipGraphAddMemcpyNode1D(&n_i, p->graph, &n_g, 1, w.dInst, p->hI, sizeof(Inst) * (size_t)k,
                                   hipMemcpyHostToDevice));
-  HIP_TRY(add_solve_nodes(p->graph, n_i, w.dG, max_n, w.cus * bpc, &last));
+  HIP_TRY(add_solve_nodes(p->graph, n_i, w.dG, max_n, grid, &last));
   HIP_TRY(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
   HIP_TRY(hipEventCreateWithFlags(&p->done, hipEventDisableTiming));
   w.last_k = k;
@@ -279,7 +281,7 @@ sssp_status sssp_autotune(const sssp_graph* const* gs, const int32_t* sources, i
   inout->beta = best.beta;
   inout->traversal_opt = best.topt ? 1 : -1;
   inout->host_driven = 0;
-  inout->blocks_per_cu = best.blocks_per_cu > 0 ? best.blocks_per_cu : w.occ;
+  inout->blocks_per_cu = best.blocks_per_cu;  // 0: the default grid rule
   inout->heavy_split = best.heavy;
   inout->fuse_rounds = best.fuse > 0 ? best.fuse : -1;
   if (report) {

@@ -124,6 +124,9 @@ struct Opts {
 };
 
 bool parse_opts(const sssp_options* o, Opts* r, std::string* err);
+// Persistent grid size for k instances of total_n vertices: the tuned or
+// requested workgroups per CU, fewer for small graphs.
+int engine_grid(const Workspace& w, const Opts& o, long long total_n);
 
 void fill_inst(Inst& I, const SlotBuf& s, const sssp_graph* g, int32_t source, uint32_t* dist,
                const Opts& o);
