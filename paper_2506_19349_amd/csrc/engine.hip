@@ -12,12 +12,15 @@
 // as one launch per tick.
 //
 // Work of a tick is a list of segments (instance, kind, item count); items are
-// cut into fixed batches and batches are dealt to workgroups round-robin.
+// cut into fixed batches and batches are dealt round-robin to the tick's
+// participating workgroups (a per-XCD quota: ticks with little work run on few
+// workgroups, the others wait aside).
 //
-// Relaxations are asynchronous within a round (atomicMin on dist; every
-// relaxation's result is a real path length, so any interleaving reaches the
-// exact distances). The per-step schedule <lb, ub, st> depends only on the
-// settled set and is therefore deterministic.
+// Relaxations are asynchronous within a round (a 64-bit atomicMin on the
+// vertex's (distance, round) word; every relaxation's result is a real path
+// length, so any interleaving reaches the exact distances). The per-step
+// schedule <lb, ub, st> depends only on the settled set and is therefore
+// deterministic.
 #include "engine.h"
 
 #include <cstring>
@@ -952,9 +955,9 @@ union BlockLds {
   RoundLds r;
 };
 
-// One workgroup settles up to 256 items: the step's touched vertices (with
-// dist < ub they are final; in the first step the rest stay pending) and the
-// pending list's compaction. Degree mass moves from the unsettled histogram
+// One workgroup settles up to kSettleBatch items (kSettlePer per thread): the
+// step's touched vertices (with dist < ub they are final; in the first step
+// the rest stay pending) and the pending list's compaction. Degree mass moves from the unsettled histogram
 // to the per-distance ring; settled vertices are appended to the settled list.
 __device__ __noinline__ void block_settle(GInst& I, int kind, int item0, int nitems, SettleLds& L) {
   GDevGraph& g = *gbl(I.g);
