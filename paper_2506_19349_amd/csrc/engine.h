@@ -18,7 +18,7 @@ constexpr int kLdsHist = 1024;           // settle: degree ranks privatised in L
 constexpr int kHeavyChunk = 256;         // edges per heavy chunk
 constexpr int kDefaultHeavy = 64;        // ranges longer than this are split
 constexpr int kStageCap = 1280;          // LDS staging of list appends per workgroup batch
-constexpr int kItemsPerThread = 4;       // round batches: items per thread
+constexpr int kItemsPerThread = 2;       // round batches: items per thread
 constexpr int kRoundBatch = kBlock * kItemsPerThread;  // items per workgroup batch
 constexpr int kHeavyPerBatch = 16;       // heavy chunks per workgroup batch
 constexpr int kSettlePer = 4;            // settle batches: items per thread

@@ -1513,7 +1513,7 @@ __device__ bool barrier_tick(GGlobals& G, BarrierState& B, unsigned int quota) {
   return s_ok != 0;
 }
 
-__global__ void __launch_bounds__(kBlock, 4) k_engine(Globals* Gp, int persistent, int max_ticks) {
+__global__ void __launch_bounds__(kBlock, 5) k_engine(Globals* Gp, int persistent, int max_ticks) {
   __shared__ BlockLds lds;
   __shared__ BarrierState s_b;
   GGlobals& G = *gbl(Gp);
