@@ -34,11 +34,12 @@ def log(*a):
 def alg_bytes(c: dict) -> int:
     """Bytes the method itself must move for one solve (counted by the engine):
     16 per expansion (frontier id, dist[u], the row bounds), 12 per pushed edge
-    (column, weight, dist[v]), 4 per successful decrease, 12 per pull-list
-    entry (id, dist, smallest weight), 12 per pulled edge, 8 per queue entry
-    (written once, read once)."""
+    (column, weight, dist[v]), 4 per successful decrease, 16 per vertex the
+    pull examines (an unsettled vertex of degree >= 1: id, dist, row bounds and
+    first weight), 12 per pulled edge, 8 per queue entry (written once, read
+    once)."""
     return (16 * c["expansions"] + 12 * c["push_scanned"] + 4 * c["relax_success"]
-            + 12 * c["pull_vertices"] + 12 * c["pull_scanned"] + 8 * c["queue_entries"])
+            + 16 * c["pull_unsettled"] + 12 * c["pull_scanned"] + 8 * c["queue_entries"])
 
 
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_engine_rmat24_counters.md")

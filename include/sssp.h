@@ -82,6 +82,8 @@ typedef struct {
   uint64_t steps;           /* scheduling-threshold pairs <lb, ub> */
   uint64_t ticks;           /* device-wide phases executed (rounds + settle passes) */
   uint64_t fused_rounds;    /* rounds run back to back by one workgroup (bucket fusion) */
+  uint64_t pull_unsettled;  /* unsettled vertices of degree >= 1 (dist >= lb) at each pull, summed:
+                               the vertices Function 1's pull examines */
   uint32_t high_d0;         /* highD(0) */
   uint32_t gap0;            /* gap(0) */
   uint32_t flags;           /* nonzero: internal condition (see sssp_status_str of status) */

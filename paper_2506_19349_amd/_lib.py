@@ -35,7 +35,8 @@ class Options(ctypes.Structure):
 class Counters(ctypes.Structure):
     _fields_ = [(name, ctypes.c_uint64) for name in (
         "expansions", "band_expansions", "push_scanned", "pull_vertices", "pull_scanned",
-        "relax_success", "queue_entries", "rounds", "pulls", "steps", "ticks", "fused_rounds")] + [
+        "relax_success", "queue_entries", "rounds", "pulls", "steps", "ticks", "fused_rounds",
+        "pull_unsettled")] + [
         ("high_d0", u32), ("gap0", u32), ("flags", u32), ("reserved", u32)]
 
 

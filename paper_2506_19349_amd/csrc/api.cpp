@@ -462,6 +462,7 @@ sssp_status collect_counters(Workspace& w, int i0, int k, sssp_counters* out) {
     out->steps += I.c.steps;
     out->ticks += I.c.ticks;
     out->fused_rounds += I.c.fused_rounds;
+    out->pull_unsettled += I.c.pull_unsettled;
     flags |= I.flags.v;
   }
   out->high_d0 = hi[0].high_d0;

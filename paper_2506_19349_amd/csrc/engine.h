@@ -51,7 +51,17 @@ struct DevGraph {
   const int32_t* deg_vals;   // D ascending distinct degrees
   const uint32_t* deg_cnt0;  // D: vertices with that degree
   const uint32_t* hub_bits;  // ceil(n/32) words: deg(v) >= highD(0)
-  const UEntry* nonisolated;  // n_nonisolated entries, ascending id
+  // n_nonisolated entries grouped by the weight bucket of their smallest
+  // weight (bucket b holds weights in [b, b + 1) * ubucket_width, the last
+  // bucket everything above), ascending, and by id within a bucket: the
+  // vertices able to pull at all (smallest weight < ub - st) lie in a prefix
+  // of whole buckets, and each bucket keeps the rows' memory order
+  const UEntry* nonisolated;
+  // kUBuckets + 1 entries: ufirst[j] is the first position of `nonisolated`
+  // in bucket j or later (ufirst[kUBuckets] = the count)
+  const int32_t* ufirst;
+  uint32_t ubucket_width;    // ceil((maxW + 1) / kUBucketDiv)
+  uint32_t pad_g;
   const uint32_t* rtow;      // 4096
   // per row, 16 int32: entry b - 1 (b = 1..15) is the first position of the
   // row whose weight is >= b * rwi_width (entry 15 unused). Written for rows
@@ -59,6 +69,12 @@ struct DevGraph {
   const int32_t* rwi;
 };
 constexpr int kRowIndexMin = 8;
+// Two pull-list buckets: smallest weight below 1/16 of the weight range (the
+// first pull of a step sequence usually needs only these), and the rest. More
+// buckets would interleave several id-ordered runs in one pull and lose the
+// memory order that the pull's row and distance reads rely on.
+constexpr int kUBuckets = 2;
+constexpr int kUBucketDiv = 16;
 
 // ------------------------------------------------------- solver instance --
 enum Phase : uint32_t { PH_ROUND = 0, PH_SETTLE = 1, PH_DONE = 2 };
@@ -94,7 +110,7 @@ struct TraceRec {
 
 struct Counters {
   unsigned long long expansions, band_expansions, push_scanned, pull_vertices, pull_scanned,
-      relax_success, queue_entries, rounds, pulls, steps, ticks, fused_rounds;
+      relax_success, queue_entries, rounds, pulls, steps, ticks, fused_rounds, pull_unsettled;
 };
 
 struct alignas(128) HotI32 {
@@ -161,6 +177,11 @@ struct Inst {
   uint32_t rounds_in_step;
   int32_t qsel, psel, usel, hsel;
   int32_t nF, wBegin, wEnd, nP, nU, nT, nH;
+  // The pull list of a step is the compacted list of earlier pulls (nU
+  // entries) followed by the part [u_done, u_end) of the sorted non-isolated
+  // list that no earlier pull has read (u_end: first entry too heavy to pull
+  // in this step).
+  int32_t u_done, u_end;
   int32_t settled_mark;
   int32_t nsteprec;
   int32_t trace_len;

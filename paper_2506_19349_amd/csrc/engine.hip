@@ -166,12 +166,17 @@ struct HeurLds {
 // cnt[r] vertices each): the threshold h minimising |mass(deg < h) -
 // mass(deg >= h)|, smallest on ties, 0 if no mass. Whole workgroup.
 __device__ uint32_t block_high_d(const SSSP_GBL int32_t* deg_vals, const SSSP_GBL uint32_t* cnt, int32_t D,
-                                 unsigned long long* mass_total, HeurLds& L) {
+                                 unsigned long long* mass_total, unsigned long long* count_total,
+                                 HeurLds& L) {
   const int tid = threadIdx.x;
   const int chunk = (D + kBlock - 1) / kBlock;
   const int r0 = min(D, tid * chunk), r1 = min(D, r0 + chunk);
-  unsigned long long local = 0;
-  for (int r = r0; r < r1; ++r) local += (unsigned long long)deg_vals[r] * cnt[r];
+  unsigned long long local = 0, lcount = 0;
+  for (int r = r0; r < r1; ++r) {
+    local += (unsigned long long)deg_vals[r] * cnt[r];
+    lcount += cnt[r];
+  }
+  (void)block_excl_scan<unsigned long long>(lcount, L.scan, count_total);
   unsigned long long total;
   unsigned long long low = block_excl_scan<unsigned long long>(local, L.scan, &total);
   // best (diff, r) packed: diff < 2^33, r < 2^31 -> key = diff << 31 | r
@@ -263,7 +268,8 @@ __device__ __noinline__ void run_heuristic(GInst& I, HeurLds& lds) {
   const int tid = threadIdx.x;
   const uint32_t L = I.ub;
   unsigned long long mass;
-  uint32_t h = block_high_d(gbl(g.deg_vals), gbl(I.hist_cnt), g.num_deg, &mass, lds);
+  unsigned long long unsettled;  // vertices of degree >= 1 with dist >= L
+  uint32_t h = block_high_d(gbl(g.deg_vals), gbl(I.hist_cnt), g.num_deg, &mass, &unsettled, lds);
   const unsigned long long S = I.S.v;
   uint32_t gapL = gap_of(S, h, g.nnz, I.M, gbl(g.rtow), I.alpha, I.beta);
   uint32_t stn = block_compute_st(I, L, gapL, g.nnz, lds);
@@ -336,6 +342,17 @@ __device__ __noinline__ void run_heuristic(GInst& I, HeurLds& lds) {
     I.st = stn;
     I.lb0 = lb0;
     I.pull_on = stn < L ? 1u : 0u;
+    if (I.pull_on) {
+      // the entries able to pull (smallest weight < ub - st) not read by an
+      // earlier pull: up to the first weight bucket starting at or above
+      // ub - st
+      const unsigned long long reach = ubn - stn;
+      const unsigned long long bw = g.ubucket_width;
+      const unsigned long long j = (reach + bw - 1) / bw;
+      const int32_t e = gbl(g.ufirst)[j < (unsigned long long)kUBuckets ? j : kUBuckets];
+      I.u_end = e > I.u_done ? e : I.u_done;
+      I.c.pull_unsettled += unsettled;
+    }
     I.gap_cur = gapL;
     I.first = 0;
     I.step += 1;
@@ -466,9 +483,11 @@ __device__ __forceinline__ void stage_append(int32_t* buf, int32_t* cnt, bool wa
   if (want) buf[base + __popcll(m & lanemask_lt())] = val;
 }
 
-// Whole workgroup: copy the pull-list entries whose positions in `src` were
-// staged in q to `dst`.
-__device__ void stage_flush_entries(StageLds& S, const SSSP_GBL UEntry* src, SSSP_GBL UEntry* dst,
+// Whole workgroup: copy the pull-list entries whose positions were staged in
+// q to `dst`. Position p is entry p of `cur` for p < ncur, else entry p - ncur
+// of `fresh`.
+__device__ void stage_flush_entries(StageLds& S, const SSSP_GBL UEntry* cur, int ncur,
+                                    const SSSP_GBL UEntry* fresh, SSSP_GBL UEntry* dst,
                                     SSSP_GBL int32_t* cnt, int cap, SSSP_GBL uint32_t* flags) {
   __syncthreads();
   const int np = S.nq;
@@ -478,8 +497,10 @@ __device__ void stage_flush_entries(StageLds& S, const SSSP_GBL UEntry* src, SSS
   }
   __syncthreads();
   const int b = S.base_q;
-  for (int i = threadIdx.x; i < np; i += kBlock)
-    if (b + i < cap) gstore(dst + b + i, gload(src + S.q[i]));
+  for (int i = threadIdx.x; i < np; i += kBlock) {
+    const int p = S.q[i];
+    if (b + i < cap) gstore(dst + b + i, gload(p < ncur ? cur + p : fresh + (p - ncur)));
+  }
   __syncthreads();
   if (threadIdx.x == 0) S.nq = 0;
   __syncthreads();
@@ -629,10 +650,13 @@ __device__ __noinline__ void block_round(GInst& I, int kind, int item0, int nite
   } else if (kind == SEG_U) {
     // unsettled-list entries carry the row's smallest weight and bounds: an
     // entry whose lightest edge cannot reach below ub from a settled vertex
-    // (>= st) is kept without reading its distance
+    // (>= st) is kept without reading its distance. The list is the compacted
+    // list of earlier pulls followed by the sorted entries no pull has read yet.
     const int usel = I.usel;
-    const SSSP_GBL UEntry* ucur = usel < 0 ? gbl(gbl(I.g)->nonisolated) : gbl(I.ulist[usel]);
-    auto unext = gbl(I.ulist[usel < 0 ? 0 : (usel ^ 1)]);
+    const int ncur = I.nU;
+    const SSSP_GBL UEntry* ucur = gbl(I.ulist[usel]);
+    const SSSP_GBL UEntry* fresh = gbl(gbl(I.g)->nonisolated) + I.u_done;
+    auto unext = gbl(I.ulist[usel ^ 1]);
     const uint32_t reach = ub - st;
     UEntry ee[kItemsPerThread];
     bool valid[kItemsPerThread];
@@ -640,7 +664,7 @@ __device__ __noinline__ void block_round(GInst& I, int kind, int item0, int nite
     for (int k = 0; k < kItemsPerThread; ++k) {
       const int it = item0 + k * kBlock + tid;
       valid[k] = it < nitems;
-      if (valid[k]) ee[k] = gload(ucur + it);
+      if (valid[k]) ee[k] = gload(it < ncur ? ucur + it : fresh + (it - ncur));
     }
     uint32_t dd[kItemsPerThread];
 #pragma unroll
@@ -660,7 +684,7 @@ __device__ __noinline__ void block_round(GInst& I, int kind, int item0, int nite
                     valid[k] ? ee[k].re : -1);
     }
     // the surviving pull list goes out now; the stage is free for phase 2
-    stage_flush_entries(S, ucur, unext, &I.u_next_cnt.v, V.n, &I.flags.v);
+    stage_flush_entries(S, ucur, ncur, fresh, unext, &I.u_next_cnt.v, V.n, &I.flags.v);
   } else {
     int uu[kItemsPerThread];
     const SSSP_GBL int32_t* src = (kind == SEG_W) ? gbl(I.settled) + I.wBegin
@@ -1194,9 +1218,10 @@ __device__ void transition(GInst& I, SSSP_GBL int32_t* cnt, SSSP_GBL int32_t* ki
   if (I.phase == PH_DONE) return;
   if (I.tick_kind == PH_ROUND) {
     if (I.init_round && I.pull_on) {
-      I.usel = (I.usel < 0) ? 0 : (I.usel ^ 1);
+      I.usel ^= 1;
       I.nU = min(I.u_next_cnt.v, I.n);
       I.u_next_cnt.v = 0;
+      I.u_done = I.u_end;
     }
     I.init_round = 0;
     if (I.first && I.ub_next.v < I.ub) I.ub = I.ub_next.v;
@@ -1245,7 +1270,7 @@ __device__ void transition(GInst& I, SSSP_GBL int32_t* cnt, SSSP_GBL int32_t* ki
   I.nF = 0;
   cnt[0] = I.wEnd - I.wBegin; kinds[0] = SEG_W; pbs[0] = kRoundBatch;
   cnt[1] = I.nP; kinds[1] = SEG_P; pbs[1] = kRoundBatch;
-  cnt[2] = I.pull_on ? I.nU : 0; kinds[2] = SEG_U; pbs[2] = kRoundBatch;
+  cnt[2] = I.pull_on ? I.nU + (I.u_end - I.u_done) : 0; kinds[2] = SEG_U; pbs[2] = kRoundBatch;
 }
 
 // Build the tick table. With do_transition, every instance first takes its
@@ -1639,8 +1664,9 @@ __global__ void __launch_bounds__(kBlock) k_init_ctl(Globals* Gp) {
       I.first = 1;
       I.step = 0;
       I.rounds_in_step = 0;
-      I.qsel = 0; I.psel = 0; I.usel = -1; I.hsel = 0;
-      I.nP = 0; I.nU = g.n_nonisolated; I.nT = 0; I.nH = 0;
+      I.qsel = 0; I.psel = 0; I.usel = 0; I.hsel = 0;
+      I.nP = 0; I.nU = 0; I.nT = 0; I.nH = 0;
+      I.u_done = 0; I.u_end = 0;
       I.wBegin = 0; I.wEnd = 0;
       I.q_next_cnt.v = 0; I.touched_cnt.v = 0; I.p_next_cnt.v = 0; I.u_next_cnt.v = 0;
       I.settled_cnt.v = 0; I.h_next_cnt.v = 0;
@@ -1753,8 +1779,8 @@ __global__ void __launch_bounds__(kBlock) k_high_d(const int32_t* deg_vals, cons
                                                    int32_t D, uint32_t* out_h,
                                                    unsigned long long* out_mass) {
   __shared__ HeurLds lds;
-  unsigned long long mass;
-  uint32_t h = block_high_d(gbl(deg_vals), gbl(cnt), D, &mass, lds);
+  unsigned long long mass, count;
+  uint32_t h = block_high_d(gbl(deg_vals), gbl(cnt), D, &mass, &count, lds);
   if (threadIdx.x == 0) {
     *out_h = h;
     *out_mass = mass;

@@ -148,7 +148,7 @@ __global__ void __launch_bounds__(kBlock) k_merge_pass(const uint64_t* src, uint
     const int64_t off = tile_row_off[t];
     const int len = tile_row_len[t];
     const int o0 = tile_out0[t];
-    const long long pair0 = (long long)(o0 / (2 * width)) * (2 * width);
+    const long long pair0 = ((long long)o0 / (2ll * width)) * (2ll * width);
     const int a0 = (int)pair0;
     const int alen = max(0, min(width, len - a0));
     const int blen = max(0, min(width, len - a0 - width));
@@ -372,6 +372,46 @@ __global__ void __launch_bounds__(kBlock) k_noniso_write(const int32_t* rowptr, 
       run += t;
     }
     __syncthreads();
+  }
+}
+
+// The pull list's order: by the weight bucket of the smallest weight, then by
+// id. A step's pull only concerns vertices whose lightest edge is below
+// ub - st: a prefix of whole buckets, found in ufirst. Within a bucket the
+// ascending ids keep the memory order of the rows and distances the pull
+// reads (and of the frontier it produces).
+__device__ __forceinline__ uint32_t ubucket(uint32_t wmin, uint32_t width) {
+  return min(wmin / width, (uint32_t)(kUBuckets - 1));
+}
+
+__global__ void k_ukeys(const UEntry* e, int32_t cnt, uint32_t width, uint64_t* keys) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
+       i += (long long)gridDim.x * blockDim.x)
+    keys[i] = ((uint64_t)ubucket(e[i].wmin, width) << 32) | (uint32_t)e[i].id;
+}
+
+__global__ void k_uentries(const uint64_t* keys, int32_t cnt, const int32_t* rowptr, const uint32_t* wmin,
+                           UEntry* out) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
+       i += (long long)gridDim.x * blockDim.x) {
+    const uint64_t k = keys[i];
+    UEntry e;
+    e.id = (int32_t)(uint32_t)(k & 0xffffffffull);
+    e.wmin = wmin[e.id];
+    e.rs = rowptr[e.id];
+    e.re = rowptr[e.id + 1];
+    out[i] = e;
+  }
+}
+
+// ufirst[j] = first position in bucket j or later; the host fills every entry
+// with cnt first (buckets past the last one present).
+__global__ void k_ufirst(const uint64_t* keys, int32_t cnt, int32_t* ufirst) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int b = (int)(keys[i] >> 32);
+    const int bp = i == 0 ? -1 : (int)(keys[i - 1] >> 32);
+    for (int j = bp + 1; j <= b; ++j) ufirst[j] = (int32_t)i;
   }
 }
 
@@ -655,8 +695,8 @@ int prep_graph(int32_t n, const int32_t* rowptr_in, const int32_t* col_in, const
       const int nt = (int)toff.size();
       uint64_t* src = adj;
       uint64_t* dst = tmp;
-      for (int width = kMedMax; width < maxlarge; width *= 2) {
-        k_merge_pass<<<grid_for(nt, 1, 65536), kBlock>>>(src, dst, d_toff, d_tlen, d_to0, nt, width);
+      for (long long width = kMedMax; width < maxlarge; width *= 2) {
+        k_merge_pass<<<grid_for(nt, 1, 65536), kBlock>>>(src, dst, d_toff, d_tlen, d_to0, nt, (int32_t)width);
         PREP_CHECK(hipGetLastError());
         std::swap(src, dst);
       }
@@ -784,6 +824,65 @@ int prep_graph(int32_t n, const int32_t* rowptr_in, const int32_t* col_in, const
   PREP_CHECK(hipMemcpy(bcnt, hb.data(), sizeof(int32_t) * (size_t)nb, hipMemcpyHostToDevice));
   k_noniso_write<<<nb, kBlock>>>(rowptr, wmin, n, bcnt, noniso);
   PREP_CHECK(hipGetLastError());
+  // ...then ordered by (weight bucket of the smallest weight, id): 4096-key
+  // chunks sorted in LDS, then merge passes over the whole list
+  const uint32_t ub_width = (uint32_t)(((unsigned long long)maxw + kUBucketDiv) / kUBucketDiv);
+  int32_t* ufirst = A.get<int32_t>(kUBuckets + 1);
+  if (!A.ok) {
+    *msg = "device allocation failed";
+    return -5;
+  }
+  {
+    std::vector<int32_t> hf((size_t)kUBuckets + 1, nonisolated);
+    PREP_CHECK(hipMemcpy(ufirst, hf.data(), sizeof(int32_t) * hf.size(), hipMemcpyHostToDevice));
+  }
+  if (nonisolated > 0) {
+    uint64_t* keys = T.get<uint64_t>((size_t)nonisolated);
+    uint64_t* ktmp = T.get<uint64_t>((size_t)nonisolated);
+    std::vector<int64_t> coff, toff;
+    std::vector<int32_t> clen, tlen, to0;
+    for (int32_t c = 0; c < nonisolated; c += kMedMax) {
+      coff.push_back(c);
+      clen.push_back(std::min(kMedMax, nonisolated - c));
+    }
+    for (int32_t o = 0; o < nonisolated; o += kMergeTile) {
+      toff.push_back(0);
+      tlen.push_back(nonisolated);
+      to0.push_back(o);
+    }
+    int64_t* d_coff = T.get<int64_t>(coff.size());
+    int32_t* d_clen = T.get<int32_t>(clen.size());
+    int64_t* d_toff = T.get<int64_t>(toff.size());
+    int32_t* d_tlen = T.get<int32_t>(tlen.size());
+    int32_t* d_to0 = T.get<int32_t>(to0.size());
+    if (!T.ok) {
+      *msg = "device allocation failed";
+      return -5;
+    }
+    PREP_CHECK(hipMemcpy(d_coff, coff.data(), sizeof(int64_t) * coff.size(), hipMemcpyHostToDevice));
+    PREP_CHECK(hipMemcpy(d_clen, clen.data(), sizeof(int32_t) * clen.size(), hipMemcpyHostToDevice));
+    PREP_CHECK(hipMemcpy(d_toff, toff.data(), sizeof(int64_t) * toff.size(), hipMemcpyHostToDevice));
+    PREP_CHECK(hipMemcpy(d_tlen, tlen.data(), sizeof(int32_t) * tlen.size(), hipMemcpyHostToDevice));
+    PREP_CHECK(hipMemcpy(d_to0, to0.data(), sizeof(int32_t) * to0.size(), hipMemcpyHostToDevice));
+    k_ukeys<<<grid_for(nonisolated), kBlock>>>(noniso, nonisolated, ub_width, keys);
+    PREP_CHECK(hipGetLastError());
+    k_sort_medium<<<grid_for((long long)coff.size(), 1, 65536), kBlock>>>(keys, d_coff, d_clen,
+                                                                          (int32_t)coff.size());
+    PREP_CHECK(hipGetLastError());
+    uint64_t* src = keys;
+    uint64_t* dst = ktmp;
+    const int nt = (int)toff.size();
+    for (long long width = kMedMax; width < nonisolated; width *= 2) {
+      k_merge_pass<<<grid_for(nt, 1, 65536), kBlock>>>(src, dst, d_toff, d_tlen, d_to0, nt, (int32_t)width);
+      PREP_CHECK(hipGetLastError());
+      std::swap(src, dst);
+    }
+    k_uentries<<<grid_for(nonisolated), kBlock>>>(src, nonisolated, rowptr, wmin, noniso);
+    PREP_CHECK(hipGetLastError());
+    k_ufirst<<<grid_for(nonisolated), kBlock>>>(src, nonisolated, ufirst);
+    PREP_CHECK(hipGetLastError());
+    PREP_CHECK(hipDeviceSynchronize());
+  }
 
   // ---- RtoW[x] = maxW(G, x / 4095): the ceil(x * nnz / 4095)-th smallest weight
   std::vector<uint32_t> hr(kRatioNum, 0);
@@ -849,6 +948,9 @@ int prep_graph(int32_t n, const int32_t* rowptr_in, const int32_t* col_in, const
   h.deg_cnt0 = d_deg_cnt;
   h.hub_bits = hub;
   h.nonisolated = noniso;
+  h.ufirst = ufirst;
+  h.ubucket_width = ub_width;
+  h.pad_g = 0;
   h.rtow = rtow;
   h.rwi = rwi;
   h.rwi_width = rwi_width;
