@@ -128,8 +128,11 @@ struct alignas(128) HotU64 {
 
 constexpr int kMaxSegPerInst = 5;  // segments one instance may have in a tick
 
-struct Inst {
-  // ---- fixed for a solve ----
+// A solver instance: fixed pointers and parameters of the solve, the control
+// words (one contiguous base, so that the epilogue can take them into
+// registers with a burst of wide loads and write them back the same way), the
+// work counters, and the words that device atomics update.
+struct InstFixed {
   const DevGraph* g;
   uint32_t* dist;          // the caller's output, written once the solve ends
   // per vertex: (tentative distance << 32) | round id of its last decrease
@@ -162,7 +165,10 @@ struct Inst {
   double beta;
   int32_t heavy_split;
   int32_t fuse_cap;        // rounds one workgroup may chain without a grid barrier (0: off)
-  // ---- control (written by the epilogue / the heuristic) ----
+};
+
+// control words: written by the epilogue and by the heuristic
+struct InstCtl {
   uint32_t phase;
   uint32_t tick_kind;      // PH_ROUND or PH_SETTLE: what the scheduled tick does
   uint32_t init_round;     // current round is a step's first (W / P / U segments)
@@ -188,9 +194,16 @@ struct Inst {
   int32_t settle_items;    // batches of the settle tick
   uint32_t high_d0, gap0;
   uint32_t pad1;
-  // this instance's segments of the next tick (written by its transition)
-  int32_t spec_cnt[kMaxSegPerInst], spec_kind[kMaxSegPerInst], spec_pb[kMaxSegPerInst];
-  int32_t pad3;
+};
+
+// an instance's segments of the next tick (written by its transition)
+struct SegSpec {
+  int32_t cnt[kMaxSegPerInst], kind[kMaxSegPerInst], pb[kMaxSegPerInst];
+  int32_t pad;
+};
+
+struct Inst : InstFixed, InstCtl {
+  SegSpec spec;
   Counters c;
   // ---- hot words: updated by device atomics from every CU, each on its own
   // 128-byte line so that they never share a line with the fields above ----

@@ -1211,112 +1211,160 @@ __device__ void run_tick(GGlobals& G, BlockLds& lds, int pid, int P) {
   }
 }
 
-// Phase transition of one instance after a tick, and its segments for the
-// next tick. Serial per instance; called by one thread per instance.
-__device__ void transition(GInst& I, SSSP_GBL int32_t* cnt, SSSP_GBL int32_t* kinds, SSSP_GBL int32_t* pbs) {
-  for (int s = 0; s < kMaxSegPerInst; ++s) { cnt[s] = 0; kinds[s] = SEG_Q; pbs[s] = kBlock; }
-  if (I.phase == PH_DONE) return;
-  if (I.tick_kind == PH_ROUND) {
-    if (I.init_round && I.pull_on) {
-      I.usel ^= 1;
-      I.nU = min(I.u_next_cnt.v, I.n);
+// Words updated by device atomics during a tick that the transition reads.
+struct HotIn {
+  int32_t u_next, q_next, h_next, touched, settled, p_next;
+  uint32_t ub_next;
+};
+
+// Phase transition of one instance after a tick, on a register copy X of its
+// control words (the caller loads and stores them in bulk); its segments of
+// the next tick go to Sp. Resets the hot words it consumed in I.
+// Serial per instance; called by one thread per instance.
+__device__ void transition(InstCtl& X, SegSpec& Sp, const HotIn& h, int32_t n, int32_t heavy_cap,
+                           unsigned long long& rounds, GInst& I) {
+#pragma unroll
+  for (int s = 0; s < kMaxSegPerInst; ++s) {
+    Sp.cnt[s] = 0;
+    Sp.kind[s] = SEG_Q;
+    Sp.pb[s] = kBlock;
+  }
+  if (X.phase == PH_DONE) return;
+  if (X.tick_kind == PH_ROUND) {
+    if (X.init_round && X.pull_on) {
+      X.usel ^= 1;
+      X.nU = min(h.u_next, n);
       I.u_next_cnt.v = 0;
-      I.u_done = I.u_end;
+      X.u_done = X.u_end;
     }
-    I.init_round = 0;
-    if (I.first && I.ub_next.v < I.ub) I.ub = I.ub_next.v;
-    I.c.rounds += 1;
-    I.rounds_in_step += 1;
-    const int nq = min(I.q_next_cnt.v, I.n), nh = min(I.h_next_cnt.v, I.heavy_cap);
+    X.init_round = 0;
+    if (X.first && h.ub_next < X.ub) X.ub = h.ub_next;
+    rounds += 1;
+    X.rounds_in_step += 1;
+    const int nq = min(h.q_next, n), nh = min(h.h_next, heavy_cap);
     I.q_next_cnt.v = 0;
     I.h_next_cnt.v = 0;
     if (nq > 0 || nh > 0) {
-      I.qsel ^= 1;
-      I.hsel ^= 1;
-      I.nF = nq;
-      I.nH = nh;
-      I.rid += 1;
-      cnt[0] = nq; kinds[0] = SEG_Q; pbs[0] = kRoundBatch;
-      cnt[1] = nh; kinds[1] = SEG_H; pbs[1] = kHeavyPerBatch;
+      X.qsel ^= 1;
+      X.hsel ^= 1;
+      X.nF = nq;
+      X.nH = nh;
+      X.rid += 1;
+      Sp.cnt[0] = nq; Sp.kind[0] = SEG_Q; Sp.pb[0] = kRoundBatch;
+      Sp.cnt[1] = nh; Sp.kind[1] = SEG_H; Sp.pb[1] = kHeavyPerBatch;
       return;
     }
-    if (I.first && I.ub == kInf) {
-      I.phase = PH_DONE;
+    if (X.first && X.ub == kInf) {
+      X.phase = PH_DONE;
       return;
     }
-    I.tick_kind = PH_SETTLE;
-    I.phase = PH_SETTLE;
-    I.nT = min(I.touched_cnt.v, I.n);
-    I.settled_mark = min(I.settled_cnt.v, I.n);
+    X.tick_kind = PH_SETTLE;
+    X.phase = PH_SETTLE;
+    X.nT = min(h.touched, n);
+    X.settled_mark = min(h.settled, n);
     I.settle_done.v = 0;
-    int bt = (I.nT + kSettleBatch - 1) / kSettleBatch;
+    int bt = (X.nT + kSettleBatch - 1) / kSettleBatch;
     if (bt < 1) bt = 1;
-    int bp = (I.nP + kSettleBatch - 1) / kSettleBatch;
-    I.settle_items = bt + bp;
+    int bp = (X.nP + kSettleBatch - 1) / kSettleBatch;
+    X.settle_items = bt + bp;
     // a settle tick always has at least one batch so that the heuristic runs:
     // -1 marks one empty batch
-    cnt[0] = I.nT == 0 ? -1 : I.nT; kinds[0] = SEG_ST; pbs[0] = kSettleBatch;
-    cnt[1] = I.nP; kinds[1] = SEG_SP; pbs[1] = kSettleBatch;
+    Sp.cnt[0] = X.nT == 0 ? -1 : X.nT; Sp.kind[0] = SEG_ST; Sp.pb[0] = kSettleBatch;
+    Sp.cnt[1] = X.nP; Sp.kind[1] = SEG_SP; Sp.pb[1] = kSettleBatch;
     return;
   }
   // a settle tick ran; the heuristic has set phase to ROUND or DONE
-  I.psel ^= 1;
-  I.nP = min(I.p_next_cnt.v, I.n);
+  X.psel ^= 1;
+  X.nP = min(h.p_next, n);
   I.p_next_cnt.v = 0;
   I.touched_cnt.v = 0;
-  if (I.phase == PH_DONE) return;
-  I.tick_kind = PH_ROUND;
-  I.init_round = 1;
-  I.nF = 0;
-  cnt[0] = I.wEnd - I.wBegin; kinds[0] = SEG_W; pbs[0] = kRoundBatch;
-  cnt[1] = I.nP; kinds[1] = SEG_P; pbs[1] = kRoundBatch;
-  cnt[2] = I.pull_on ? I.nU + (I.u_end - I.u_done) : 0; kinds[2] = SEG_U; pbs[2] = kRoundBatch;
+  if (X.phase == PH_DONE) return;
+  X.tick_kind = PH_ROUND;
+  X.init_round = 1;
+  X.nF = 0;
+  Sp.cnt[0] = X.wEnd - X.wBegin; Sp.kind[0] = SEG_W; Sp.pb[0] = kRoundBatch;
+  Sp.cnt[1] = X.nP; Sp.kind[1] = SEG_P; Sp.pb[1] = kRoundBatch;
+  Sp.cnt[2] = X.pull_on ? X.nU + (X.u_end - X.u_done) : 0; Sp.kind[2] = SEG_U;
+  Sp.pb[2] = kRoundBatch;
 }
 
 // Build the tick table. With do_transition, every instance first takes its
-// phase transition, which records its segments of the next tick in the
-// instance; otherwise the recorded segments are laid out as they are (a new
-// launch continuing earlier instances, or the first tick of new ones). One
-// workgroup.
-__device__ void build_table(GGlobals& G, bool do_transition) {
+// phase transition (and, with count, an active instance counts the tick that
+// just ended), which records its segments of the next tick in the instance;
+// otherwise the recorded segments are laid out as they are (a new launch
+// continuing earlier instances, or the first tick of new ones). One
+// workgroup; each thread handles a contiguous run of instances, and every
+// word an instance's transition needs is loaded before any of them is used.
+__device__ void build_table(GGlobals& G, bool do_transition, bool count) {
   const int tid = threadIdx.x;
   const int k = G.ninst;
   __shared__ unsigned long long sh[kBlock / kWave + 1];
   __shared__ int s_active;
   if (tid == 0) s_active = 0;
   __syncthreads();
-  // each thread handles a contiguous run of instances
   const int per = (k + kBlock - 1) / kBlock;
   const int i0 = min(k, tid * per), i1 = min(k, i0 + per);
+  SSSP_GBL Inst* insts = gbl(G.insts);
   int local_batches = 0;
+  int nb_last[kMaxSegPerInst];
+#pragma unroll
+  for (int s = 0; s < kMaxSegPerInst; ++s) nb_last[s] = 0;
   for (int i = i0; i < i1; ++i) {
-    GInst& I = gbl(G.insts)[i];
-    if (do_transition) transition(I, I.spec_cnt, I.spec_kind, I.spec_pb);
-    if (I.phase != PH_DONE) atomicAdd(&s_active, 1);
+    GInst& I = insts[i];
+    SSSP_GBL InstCtl* ctl = (SSSP_GBL InstCtl*)&I;
+    InstCtl X = gload((const SSSP_GBL InstCtl*)ctl);
+    SegSpec Sp;
+    if (do_transition) {
+      const HotIn h = {I.u_next_cnt.v, I.q_next_cnt.v, I.h_next_cnt.v, I.touched_cnt.v,
+                       I.settled_cnt.v, I.p_next_cnt.v, I.ub_next.v};
+      const int32_t n = I.n, heavy_cap = I.heavy_cap;
+      unsigned long long rounds = I.c.rounds, ticks = I.c.ticks;
+      if (count && X.phase != PH_DONE) ticks += 1;
+      transition(X, Sp, h, n, heavy_cap, rounds, I);
+      gstore(ctl, X);
+      gstore(&I.spec, Sp);
+      I.c.rounds = rounds;
+      I.c.ticks = ticks;
+    } else {
+      Sp = gload((const SSSP_GBL SegSpec*)&I.spec);
+    }
+    if (X.phase != PH_DONE) atomicAdd(&s_active, 1);
+#pragma unroll
     for (int s = 0; s < kMaxSegPerInst; ++s) {
-      int sg = i * kMaxSegPerInst + s;
-      int c = I.phase == PH_DONE ? 0 : I.spec_cnt[s];
-      int pb = I.spec_pb[s] > 0 ? I.spec_pb[s] : kBlock;
+      const int sg = i * kMaxSegPerInst + s;
+      int c = X.phase == PH_DONE ? 0 : Sp.cnt[s];
+      const int pb = Sp.pb[s] > 0 ? Sp.pb[s] : kBlock;
       int nb;
       if (c < 0) { nb = 1; c = 0; }
       else nb = (c + pb - 1) / pb;
       gbl(G.seg_inst)[sg] = i;
-      gbl(G.seg_kind)[sg] = I.spec_kind[s];
+      gbl(G.seg_kind)[sg] = Sp.kind[s];
       gbl(G.seg_count)[sg] = c;
       gbl(G.seg_per_batch)[sg] = pb;
-      gbl(G.seg_first_batch)[sg] = nb;  // temporarily the batch count
+      if (per > 1) gbl(G.seg_first_batch)[sg] = nb;  // temporarily the batch count
+      nb_last[s] = nb;
       local_batches += nb;
     }
   }
   unsigned long long total;
   unsigned long long before = block_excl_scan<unsigned long long>((unsigned long long)local_batches, sh, &total);
   int run = (int)before;
-  for (int i = i0; i < i1; ++i) {
-    for (int s = 0; s < kMaxSegPerInst; ++s) {
-      int sg = i * kMaxSegPerInst + s;
-      int nb = gbl(G.seg_first_batch)[sg];
-      gbl(G.seg_first_batch)[sg] = run;
-      run += nb;
+  if (per == 1) {
+    if (i0 < i1) {
+#pragma unroll
+      for (int s = 0; s < kMaxSegPerInst; ++s) {
+        gbl(G.seg_first_batch)[i0 * kMaxSegPerInst + s] = run;
+        run += nb_last[s];
+      }
+    }
+  } else {
+    for (int i = i0; i < i1; ++i) {
+      for (int s = 0; s < kMaxSegPerInst; ++s) {
+        const int sg = i * kMaxSegPerInst + s;
+        const int nb = gbl(G.seg_first_batch)[sg];
+        gbl(G.seg_first_batch)[sg] = run;
+        run += nb;
+      }
     }
   }
   __syncthreads();
@@ -1325,15 +1373,6 @@ __device__ void build_table(GGlobals& G, bool do_transition) {
     gbl(G.seg_first_batch)[G.nseg] = (int)total;
     G.total_batches = (int)total;
     G.all_done = (s_active == 0) ? 1u : 0u;
-  }
-  __syncthreads();
-}
-
-// Ticks counted for the counters (every active instance).
-__device__ void count_ticks(GGlobals& G) {
-  for (int i = threadIdx.x; i < G.ninst; i += kBlock) {
-    GInst& I = gbl(G.insts)[i];
-    if (I.phase != PH_DONE) I.c.ticks += 1;
   }
   __syncthreads();
 }
@@ -1392,7 +1431,7 @@ __device__ __forceinline__ unsigned int quota_for(int total_batches, unsigned in
 
 // The serial part between two ticks (one workgroup): tick log, phase
 // transitions and the next tick's work layout.
-__device__ __noinline__ void epilogue(GGlobals& G, unsigned int gen, unsigned int nxcd,
+__device__ __forceinline__ void epilogue(GGlobals& G, unsigned int gen, unsigned int nxcd,
                                      unsigned int min_members) {
   if (threadIdx.x == 0) {
     if (gbl(G.tick_log) && G.ticks < G.tick_log_cap) {
@@ -1405,8 +1444,7 @@ __device__ __noinline__ void epilogue(GGlobals& G, unsigned int gen, unsigned in
     }
   }
   __syncthreads();
-  count_ticks(G);
-  build_table(G, true);
+  build_table(G, true, true);
   if (threadIdx.x == 0) {
     // the next tick starts at generation gen + 1
     __hip_atomic_store(&G.quota[(gen + 1u) & 7u], quota_for(G.total_batches, nxcd, min_members),
@@ -1695,11 +1733,11 @@ __global__ void __launch_bounds__(kBlock) k_init_ctl(Globals* Gp) {
       I.phase = deg_s > 0 ? PH_ROUND : PH_DONE;
       // first tick: the source alone
       for (int sg = 0; sg < kMaxSegPerInst; ++sg) {
-        I.spec_cnt[sg] = 0;
-        I.spec_kind[sg] = SEG_Q;
-        I.spec_pb[sg] = kRoundBatch;
+        I.spec.cnt[sg] = 0;
+        I.spec.kind[sg] = SEG_Q;
+        I.spec.pb[sg] = kRoundBatch;
       }
-      I.spec_cnt[0] = I.nF;
+      I.spec.cnt[0] = I.nF;
     }
     __syncthreads();
     // gap(0) from whole-graph statistics: sumD(0) = nnz, highD(0)
@@ -1721,7 +1759,7 @@ __global__ void __launch_bounds__(kBlock) k_init_ctl(Globals* Gp) {
     G.ticks = 0;
   }
   __syncthreads();
-  build_table(G, false);
+  build_table(G, false, false);
 }
 
 // Overflow confirmation (only when a range was cut by the +inf clamp): a
