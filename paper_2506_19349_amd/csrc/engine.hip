@@ -1403,10 +1403,15 @@ __device__ __forceinline__ uint32_t xcd_of_this_wg() {
 // invalidate is not enough: measured, stale data was read.)
 __device__ __forceinline__ void acquire_after_release() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
 
+// Wait until *word differs from old. kSleep (units of 64 cycles) paces the
+// polling: every poll is a coherent load of the same line, and hundreds of
+// workgroups polling one line slow down the memory channel behind it, the
+// release write included.
+template <int kSleep>
 __device__ bool spin_until_changed(SSSP_GBL unsigned int* word, unsigned int old, SSSP_GBL unsigned int* err) {
   unsigned long long spins = 0;
   while (__hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == old) {
-    __builtin_amdgcn_s_sleep(1);
+    __builtin_amdgcn_s_sleep(kSleep);
     if (++spins > (1ull << 27)) {
       atomicOr(err, FLAG_TIMEOUT);
       return false;
@@ -1496,7 +1501,7 @@ __device__ bool barrier_flat(GGlobals& G, unsigned int& gen, bool wait, bool run
     }
   } else if (wait) {
     if (threadIdx.x == 0) {
-      s_ok = spin_until_changed(&G.bar_gen.v, gen, &G.error) ? 1 : 0;
+      s_ok = spin_until_changed<1>(&G.bar_gen.v, gen, &G.error) ? 1 : 0;
       __threadfence();
     }
   }
@@ -1505,23 +1510,25 @@ __device__ bool barrier_flat(GGlobals& G, unsigned int& gen, bool wait, bool run
   return s_ok != 0;
 }
 
-// A workgroup outside the current tick waits for the tick's release (longer
-// sleeps: it is not on the tick's critical path) and returns the new release
-// generation, or gen if the engine is done or a wait gave up.
-__device__ unsigned int park_until_released(GGlobals& G, unsigned int gen) {
+// A workgroup outside the current tick waits for its XCD's release of the
+// tick: one line per XCD, polled with long sleeps (it is not on the tick's
+// critical path, and hundreds of parked workgroups polling one line would slow
+// the channel behind it). Returns how many ticks have passed, 0 if an error
+// stopped the engine or the wait gave up. (The end of the engine is released
+// like any tick, after the done flag is set.)
+__device__ unsigned int park_until_released(GGlobals& G, unsigned int xcd, unsigned int xgen) {
   unsigned long long spins = 0;
   unsigned int g;
-  while ((g = __hip_atomic_load(&G.bar_gen.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == gen) {
-    if (__hip_atomic_load(&G.all_done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
-        __hip_atomic_load(&G.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-      return gen;
+  while ((g = __hip_atomic_load(&G.xcd_gen[xcd].v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == xgen) {
     __builtin_amdgcn_s_sleep(16);
-    if (++spins > (1ull << 23)) {
+    ++spins;
+    if ((spins & 63u) == 0 && __hip_atomic_load(&G.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return 0u;
+    if (spins > (1ull << 23)) {
       atomicOr(&G.error, FLAG_TIMEOUT);
-      return gen;
+      return 0u;
     }
   }
-  return g;
+  return g - xgen;
 }
 
 // Two-level barrier of the persistent engine among the tick's participants
@@ -1545,7 +1552,7 @@ __device__ bool barrier_tick(GGlobals& G, BarrierState& B, unsigned int quota) {
         __threadfence();  // see every XCD's written-back data
         s_role = 2;
       } else {
-        s_ok = spin_until_changed(&G.bar_gen.v, B.gen, &G.error) ? 1 : 0;
+        s_ok = spin_until_changed<2>(&G.bar_gen.v, B.gen, &G.error) ? 1 : 0;
         __threadfence();  // drop stale lines from this XCD's L2
         s_role = 1;
       }
@@ -1566,7 +1573,7 @@ __device__ bool barrier_tick(GGlobals& G, BarrierState& B, unsigned int quota) {
     if (threadIdx.x == 0) atomicAdd(&G.xcd_gen[B.xcd].v, 1u);
   } else {
     if (threadIdx.x == 0) {
-      s_ok = spin_until_changed(&G.xcd_gen[B.xcd].v, B.xgen, &G.error) ? 1 : 0;
+      s_ok = spin_until_changed<4>(&G.xcd_gen[B.xcd].v, B.xgen, &G.error) ? 1 : 0;
       acquire_after_release();
     }
   }
@@ -1647,13 +1654,13 @@ __global__ void __launch_bounds__(kBlock, 5) k_engine(Globals* Gp, int persisten
     } else {
       // not needed in this tick: wait for its release
       __shared__ unsigned int s_gen;
-      if (threadIdx.x == 0) s_gen = park_until_released(G, B.gen);
+      if (threadIdx.x == 0) s_gen = park_until_released(G, B.xcd, B.xgen);
       __syncthreads();
-      const unsigned int g = s_gen;
-      if (g == B.gen) break;  // done, error or timeout
-      t += (int)(g - B.gen);
-      B.xgen += g - B.gen;
-      B.gen = g;
+      const unsigned int d = s_gen;
+      if (d == 0u) break;  // error or timeout
+      t += (int)d;
+      B.xgen += d;
+      B.gen += d;
       stale = true;
     }
     if (max_ticks > 0 && t >= max_ticks) {
