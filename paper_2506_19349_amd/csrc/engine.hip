@@ -895,66 +895,97 @@ __device__ __noinline__ void block_round(GInst& I, int kind, int item0, int nite
   __syncthreads();
 
   // ---------------------------------------------------------- phase 2b: edges
+  // Each thread takes kEdgesPerThread edges per pass; their row loads, then
+  // their neighbour-distance loads, then their atomics are in flight together.
   const bool any_pull = (kind == SEG_U) || (kind == SEG_H);
   SSSP_GBL int32_t* qnext = V.q_next;
-  for (int base = 0; base < total; base += kBlock) {
+  constexpr int kPass = kEdgesPerThread * kBlock;
+  for (int base = 0; base < total; base += kPass) {
     __syncthreads();
-    if (S.nq > kStageCap - kBlock || S.nt > kStageCap - kBlock)
+    if (S.nq > kStageCap - kPass || S.nt > kStageCap - kPass)
       stage_flush(S, qnext, &I.q_next_cnt.v, V.touched, &I.touched_cnt.v, V.n, &I.flags.v);
-    const int e = base + tid;
-    bool ok = false;
-    int t = 0;
-    uint32_t c = 0, prev = 0;
-    if (e < total) {
-      int lo_j = 0, hi_j = m;  // largest j with offset[j] <= e
-      while (hi_j - lo_j > 1) {
-        const int mid = (lo_j + hi_j) >> 1;
-        if (L.sz[mid] <= e) lo_j = mid; else hi_j = mid;
+    int jj[kEdgesPerThread];
+    uint64_t ent[kEdgesPerThread];
+#pragma unroll
+    for (int x = 0; x < kEdgesPerThread; ++x) {
+      const int e = base + x * kBlock + tid;
+      jj[x] = -1;
+      ent[x] = 0;
+      if (e < total) {
+        int lo_j = 0, hi_j = m;  // largest j with offset[j] <= e
+        while (hi_j - lo_j > 1) {
+          const int mid = (lo_j + hi_j) >> 1;
+          if (L.sz[mid] <= e) lo_j = mid; else hi_j = mid;
+        }
+        jj[x] = lo_j;
+        ent[x] = V.adj[L.lo[lo_j] + (e - L.sz[lo_j])];
       }
-      const int j = lo_j;
-      const uint64_t ent = V.adj[L.lo[j] + (e - L.sz[j])];
-      const int v = (int)(uint32_t)(ent & 0xffffffffull);
-      const uint32_t w = (uint32_t)(ent >> 32);
+    }
+    uint32_t dv[kEdgesPerThread];
+#pragma unroll
+    for (int x = 0; x < kEdgesPerThread; ++x)
+      dv[x] = jj[x] >= 0 ? dist_of(V.state, (int)(uint32_t)(ent[x] & 0xffffffffull)) : 0u;
+    bool ok[kEdgesPerThread];
+    int t[kEdgesPerThread];
+    uint32_t c[kEdgesPerThread], prev[kEdgesPerThread];
+#pragma unroll
+    for (int x = 0; x < kEdgesPerThread; ++x) {
+      ok[x] = false;
+      t[x] = 0;
+      c[x] = 0;
+      prev[x] = 0;
+      if (jj[x] < 0) continue;
+      const int j = jj[x];
+      const int v = (int)(uint32_t)(ent[x] & 0xffffffffull);
+      const uint32_t w = (uint32_t)(ent[x] >> 32);
       const uint32_t dj = L.d[j];
       if (!(any_pull && L.pull[j])) {
-        c = dj + w;  // < ub by the range
-        t = v;
-        if (c < dist_of(V.state, v)) {
-          const uint64_t old = relax_state(V.state, v, c, V.rid);
-          ok = c < (uint32_t)(old >> 32);
-          prev = (uint32_t)old;
+        c[x] = dj + w;  // < ub by the range
+        t[x] = v;
+        if (c[x] < dv[x]) {
+          const uint64_t old = relax_state(V.state, v, c[x], V.rid);
+          ok[x] = c[x] < (uint32_t)(old >> 32);
+          prev[x] = (uint32_t)old;
         }
       } else {
         // pull: the best candidate of u over this batch's edges, in LDS
-        const uint32_t dv = dist_of(V.state, v);
-        if (dv >= st && dv < lb) {
-          unsigned long long cc = (unsigned long long)dv + w;
+        if (dv[x] >= st && dv[x] < lb) {
+          unsigned long long cc = (unsigned long long)dv[x] + w;
           if (cc < ub && cc < dj) atomicMin(&L.pmin[j], (uint32_t)cc);
         }
       }
     }
-    on_success(V, ok, t, c, prev, acc, S);
+#pragma unroll
+    for (int x = 0; x < kEdgesPerThread; ++x) on_success(V, ok[x], t[x], c[x], prev[x], acc, S);
   }
   if (any_pull) {
     // one device atomic per pulled vertex
-    for (int base = 0; base < m; base += kBlock) {
+    for (int base = 0; base < m; base += kPass) {
       __syncthreads();
-      if (S.nq > kStageCap - kBlock || S.nt > kStageCap - kBlock)
+      if (S.nq > kStageCap - kPass || S.nt > kStageCap - kPass)
         stage_flush(S, qnext, &I.q_next_cnt.v, V.touched, &I.touched_cnt.v, V.n, &I.flags.v);
-      const int w = base + tid;
-      bool ok = false;
-      int t = 0;
-      uint32_t c = 0, prev = 0;
-      if (w < m && L.pull[w]) {
-        c = L.pmin[w];
-        if (c < L.d[w]) {
-          t = L.u[w];
-          const uint64_t old = relax_state(V.state, t, c, V.rid);
-          ok = c < (uint32_t)(old >> 32);
-          prev = (uint32_t)old;
+      bool ok[kEdgesPerThread];
+      int t[kEdgesPerThread];
+      uint32_t c[kEdgesPerThread], prev[kEdgesPerThread];
+#pragma unroll
+      for (int x = 0; x < kEdgesPerThread; ++x) {
+        const int w = base + x * kBlock + tid;
+        ok[x] = false;
+        t[x] = 0;
+        c[x] = 0;
+        prev[x] = 0;
+        if (w < m && L.pull[w]) {
+          c[x] = L.pmin[w];
+          if (c[x] < L.d[w]) {
+            t[x] = L.u[w];
+            const uint64_t old = relax_state(V.state, t[x], c[x], V.rid);
+            ok[x] = c[x] < (uint32_t)(old >> 32);
+            prev[x] = (uint32_t)old;
+          }
         }
       }
-      on_success(V, ok, t, c, prev, acc, S);
+#pragma unroll
+      for (int x = 0; x < kEdgesPerThread; ++x) on_success(V, ok[x], t[x], c[x], prev[x], acc, S);
     }
   }
   stage_flush(S, qnext, &I.q_next_cnt.v, V.touched, &I.touched_cnt.v, V.n, &I.flags.v);
