@@ -162,6 +162,20 @@ sssp_status sssp_solve(const sssp_graph* g, int32_t source, uint32_t* dist_out,
 sssp_status sssp_solve_ex(const sssp_graph* g, int32_t source, uint32_t* dist_out,
                           const sssp_options* opt, hipStream_t stream);
 
+/* Distances and a shortest-path tree from `source` (Section 2.1's output:
+ * dist and the predecessor of every vertex). dist_out as sssp_solve;
+ * parent_out (device, n int32): parent_out[source] = source, parent_out[v] =
+ * the vertex before v on a shortest source-v path, -1 for unreachable
+ * vertices. Every parent edge is tight, dist[parent[v]] + w = dist[v], and
+ * following parents from a reachable vertex ends at the source (also with
+ * zero weights: a parent always reached its distance before its child). Where
+ * several shortest paths exist, which one is reported may vary between runs.
+ * Both buffers are caller-owned; enqueued on `stream`; options as
+ * sssp_solve_ex (NULL = defaults). The solve keeps 8 more bytes per vertex of
+ * device workspace while a tree is requested. */
+sssp_status sssp_solve_tree(const sssp_graph* g, int32_t source, uint32_t* dist_out,
+                            int32_t* parent_out, const sssp_options* opt, hipStream_t stream);
+
 /* k sources on one graph in one persistent launch. sources: host array of k
  * vertex ids; dist_out: device, k * n uint32, row i for sources[i]. */
 sssp_status sssp_solve_batch(const sssp_graph* g, const int32_t* sources, int32_t k,

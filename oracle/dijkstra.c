@@ -17,10 +17,16 @@
  * vertex whose true distance does not fit below UINT32_MAX makes the call
  * return ORACLE_OVERFLOW (its slot holds UINT32_MAX).
  *
+ * Optionally the predecessor array of the same problem statement (Section
+ * 2.1): the textbook Dijkstra keeps, for every vertex, the vertex whose edge
+ * last lowered its tentative distance; at the end that edge is tight and the
+ * predecessors form a tree rooted at s (parent[s] = s, -1 when unreachable).
+ *
  * Also here: an invariant checker over a CSR (dist[s] = 0; no edge can
  * improve a distance; every finite vertex other than s has a tight incoming
  * edge; every finite vertex is reached from s over tight edges; infinite
- * vertices only have infinite neighbours), used as the any-size property check.
+ * vertices only have infinite neighbours), used as the any-size property check,
+ * and a checker of a candidate predecessor array against a distance vector.
  */
 #include <pthread.h>
 #include <stdint.h>
@@ -133,8 +139,8 @@ static heap_item heap_pop(heap *h) {
 
 /* Dijkstra from s on a built adjacency. Returns ORACLE_OK / ORACLE_OVERFLOW /
  * an error code. dist_out has n entries. */
-int oracle_adj_dijkstra(const void *hv, int32_t s, uint32_t *dist_out) {
-  const oracle_adj *a = (const oracle_adj *)hv;
+/* parent_out may be NULL (distances only). */
+static int adj_dijkstra(const oracle_adj *a, int32_t s, uint32_t *dist_out, int32_t *parent_out) {
   if (!a || s < 0 || s >= a->n) return ORACLE_BAD_ARGS;
   const int64_t n = a->n;
   uint64_t *d = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n);
@@ -145,7 +151,10 @@ int oracle_adj_dijkstra(const void *hv, int32_t s, uint32_t *dist_out) {
     return ORACLE_NOMEM;
   }
   for (int64_t v = 0; v < n; ++v) d[v] = UINT64_MAX;
+  if (parent_out)
+    for (int64_t v = 0; v < n; ++v) parent_out[v] = -1;
   d[s] = 0;
+  if (parent_out) parent_out[s] = s;
   int rc = ORACLE_OK;
   if (heap_push(&h, 0, s)) rc = ORACLE_NOMEM;
   while (rc == ORACLE_OK && h.size > 0) {
@@ -158,6 +167,7 @@ int oracle_adj_dijkstra(const void *hv, int32_t s, uint32_t *dist_out) {
       uint64_t nd = d[u] + (uint64_t)a->wt[e];
       if (nd < d[v]) {
         d[v] = nd;
+        if (parent_out) parent_out[v] = u;
         if (heap_push(&h, nd, v)) {
           rc = ORACLE_NOMEM;
           break;
@@ -181,6 +191,16 @@ int oracle_adj_dijkstra(const void *hv, int32_t s, uint32_t *dist_out) {
   free(d);
   free(done);
   return rc;
+}
+
+int oracle_adj_dijkstra(const void *hv, int32_t s, uint32_t *dist_out) {
+  return adj_dijkstra((const oracle_adj *)hv, s, dist_out, NULL);
+}
+
+/* Distances and the predecessor array (parent_out: n entries). */
+int oracle_adj_dijkstra_tree(const void *hv, int32_t s, uint32_t *dist_out, int32_t *parent_out) {
+  if (!parent_out) return ORACLE_BAD_ARGS;
+  return adj_dijkstra((const oracle_adj *)hv, s, dist_out, parent_out);
 }
 
 /* One-shot: build the adjacency from the raw edge list, solve, free. */
@@ -303,4 +323,69 @@ int64_t oracle_check_sssp(int64_t n, const int32_t *rowptr, const int32_t *col, 
   free(seen);
   free(queue);
   return counts[0] + counts[1] + counts[2] + counts[3] + counts[4];
+}
+
+/* Checker of a candidate predecessor array on a CSR (rowptr[n+1], col[nnz],
+ * w[nnz]; undirected: row v lists the edges at v) against a distance vector
+ * (taken as given: check it with oracle_check_sssp). counts[0..3] receive the
+ * number of violations of:
+ *   0  parent[s] != s
+ *   1  an unreachable vertex (dist = +inf) with parent != -1, or a reachable
+ *      vertex other than s whose parent is not a vertex id
+ *   2  a reachable vertex v != s with no edge (parent[v], v, w) in its row
+ *      such that dist[parent[v]] + w == dist[v] (the parent edge is not tight)
+ *   3  a reachable vertex from which following parents does not end at s
+ *      (a cycle, or a chain through an invalid or unreachable vertex)
+ * Returns the total, -1 for bad arguments, -2 when out of memory. */
+int64_t oracle_check_tree(int64_t n, const int32_t *rowptr, const int32_t *col, const uint32_t *w,
+                          int32_t s, const uint32_t *dist, const int32_t *parent, int64_t *counts) {
+  for (int i = 0; i < 4; ++i) counts[i] = 0;
+  if (n < 1 || s < 0 || s >= n) return -1;
+  if (parent[s] != s) counts[0]++;
+  for (int64_t v = 0; v < n; ++v) {
+    if (dist[v] == INF32) {
+      if (parent[v] != -1) counts[1]++;
+      continue;
+    }
+    if (v == s) continue;
+    const int32_t p = parent[v];
+    if (p < 0 || p >= n) {
+      counts[1]++;
+      continue;
+    }
+    int tight = 0;
+    if (dist[p] != INF32)
+      for (int64_t e = rowptr[v]; e < rowptr[v + 1] && !tight; ++e)
+        if (col[e] == p && (uint64_t)dist[p] + w[e] == (uint64_t)dist[v]) tight = 1;
+    if (!tight) counts[2]++;
+  }
+  /* chains: 0 unvisited, 1 on the current walk, 2 ends at s, 3 does not */
+  unsigned char *color = (unsigned char *)calloc((size_t)n, 1);
+  int32_t *path = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+  if (!color || !path) {
+    free(color); free(path);
+    return -2;
+  }
+  color[s] = parent[s] == s ? 2 : 3;
+  for (int64_t v0 = 0; v0 < n; ++v0) {
+    if (dist[v0] == INF32 || color[v0]) continue;
+    int64_t len = 0;
+    int64_t v = v0;
+    unsigned char end;
+    for (;;) {
+      if (v < 0 || v >= n || dist[v] == INF32) { end = 3; break; }
+      if (color[v] == 2 || color[v] == 3) { end = color[v]; break; }
+      if (color[v] == 1) { end = 3; break; } /* a cycle */
+      color[v] = 1;
+      path[len++] = (int32_t)v;
+      v = parent[v];
+    }
+    for (int64_t i = 0; i < len; ++i) {
+      color[path[i]] = end;
+      if (end == 3) counts[3]++;
+    }
+  }
+  free(color);
+  free(path);
+  return counts[0] + counts[1] + counts[2] + counts[3];
 }

@@ -39,6 +39,11 @@ def _load():
     lib.oracle_check_sssp.argtypes = [i64, i32p, i32p, u32p, ctypes.c_int32, u32p,
                                       ctypes.POINTER(ctypes.c_int64)]
     lib.oracle_check_sssp.restype = ctypes.c_int64
+    lib.oracle_adj_dijkstra_tree.argtypes = [ctypes.c_void_p, ctypes.c_int32, u32p, i32p]
+    lib.oracle_adj_dijkstra_tree.restype = ctypes.c_int
+    lib.oracle_check_tree.argtypes = [i64, i32p, i32p, u32p, ctypes.c_int32, u32p, i32p,
+                                      ctypes.POINTER(ctypes.c_int64)]
+    lib.oracle_check_tree.restype = ctypes.c_int64
     _lib = lib
     return lib
 
@@ -69,6 +74,17 @@ class Adjacency:
         if rc != OK:
             raise RuntimeError("oracle_adj_dijkstra failed: %d" % rc)
         return out
+
+    def dijkstra_tree(self, s: int):
+        """Distances and the predecessor array (parent[s] = s, -1 where unreachable)."""
+        out = np.empty(self.n, np.uint32)
+        par = np.empty(self.n, np.int32)
+        rc = _load().oracle_adj_dijkstra_tree(self._h, int(s), _p(out, ctypes.c_uint32), _p(par, ctypes.c_int32))
+        if rc == OVERFLOW:
+            raise OverflowError("a shortest-path length does not fit below 2^32-1")
+        if rc != OK:
+            raise RuntimeError("oracle_adj_dijkstra_tree failed: %d" % rc)
+        return out, par
 
     def dijkstra_many(self, sources, threads: int) -> np.ndarray:
         srcs = np.ascontiguousarray(sources, np.int32)
@@ -113,4 +129,25 @@ def check_sssp(n, rowptr, col, w, s, dist):
                                 _p(w, ctypes.c_uint32), int(s), _p(dist, ctypes.c_uint32), counts)
     if tot < 0:
         raise ValueError("oracle_check_sssp: bad arguments")
+    return [int(c) for c in counts]
+
+
+def check_tree(n, rowptr, col, w, s, dist, parent):
+    """Violation counts of a candidate predecessor array against a distance vector on a
+    CSR: [parent(s) != s, bad entry (unreachable with a parent, or not a vertex id),
+    parent edge not tight, chain not ending at s]."""
+    lib = _load()
+    rowptr = np.ascontiguousarray(rowptr, np.int32)
+    col = np.ascontiguousarray(col, np.int32)
+    w = np.ascontiguousarray(w, np.uint32)
+    dist = np.ascontiguousarray(dist, np.uint32)
+    parent = np.ascontiguousarray(parent, np.int32)
+    counts = (ctypes.c_int64 * 4)()
+    tot = lib.oracle_check_tree(int(n), _p(rowptr, ctypes.c_int32), _p(col, ctypes.c_int32),
+                                _p(w, ctypes.c_uint32), int(s), _p(dist, ctypes.c_uint32),
+                                _p(parent, ctypes.c_int32), counts)
+    if tot == -1:
+        raise ValueError("oracle_check_tree: bad arguments")
+    if tot < 0:
+        raise MemoryError("oracle_check_tree: out of memory")
     return [int(c) for c in counts]

@@ -134,6 +134,20 @@ class Graph:
                                       _stream_handle(stream)))
         return out
 
+    def solve_tree(self, source: int, out=None, parent=None, stream=None, **opts):
+        """Distances and a shortest-path tree from `source`: (dist, parent), a uint32
+        and an int32 cuda tensor of n entries; parent[source] = source, -1 where
+        unreachable."""
+        if out is None:
+            out = _empty_dist(self.n)
+        if parent is None:
+            torch = _torch()
+            parent = torch.empty(self.n, dtype=torch.int32, device="cuda")
+        o = _options(**opts)
+        _lib.check(_lib.sssp_solve_tree(self._h, int(source), _ptr(out), _ptr(parent), ctypes.byref(o),
+                                        _stream_handle(stream)))
+        return out, parent
+
     def solve_batch(self, sources: Sequence[int], out=None, stream=None):
         """k sources in one launch: a (k, n) uint32 cuda tensor, row i for sources[i]."""
         srcs = np.ascontiguousarray(np.asarray(sources, dtype=np.int32))

@@ -86,6 +86,19 @@ size_t needs_bytes(const Needs& m) {
   return b;
 }
 
+hipError_t ensure_best(SlotBuf& s, int32_t n) {
+  if (s.best_cap >= n) return hipSuccess;
+  uint64_t* p = nullptr;
+  hipError_t e = dev_alloc(&p, (size_t)n, s.allocs);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return e;
+  }
+  s.best = p;  // an older, smaller array stays in allocs until the slot is released
+  s.best_cap = n;
+  return hipSuccess;
+}
+
 bool slot_fits(const SlotBuf& s, const Needs& nd) {
   return s.n_cap >= nd.n && s.list_cap >= nd.list && s.maxw >= nd.maxw && s.heavy_cap >= nd.heavy &&
          s.hist_cap >= nd.hist && s.trace_cap >= nd.trace && s.ring_cap >= nd.ring &&
@@ -282,10 +295,12 @@ bool parse_opts(const sssp_options* o, Opts* r, std::string* err) {
 
 // Host image of one solve instance (its control words are set on the device).
 void fill_inst(Inst& I, const SlotBuf& s, const sssp_graph* g, int32_t source, uint32_t* dist,
-               const Opts& o) {
+               const Opts& o, int32_t* parent) {
   std::memset(&I, 0, sizeof(Inst));
   I.g = g->gh.d;
   I.dist = dist;
+  I.parent = parent;
+  I.best = parent ? s.best : nullptr;
   I.state = s.state;
   I.q[0] = s.q[0];
   I.q[1] = s.q[1];
@@ -320,16 +335,18 @@ void fill_inst(Inst& I, const SlotBuf& s, const sssp_graph* g, int32_t source, u
 }
 
 sssp_status run_instances(const sssp_graph* const* gs, const int32_t* sources, int k,
-                          uint32_t* const* dists, const Opts& o, hipStream_t stream) {
+                          uint32_t* const* dists, const Opts& o, hipStream_t stream,
+                          int32_t* const* parents) {
   std::string err;
   Workspace* wp = get_ws(stream, &err);
   if (!wp) return fail(SSSP_E_DEVICE, err);
-  return run_instances_ws(*wp, gs, sources, k, dists, o, stream);
+  return run_instances_ws(*wp, gs, sources, k, dists, o, stream, parents);
 }
 
 // Enqueue k instances on workspace w; every argument has been checked.
 sssp_status run_instances_ws(Workspace& w, const sssp_graph* const* gs, const int32_t* sources, int k,
-                             uint32_t* const* dists, const Opts& o, hipStream_t stream) {
+                             uint32_t* const* dists, const Opts& o, hipStream_t stream,
+                             int32_t* const* parents) {
   HIP_TRY(ws_ensure_insts(w, k));
   long long max_n = 0;
   for (int i = 0; i < k; ++i) {
@@ -340,6 +357,13 @@ sssp_status run_instances_ws(Workspace& w, const sssp_graph* const* gs, const in
     if (!slot_fits(s, nd)) {
       (void)hipStreamSynchronize(stream);
       hipError_t e = ensure_slot(s, nd);
+      if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+        return fail(SSSP_E_NOMEM, "workspace allocation failed");
+      HIP_TRY(e);
+    }
+    if (parents && parents[i] && s.best_cap < g.n) {
+      (void)hipStreamSynchronize(stream);
+      hipError_t e = ensure_best(s, g.n);
       if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
         return fail(SSSP_E_NOMEM, "workspace allocation failed");
       HIP_TRY(e);
@@ -365,7 +389,8 @@ sssp_status run_instances_ws(Workspace& w, const sssp_graph* const* gs, const in
   hG->insts = w.dInst;
   hG->sel_list = nullptr;
   hG->n_sel = -1;
-  for (int i = 0; i < k; ++i) fill_inst(hI[i], w.slots[(size_t)i], gs[i], sources[i], dists[i], o);
+  for (int i = 0; i < k; ++i)
+    fill_inst(hI[i], w.slots[(size_t)i], gs[i], sources[i], dists[i], o, parents ? parents[i] : nullptr);
   HIP_TRY(hipMemcpyAsync(w.dG, hG, sizeof(Globals), hipMemcpyHostToDevice, stream));
   HIP_TRY(hipMemcpyAsync(w.dInst, hI, sizeof(Inst) * (size_t)k, hipMemcpyHostToDevice, stream));
   HIP_TRY(hipEventRecord(w.stage_ev[si], stream));
@@ -582,6 +607,21 @@ sssp_status sssp_solve_ex(const sssp_graph* g, int32_t source, uint32_t* dist_ou
   int32_t src[1] = {source};
   uint32_t* d[1] = {dist_out};
   return run_instances(gs, src, 1, d, o, stream);
+}
+
+sssp_status sssp_solve_tree(const sssp_graph* g, int32_t source, uint32_t* dist_out, int32_t* parent_out,
+                            const sssp_options* opt, hipStream_t stream) {
+  std::string err;
+  if (!check_graph(g, &err)) return fail(SSSP_E_INVAL, err);
+  if (source < 0 || source >= g->gh.h.n) return fail(SSSP_E_INVAL, "source out of range");
+  if (!dist_out || !parent_out) return fail(SSSP_E_INVAL, "dist_out and parent_out are required");
+  Opts o;
+  if (!parse_opts(opt, &o, &err)) return fail(SSSP_E_INVAL, err);
+  const sssp_graph* gs[1] = {g};
+  int32_t src[1] = {source};
+  uint32_t* d[1] = {dist_out};
+  int32_t* par[1] = {parent_out};
+  return run_instances(gs, src, 1, d, o, stream, par);
 }
 
 sssp_status sssp_solve(const sssp_graph* g, int32_t source, uint32_t* dist_out, hipStream_t stream) {

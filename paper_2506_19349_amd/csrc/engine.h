@@ -136,6 +136,11 @@ constexpr int kMaxSegPerInst = 5;  // segments one instance may have in a tick
 struct InstFixed {
   const DevGraph* g;
   uint32_t* dist;          // the caller's output, written once the solve ends
+  int32_t* parent;         // the caller's tree output (Section 2.1's predecessors), or null
+  // with a tree: per vertex (distance << 32) | the vertex whose relaxation set
+  // that distance. A relaxation that lowers a distance is the only one that
+  // sets that value, so the 64-bit atomicMin keeps the last one's source.
+  uint64_t* best;
   // per vertex: (tentative distance << 32) | round id of its last decrease
   // (0: never decreased). One 64-bit atomicMin both lowers the distance and
   // returns the round of the previous decrease, which de-duplicates the next
@@ -220,6 +225,7 @@ constexpr uint32_t FLAG_MASS = 4u;            // degree-mass bookkeeping mismatc
 constexpr uint32_t FLAG_TIMEOUT = 8u;         // a grid barrier wait gave up
 constexpr uint32_t FLAG_OVERFLOW = 16u;       // confirmed: a distance does not fit below kInf
 constexpr uint32_t FLAG_TICKS = 32u;          // the tick limit stopped the engine
+constexpr uint32_t FLAG_TREE = 64u;           // a tree entry disagrees with its distance (bug guard)
 
 // ------------------------------------------------------------- tick table --
 

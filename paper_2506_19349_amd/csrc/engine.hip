@@ -382,6 +382,7 @@ struct View {
   SSSP_GBL uint64_t* state;
   SSSP_GBL int32_t* q_next;
   SSSP_GBL int32_t* touched;
+  SSSP_GBL uint64_t* best;  // null: no tree
   GInst* inst;
   uint32_t lb, ub, st, lb0, rid, step_rid0;
   int32_t n, heavy_split, maxw;
@@ -401,6 +402,7 @@ __device__ __forceinline__ View make_view(GInst& I) {
   v.state = gbl(I.state);
   v.q_next = gbl(I.q[I.qsel ^ 1]);
   v.touched = gbl(I.touched);
+  v.best = I.best ? gbl(I.best) : nullptr;
   v.inst = &I;
   v.lb = I.lb;
   v.ub = I.ub;
@@ -531,16 +533,18 @@ __device__ void stage_flush(StageLds& S, SSSP_GBL int32_t* qlist, SSSP_GBL int32
   __syncthreads();
 }
 
-// A successful decrease of dist[t] to c during round `rid`, whose previous
-// decrease was in round `prev`: t joins the next frontier once per round
+// A successful decrease of dist[t] to c by vertex src during round `rid`,
+// whose previous decrease was in round `prev`: t joins the next frontier once per round
 // (SAP) and the step's touched list once per step. Convergent within a wave.
-__device__ __forceinline__ void on_success(const View& V, bool ok, int t, uint32_t c, uint32_t prev,
+__device__ __forceinline__ void on_success(const View& V, bool ok, int t, uint32_t c, uint32_t prev, int src,
                                            WaveAcc& acc, StageLds& S) {
   bool wq = false, wt = false;
   if (ok) {
     wq = prev != V.rid;
     wt = prev < V.step_rid0;
     acc.success += 1;
+    // the tree: src set dist[t] to c (a later, smaller c replaces it)
+    if (V.best) atomicMin((SSSP_GBL unsigned long long*)(V.best + t), ((unsigned long long)c << 32) | (uint32_t)src);
     acc.qent += (wq ? 1 : 0) + (wt ? 1 : 0);
     if (V.first && hub_bit(V.hub_bits, t) && c < acc.hubmin) acc.hubmin = c;
   }
@@ -581,7 +585,9 @@ __device__ void emit_heavy(GInst& I, int u, uint32_t d, int lo, int hi, bool pul
 struct RoundLds {
   int32_t u[kRoundBatch];
   uint32_t d[kRoundBatch];
-  uint32_t pmin[kRoundBatch];  // pull items: best candidate for dist[u] found in this batch
+  // pull items: best candidate for dist[u] found in this batch, as
+  // (candidate << 32) | the settled neighbour it comes from
+  unsigned long long pmin[kRoundBatch];
   int32_t lo[kRoundBatch];
   int32_t re[kRoundBatch];  // row end when the row is known (pull-list items), else -1
   int32_t sz[kRoundBatch];  // size, -1 = range still to find; then exclusive offsets
@@ -727,7 +733,7 @@ __device__ __noinline__ void block_round(GInst& I, int kind, int item0, int nite
   }
   __syncthreads();
   const int m = L.count;
-  for (int w = tid; w < m; w += kBlock) L.pmin[w] = kInf;
+  for (int w = tid; w < m; w += kBlock) L.pmin[w] = ~0ull;
 
   // ---------------------------------------------------------- phase 2a: ranges
   // An item's range is [first weight >= lo key, first weight >= hi key) of
@@ -926,12 +932,13 @@ __device__ __noinline__ void block_round(GInst& I, int kind, int item0, int nite
     for (int x = 0; x < kEdgesPerThread; ++x)
       dv[x] = jj[x] >= 0 ? dist_of(V.state, (int)(uint32_t)(ent[x] & 0xffffffffull)) : 0u;
     bool ok[kEdgesPerThread];
-    int t[kEdgesPerThread];
+    int t[kEdgesPerThread], from[kEdgesPerThread];
     uint32_t c[kEdgesPerThread], prev[kEdgesPerThread];
 #pragma unroll
     for (int x = 0; x < kEdgesPerThread; ++x) {
       ok[x] = false;
       t[x] = 0;
+      from[x] = 0;
       c[x] = 0;
       prev[x] = 0;
       if (jj[x] < 0) continue;
@@ -942,6 +949,7 @@ __device__ __noinline__ void block_round(GInst& I, int kind, int item0, int nite
       if (!(any_pull && L.pull[j])) {
         c[x] = dj + w;  // < ub by the range
         t[x] = v;
+        from[x] = L.u[j];
         if (c[x] < dv[x]) {
           const uint64_t old = relax_state(V.state, v, c[x], V.rid);
           ok[x] = c[x] < (uint32_t)(old >> 32);
@@ -951,12 +959,12 @@ __device__ __noinline__ void block_round(GInst& I, int kind, int item0, int nite
         // pull: the best candidate of u over this batch's edges, in LDS
         if (dv[x] >= st && dv[x] < lb) {
           unsigned long long cc = (unsigned long long)dv[x] + w;
-          if (cc < ub && cc < dj) atomicMin(&L.pmin[j], (uint32_t)cc);
+          if (cc < ub && cc < dj) atomicMin(&L.pmin[j], (cc << 32) | (uint32_t)v);
         }
       }
     }
 #pragma unroll
-    for (int x = 0; x < kEdgesPerThread; ++x) on_success(V, ok[x], t[x], c[x], prev[x], acc, S);
+    for (int x = 0; x < kEdgesPerThread; ++x) on_success(V, ok[x], t[x], c[x], prev[x], from[x], acc, S);
   }
   if (any_pull) {
     // one device atomic per pulled vertex
@@ -965,17 +973,20 @@ __device__ __noinline__ void block_round(GInst& I, int kind, int item0, int nite
       if (S.nq > kStageCap - kPass || S.nt > kStageCap - kPass)
         stage_flush(S, qnext, &I.q_next_cnt.v, V.touched, &I.touched_cnt.v, V.n, &I.flags.v);
       bool ok[kEdgesPerThread];
-      int t[kEdgesPerThread];
+      int t[kEdgesPerThread], from[kEdgesPerThread];
       uint32_t c[kEdgesPerThread], prev[kEdgesPerThread];
 #pragma unroll
       for (int x = 0; x < kEdgesPerThread; ++x) {
         const int w = base + x * kBlock + tid;
         ok[x] = false;
         t[x] = 0;
+        from[x] = 0;
         c[x] = 0;
         prev[x] = 0;
         if (w < m && L.pull[w]) {
-          c[x] = L.pmin[w];
+          const unsigned long long pm = L.pmin[w];
+          c[x] = (uint32_t)(pm >> 32);
+          from[x] = (int)(uint32_t)pm;
           if (c[x] < L.d[w]) {
             t[x] = L.u[w];
             const uint64_t old = relax_state(V.state, t[x], c[x], V.rid);
@@ -985,7 +996,7 @@ __device__ __noinline__ void block_round(GInst& I, int kind, int item0, int nite
         }
       }
 #pragma unroll
-      for (int x = 0; x < kEdgesPerThread; ++x) on_success(V, ok[x], t[x], c[x], prev[x], acc, S);
+      for (int x = 0; x < kEdgesPerThread; ++x) on_success(V, ok[x], t[x], c[x], prev[x], from[x], acc, S);
     }
   }
   stage_flush(S, qnext, &I.q_next_cnt.v, V.touched, &I.touched_cnt.v, V.n, &I.flags.v);
@@ -1713,6 +1724,8 @@ __global__ void k_init_arrays(Globals* Gp) {
     GDevGraph& g = *gbl(I.g);
     auto state = gbl(I.state);
     for (long long v = tid; v < I.n; v += stride) state[v] = (unsigned long long)kInf << 32;
+    if (I.best)
+      for (long long v = tid; v < I.n; v += stride) gbl(I.best)[v] = ~0ull;
     for (long long x = tid; x < I.maxw; x += stride) {
       Counters z = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
       gstore(gbl(I.cslot) + x, z);
@@ -1762,6 +1775,7 @@ __global__ void __launch_bounds__(kBlock) k_init_ctl(Globals* Gp) {
       // round ids restart with every solve (the state words are reset)
       I.step_rid0 = 1;
       gbl(I.state)[s] = (unsigned long long)I.step_rid0;  // distance 0, touched in step 1
+      if (I.best) gbl(I.best)[s] = (unsigned long long)(uint32_t)s;  // the root is its own parent
       I.rid = I.step_rid0 + 1;
       gbl(I.touched)[0] = s;
       I.touched_cnt.v = 1;
@@ -1837,6 +1851,16 @@ __global__ void k_finish(Globals* Gp) {
     auto state = gbl(I.state);
     auto dist = gbl(I.dist);
     for (long long v = tid; v < I.n; v += stride) dist[v] = (uint32_t)(state[v] >> 32);
+    if (I.parent && I.best) {
+      auto parent = gbl(I.parent);
+      auto best = gbl(I.best);
+      for (long long v = tid; v < I.n; v += stride) {
+        const uint32_t d = (uint32_t)(state[v] >> 32);
+        const unsigned long long b = best[v];
+        parent[v] = d == kInf ? -1 : (int32_t)(uint32_t)b;
+        if (d != kInf && (uint32_t)(b >> 32) != d) atomicOr(&I.flags.v, FLAG_TREE);
+      }
+    }
   }
 }
 

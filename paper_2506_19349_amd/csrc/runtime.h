@@ -49,12 +49,17 @@ struct SlotBuf {
   StepRec* steprec = nullptr;
   TraceRec* trace = nullptr;
   Counters* cslot = nullptr;
+  // the tree's (distance, source) words: only for solves that ask for a tree
+  uint64_t* best = nullptr;
+  int32_t best_cap = 0;
   std::vector<void*> allocs;
   void release() {
     for (void* p : allocs) (void)hipFree(p);
     allocs.clear();
     n_cap = list_cap = maxw = heavy_cap = hist_cap = trace_cap = 0;
     ring_cap = steprec_cap = 0;
+    best = nullptr;
+    best_cap = 0;
   }
 };
 
@@ -66,6 +71,8 @@ struct Needs {
 Needs needs_for(const DevGraph& g, int maxw);
 bool slot_fits(const SlotBuf& s, const Needs& nd);
 hipError_t ensure_slot(SlotBuf& s, const Needs& nd);
+// the tree's words for n vertices in slot s
+hipError_t ensure_best(SlotBuf& s, int32_t n);
 // device bytes a slot of these sizes holds
 size_t needs_bytes(const Needs& nd);
 
@@ -128,12 +135,16 @@ bool parse_opts(const sssp_options* o, Opts* r, std::string* err);
 // requested workgroups per CU, fewer for small graphs.
 int engine_grid(const Workspace& w, const Opts& o, long long total_n);
 
+// parent: the caller's tree output, or null (then the slot needs no tree words)
 void fill_inst(Inst& I, const SlotBuf& s, const sssp_graph* g, int32_t source, uint32_t* dist,
-               const Opts& o);
+               const Opts& o, int32_t* parent = nullptr);
+// parents: null, or k tree outputs (entries may be null)
 sssp_status run_instances(const sssp_graph* const* gs, const int32_t* sources, int k,
-                          uint32_t* const* dists, const Opts& o, hipStream_t stream);
+                          uint32_t* const* dists, const Opts& o, hipStream_t stream,
+                          int32_t* const* parents = nullptr);
 sssp_status run_instances_ws(Workspace& w, const sssp_graph* const* gs, const int32_t* sources, int k,
-                             uint32_t* const* dists, const Opts& o, hipStream_t stream);
+                             uint32_t* const* dists, const Opts& o, hipStream_t stream,
+                             int32_t* const* parents = nullptr);
 bool check_graph(const sssp_graph* g, std::string* err);
 sssp_status collect_counters(Workspace& w, int i0, int k, sssp_counters* out);
 sssp_status ws_take_times(Workspace& w, std::vector<float>* us);

@@ -1,7 +1,8 @@
 """GPU parity at the full sizes of the measured workloads, in the launch
 configuration bench.py times: RMAT-24 (every distance checked by the
 oracle's invariant checker, which characterises them completely for weights
->= 1; bench.py compares one source with the oracle's Dijkstra), ER-22 and the
+>= 1; bench.py compares one source with the oracle's Dijkstra; a
+shortest-path tree checked by the oracle's tree checker), ER-22 and the
 2048 x 2048 grid against the oracle's Dijkstra, and the 64-source RMAT-22
 plan (sampled rows)."""
 import numpy as np
@@ -43,6 +44,23 @@ def test_rmat24_invariants():
     # filter off: the same distances
     d_off = g.solve(srcs[0], traversal_opt=False).cpu().numpy()
     assert_same(d_off, outs[0], "rmat24 filter off")
+    g.close()
+
+
+def test_rmat24_tree():
+    # a shortest-path tree at full size: the same distances as the plain solve,
+    # and a valid predecessor array for them (the oracle's tree checker)
+    wl = graphgen.workload("rmat24")
+    c = wl.csr
+    g = sssp.Graph.from_csr(c)
+    s = int(wl.sources(1)[0])
+    plain = g.solve(s).cpu().numpy()
+    d, p = g.solve_tree(s)
+    assert sssp.counters()["flags"] == 0
+    d = d.cpu().numpy()
+    assert_same(d, plain, "rmat24 tree distances")
+    assert invariant_ok(c, s, d)
+    assert native.check_tree(c.n, c.rowptr, c.col, c.w, s, d, p.cpu().numpy()) == [0, 0, 0, 0]
     g.close()
 
 
