@@ -536,6 +536,7 @@ __device__ void stage_flush(StageLds& S, SSSP_GBL int32_t* qlist, SSSP_GBL int32
 // A successful decrease of dist[t] to c by vertex src during round `rid`,
 // whose previous decrease was in round `prev`: t joins the next frontier once per round
 // (SAP) and the step's touched list once per step. Convergent within a wave.
+template <bool kTree>
 __device__ __forceinline__ void on_success(const View& V, bool ok, int t, uint32_t c, uint32_t prev, int src,
                                            WaveAcc& acc, StageLds& S) {
   bool wq = false, wt = false;
@@ -544,7 +545,7 @@ __device__ __forceinline__ void on_success(const View& V, bool ok, int t, uint32
     wt = prev < V.step_rid0;
     acc.success += 1;
     // the tree: src set dist[t] to c (a later, smaller c replaces it)
-    if (V.best) atomicMin((SSSP_GBL unsigned long long*)(V.best + t), ((unsigned long long)c << 32) | (uint32_t)src);
+    if (kTree) atomicMin((SSSP_GBL unsigned long long*)(V.best + t), ((unsigned long long)c << 32) | (uint32_t)src);
     acc.qent += (wq ? 1 : 0) + (wt ? 1 : 0);
     if (V.first && hub_bit(V.hub_bits, t) && c < acc.hubmin) acc.hubmin = c;
   }
@@ -585,9 +586,12 @@ __device__ void emit_heavy(GInst& I, int u, uint32_t d, int lo, int hi, bool pul
 struct RoundLds {
   int32_t u[kRoundBatch];
   uint32_t d[kRoundBatch];
-  // pull items: best candidate for dist[u] found in this batch, as
+  // pull items: best candidate for dist[u] found in this batch; with a tree
   // (candidate << 32) | the settled neighbour it comes from
-  unsigned long long pmin[kRoundBatch];
+  union {
+    uint32_t pmin32[kRoundBatch];
+    unsigned long long pmin64[kRoundBatch];
+  };
   int32_t lo[kRoundBatch];
   int32_t re[kRoundBatch];  // row end when the row is known (pull-list items), else -1
   int32_t sz[kRoundBatch];  // size, -1 = range still to find; then exclusive offsets
@@ -616,6 +620,9 @@ __device__ __forceinline__ void lds_push_item(RoundLds& L, bool want, int u, uin
   }
 }
 
+// kTree: the instance also records a shortest-path tree (a separate
+// instantiation, so that solves without one pay nothing for it).
+template <bool kTree>
 __device__ __noinline__ void block_round(GInst& I, int kind, int item0, int nitems, RoundLds& L) {
   const View V = make_view(I);
   const int tid = threadIdx.x;
@@ -733,7 +740,10 @@ __device__ __noinline__ void block_round(GInst& I, int kind, int item0, int nite
   }
   __syncthreads();
   const int m = L.count;
-  for (int w = tid; w < m; w += kBlock) L.pmin[w] = ~0ull;
+  for (int w = tid; w < m; w += kBlock) {
+    if (kTree) L.pmin64[w] = ~0ull;
+    else L.pmin32[w] = kInf;
+  }
 
   // ---------------------------------------------------------- phase 2a: ranges
   // An item's range is [first weight >= lo key, first weight >= hi key) of
@@ -959,12 +969,15 @@ __device__ __noinline__ void block_round(GInst& I, int kind, int item0, int nite
         // pull: the best candidate of u over this batch's edges, in LDS
         if (dv[x] >= st && dv[x] < lb) {
           unsigned long long cc = (unsigned long long)dv[x] + w;
-          if (cc < ub && cc < dj) atomicMin(&L.pmin[j], (cc << 32) | (uint32_t)v);
+          if (cc < ub && cc < dj) {
+            if (kTree) atomicMin(&L.pmin64[j], (cc << 32) | (uint32_t)v);
+            else atomicMin(&L.pmin32[j], (uint32_t)cc);
+          }
         }
       }
     }
 #pragma unroll
-    for (int x = 0; x < kEdgesPerThread; ++x) on_success(V, ok[x], t[x], c[x], prev[x], from[x], acc, S);
+    for (int x = 0; x < kEdgesPerThread; ++x) on_success<kTree>(V, ok[x], t[x], c[x], prev[x], from[x], acc, S);
   }
   if (any_pull) {
     // one device atomic per pulled vertex
@@ -984,9 +997,13 @@ __device__ __noinline__ void block_round(GInst& I, int kind, int item0, int nite
         c[x] = 0;
         prev[x] = 0;
         if (w < m && L.pull[w]) {
-          const unsigned long long pm = L.pmin[w];
-          c[x] = (uint32_t)(pm >> 32);
-          from[x] = (int)(uint32_t)pm;
+          if (kTree) {
+            const unsigned long long pm = L.pmin64[w];
+            c[x] = (uint32_t)(pm >> 32);
+            from[x] = (int)(uint32_t)pm;
+          } else {
+            c[x] = L.pmin32[w];
+          }
           if (c[x] < L.d[w]) {
             t[x] = L.u[w];
             const uint64_t old = relax_state(V.state, t[x], c[x], V.rid);
@@ -996,7 +1013,7 @@ __device__ __noinline__ void block_round(GInst& I, int kind, int item0, int nite
         }
       }
 #pragma unroll
-      for (int x = 0; x < kEdgesPerThread; ++x) on_success(V, ok[x], t[x], c[x], prev[x], from[x], acc, S);
+      for (int x = 0; x < kEdgesPerThread; ++x) on_success<kTree>(V, ok[x], t[x], c[x], prev[x], from[x], acc, S);
     }
   }
   stage_flush(S, qnext, &I.q_next_cnt.v, V.touched, &I.touched_cnt.v, V.n, &I.flags.v);
@@ -1177,6 +1194,7 @@ __device__ int find_segment(const GGlobals& G, int b) {
 // any grouping of rounds reaches the same settled set. When the frontier
 // empties or grows past one batch, the epilogue takes over with its usual
 // transition of the last round.
+template <bool kTree>
 __device__ __noinline__ void fused_rounds(GInst& I, RoundLds& L) {
   __shared__ int s_go, s_nq;
   const int cap = I.fuse_cap;
@@ -1209,7 +1227,7 @@ __device__ __noinline__ void fused_rounds(GInst& I, RoundLds& L) {
     }
     __syncthreads();
     if (!s_go) break;
-    block_round(I, SEG_Q, 0, s_nq, L);
+    block_round<kTree>(I, SEG_Q, 0, s_nq, L);
   }
 }
 
@@ -1245,10 +1263,15 @@ __device__ void run_tick(GGlobals& G, BlockLds& lds, int pid, int P) {
       }
       __syncthreads();
     } else {
-      block_round(I, kind, item0, cnt, lds.r);
+      const bool tree = I.best != nullptr;
+      if (tree) block_round<true>(I, kind, item0, cnt, lds.r);
+      else block_round<false>(I, kind, item0, cnt, lds.r);
       // a frontier that fits one batch, with no heavy chunks, belongs to this
       // workgroup alone for the whole tick: chain its next rounds here
-      if (kind == SEG_Q && cnt <= pb && I.nH == 0 && I.fuse_cap > 0) fused_rounds(I, lds.r);
+      if (kind == SEG_Q && cnt <= pb && I.nH == 0 && I.fuse_cap > 0) {
+        if (tree) fused_rounds<true>(I, lds.r);
+        else fused_rounds<false>(I, lds.r);
+      }
     }
   }
 }
