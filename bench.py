@@ -167,6 +167,49 @@ def batched_section(args, sssp, torch, np, graphgen):
     return res
 
 
+def variants_section(args, sssp, torch, np, graphgen):
+    """The integer-power weight variants (Eq. 7) of RMAT-22: the same topology
+    with 2^power - 1 distinct weights. Per power: GTEPS over 4 solves and the
+    paper's nTrav (Section 4.4: worst with one weight, about 5 or less with 255
+    or more); every source's distances pass the oracle's invariant checker."""
+    from oracle import native  # the any-size distance check
+    out = {}
+    for p in (1, 2, 3, 4, 6, 8, 10):
+        wl = graphgen.workload("rmat22p%d" % p)
+        csr = wl.csr
+        deg = csr.degrees()
+        g = sssp.Graph.from_csr(csr)
+        srcs = [int(s) for s in wl.sources(5)]
+        o = torch.empty(csr.n, dtype=torch.uint32, device="cuda")
+        g.solve(srcs[0], out=o)
+        torch.cuda.synchronize()
+        sssp.engine_times()
+        m_cc, dt, ntrav, ok = 0, 0.0, [], True
+        for s in srcs[1:]:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            g.solve(s, out=o)
+            torch.cuda.synchronize()
+            dt += time.perf_counter() - t0
+            c = sssp.counters()
+            d = o.cpu().numpy()
+            reach = d != INF
+            m_cc += int(deg[reach].sum()) // 2
+            ntrav.append((c["push_scanned"] + c["pull_scanned"]) / max(int(reach.sum()), 1))
+            ok = ok and sum(native.check_sssp(csr.n, csr.rowptr, csr.col, csr.w, s, d)) == 0
+        eng = sssp.engine_times()
+        out["power%d" % p] = {"distinct_weights": (1 << p) - 1, "gteps": round(m_cc / dt / 1e9, 3),
+                              "ms_per_solve": round(dt * 1e3 / (len(srcs) - 1), 3),
+                              "engine_us_mean": round(sum(eng) / max(len(eng), 1), 1),
+                              "nTrav": round(sum(ntrav) / len(ntrav), 3), "steps": c["steps"],
+                              "ticks": c["ticks"], "invariants_ok": ok}
+        log("variant power %d: %.2f GTEPS, nTrav %.2f, %d steps, invariants %s"
+            % (p, out["power%d" % p]["gteps"], out["power%d" % p]["nTrav"], c["steps"], ok))
+        del o
+        g.close()
+    return out
+
+
 def served_section(args, sssp, torch, np, graphgen):
     """Poisson stream of single-source queries over resident graphs (RMAT-20,
     RMAT-22, RMAT-23 and the 2048 x 2048 road-like grid), graph uniform per
@@ -256,6 +299,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched measurements")
     ap.add_argument("--no-served", action="store_true", help="skip the served measurements")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the integer-power weight variants of RMAT-22")
     ap.add_argument("--serve-queries", type=int, default=128)
     ap.add_argument("--serve-load", type=float, default=0.8,
                     help="arrival rate as a fraction of the one-at-a-time capacity of the mix")
@@ -388,6 +433,7 @@ def main():
 
     batched = None
     served = None
+    variants = None
     if wl.name == "rmat24":
         del outs
         g.close()
@@ -395,6 +441,8 @@ def main():
             batched = batched_section(args, sssp, torch, np, graphgen)
         if not args.no_served:
             served = served_section(args, sssp, torch, np, graphgen)
+        if not args.no_variants:
+            variants = variants_section(args, sssp, torch, np, graphgen)
 
     traffic = measured_traffic(wl.name)
     config = {"workload": "rmat24-plain-sssp" if wl.name == "rmat24" else wl.name,
@@ -429,6 +477,7 @@ def main():
         "ablation_filter_off": ablation,
         "batched": batched,
         "served": served,
+        "weight_variants": variants,
         "prep_s": round(prep_s, 4),
         "counters": counters,
     }

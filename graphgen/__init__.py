@@ -43,6 +43,8 @@ def _load():
     lib.gg_rmat.restype = ctypes.c_int
     lib.gg_gnm.argtypes = [i64, i64, ctypes.c_uint32, ctypes.c_uint64, i32p, i32p, u32p]
     lib.gg_gnm.restype = ctypes.c_int
+    lib.gg_weights_power.argtypes = [i64, ctypes.c_uint64, ctypes.c_int32, u32p]
+    lib.gg_weights_power.restype = ctypes.c_int
     lib.gg_grid.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                             ctypes.c_uint32, ctypes.c_uint64, i32p, i32p, u32p]
     lib.gg_grid.restype = i64
@@ -110,6 +112,16 @@ def rmat(scale: int, edge_factor: int = 16, a: float = 0.57, b: float = 0.19, c:
     if rc != 0:
         raise ValueError("gg_rmat: bad arguments")
     return EdgeList(n, src, dst, w)
+
+
+def weights_power(m: int, power: int, seed: int) -> np.ndarray:
+    """The integer-power variant weights (Eq. 7) of m edges: the integer
+    nearest to 1 + x (2^power - 2), x uniform on (0, 1], halves rounded up."""
+    lib = _load()
+    w = np.empty(m, np.uint32)
+    if lib.gg_weights_power(m, seed, power, _p(w, ctypes.c_uint32)) != 0:
+        raise ValueError("gg_weights_power: bad arguments")
+    return w
 
 
 def rmat_degrees(scale: int, edge_factor: int = 16, a: float = 0.57, b: float = 0.19,
@@ -218,8 +230,16 @@ def workload(name: str, scale: Optional[int] = None) -> Workload:
     ``rmat24``  R-MAT scale 24, edge factor 16, w in 1..255
     ``grid2048`` 2048 x 2048 grid, 5% of edges dropped, 1% diagonals, w in 1..1000
     ``rmat<k>`` / ``er<k>`` / ``grid<k>`` the same recipes at other sizes
+    ``rmat<k>p<power>``  the R-MAT graph rmat<k> with its weights replaced by the
+                 integer-power variant's (Eq. 7): 2^power - 1 distinct weights
     """
-    if name.startswith("rmat"):
+    if name.startswith("rmat") and "p" in name[4:]:
+        sk, pw = name[4:].split("p")
+        s = int(sk) if scale is None else scale
+        seed = SEED_BASE + {14: 1, 24: 3, 22: 5}.get(s, 100 + s)
+        el = rmat(s, 16, 0.57, 0.19, 0.19, 255, seed)
+        el = EdgeList(el.n, el.src, el.dst, weights_power(el.src.shape[0], int(pw), seed))
+    elif name.startswith("rmat"):
         s = int(name[4:]) if scale is None else scale
         seed = SEED_BASE + {14: 1, 24: 3, 22: 5}.get(s, 100 + s)
         el = rmat(s, 16, 0.57, 0.19, 0.19, 255, seed)

@@ -179,6 +179,24 @@ int gg_rmat_degrees(int32_t scale, int64_t edge_factor, double a, double b, doub
 }
 
 // G(n, m): m endpoint pairs, each endpoint uniform on [0, n).
+// Weights of a variant graph (the paper's integer-power variants, Eq. 7):
+// x uniform on (0, 1] from the weight stream of `seed` (edge i uses counter
+// i, as the generators do), then the integer nearest to 1 + x * (2^power - 2),
+// halves rounded up, so that the 2^power - 1 integers 1 .. 2^power - 1 occur.
+// power = 1 gives unit weights.
+int gg_weights_power(int64_t m, uint64_t seed, int32_t power, uint32_t* w) {
+  if (m < 0 || power < 1 || power > 31) return -1;
+  const uint64_t wkey = stream_key(seed, kStreamWeight);
+  const double span = (double)((1ULL << power) - 2);
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < m; ++i) {
+    const uint64_t r = draw(wkey, (uint64_t)i);
+    const double x = (double)((r >> 11) + 1) * (1.0 / 9007199254740992.0);  // (0, 1]
+    w[i] = (uint32_t)(1.0 + x * span + 0.5);
+  }
+  return 0;
+}
+
 int gg_gnm(int64_t n, int64_t m, uint32_t wmax, uint64_t seed, int32_t* src, int32_t* dst,
            uint32_t* w) {
   if (n < 1 || n > INT32_MAX || m < 0 || wmax < 1) return -1;

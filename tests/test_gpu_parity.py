@@ -81,7 +81,7 @@ def test_rmat14_host_driven_mode():
         assert_same(gpu_dist(g, s, host_driven=True), oracle_dist(wl.edges, s), "host-driven")
 
 
-@pytest.mark.parametrize("name", ["rmat14", "er12", "grid64", "rmat12"])
+@pytest.mark.parametrize("name", ["rmat14", "er12", "grid64", "rmat12", "rmat12p1", "rmat12p4"])
 def test_schedule_matches_model(name):
     """The per-step <lb, ub, st> and the statistics taken at each step's end
     are determined by the settled set, so the GPU must reproduce the
@@ -143,6 +143,19 @@ def test_medium_graphs_bit_exact(name):
     for s in wl.sources(3):
         assert_same(gpu_dist(g, s), oracle_dist(wl.edges, s), "%s s=%d" % (name, s))
         assert sssp.counters()["flags"] == 0
+
+
+@pytest.mark.parametrize("power", [1, 2, 3, 4, 6, 8, 10])
+def test_integer_power_variants_bit_exact(power):
+    """The paper's integer-power variant graphs (Eq. 7; power 1 is unit weights,
+    every shortest path tied), with and without the traversal filter."""
+    wl = graphgen.workload("rmat14p%d" % power)
+    g = sssp.Graph.from_csr(wl.csr)
+    for s in wl.sources(3):
+        ref = oracle_dist(wl.edges, s)
+        for topt in (True, False):
+            assert_same(gpu_dist(g, s, traversal_opt=topt), ref, "rmat14p%d s=%d" % (power, s))
+            assert sssp.counters()["flags"] == 0
 
 
 def test_edge_cases():

@@ -2,6 +2,7 @@
 import hashlib
 
 import numpy as np
+import pytest
 
 import graphgen
 from graphgen import small
@@ -79,3 +80,31 @@ def test_sources_have_edges_and_are_distinct():
     assert len(set(srcs.tolist())) == 64
     assert np.all(deg[srcs] >= 1)
     assert np.array_equal(srcs, wl.sources(64))
+
+
+@pytest.mark.parametrize("power", [1, 2, 3, 4, 6, 8, 10])
+def test_integer_power_weights(power):
+    """Eq. 7's variant weights: exactly the 2^power - 1 integers 1 .. 2^power - 1,
+    the inner ones equally likely and the two ends half as likely (the nearest
+    integer to 1 + x (2^power - 2), x uniform on (0, 1]); repeatable."""
+    m = 400000
+    w = graphgen.weights_power(m, power, 4242)
+    assert np.array_equal(w, graphgen.weights_power(m, power, 4242))
+    k = (1 << power) - 1
+    assert int(w.min()) == 1 and int(w.max()) == k
+    cnt = np.bincount(w, minlength=k + 1)[1:]
+    assert cnt.shape[0] == k and (cnt > 0).all()
+    if power == 1:
+        assert cnt[0] == m
+    else:
+        inner = m / (k - 1)
+        assert abs(cnt[0] - inner / 2) < 0.1 * inner and abs(cnt[-1] - inner / 2) < 0.1 * inner
+        if k > 2:
+            assert np.all(np.abs(cnt[1:-1] - inner) < 0.1 * inner + 5 * np.sqrt(inner))
+
+
+def test_power_variant_keeps_the_topology():
+    a = graphgen.workload("rmat12")
+    b = graphgen.workload("rmat12p3")
+    assert np.array_equal(a.edges.src, b.edges.src) and np.array_equal(a.edges.dst, b.edges.dst)
+    assert set(np.unique(b.edges.w).tolist()) <= set(range(1, 8))

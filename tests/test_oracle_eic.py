@@ -135,3 +135,25 @@ def test_no_hub_reachable_ends_after_first_step():
     ref = native.dijkstra(el.n, el.src, el.dst, el.w, s)
     assert np.array_equal(r.dist, ref)
     assert len(r.steps) == 1 and r.steps[0].ub == INF
+
+
+def test_model_on_integer_power_variants():
+    """Section 4.4 on the integer-power variant graphs (Eq. 7): traversals per
+    reachable vertex are worst with a single weight (power 1: every shortest
+    path ties, each edge is scanned from both sides) and about 3-5.5 once there
+    are at least 255 distinct weights; distances stay exact throughout."""
+    ntrav = {}
+    for p in (1, 4, 8, 10):
+        wl = graphgen.workload("rmat14p%d" % p)
+        c = wl.csr
+        vals = []
+        for s in wl.sources(2):
+            r = eic.eic_sssp(c.n, c.rowptr, c.col, c.w, int(s))
+            ref = native.dijkstra(wl.edges.n, wl.edges.src, wl.edges.dst, wl.edges.w, int(s))
+            assert np.array_equal(r.dist, ref), (p, s)
+            vals.append(eic.normalised(r, c.n, c.degrees())["nTrav"])
+        ntrav[p] = float(np.mean(vals))
+    assert ntrav[1] > 4 * ntrav[10], ntrav
+    assert ntrav[1] > ntrav[4] > ntrav[8] * 0.9, ntrav
+    for p in (8, 10):
+        assert 2.5 <= ntrav[p] <= 5.5, ntrav
