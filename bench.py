@@ -404,6 +404,33 @@ def main():
     sssp.engine_times()
     log("filter off: %.2f GTEPS, nTrav %.2f" % (ablation["gteps"], ablation["nTrav"]))
 
+    # point-to-point queries: the solve stops once the target is settled;
+    # targets drawn among the vertices the first timed source reaches
+    d_all = outs[0].cpu().numpy()  # distances of timed[-1] (counters pass)
+    reach = np.nonzero(d_all != INF)[0]
+    rng = np.random.default_rng(wl.seed + 31)
+    pairs = [(timed[i % len(timed)], int(rng.choice(reach))) for i in range(8)]
+    p2p_out = torch.empty(csr.n, dtype=torch.uint32, device="cuda")
+    g.solve_p2p(pairs[0][0], pairs[0][1], out=p2p_out)
+    sssp.engine_times()
+    steps_p2p = []
+    for s, t in pairs:
+        g.solve_p2p(s, t, out=p2p_out)
+        steps_p2p.append(sssp.counters()["steps"])
+    p2p_us = sssp.engine_times()
+    # the last pair's target distance against the full solve of its source
+    # (its own buffer: outs[0] still holds timed[-1]'s distances)
+    chk = torch.empty(csr.n, dtype=torch.uint32, device="cuda")
+    g.solve(pairs[-1][0], out=chk)
+    sssp.engine_times()
+    exact = int(p2p_out[pairs[-1][1]].item()) == int(chk[pairs[-1][1]].item())
+    del p2p_out, chk
+    p2p = {"pairs": len(pairs), "engine_us_mean": round(sum(p2p_us) / len(p2p_us), 1),
+           "vs_full_solve": round(sum(p2p_us) / len(p2p_us) / eng_mean_us, 3),
+           "steps_mean": round(sum(steps_p2p) / len(steps_p2p), 2), "last_target_exact": exact}
+    log("point-to-point: %.1f us per query (%.2f of a full solve), %.1f steps; exact: %s"
+        % (p2p["engine_us_mean"], p2p["vs_full_solve"], p2p["steps_mean"], exact))
+
     cpu = None
     if not args.no_cpu_baseline:
         from oracle import native  # CPU baseline leg only
@@ -477,6 +504,7 @@ def main():
         "ablation_filter_off": ablation,
         "batched": batched,
         "served": served,
+        "point_to_point": p2p,
         "weight_variants": variants,
         "prep_s": round(prep_s, 4),
         "counters": counters,

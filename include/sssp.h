@@ -176,6 +176,17 @@ sssp_status sssp_solve_ex(const sssp_graph* g, int32_t source, uint32_t* dist_ou
 sssp_status sssp_solve_tree(const sssp_graph* g, int32_t source, uint32_t* dist_out,
                             int32_t* parent_out, const sssp_options* opt, hipStream_t stream);
 
+/* Point-to-point query (Section 5 names it among the method's uses): the
+ * solve stops at the end of the first step after which `target` is settled.
+ * dist_out (device, n uint32, caller-owned) then holds the exact distance of
+ * target, and of every vertex whose entry is <= that distance; the other
+ * entries are upper bounds of their distances (UINT32_MAX where no path has
+ * been found yet). An unreachable target runs the whole solve and reads
+ * UINT32_MAX. Options as sssp_solve_ex (NULL = defaults); enqueued on
+ * `stream`; sssp_get_counters and sssp_get_schedule describe the steps run. */
+sssp_status sssp_solve_p2p(const sssp_graph* g, int32_t source, int32_t target, uint32_t* dist_out,
+                           const sssp_options* opt, hipStream_t stream);
+
 /* k sources on one graph in one persistent launch. sources: host array of k
  * vertex ids; dist_out: device, k * n uint32, row i for sources[i]. */
 sssp_status sssp_solve_batch(const sssp_graph* g, const int32_t* sources, int32_t k,

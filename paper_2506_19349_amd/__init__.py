@@ -148,6 +148,18 @@ class Graph:
                                         _stream_handle(stream)))
         return out, parent
 
+    def solve_p2p(self, source: int, target: int, out=None, stream=None, **opts):
+        """Point-to-point query: the solve stops once `target` is settled. Returns
+        (distance of target, the uint32 distance tensor): exact for target and
+        for every entry not above its distance, upper bounds elsewhere. Waits
+        for the stream."""
+        if out is None:
+            out = _empty_dist(self.n)
+        o = _options(**opts)
+        _lib.check(_lib.sssp_solve_p2p(self._h, int(source), int(target), _ptr(out), ctypes.byref(o),
+                                       _stream_handle(stream)))
+        return int(out[int(target)].item()), out
+
     def solve_batch(self, sources: Sequence[int], out=None, stream=None):
         """k sources in one launch: a (k, n) uint32 cuda tensor, row i for sources[i]."""
         srcs = np.ascontiguousarray(np.asarray(sources, dtype=np.int32))

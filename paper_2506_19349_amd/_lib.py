@@ -93,6 +93,7 @@ sssp_graph_rtow = _sig("sssp_graph_rtow", i32, vp, vp)
 sssp_solve = _sig("sssp_solve", i32, vp, i32, vp, vp)
 sssp_solve_ex = _sig("sssp_solve_ex", i32, vp, i32, vp, ctypes.POINTER(Options), vp)
 sssp_solve_tree = _sig("sssp_solve_tree", i32, vp, i32, vp, vp, ctypes.POINTER(Options), vp)
+sssp_solve_p2p = _sig("sssp_solve_p2p", i32, vp, i32, i32, vp, ctypes.POINTER(Options), vp)
 sssp_solve_batch = _sig("sssp_solve_batch", i32, vp, vp, i32, vp, vp)
 sssp_solve_multi = _sig("sssp_solve_multi", i32, vp, vp, i32, vp, ctypes.POINTER(Options), vp)
 sssp_get_counters = _sig("sssp_get_counters", i32, vp, ctypes.POINTER(Counters))

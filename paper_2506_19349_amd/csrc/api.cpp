@@ -325,6 +325,7 @@ void fill_inst(Inst& I, const SlotBuf& s, const sssp_graph* g, int32_t source, u
   I.steprec_mask = nd.steprec - 1;
   I.trace_cap = s.trace_cap;
   I.source = source;
+  I.target = -1;
   I.n = g->gh.h.n;
   I.alpha = o.alpha;
   I.traversal_opt = o.topt;
@@ -336,17 +337,17 @@ void fill_inst(Inst& I, const SlotBuf& s, const sssp_graph* g, int32_t source, u
 
 sssp_status run_instances(const sssp_graph* const* gs, const int32_t* sources, int k,
                           uint32_t* const* dists, const Opts& o, hipStream_t stream,
-                          int32_t* const* parents) {
+                          int32_t* const* parents, const int32_t* targets) {
   std::string err;
   Workspace* wp = get_ws(stream, &err);
   if (!wp) return fail(SSSP_E_DEVICE, err);
-  return run_instances_ws(*wp, gs, sources, k, dists, o, stream, parents);
+  return run_instances_ws(*wp, gs, sources, k, dists, o, stream, parents, targets);
 }
 
 // Enqueue k instances on workspace w; every argument has been checked.
 sssp_status run_instances_ws(Workspace& w, const sssp_graph* const* gs, const int32_t* sources, int k,
                              uint32_t* const* dists, const Opts& o, hipStream_t stream,
-                             int32_t* const* parents) {
+                             int32_t* const* parents, const int32_t* targets) {
   HIP_TRY(ws_ensure_insts(w, k));
   long long max_n = 0;
   for (int i = 0; i < k; ++i) {
@@ -389,8 +390,10 @@ sssp_status run_instances_ws(Workspace& w, const sssp_graph* const* gs, const in
   hG->insts = w.dInst;
   hG->sel_list = nullptr;
   hG->n_sel = -1;
-  for (int i = 0; i < k; ++i)
+  for (int i = 0; i < k; ++i) {
     fill_inst(hI[i], w.slots[(size_t)i], gs[i], sources[i], dists[i], o, parents ? parents[i] : nullptr);
+    if (targets) hI[i].target = targets[i];
+  }
   HIP_TRY(hipMemcpyAsync(w.dG, hG, sizeof(Globals), hipMemcpyHostToDevice, stream));
   HIP_TRY(hipMemcpyAsync(w.dInst, hI, sizeof(Inst) * (size_t)k, hipMemcpyHostToDevice, stream));
   HIP_TRY(hipEventRecord(w.stage_ev[si], stream));
@@ -622,6 +625,22 @@ sssp_status sssp_solve_tree(const sssp_graph* g, int32_t source, uint32_t* dist_
   uint32_t* d[1] = {dist_out};
   int32_t* par[1] = {parent_out};
   return run_instances(gs, src, 1, d, o, stream, par);
+}
+
+sssp_status sssp_solve_p2p(const sssp_graph* g, int32_t source, int32_t target, uint32_t* dist_out,
+                           const sssp_options* opt, hipStream_t stream) {
+  std::string err;
+  if (!check_graph(g, &err)) return fail(SSSP_E_INVAL, err);
+  if (source < 0 || source >= g->gh.h.n) return fail(SSSP_E_INVAL, "source out of range");
+  if (target < 0 || target >= g->gh.h.n) return fail(SSSP_E_INVAL, "target out of range");
+  if (!dist_out) return fail(SSSP_E_INVAL, "dist_out is NULL");
+  Opts o;
+  if (!parse_opts(opt, &o, &err)) return fail(SSSP_E_INVAL, err);
+  const sssp_graph* gs[1] = {g};
+  int32_t src[1] = {source};
+  uint32_t* d[1] = {dist_out};
+  int32_t tgt[1] = {target};
+  return run_instances(gs, src, 1, d, o, stream, nullptr, tgt);
 }
 
 sssp_status sssp_solve(const sssp_graph* g, int32_t source, uint32_t* dist_out, hipStream_t stream) {

@@ -165,6 +165,7 @@ struct InstFixed {
   uint32_t steprec_mask;
   int32_t trace_cap;
   int32_t source;
+  int32_t target;          // point-to-point query: stop once this vertex is settled; -1: none
   int32_t n;
   uint32_t alpha;
   uint32_t traversal_opt;

@@ -291,8 +291,11 @@ __device__ __noinline__ void run_heuristic(GInst& I, HeurLds& lds) {
     I.trace_len += 1;
     I.c.steps += 1;
   }
+  // a point-to-point query (Section 5 lists them among the method's uses)
+  // ends once its target is settled: every distance below L is final now
   const bool done = (L == kInf) ||
-                    (I.p_next_cnt.v == 0 && (unsigned long long)I.max_settled.v + I.M < L);
+                    (I.p_next_cnt.v == 0 && (unsigned long long)I.max_settled.v + I.M < L) ||
+                    (I.target >= 0 && (uint32_t)(gbl(I.state)[I.target] >> 32) < L);
   if (done) {
     if (tid == 0) I.phase = PH_DONE;
     __syncthreads();

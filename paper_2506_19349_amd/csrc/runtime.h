@@ -138,13 +138,14 @@ int engine_grid(const Workspace& w, const Opts& o, long long total_n);
 // parent: the caller's tree output, or null (then the slot needs no tree words)
 void fill_inst(Inst& I, const SlotBuf& s, const sssp_graph* g, int32_t source, uint32_t* dist,
                const Opts& o, int32_t* parent = nullptr);
-// parents: null, or k tree outputs (entries may be null)
+// parents: null, or k tree outputs (entries may be null); targets: null, or k
+// point-to-point targets (-1: none)
 sssp_status run_instances(const sssp_graph* const* gs, const int32_t* sources, int k,
                           uint32_t* const* dists, const Opts& o, hipStream_t stream,
-                          int32_t* const* parents = nullptr);
+                          int32_t* const* parents = nullptr, const int32_t* targets = nullptr);
 sssp_status run_instances_ws(Workspace& w, const sssp_graph* const* gs, const int32_t* sources, int k,
                              uint32_t* const* dists, const Opts& o, hipStream_t stream,
-                             int32_t* const* parents = nullptr);
+                             int32_t* const* parents = nullptr, const int32_t* targets = nullptr);
 bool check_graph(const sssp_graph* g, std::string* err);
 sssp_status collect_counters(Workspace& w, int i0, int k, sssp_counters* out);
 sssp_status ws_take_times(Workspace& w, std::vector<float>* us);
