@@ -45,6 +45,8 @@ def _load():
     lib.gg_gnm.restype = ctypes.c_int
     lib.gg_weights_power.argtypes = [i64, ctypes.c_uint64, ctypes.c_int32, u32p]
     lib.gg_weights_power.restype = ctypes.c_int
+    lib.gg_weights_f32.argtypes = [i64, ctypes.c_uint64, ctypes.c_int32, ctypes.c_double, u32p]
+    lib.gg_weights_f32.restype = ctypes.c_int
     lib.gg_grid.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                             ctypes.c_uint32, ctypes.c_uint64, i32p, i32p, u32p]
     lib.gg_grid.restype = i64
@@ -121,6 +123,18 @@ def weights_power(m: int, power: int, seed: int) -> np.ndarray:
     w = np.empty(m, np.uint32)
     if lib.gg_weights_power(m, seed, power, _p(w, ctypes.c_uint32)) != 0:
         raise ValueError("gg_weights_power: bad arguments")
+    return w
+
+
+def weights_f32(m: int, seed: int, pivot: Optional[float] = None) -> np.ndarray:
+    """Real weights as binary32 bit patterns (uint32): x uniform on (0, 1] (the
+    gr26 graphs), or with a pivot the float-pivot variant converge(x, pivot)
+    of Eq. 8."""
+    lib = _load()
+    w = np.empty(m, np.uint32)
+    mode, p = (0, 0.5) if pivot is None else (1, float(pivot))
+    if lib.gg_weights_f32(m, seed, mode, p, _p(w, ctypes.c_uint32)) != 0:
+        raise ValueError("gg_weights_f32: bad arguments")
     return w
 
 
@@ -230,10 +244,25 @@ def workload(name: str, scale: Optional[int] = None) -> Workload:
     ``rmat24``  R-MAT scale 24, edge factor 16, w in 1..255
     ``grid2048`` 2048 x 2048 grid, 5% of edges dropped, 1% diagonals, w in 1..1000
     ``rmat<k>`` / ``er<k>`` / ``grid<k>`` the same recipes at other sizes
+    ``rmat<k>f``  the R-MAT graph rmat<k> with real weights uniform on (0, 1] (binary32 bits)
+    ``rmat<k>c<d>``  the same with the float-pivot variant's weights (Eq. 8), pivot d / 10
     ``rmat<k>p<power>``  the R-MAT graph rmat<k> with its weights replaced by the
                  integer-power variant's (Eq. 7): 2^power - 1 distinct weights
     """
-    if name.startswith("rmat") and "p" in name[4:]:
+    if name.startswith("rmat") and (name.endswith("f") or "c" in name[4:]):
+        # rmat<k>f: real weights uniform on (0, 1]; rmat<k>c<d>: the float-pivot
+        # variant (Eq. 8) with pivot d / 10 -- binary32 bit patterns
+        body = name[4:]
+        if body.endswith("f"):
+            sk, pivot = body[:-1], None
+        else:
+            sk, d = body.split("c")
+            pivot = int(d) / 10.0
+        s = int(sk) if scale is None else scale
+        seed = SEED_BASE + {14: 1, 24: 3, 22: 5}.get(s, 100 + s)
+        el = rmat(s, 16, 0.57, 0.19, 0.19, 255, seed)
+        el = EdgeList(el.n, el.src, el.dst, weights_f32(el.src.shape[0], seed, pivot))
+    elif name.startswith("rmat") and "p" in name[4:]:
         sk, pw = name[4:].split("p")
         s = int(sk) if scale is None else scale
         seed = SEED_BASE + {14: 1, 24: 3, 22: 5}.get(s, 100 + s)

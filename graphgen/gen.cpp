@@ -197,6 +197,31 @@ int gg_weights_power(int64_t m, uint64_t seed, int32_t power, uint32_t* w) {
   return 0;
 }
 
+// Real weights as IEEE binary32 bit patterns, from the same weight stream:
+// mode 0 the gr26 graphs' weights, x uniform on (0, 1]; mode 1 the float-pivot
+// variants (Eq. 8), converge(x, pivot) = pivot - pivot (1 - 2x)^2 for x <= 1/2,
+// pivot + (1 - pivot)(1 - 2x)^2 above, computed in double and rounded to the
+// nearest binary32.
+int gg_weights_f32(int64_t m, uint64_t seed, int32_t mode, double pivot, uint32_t* w) {
+  if (m < 0 || mode < 0 || mode > 1 || !(pivot > 0.0 && pivot < 1.0)) return -1;
+  const uint64_t wkey = stream_key(seed, kStreamWeight);
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < m; ++i) {
+    const uint64_t r = draw(wkey, (uint64_t)i);
+    const double x = (double)((r >> 11) + 1) * (1.0 / 9007199254740992.0);  // (0, 1]
+    double y = x;
+    if (mode == 1) {
+      const double t = (1.0 - 2.0 * x) * (1.0 - 2.0 * x);
+      y = x <= 0.5 ? pivot - pivot * t : pivot + (1.0 - pivot) * t;
+    }
+    const float f = (float)y;
+    uint32_t b;
+    memcpy(&b, &f, sizeof b);
+    w[i] = b;
+  }
+  return 0;
+}
+
 int gg_gnm(int64_t n, int64_t m, uint32_t wmax, uint64_t seed, int32_t* src, int32_t* dst,
            uint32_t* w) {
   if (n < 1 || n > INT32_MAX || m < 0 || wmax < 1) return -1;

@@ -130,6 +130,15 @@ sssp_graph* sssp_graph_create(int32_t n, const int32_t* rowptr, const int32_t* c
                               const uint32_t* weight);
 
 #define SSSP_CREATE_SKIP_SYMMETRY_CHECK 1
+/* Real weights (the paper's gr26 graphs and their Eq. 8 variants): `weight`
+ * holds IEEE binary32 bit patterns of finite non-negative values (-0.0, inf
+ * and NaN are rejected). Distances are then binary32 bit patterns too: each
+ * is the smallest, over all paths, of the path's weights summed in order in
+ * binary32 (round to nearest), the value the textbook Dijkstra computes in
+ * binary32; UINT32_MAX still marks unreachable vertices. Such graphs run the
+ * dynamic stepping (Eq. 1-3) with the selection threshold at lb: computeST's
+ * window (Eq. 4-6) is kept for integer distances only. */
+#define SSSP_CREATE_FLOAT_WEIGHTS 2
 /* As sssp_graph_create, with flags (SSSP_CREATE_*). Skipping the symmetry
  * check leaves correctness to the caller: the pull (Section 3.2) relies on it. */
 sssp_graph* sssp_graph_create_ex(int32_t n, const int32_t* rowptr, const int32_t* colidx,

@@ -9,7 +9,10 @@ LIB = os.path.join(HERE, "liboracle.so")
 def build(verbose: bool = False) -> str:
     src = os.path.join(HERE, "dijkstra.c")
     tmp = LIB + ".tmp"
-    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-pthread", "-o", tmp, src]
+    # binary32 sums must be single IEEE additions: no contraction into fused
+    # multiply-adds, no wider intermediates (x86-64 SSE arithmetic)
+    cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fexcess-precision=standard", "-fPIC", "-shared",
+           "-pthread", "-o", tmp, src]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)

@@ -17,6 +17,13 @@
  * vertex whose true distance does not fit below UINT32_MAX makes the call
  * return ORACLE_OVERFLOW (its slot holds UINT32_MAX).
  *
+ * Real weights (the gr26 graphs and their Eq. 8 variants): with weights
+ * given as IEEE binary32 bit patterns, the same Dijkstra with binary32
+ * distances: d[v] = min over u of fl(d[u] + w), each addition a single
+ * binary32 round-to-nearest. fl(a + w) never decreases as a grows, so this is
+ * the smallest over all paths of the path's weights summed in order in
+ * binary32, which is what any complete relaxation order converges to.
+ *
  * Optionally the predecessor array of the same problem statement (Section
  * 2.1): the textbook Dijkstra keeps, for every vertex, the vertex whose edge
  * last lowered its tentative distance; at the end that edge is tight and the
@@ -201,6 +208,61 @@ int oracle_adj_dijkstra(const void *hv, int32_t s, uint32_t *dist_out) {
 int oracle_adj_dijkstra_tree(const void *hv, int32_t s, uint32_t *dist_out, int32_t *parent_out) {
   if (!parent_out) return ORACLE_BAD_ARGS;
   return adj_dijkstra((const oracle_adj *)hv, s, dist_out, parent_out);
+}
+
+static float f32_of(uint32_t b) {
+  float f;
+  memcpy(&f, &b, sizeof f);
+  return f;
+}
+
+static uint32_t bits_of(float f) {
+  uint32_t b;
+  memcpy(&b, &f, sizeof b);
+  return b;
+}
+
+/* Binary32 weights and distances (bit patterns in and out; INF32 for
+ * unreachable vertices). Non-negative binary32 bit patterns order like their
+ * values, so the heap keys on them. */
+int oracle_adj_dijkstra_f32(const void *hv, int32_t s, uint32_t *dist_out) {
+  const oracle_adj *a = (const oracle_adj *)hv;
+  if (!a || s < 0 || s >= a->n) return ORACLE_BAD_ARGS;
+  const int64_t n = a->n;
+  uint32_t *d = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)n);
+  unsigned char *done = (unsigned char *)calloc((size_t)n, 1);
+  heap h = {NULL, 0, 0};
+  if (!d || !done) {
+    free(d); free(done);
+    return ORACLE_NOMEM;
+  }
+  for (int64_t v = 0; v < n; ++v) d[v] = INF32;
+  d[s] = bits_of(0.0f);
+  int rc = ORACLE_OK;
+  if (heap_push(&h, d[s], s)) rc = ORACLE_NOMEM;
+  while (rc == ORACLE_OK && h.size > 0) {
+    heap_item it = heap_pop(&h);
+    int32_t u = it.v;
+    if (done[u] || it.d != d[u]) continue; /* stale entry */
+    done[u] = 1;
+    const float du = f32_of(d[u]);
+    for (int64_t e = a->off[u]; e < a->off[u + 1]; ++e) {
+      int32_t v = a->nbr[e];
+      const uint32_t c = bits_of(du + f32_of(a->wt[e]));
+      if (c < d[v]) {
+        d[v] = c;
+        if (heap_push(&h, c, v)) {
+          rc = ORACLE_NOMEM;
+          break;
+        }
+      }
+    }
+  }
+  if (rc == ORACLE_OK) memcpy(dist_out, d, sizeof(uint32_t) * (size_t)n);
+  free(h.a);
+  free(d);
+  free(done);
+  return rc;
 }
 
 /* One-shot: build the adjacency from the raw edge list, solve, free. */

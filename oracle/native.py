@@ -39,6 +39,8 @@ def _load():
     lib.oracle_check_sssp.argtypes = [i64, i32p, i32p, u32p, ctypes.c_int32, u32p,
                                       ctypes.POINTER(ctypes.c_int64)]
     lib.oracle_check_sssp.restype = ctypes.c_int64
+    lib.oracle_adj_dijkstra_f32.argtypes = [ctypes.c_void_p, ctypes.c_int32, u32p]
+    lib.oracle_adj_dijkstra_f32.restype = ctypes.c_int
     lib.oracle_adj_dijkstra_tree.argtypes = [ctypes.c_void_p, ctypes.c_int32, u32p, i32p]
     lib.oracle_adj_dijkstra_tree.restype = ctypes.c_int
     lib.oracle_check_tree.argtypes = [i64, i32p, i32p, u32p, ctypes.c_int32, u32p, i32p,
@@ -73,6 +75,15 @@ class Adjacency:
             raise OverflowError("a shortest-path length does not fit below 2^32-1")
         if rc != OK:
             raise RuntimeError("oracle_adj_dijkstra failed: %d" % rc)
+        return out
+
+    def dijkstra_f32(self, s: int) -> np.ndarray:
+        """Binary32 weights (bit patterns) and distances: uint32 bit patterns,
+        0xFFFFFFFF where unreachable."""
+        out = np.empty(self.n, np.uint32)
+        rc = _load().oracle_adj_dijkstra_f32(self._h, int(s), _p(out, ctypes.c_uint32))
+        if rc != OK:
+            raise RuntimeError("oracle_adj_dijkstra_f32 failed: %d" % rc)
         return out
 
     def dijkstra_tree(self, s: int):

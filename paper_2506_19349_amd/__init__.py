@@ -82,10 +82,14 @@ def _empty_dist(n: int, k: Optional[int] = None):
 class Graph:
     """A symmetric CSR graph prepared on the current GPU (sssp_graph_create)."""
 
-    def __init__(self, rowptr, colidx, weight, check_symmetry: bool = True):
+    def __init__(self, rowptr, colidx, weight, check_symmetry: bool = True, float_weights: bool = False):
+        """float_weights: `weight` holds binary32 bit patterns (uint32) or float32
+        values; distances are then binary32 bit patterns (view them as float32)."""
+        if float_weights and getattr(weight, "dtype", None) is not None and str(weight.dtype).endswith("float32"):
+            weight = weight.view(np.uint32) if isinstance(weight, np.ndarray) else weight.view(_torch().int32)
         rp, ci, w = _as_i32(rowptr), _as_i32(colidx), _as_u32(weight)
         n = int(rp.shape[0]) - 1
-        flags = 0 if check_symmetry else 1
+        flags = (0 if check_symmetry else 1) | (2 if float_weights else 0)
         h = _lib.sssp_graph_create_ex(n, _ptr(rp), _ptr(ci), _ptr(w), flags)
         if not h:
             _lib.check(_lib.sssp_last_error() or -6)
@@ -95,8 +99,8 @@ class Graph:
         self.nnz = info["nnz"]
 
     @classmethod
-    def from_csr(cls, csr, check_symmetry: bool = True) -> "Graph":
-        return cls(csr.rowptr, csr.col, csr.w, check_symmetry)
+    def from_csr(cls, csr, check_symmetry: bool = True, float_weights: bool = False) -> "Graph":
+        return cls(csr.rowptr, csr.col, csr.w, check_symmetry, float_weights)
 
     def close(self):
         if getattr(self, "_h", None):

@@ -301,6 +301,7 @@ void fill_inst(Inst& I, const SlotBuf& s, const sssp_graph* g, int32_t source, u
   I.dist = dist;
   I.parent = parent;
   I.best = parent ? s.best : nullptr;
+  I.mode = (I.best ? 1u : 0u) | (g->gh.h.float_w ? 2u : 0u);
   I.state = s.state;
   I.q[0] = s.q[0];
   I.q[1] = s.q[1];

@@ -62,7 +62,12 @@ struct DevGraph {
   // in bucket j or later (ufirst[kUBuckets] = the count)
   const int32_t* ufirst;
   uint32_t ubucket_width;    // ceil((maxW + 1) / kUBucketDiv)
-  uint32_t pad_g;
+  // 1: weights (and so distances) are IEEE binary32 bit patterns of finite
+  // non-negative values. Such bit patterns order like the values, so every
+  // comparison stays an unsigned one; only sums are taken in fp32.
+  uint32_t float_w;
+  uint32_t min_pos_w;        // smallest positive weight (UINT32_MAX if none)
+  uint32_t pad_g2;
   const uint32_t* rtow;      // 4096
   // per row, 16 int32: entry b - 1 (b = 1..15) is the first position of the
   // row whose weight is >= b * rwi_width (entry 15 unused). Written for rows
@@ -166,6 +171,10 @@ struct InstFixed {
   int32_t trace_cap;
   int32_t source;
   int32_t target;          // point-to-point query: stop once this vertex is settled; -1: none
+  // which round-batch instantiation runs this instance: bit 0 a tree is
+  // recorded (best != null), bit 1 the graph has binary32 weights
+  uint32_t mode;
+  uint32_t pad_mode;
   int32_t n;
   uint32_t alpha;
   uint32_t traversal_opt;
@@ -216,6 +225,7 @@ struct Inst : InstFixed, InstCtl {
   // 128-byte line so that they never share a line with the fields above ----
   HotI32 q_next_cnt, touched_cnt, p_next_cnt, u_next_cnt, settled_cnt, h_next_cnt, settle_done;
   HotU32 ub_next, max_settled, flags;
+  HotU32 pend_min;  // binary32 weights: smallest distance left pending by a settle pass
   HotU64 S;  // sumD(lb): degree mass of the unsettled set
 };
 

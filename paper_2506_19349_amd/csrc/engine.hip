@@ -116,6 +116,14 @@ __device__ T block_excl_scan(T x, T* sh /* kBlock/kWave + 1 */, T* total) {
   return res;
 }
 
+// The sum of a distance and a weight: integers, or binary32 values held as
+// bit patterns (rounded to nearest, as the CPU reference rounds).
+template <bool kFloat>
+__device__ __forceinline__ uint32_t dadd(uint32_t a, uint32_t b) {
+  if (kFloat) return __float_as_uint(__uint_as_float(a) + __uint_as_float(b));
+  return a + b;
+}
+
 // ---------------------------------------------------------- the heuristic --
 // Eq. (1)-(3) and Eq. (4)-(6) in IEEE double, operation order fixed, no fused
 // multiply-add (the file is compiled with -ffp-contract=off).
@@ -272,7 +280,12 @@ __device__ __noinline__ void run_heuristic(GInst& I, HeurLds& lds) {
   uint32_t h = block_high_d(gbl(g.deg_vals), gbl(I.hist_cnt), g.num_deg, &mass, &unsettled, lds);
   const unsigned long long S = I.S.v;
   uint32_t gapL = gap_of(S, h, g.nnz, I.M, gbl(g.rtow), I.alpha, I.beta);
-  uint32_t stn = block_compute_st(I, L, gapL, g.nnz, lds);
+  // binary32 weights: computeST's window of settled distances needs integer
+  // distances, so the selection threshold stays at lb (st = L: no pull, the
+  // deferred pushes cover [L - M, L]), as for integer weights beyond the
+  // window's size limit
+  const bool fw = g.float_w != 0;
+  uint32_t stn = fw ? L : block_compute_st(I, L, gapL, g.nnz, lds);
   if (tid == 0) {
     if (mass != S) I.flags.v |= FLAG_MASS;
     StepRec rec;
@@ -293,19 +306,42 @@ __device__ __noinline__ void run_heuristic(GInst& I, HeurLds& lds) {
   }
   // a point-to-point query (Section 5 lists them among the method's uses)
   // ends once its target is settled: every distance below L is final now
-  const bool done = (L == kInf) ||
-                    (I.p_next_cnt.v == 0 && (unsigned long long)I.max_settled.v + I.M < L) ||
+  const bool beyond = fw ? dadd<true>(I.max_settled.v, I.M) < L
+                        : (unsigned long long)I.max_settled.v + I.M < L;
+  const bool done = (L == kInf) || (I.p_next_cnt.v == 0 && beyond) ||
                     (I.target >= 0 && (uint32_t)(gbl(I.state)[I.target] >> 32) < L);
   if (done) {
     if (tid == 0) I.phase = PH_DONE;
     __syncthreads();
     return;
   }
-  unsigned long long ubn = (unsigned long long)L + gapL;
-  if (ubn > kInf) ubn = kInf;
-  const uint32_t lb0 = L > I.M ? L - I.M : 0u;
+  unsigned long long ubn;
+  uint32_t lb0;
+  if (fw) {
+    // The next band ends at L + gap rounded, with two floors that play the
+    // role of the integer gap's floor of 1 (R5): the gap is at least the
+    // smallest positive weight (a zero weight quantile would otherwise give a
+    // gap of the least denormal), and the band reaches past the smallest
+    // pending distance, so that every step settles a vertex or fills the
+    // pending list. Infinity and beyond are the +inf sentinel.
+    const uint32_t gf = gapL > g.min_pos_w || g.min_pos_w == kInf ? gapL : g.min_pos_w;
+    uint32_t e = dadd<true>(L, gf);
+    if (e <= L) e = L + 1u;
+    const uint32_t pm = I.pend_min.v;
+    if (pm != kInf && pm >= L && e <= pm) e = pm + 1u;
+    ubn = e >= 0x7f800000u ? (unsigned long long)kInf : (unsigned long long)e;
+    // lb0 = L - M, lowered by two units in the last place of L: a settled
+    // distance d whose rounded d + M still reaches L lies above it
+    const float ulp = __uint_as_float(L + 1u) - __uint_as_float(L);
+    const float lo = (__uint_as_float(L) - __uint_as_float(I.M)) - 2.0f * ulp;
+    lb0 = lo > 0.0f ? __float_as_uint(lo) : 0u;
+  } else {
+    ubn = (unsigned long long)L + gapL;
+    if (ubn > kInf) ubn = kInf;
+    lb0 = L > I.M ? L - I.M : 0u;
+  }
   // clear the ring slots of the next band [L, ubn) before its settle pass
-  const uint32_t width = (uint32_t)(ubn - L);
+  const uint32_t width = fw ? 0u : (uint32_t)(ubn - L);
   const uint32_t clr = width > I.ring_mask + 1 ? I.ring_mask + 1 : width;
   for (uint32_t k = tid; k < clr; k += kBlock) {
     uint32_t slot = (L + k) & I.ring_mask;
@@ -625,7 +661,9 @@ __device__ __forceinline__ void lds_push_item(RoundLds& L, bool want, int u, uin
 
 // kTree: the instance also records a shortest-path tree (a separate
 // instantiation, so that solves without one pay nothing for it).
-template <bool kTree>
+// kFloat: binary32 weights; the band searches then test dist + w itself
+// against the band ends, rounded as the relaxation rounds it.
+template <bool kTree, bool kFloat>
 __device__ __noinline__ void block_round(GInst& I, int kind, int item0, int nitems, RoundLds& L) {
   const View V = make_view(I);
   const int tid = threadIdx.x;
@@ -673,7 +711,7 @@ __device__ __noinline__ void block_round(GInst& I, int kind, int item0, int nite
     const SSSP_GBL UEntry* ucur = gbl(I.ulist[usel]);
     const SSSP_GBL UEntry* fresh = gbl(gbl(I.g)->nonisolated) + I.u_done;
     auto unext = gbl(I.ulist[usel ^ 1]);
-    const uint32_t reach = ub - st;
+    const uint32_t reach = ub - st;  // integer weights
     UEntry ee[kItemsPerThread];
     bool valid[kItemsPerThread];
 #pragma unroll
@@ -685,13 +723,13 @@ __device__ __noinline__ void block_round(GInst& I, int kind, int item0, int nite
     uint32_t dd[kItemsPerThread];
 #pragma unroll
     for (int k = 0; k < kItemsPerThread; ++k) {
-      const bool cand = valid[k] && ee[k].wmin < reach;
+      const bool cand = valid[k] && (kFloat ? dadd<true>(st, ee[k].wmin) < ub : ee[k].wmin < reach);
       dd[k] = cand ? dist_of(V.state, ee[k].id) : 0u;
     }
 #pragma unroll
     for (int k = 0; k < kItemsPerThread; ++k) {
       const int it = item0 + k * kBlock + tid;
-      const bool cand = valid[k] && ee[k].wmin < reach;
+      const bool cand = valid[k] && (kFloat ? dadd<true>(st, ee[k].wmin) < ub : ee[k].wmin < reach);
       const bool keep = valid[k] && (!cand || dd[k] >= lb);
       const bool active = cand && dd[k] > lb;
       acc.pvert += valid[k] ? 1 : 0;
@@ -761,6 +799,9 @@ __device__ __noinline__ void block_round(GInst& I, int kind, int item0, int nite
     int wi[kItemsPerThread], rs[kItemsPerThread], re[kItemsPerThread];
     int pb[K2][2];  // bucket bounds (positions) of each search
     uint32_t key[K2];
+    // binary32 weights: search x looks for the first w with base + w >= bnd
+    // (push: base d, bnd lb / ub; pull: base st, bnd ub), the row index unused
+    uint32_t fbase[K2], fbnd[K2];
     bool need[kItemsPerThread], leaf[kItemsPerThread];
     const uint32_t W = V.rwi_width;
 #pragma unroll
@@ -776,6 +817,13 @@ __device__ __noinline__ void block_round(GInst& I, int kind, int item0, int nite
       const bool pull = L.pull[wi[k]] != 0;
       key[2 * k] = pull ? 0u : (lb > d ? lb - d : 0u);
       key[2 * k + 1] = pull ? ub - st : ub - d;
+      if (kFloat) {
+        key[2 * k] = (pull || lb <= d) ? 0u : 1u;  // 0: the range starts at the row start
+        fbase[2 * k] = d;
+        fbnd[2 * k] = lb;
+        fbase[2 * k + 1] = pull ? st : d;
+        fbnd[2 * k + 1] = ub;
+      }
       // row bounds: carried by pull-list items, else loaded
       const int kre = L.re[wi[k]];
       const bool known = kre >= 0;
@@ -783,7 +831,7 @@ __device__ __noinline__ void block_round(GInst& I, int kind, int item0, int nite
       re[k] = known ? kre : V.rowptr[u + 1];
       // the bucket bounds are loaded with the row bounds (a known short row
       // needs none)
-      const bool idx = !known || kre - L.lo[wi[k]] > kRowIndexMin;
+      const bool idx = !kFloat && (!known || kre - L.lo[wi[k]] > kRowIndexMin);
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         // bucket b (clamped to 16: past the last boundary) spans
@@ -805,7 +853,7 @@ __device__ __noinline__ void block_round(GInst& I, int kind, int item0, int nite
         if (!need[k]) continue;
         const uint32_t kk = key[2 * k + h];
         const uint32_t b = min(kk / W, 16u);
-        if (re[k] - rs[k] <= kRowIndexMin) {
+        if (kFloat || re[k] - rs[k] <= kRowIndexMin) {
           a[2 * k + h] = rs[k];
           c[2 * k + h] = re[k];
         } else {
@@ -842,7 +890,10 @@ __device__ __noinline__ void block_round(GInst& I, int kind, int item0, int nite
           if (a[2 * k + h] >= c[2 * k + h]) continue;  // already decided (row start)
           int cnt = 0;
 #pragma unroll
-          for (int i = 0; i < kRowIndexMin; ++i) cnt += pw[j][i] < key[2 * k + h] ? 1 : 0;
+          for (int i = 0; i < kRowIndexMin; ++i) {
+            if (kFloat) cnt += (pw[j][i] != 0xffffffffu && dadd<true>(fbase[2 * k + h], pw[j][i]) < fbnd[2 * k + h]) ? 1 : 0;
+            else cnt += pw[j][i] < key[2 * k + h] ? 1 : 0;
+          }
           a[2 * k + h] = c[2 * k + h] = rs[k] + cnt;
         }
       }
@@ -863,7 +914,8 @@ __device__ __noinline__ void block_round(GInst& I, int kind, int item0, int nite
 #pragma unroll
       for (int x = 0; x < K2; ++x) {
         if (a[x] < c[x]) {
-          if (val[x] < key[x]) a[x] = mid[x] + 1; else c[x] = mid[x];
+          const bool below = kFloat ? dadd<true>(fbase[x], val[x]) < fbnd[x] : val[x] < key[x];
+          if (below) a[x] = mid[x] + 1; else c[x] = mid[x];
         }
       }
     }
@@ -960,7 +1012,7 @@ __device__ __noinline__ void block_round(GInst& I, int kind, int item0, int nite
       const uint32_t w = (uint32_t)(ent[x] >> 32);
       const uint32_t dj = L.d[j];
       if (!(any_pull && L.pull[j])) {
-        c[x] = dj + w;  // < ub by the range
+        c[x] = dadd<kFloat>(dj, w);  // in [lb, ub) by the range
         t[x] = v;
         from[x] = L.u[j];
         if (c[x] < dv[x]) {
@@ -971,7 +1023,8 @@ __device__ __noinline__ void block_round(GInst& I, int kind, int item0, int nite
       } else {
         // pull: the best candidate of u over this batch's edges, in LDS
         if (dv[x] >= st && dv[x] < lb) {
-          unsigned long long cc = (unsigned long long)dv[x] + w;
+          unsigned long long cc = kFloat ? (unsigned long long)dadd<true>(dv[x], w)
+                                         : (unsigned long long)dv[x] + w;
           if (cc < ub && cc < dj) {
             if (kTree) atomicMin(&L.pmin64[j], (cc << 32) | (uint32_t)v);
             else atomicMin(&L.pmin32[j], (uint32_t)cc);
@@ -1049,8 +1102,11 @@ __device__ __noinline__ void block_settle(GInst& I, int kind, int item0, int nit
   GDevGraph& g = *gbl(I.g);
   const int tid = threadIdx.x;
   const uint32_t lb = I.lb, ub = I.ub, M = I.M;
+  // the per-distance ring feeds computeST, which needs integer distances:
+  // nothing to record with binary32 weights
+  const bool fw = g.float_w != 0;
   const uint32_t band = ub - lb;
-  const uint32_t nb = band < (uint32_t)kLdsRing ? band : (uint32_t)kLdsRing;
+  const uint32_t nb = fw ? 0u : (band < (uint32_t)kLdsRing ? band : (uint32_t)kLdsRing);
   const int nh = g.num_deg < kLdsHist ? g.num_deg : kLdsHist;
   auto dinfo = gbl(g.dinfo);
   auto state = gbl(I.state);
@@ -1086,7 +1142,7 @@ __device__ __noinline__ void block_settle(GInst& I, int kind, int item0, int nit
     }
   }
   unsigned long long sdec = 0;
-  uint32_t maxd = 0;
+  uint32_t maxd = 0, pmin = kInf;
   int ns = 0, np = 0;
 #pragma unroll
   for (int k = 0; k < kSettlePer; ++k) {
@@ -1096,12 +1152,13 @@ __device__ __noinline__ void block_settle(GInst& I, int kind, int item0, int nit
     const bool pend = v >= 0 && d >= ub;
     ns += settle ? 1 : 0;
     np += pend ? 1 : 0;
+    if (pend && d < pmin) pmin = d;
     if (!settle) continue;
     const int deg = (int)(uint32_t)di[k];
     const uint32_t off = d - lb;
     // only the window [ub - M, ub) is read by the next computeST; the first
     // step's band may be wider, and older values would alias ring slots
-    if ((unsigned long long)d + M >= ub) {
+    if (!fw && (unsigned long long)d + M >= ub) {
       if (off < nb) {
         atomicAdd(&L.mass[off], (uint32_t)deg);
         atomicAdd(&L.cnt[off], 1u);
@@ -1146,6 +1203,10 @@ __device__ __noinline__ void block_settle(GInst& I, int kind, int item0, int nit
     wm = y > wm ? y : wm;
   }
   unsigned long long qe = wave_sum((unsigned long long)(ns + np));
+  if (fw) {
+    const uint32_t pm = wave_min_u32(pmin);
+    if (lane_id() == 0 && pm != kInf) atomicMin(&I.pend_min.v, pm);
+  }
   if (lane_id() == 0) {
     L.sdec[tid / kWave] = ws;
     L.maxd[tid / kWave] = wm;
@@ -1197,7 +1258,7 @@ __device__ int find_segment(const GGlobals& G, int b) {
 // any grouping of rounds reaches the same settled set. When the frontier
 // empties or grows past one batch, the epilogue takes over with its usual
 // transition of the last round.
-template <bool kTree>
+template <bool kTree, bool kFloat>
 __device__ __noinline__ void fused_rounds(GInst& I, RoundLds& L) {
   __shared__ int s_go, s_nq;
   const int cap = I.fuse_cap;
@@ -1230,7 +1291,7 @@ __device__ __noinline__ void fused_rounds(GInst& I, RoundLds& L) {
     }
     __syncthreads();
     if (!s_go) break;
-    block_round<kTree>(I, SEG_Q, 0, s_nq, L);
+    block_round<kTree, kFloat>(I, SEG_Q, 0, s_nq, L);
   }
 }
 
@@ -1266,14 +1327,26 @@ __device__ void run_tick(GGlobals& G, BlockLds& lds, int pid, int P) {
       }
       __syncthreads();
     } else {
-      const bool tree = I.best != nullptr;
-      if (tree) block_round<true>(I, kind, item0, cnt, lds.r);
-      else block_round<false>(I, kind, item0, cnt, lds.r);
+      const uint32_t mode = I.mode;
+      const bool tree = (mode & 1u) != 0;
+      const bool fw = (mode & 2u) != 0;
+      if (fw) {
+        if (tree) block_round<true, true>(I, kind, item0, cnt, lds.r);
+        else block_round<false, true>(I, kind, item0, cnt, lds.r);
+      } else {
+        if (tree) block_round<true, false>(I, kind, item0, cnt, lds.r);
+        else block_round<false, false>(I, kind, item0, cnt, lds.r);
+      }
       // a frontier that fits one batch, with no heavy chunks, belongs to this
       // workgroup alone for the whole tick: chain its next rounds here
       if (kind == SEG_Q && cnt <= pb && I.nH == 0 && I.fuse_cap > 0) {
-        if (tree) fused_rounds<true>(I, lds.r);
-        else fused_rounds<false>(I, lds.r);
+        if (fw) {
+          if (tree) fused_rounds<true, true>(I, lds.r);
+          else fused_rounds<false, true>(I, lds.r);
+        } else {
+          if (tree) fused_rounds<true, false>(I, lds.r);
+          else fused_rounds<false, false>(I, lds.r);
+        }
       }
     }
   }
@@ -1331,6 +1404,7 @@ __device__ void transition(InstCtl& X, SegSpec& Sp, const HotIn& h, int32_t n, i
     X.nT = min(h.touched, n);
     X.settled_mark = min(h.settled, n);
     I.settle_done.v = 0;
+    I.pend_min.v = kInf;
     int bt = (X.nT + kSettleBatch - 1) / kSettleBatch;
     if (bt < 1) bt = 1;
     int bp = (X.nP + kSettleBatch - 1) / kSettleBatch;
@@ -1791,6 +1865,7 @@ __global__ void __launch_bounds__(kBlock) k_init_ctl(Globals* Gp) {
       I.max_settled.v = 0;
       I.S.v = (unsigned long long)g.nnz;
       I.settle_items = 0; I.settle_done.v = 0;
+      I.pend_min.v = kInf;
       I.flags.v = 0;
       I.pull_on = 0;
       I.init_round = 0;

@@ -19,7 +19,8 @@ namespace sssp {
 // ----------------------------------------------------------- validation --
 
 __global__ void k_validate(const int32_t* rowptr, const int32_t* col, const uint32_t* w, int32_t n,
-                           int32_t nnz, unsigned int* err, unsigned int* maxw, int* maxdeg) {
+                           int32_t nnz, unsigned int* err, unsigned int* maxw, int* maxdeg,
+                           unsigned int* minpos) {
   const long long stride = (long long)gridDim.x * blockDim.x;
   const long long t0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   for (long long v = t0; v < n; v += stride) {
@@ -27,16 +28,18 @@ __global__ void k_validate(const int32_t* rowptr, const int32_t* col, const uint
     if (b < a) atomicOr(err, 1u);
     else atomicMax(maxdeg, b - a);
   }
-  uint32_t mw = 0;
+  uint32_t mw = 0, mp = 0xffffffffu;
   bool bad = false;
   for (long long e = t0; e < nnz; e += stride) {
     int c = col[e];
     if (c < 0 || c >= n) bad = true;
     uint32_t x = w[e];
     mw = x > mw ? x : mw;
+    if (x > 0u && x < mp) mp = x;
   }
   if (bad) atomicOr(err, 2u);
   if (mw) atomicMax(maxw, mw);
+  if (mp != 0xffffffffu) atomicMin(minpos, mp);
 }
 
 __global__ void k_pack(const int32_t* col, const uint32_t* w, int32_t nnz, uint64_t* adj) {
@@ -579,6 +582,7 @@ int prep_graph(int32_t n, const int32_t* rowptr_in, const int32_t* col_in, const
   PREP_CHECK(hipMemset(d_flags, 0, sizeof(unsigned int) * 4));
   PREP_CHECK(hipMemset(d_int, 0, sizeof(int) * 8));
   uint32_t maxw = 0;
+  uint32_t minpos = 0xffffffffu;  // smallest positive weight
   int maxdeg = 0;
   if (nnz > 0) {
     int32_t* col = T.get<int32_t>((size_t)nnz);
@@ -589,11 +593,14 @@ int prep_graph(int32_t n, const int32_t* rowptr_in, const int32_t* col_in, const
     }
     PREP_CHECK(hipMemcpy(col, col_in, sizeof(int32_t) * (size_t)nnz, hipMemcpyDefault));
     PREP_CHECK(hipMemcpy(w, w_in, sizeof(uint32_t) * (size_t)nnz, hipMemcpyDefault));
+    const unsigned int none = 0xffffffffu;
+    PREP_CHECK(hipMemcpy(d_flags + 2, &none, sizeof(none), hipMemcpyHostToDevice));
     k_validate<<<grid_for(std::max<long long>(n, nnz)), kBlock>>>(rowptr, col, w, n, nnz, d_flags,
-                                                                  d_flags + 1, d_int);
+                                                                  d_flags + 1, d_int, d_flags + 2);
     PREP_CHECK(hipGetLastError());
-    unsigned int hf[2];
+    unsigned int hf[3];
     PREP_CHECK(hipMemcpy(hf, d_flags, sizeof(hf), hipMemcpyDeviceToHost));
+    minpos = hf[2];
     PREP_CHECK(hipMemcpy(&maxdeg, d_int, sizeof(int), hipMemcpyDeviceToHost));
     if (hf[0] & 1u) {
       *msg = "rowptr is not non-decreasing";
@@ -604,6 +611,12 @@ int prep_graph(int32_t n, const int32_t* rowptr_in, const int32_t* col_in, const
       return -1;
     }
     maxw = hf[1];
+    // binary32 weights: the largest bit pattern is below +inf exactly when
+    // every weight is finite and non-negative (the sign bit set is above it)
+    if ((flags & 2) && maxw >= 0x7f800000u) {
+      *msg = "binary32 weights must be finite and non-negative";
+      return -1;
+    }
     k_pack<<<grid_for(nnz), kBlock>>>(col, w, nnz, adj);
     PREP_CHECK(hipGetLastError());
   } else {
@@ -950,7 +963,9 @@ int prep_graph(int32_t n, const int32_t* rowptr_in, const int32_t* col_in, const
   h.nonisolated = noniso;
   h.ufirst = ufirst;
   h.ubucket_width = ub_width;
-  h.pad_g = 0;
+  h.float_w = (flags & 2) ? 1u : 0u;
+  h.min_pos_w = minpos;
+  h.pad_g2 = 0;
   h.rtow = rtow;
   h.rwi = rwi;
   h.rwi_width = rwi_width;
