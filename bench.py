@@ -208,36 +208,49 @@ def variants_section(args, sssp, torch, np, graphgen):
         del o
         g.close()
     # real weights (binary32): the gr26 graphs' (0, 1] weights and a float-pivot
-    # variant (Eq. 8) on the same topology; one source each against the oracle's
+    # variant (Eq. 8) on the RMAT-22 topology, and the (0, 1] weights on the
+    # RMAT-24 topology; 4 solves each with the traversal optimisation (the
+    # ST_NUM grid) and 4 without; one source each against the oracle's
     # binary32 Dijkstra
-    for name in ("rmat22f", "rmat22c5"):
+    for name in ("rmat22f", "rmat22c5", "rmat24f"):
         wl = graphgen.workload(name)
         csr = wl.csr
         deg = csr.degrees()
         g = sssp.Graph.from_csr(csr, float_weights=True)
         srcs = [int(s) for s in wl.sources(5)]
         o = torch.empty(csr.n, dtype=torch.uint32, device="cuda")
-        g.solve(srcs[0], out=o)
-        torch.cuda.synchronize()
-        sssp.engine_times()
-        m_cc, dt = 0, 0.0
-        for s in srcs[1:]:
+        rec = {"weights": "binary32, " + ("uniform on (0, 1]" if name.endswith("f") else "converge(x, 0.5) (Eq. 8)")}
+        for topt in (True, False):
+            g.solve(srcs[0], out=o, traversal_opt=topt)
             torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            g.solve(s, out=o)
-            torch.cuda.synchronize()
-            dt += time.perf_counter() - t0
-            c = sssp.counters()
-            m_cc += int(deg[o.cpu().numpy() != INF].sum()) // 2
-        eng = sssp.engine_times()
+            sssp.engine_times()
+            m_cc, dt, ntrav = 0, 0.0, []
+            for s in srcs[1:]:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                g.solve(s, out=o, traversal_opt=topt)
+                torch.cuda.synchronize()
+                dt += time.perf_counter() - t0
+                c = sssp.counters()
+                reach = o.cpu().numpy() != INF
+                m_cc += int(deg[reach].sum()) // 2
+                ntrav.append((c["push_scanned"] + c["pull_scanned"]) / max(int(reach.sum()), 1))
+            eng = sssp.engine_times()
+            leg = {"gteps": round(m_cc / dt / 1e9, 3), "ms_per_solve": round(dt * 1e3 / (len(srcs) - 1), 3),
+                   "engine_us_mean": round(sum(eng) / max(len(eng), 1), 1),
+                   "nTrav": round(sum(ntrav) / len(ntrav), 3), "steps": c["steps"], "ticks": c["ticks"]}
+            if topt:
+                rec.update(leg)
+            else:
+                rec["filter_off"] = leg
         adj = native.Adjacency(wl.edges.n, wl.edges.src, wl.edges.dst, wl.edges.w)
-        exact = bool(np.array_equal(adj.dijkstra_f32(srcs[-1]), o.cpu().numpy()))
+        g.solve(srcs[-1], out=o)
+        rec["bit_exact_vs_oracle"] = bool(np.array_equal(adj.dijkstra_f32(srcs[-1]), o.cpu().numpy()))
         adj.close()
-        out[name] = {"weights": "binary32, " + ("uniform on (0, 1]" if name.endswith("f") else "converge(x, 0.5) (Eq. 8)"),
-                     "gteps": round(m_cc / dt / 1e9, 3), "ms_per_solve": round(dt * 1e3 / (len(srcs) - 1), 3),
-                     "engine_us_mean": round(sum(eng) / max(len(eng), 1), 1), "steps": c["steps"],
-                     "ticks": c["ticks"], "bit_exact_vs_oracle": exact}
-        log("real weights %s: %.2f GTEPS, %d steps; bit-exact: %s" % (name, out[name]["gteps"], c["steps"], exact))
+        out[name] = rec
+        log("real weights %s: %.2f GTEPS, nTrav %.2f (filter off: %.2f GTEPS, nTrav %.2f), %d steps; bit-exact: %s"
+            % (name, rec["gteps"], rec["nTrav"], rec["filter_off"]["gteps"], rec["filter_off"]["nTrav"],
+               rec["steps"], rec["bit_exact_vs_oracle"]))
         del o
         g.close()
     return out

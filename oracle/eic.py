@@ -168,6 +168,125 @@ def eic_sssp(n: int, rowptr: np.ndarray, col: np.ndarray, w: np.ndarray, s: int,
     return res
 
 
+def _fadd(a, b) -> np.ndarray:
+    """fl(a + b) of binary32 bit patterns, elementwise, as bit patterns (int64)."""
+    a = np.asarray(a, dtype=np.int64).astype(np.uint32).view(np.float32)
+    b = np.asarray(b, dtype=np.int64).astype(np.uint32).view(np.float32)
+    return (a + b).astype(np.float32).view(np.uint32).astype(np.int64)
+
+
+def eic_sssp_f32(n: int, rowptr: np.ndarray, col: np.ndarray, wbits: np.ndarray, s: int,
+                 alpha: int = H.ALPHA, beta: float = H.BETA, traversal_opt: bool = True,
+                 max_steps: int = 10_000_000) -> Result:
+    """The same model with real weights: weights and distances are binary32
+    bit patterns (finite, non-negative, so they order like their values) and
+    every path sum is one binary32 addition, rounded to nearest.  The readings
+    that differ from the integer model: the next band ends at fl(L + gap)
+    with the gap at least the smallest positive weight and the band reaching
+    past the smallest pending distance (one unit in the last place when the
+    sum does not move); lb0 = fl(fl(L - M) - 2 ulp(L)); the pull takes an edge
+    while fl(st + w) < ub; computeST works on the ST_NUM grid."""
+    rowptr = np.asarray(rowptr, dtype=np.int64)
+    col = np.asarray(col, dtype=np.int64)
+    w = np.asarray(wbits, dtype=np.uint32).astype(np.int64)
+    deg = np.diff(rowptr)
+    nnz = int(rowptr[-1])
+    M = int(w.max()) if nnz else 0
+    pos = w[w > 0]
+    minpos = int(pos.min()) if pos.shape[0] else INF
+    rtow = H.rtow_table(w)
+    hd0 = H.high_d(deg)
+    hub = (deg >= max(hd0, 1))
+
+    dist = np.full(n, INF, dtype=np.int64)
+    dist[s] = 0
+    res = Result(dist=dist, steps=[], high_d0=hd0)
+    if deg[s] == 0:
+        res.dist = dist.astype(np.uint32)
+        return res
+    res.gap0 = H.gap(nnz, hd0, nnz, M, rtow, alpha, beta)
+
+    st, lb, ub, lb0 = 0, 0, INF, 0
+    first = True
+    gap_lb = res.gap0
+    for _ in range(max_steps):
+        # ---- Function 1: initFrontiers(st, lb, ub) ----
+        push_set = np.nonzero((dist >= lb0) & (dist <= st))[0]
+        pulled = False
+        if st < lb:
+            pulled = True
+            res.pulls += 1
+            U = np.nonzero((dist > lb) & (deg > 0))[0]
+            res.pull_vertices += int(U.shape[0])
+            idx, owner = _row_edges(rowptr, U)
+            sel = _fadd(np.full(idx.shape[0], st), w[idx]) < ub
+            idx, owner = idx[sel], owner[sel]
+            res.pull_scanned += int(idx.shape[0])
+            dv = dist[col[idx]]
+            ok = (dv >= st) & (dv < lb)
+            cand = _fadd(np.where(ok, dv, 0), w[idx])
+            ok &= cand < ub
+            np.minimum.at(dist, owner[ok], cand[ok])
+        band = np.nonzero((dist >= lb) & (dist < ub))[0]
+        F = np.union1d(push_set, band)
+        rounds = 0
+        # ---- the Algorithm's round loop ----
+        while F.shape[0] > 0:
+            paths = F[~((dist[F] > 0) & (deg[F] == 1))]
+            res.expansions += int(paths.shape[0])
+            res.band_expansions += int(np.count_nonzero(dist[paths] >= lb))
+            idx, owner = _row_edges(rowptr, paths)
+            cand = _fadd(dist[owner], w[idx])
+            sel = (cand >= lb) & (cand < ub)
+            idx, cand = idx[sel], cand[sel]
+            res.push_scanned += int(idx.shape[0])
+            before = dist.copy()
+            np.minimum.at(dist, col[idx], cand)
+            F = np.nonzero(dist < before)[0]
+            rounds += 1
+            if first:
+                hub_d = dist[hub]
+                ub = int(hub_d.min()) if hub_d.shape[0] else INF
+        res.rounds += rounds
+        if first and ub == INF:
+            res.steps.append(Step(lb, ub, st, rounds, pulled, ub, 0, 0, 0, ub))
+            break
+        # ---- statistics at L = ub; the next band, lb0 and computeST ----
+        L = ub
+        in_vs = dist >= L
+        S = int(deg[in_vs].sum())
+        h = H.high_d(deg[in_vs])
+        gap_L = H.gap(S, h, nnz, M, rtow, alpha, beta)
+        if L == INF:
+            res.steps.append(Step(lb, ub, st, rounds, pulled, L, S, h, gap_L, L))
+            break
+        gf = gap_L if (gap_L > minpos or minpos == INF) else minpos
+        e = int(_fadd(L, gf))
+        if e <= L:
+            e = L + 1
+        pend = dist[(dist >= L) & (dist < INF)]
+        pm = int(pend.min()) if pend.shape[0] else INF
+        if pm != INF and e <= pm:
+            e = pm + 1
+        ub_next = INF if e >= H.F32_INF_BITS else e
+        Lf = np.float32(H.f32(L))
+        ulp = np.float32(H.f32(L + 1)) - Lf
+        lo = np.float32(np.float32(Lf - np.float32(H.f32(M))) - np.float32(np.float32(2.0) * ulp))
+        lb0_next = int(np.asarray(lo, dtype=np.float32).view(np.uint32)) if lo > 0 else 0
+        settled = dist < L
+        st_next = H.compute_st_f32(L, gap_L, gap_lb, S, nnz, M, lb0_next, ub_next, dist[settled],
+                                   deg[settled], traversal_opt)
+        res.steps.append(Step(lb, ub, st, rounds, pulled, L, S, h, gap_L, st_next))
+        st, lb, ub, lb0 = st_next, L, ub_next, lb0_next
+        gap_lb = gap_L
+        first = False
+        finite = dist[dist < INF]
+        if int(_fadd(int(finite.max()), M)) < lb:
+            break
+    res.dist = dist.astype(np.uint32)
+    return res
+
+
 def normalised(res: Result, n: int, deg: np.ndarray) -> dict:
     """The paper's normalised counters (Section 4): nFrontier over reachable
     non-leaf vertices, nSync over log2|V|, nTrav over reachable vertices.

@@ -31,6 +31,11 @@ Readings where the text is silent or ambiguous:
   off (st = L): the exact window of candidate distances is not kept.
 * A single sentinel INF = 2^32 - 1 stands for +infinity in dist, ub and every
   threshold; sums are clamped to it.
+* Real (binary32) weights: computeST scores the points of a grid of ST_NUM
+  (Section 4.1: 2^10) equal bins per maxW, bin(d) = floor(d * ST_NUM / maxW) in
+  double; a candidate is a grid point whose bin holds a settled vertex in the
+  window above lb0 = L - M (lowered by two units in the last place of L), and
+  the threshold returned is the smallest binary32 value of the winning bin.
 """
 from __future__ import annotations
 
@@ -43,6 +48,8 @@ BETA = 0.9
 RATIO_NUM = 4096   # Section 4.1: RATIO_NUM = 2^12
 INF = 0xFFFFFFFF
 ST_WINDOW_MAX = 65536
+ST_NUM = 1024      # Section 4.1: ST_NUM = 2^10
+F32_INF_BITS = 0x7F800000
 
 
 def rtow_table(weights: np.ndarray, ratio_num: int = RATIO_NUM) -> np.ndarray:
@@ -149,3 +156,79 @@ def compute_st(L: int, gap_L: int, gap_lb: int, S: int, nnz: int, M: int,
         if p > max_p:
             best, max_p = x, p
     return best
+
+
+# --------------------------------------------------------------- binary32 --
+
+def f32(bits: int) -> float:
+    """The value of a binary32 bit pattern, as a Python (double) float."""
+    return float(np.asarray(bits, dtype=np.uint32).view(np.float32))
+
+
+def grid_bin(bits: int, inv: float):
+    """bin(d) = floor(d * inv) for inv = ST_NUM / maxW, in double; None past
+    2^31 bins, for +inf and for the sentinel."""
+    if bits >= F32_INF_BITS:
+        return None
+    x = f32(bits) * inv
+    return int(math.floor(x)) if x < 2147483648.0 else None
+
+
+def profit_f(x: float, L: float, Y: float, S: int, Sx: int, M: float, nnz: int) -> float:
+    """Eq. (4)-(6) with real-valued ends, for a grid point x at or above about
+    L - M (there lb_0 = max(x, L - M) changes no term)."""
+    ub0 = min(Y, L + M)
+    ub1 = min(Y, x + M)
+    pushed = (ub0 - L) * float(Sx - S) / M
+    pulled = (ub1 - x) * float(S) / M
+    long_ = pulled * float(Sx - S) / float(nnz)
+    return (pushed - long_) - pulled
+
+
+def compute_st_f32(L: int, gap_L: int, gap_lb: int, S: int, nnz: int, M: int, lb0: int, Y: int,
+                   settled_dist: np.ndarray, settled_deg: np.ndarray,
+                   traversal_opt: bool = True) -> int:
+    """Function 2 (computeST) with binary32 distances (bit patterns), over the
+    ST_NUM grid.  settled_dist / settled_deg: the settled vertices (dist < L)."""
+    if not traversal_opt or M == 0 or L >= F32_INF_BITS:
+        return L
+    if 2 * S >= nnz or gap_lb == M:
+        return L
+    if gap_L == M:
+        return lb0
+    inv = float(ST_NUM) / f32(M)
+    kL = grid_bin(L, inv)
+    if kL is None:
+        return L
+    klo = 0 if lb0 == 0 else grid_bin(lb0, inv) + 1
+    if klo > kL:
+        return L
+    d = np.asarray(settled_dist, dtype=np.uint32).view(np.float32).astype(np.float64)
+    b = np.floor(d * inv).astype(np.int64)
+    sel = (b >= klo) & (b <= kL)
+    mass = {}
+    for k, m in zip(b[sel].tolist(), np.asarray(settled_deg, dtype=np.int64)[sel].tolist()):
+        mass[k] = mass.get(k, 0) + m
+    Mf, Lf = f32(M), f32(L)
+    Yf = math.inf if Y >= F32_INF_BITS else f32(Y)
+    delta = Mf / float(ST_NUM)
+    keys = sorted(mass)
+    suffix, acc = {}, 0
+    for k in reversed(keys):
+        acc += mass[k]
+        suffix[k] = acc
+    best, max_p = None, 0.0
+    for k in keys:
+        p = profit_f(float(k) * delta, Lf, Yf, S, S + suffix[k], Mf, nnz)
+        if p > max_p:
+            best, max_p = k, p
+    if best is None:
+        return L
+    lo, hi = 0, L   # smallest bit pattern whose bin is at least best
+    while lo < hi:
+        mid = (lo + hi) // 2
+        if grid_bin(mid, inv) >= best:
+            hi = mid
+        else:
+            lo = mid + 1
+    return lo

@@ -50,7 +50,11 @@ Needs needs_for(const DevGraph& g, int maxw) {
   r.heavy = g.nnz / 128 + 4096;
   r.hist = std::max(g.num_deg, 1);
   r.trace = 1 << 16;
-  if (g.max_w <= kRingMax) {
+  if (g.float_w) {
+    // binary32 weights: the selection-threshold grid (kStNum bins per maxW)
+    r.ring = kFloatRing;
+    r.steprec = 1u << 17;
+  } else if (g.max_w <= kRingMax) {
     r.ring = pow2_at_least(std::max<uint64_t>(64, 2ull * g.max_w + 2));
     r.steprec = pow2_at_least(std::max<uint64_t>(64, 2ull * g.max_w + 64));
   } else {

@@ -14,6 +14,9 @@ constexpr int kBlock = 256;              // threads per workgroup (4 waves)
 constexpr int kRatioNum = 4096;          // RATIO_NUM, Section 4.1
 constexpr uint32_t kRingMax = 65536;     // exact selection-threshold window up to this max weight
 constexpr int kLdsRing = 1024;           // settle: distance bins privatised in LDS
+constexpr int kStNum = 1024;             // ST_NUM, Section 4.1: selection-threshold grid per max weight
+constexpr uint32_t kFloatRing = 4096;    // grid bins kept with binary32 weights (>= 2 ST_NUM + 2)
+constexpr uint32_t kNoBin = 0xFFFFFFFFu; // a binary32 distance too large for the grid
 constexpr int kLdsHist = 1024;           // settle: degree ranks privatised in LDS
 constexpr int kHeavyChunk = 256;         // edges per heavy chunk
 constexpr int kDefaultHeavy = 64;        // ranges longer than this are split
@@ -61,7 +64,9 @@ struct DevGraph {
   // kUBuckets + 1 entries: ufirst[j] is the first position of `nonisolated`
   // in bucket j or later (ufirst[kUBuckets] = the count)
   const int32_t* ufirst;
-  uint32_t ubucket_width;    // ceil((maxW + 1) / kUBucketDiv)
+  // ceil((maxW + 1) / kUBucketDiv); binary32 weights: the bit pattern of
+  // maxW / kUBucketDiv (bucket 0 holds the rows whose lightest edge is lighter)
+  uint32_t ubucket_width;
   // 1: weights (and so distances) are IEEE binary32 bit patterns of finite
   // non-negative values. Such bit patterns order like the values, so every
   // comparison stays an unsigned one; only sums are taken in fp32.

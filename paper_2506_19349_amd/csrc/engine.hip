@@ -268,6 +268,110 @@ __device__ uint32_t block_compute_st(const GInst& I, uint32_t L, uint32_t gapL, 
   return res;
 }
 
+// Binary32 distances on the selection-threshold grid (Section 4.1: ST_NUM
+// candidates per span): bin(d) = floor(d * kStNum / maxW), evaluated in double,
+// so it never decreases as d grows; kNoBin past 2^31 bins, for +inf and for
+// the sentinel.
+__device__ __forceinline__ double grid_inv(uint32_t M) {
+  return (double)kStNum / (double)__uint_as_float(M);
+}
+
+__device__ __forceinline__ uint32_t fbin(uint32_t d, double inv) {
+  const double x = (double)__uint_as_float(d) * inv;
+  return x < 2147483648.0 ? (uint32_t)x : kNoBin;
+}
+
+// Eq. 4-6 with real-valued ends: x is a grid point at or above about L - M
+// (the clamp lb_0 = max(x, L - M) changes no term there, since x + M and
+// L - M + M both stay at or below L < Y).
+__device__ __forceinline__ double profit_of_f(double x, double L, double Y, unsigned long long S,
+                                              unsigned long long Sx, double M, int32_t nnz) {
+  double ub0 = L + M;
+  if (Y < ub0) ub0 = Y;
+  double ub1 = x + M;
+  if (Y < ub1) ub1 = Y;
+  double pushed = (ub0 - L) * (double)(Sx - S) / M;   // Eq. (4)
+  double pulled = (ub1 - x) * (double)S / M;          // Eq. (5)
+  double lng = pulled * (double)(Sx - S) / (double)nnz;  // Eq. (6)
+  return (pushed - lng) - pulled;
+}
+
+// Function 2 (computeST) with binary32 distances. The candidates are the
+// grid points (kStNum per maxW, Section 4.1) whose bin holds a settled vertex
+// and lies inside the window above lb0 = L - M; each is scored by Eq. 4-6 at
+// the grid point with the settled mass of its bin and the bins above it. The
+// threshold returned for the winning bin is the smallest binary32 value in
+// it, so that dist >= st holds exactly for the vertices of that bin and
+// above. Whole workgroup.
+__device__ uint32_t block_compute_st_f(const GInst& I, uint32_t L, uint32_t gapL, uint32_t lb0,
+                                       uint32_t ubn, int32_t nnz, HeurLds& lds) {
+  const uint32_t M = I.M;
+  const unsigned long long S = I.S.v;
+  if (!I.traversal_opt || M == 0u || L >= 0x7f800000u) return L;
+  if (2ull * S >= (unsigned long long)nnz || I.gap_cur == M) return L;
+  if (gapL == M) return lb0;
+  const double inv = grid_inv(M);
+  const uint32_t kL = fbin(L, inv);
+  if (kL == kNoBin) return L;
+  const uint32_t klo = lb0 == 0u ? 0u : fbin(lb0, inv) + 1u;
+  if (klo > kL) return L;
+  const uint32_t W = kL - klo + 1u;
+  const double Mf = (double)__uint_as_float(M);
+  const double Lf = (double)__uint_as_float(L);
+  const double Y = ubn >= 0x7f800000u ? __builtin_huge_val() : (double)__uint_as_float(ubn);
+  const double delta = Mf / (double)kStNum;
+  const int tid = threadIdx.x;
+  const uint32_t chunk = (W + kBlock - 1) / kBlock;
+  // thread t owns bins klo + [a, b), ascending
+  const uint32_t a = min(W, (uint32_t)tid * chunk), b = min(W, a + chunk);
+  unsigned long long local = 0;
+  for (uint32_t k = a; k < b; ++k) local += gbl(I.ring_mass)[(klo + k) & I.ring_mask];
+  unsigned long long total;
+  unsigned long long before = block_excl_scan<unsigned long long>(local, lds.scan, &total);
+  unsigned long long acc = total - before - local;
+  double bp = 0.0;
+  uint32_t bx = kNoBin;
+  for (uint32_t k = b; k > a; --k) {
+    const uint32_t x = klo + k - 1;
+    const uint32_t slot = x & I.ring_mask;
+    acc += gbl(I.ring_mass)[slot];
+    if (gbl(I.ring_cnt)[slot]) {
+      double p = profit_of_f((double)x * delta, Lf, Y, S, S + acc, Mf, nnz);
+      if (p > bp || (p == bp && p > 0.0 && x < bx)) {
+        bp = p;
+        bx = x;
+      }
+    }
+  }
+  lds.pbest[tid] = bp;
+  lds.xbest[tid] = bx;
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if (tid < s) {
+      double p2 = lds.pbest[tid + s];
+      uint32_t x2 = lds.xbest[tid + s];
+      if (p2 > lds.pbest[tid] || (p2 == lds.pbest[tid] && p2 > 0.0 && x2 < lds.xbest[tid])) {
+        lds.pbest[tid] = p2;
+        lds.xbest[tid] = x2;
+      }
+    }
+    __syncthreads();
+  }
+  uint32_t res = L;
+  if (lds.pbest[0] > 0.0) {
+    // smallest binary32 value in bin kb (bin(L) = kL >= kb, so within [0, L])
+    const uint32_t kb = lds.xbest[0];
+    uint32_t lo = 0u, hi = L;
+    while (lo < hi) {
+      const uint32_t mid = lo + ((hi - lo) >> 1);
+      if (fbin(mid, inv) >= kb) hi = mid; else lo = mid + 1u;
+    }
+    res = lo;
+  }
+  __syncthreads();
+  return res;
+}
+
 // The end-of-step heuristic for one instance: statistics at L = ub, gap(L),
 // computeST, step bookkeeping, termination test, and the next step's setup.
 // Runs on one workgroup, after every settle batch of the instance is done.
@@ -280,12 +384,35 @@ __device__ __noinline__ void run_heuristic(GInst& I, HeurLds& lds) {
   uint32_t h = block_high_d(gbl(g.deg_vals), gbl(I.hist_cnt), g.num_deg, &mass, &unsettled, lds);
   const unsigned long long S = I.S.v;
   uint32_t gapL = gap_of(S, h, g.nnz, I.M, gbl(g.rtow), I.alpha, I.beta);
-  // binary32 weights: computeST's window of settled distances needs integer
-  // distances, so the selection threshold stays at lb (st = L: no pull, the
-  // deferred pushes cover [L - M, L]), as for integer weights beyond the
-  // window's size limit
   const bool fw = g.float_w != 0;
-  uint32_t stn = fw ? L : block_compute_st(I, L, gapL, g.nnz, lds);
+  unsigned long long ubn;
+  uint32_t lb0;
+  if (fw) {
+    // The next band ends at L + gap rounded, with two floors that play the
+    // role of the integer gap's floor of 1 (R5): the gap is at least the
+    // smallest positive weight (a zero weight quantile would otherwise give a
+    // gap of the least denormal), and the band reaches past the smallest
+    // pending distance, so that every step settles a vertex or fills the
+    // pending list. Infinity and beyond are the +inf sentinel.
+    const uint32_t gf = gapL > g.min_pos_w || g.min_pos_w == kInf ? gapL : g.min_pos_w;
+    uint32_t e = dadd<true>(L, gf);
+    if (e <= L) e = L + 1u;
+    const uint32_t pm = I.pend_min.v;
+    if (pm != kInf && pm >= L && e <= pm) e = pm + 1u;
+    ubn = e >= 0x7f800000u ? (unsigned long long)kInf : (unsigned long long)e;
+    // lb0 = L - M, lowered by two units in the last place of L: a settled
+    // distance d whose rounded d + M still reaches L lies above it
+    const float ulp = __uint_as_float(L + 1u) - __uint_as_float(L);
+    const float lo = (__uint_as_float(L) - __uint_as_float(I.M)) - 2.0f * ulp;
+    lb0 = lo > 0.0f ? __float_as_uint(lo) : 0u;
+  } else {
+    ubn = (unsigned long long)L + gapL;
+    if (ubn > kInf) ubn = kInf;
+    lb0 = L > I.M ? L - I.M : 0u;
+  }
+  // binary32 weights: computeST scores the points of the ST_NUM grid
+  uint32_t stn = fw ? block_compute_st_f(I, L, gapL, lb0, (uint32_t)ubn, g.nnz, lds)
+                    : block_compute_st(I, L, gapL, g.nnz, lds);
   if (tid == 0) {
     if (mass != S) I.flags.v |= FLAG_MASS;
     StepRec rec;
@@ -315,36 +442,23 @@ __device__ __noinline__ void run_heuristic(GInst& I, HeurLds& lds) {
     __syncthreads();
     return;
   }
-  unsigned long long ubn;
-  uint32_t lb0;
+  // clear the ring slots of the next band [L, ubn) before its settle pass;
+  // binary32 weights: the grid bins after bin(L) up to bin(ubn) (bin(L) may
+  // already hold settled vertices below L)
+  uint32_t width, key0;
   if (fw) {
-    // The next band ends at L + gap rounded, with two floors that play the
-    // role of the integer gap's floor of 1 (R5): the gap is at least the
-    // smallest positive weight (a zero weight quantile would otherwise give a
-    // gap of the least denormal), and the band reaches past the smallest
-    // pending distance, so that every step settles a vertex or fills the
-    // pending list. Infinity and beyond are the +inf sentinel.
-    const uint32_t gf = gapL > g.min_pos_w || g.min_pos_w == kInf ? gapL : g.min_pos_w;
-    uint32_t e = dadd<true>(L, gf);
-    if (e <= L) e = L + 1u;
-    const uint32_t pm = I.pend_min.v;
-    if (pm != kInf && pm >= L && e <= pm) e = pm + 1u;
-    ubn = e >= 0x7f800000u ? (unsigned long long)kInf : (unsigned long long)e;
-    // lb0 = L - M, lowered by two units in the last place of L: a settled
-    // distance d whose rounded d + M still reaches L lies above it
-    const float ulp = __uint_as_float(L + 1u) - __uint_as_float(L);
-    const float lo = (__uint_as_float(L) - __uint_as_float(I.M)) - 2.0f * ulp;
-    lb0 = lo > 0.0f ? __float_as_uint(lo) : 0u;
+    const double inv = grid_inv(I.M);
+    const uint32_t kl = fbin(L, inv), ku = ubn >= 0x7f800000u ? kNoBin : fbin((uint32_t)ubn, inv);
+    const bool ok = kl != kNoBin && ku != kNoBin;
+    width = ok ? ku - kl : 0u;
+    key0 = kl + 1u;
   } else {
-    ubn = (unsigned long long)L + gapL;
-    if (ubn > kInf) ubn = kInf;
-    lb0 = L > I.M ? L - I.M : 0u;
+    width = (uint32_t)(ubn - L);
+    key0 = L;
   }
-  // clear the ring slots of the next band [L, ubn) before its settle pass
-  const uint32_t width = fw ? 0u : (uint32_t)(ubn - L);
   const uint32_t clr = width > I.ring_mask + 1 ? I.ring_mask + 1 : width;
   for (uint32_t k = tid; k < clr; k += kBlock) {
-    uint32_t slot = (L + k) & I.ring_mask;
+    uint32_t slot = (key0 + k) & I.ring_mask;
     gbl(I.ring_mass)[slot] = 0;
     gbl(I.ring_cnt)[slot] = 0;
   }
@@ -385,9 +499,17 @@ __device__ __noinline__ void run_heuristic(GInst& I, HeurLds& lds) {
       // the entries able to pull (smallest weight < ub - st) not read by an
       // earlier pull: up to the first weight bucket starting at or above
       // ub - st
-      const unsigned long long reach = ubn - stn;
       const unsigned long long bw = g.ubucket_width;
-      const unsigned long long j = (reach + bw - 1) / bw;
+      unsigned long long j;
+      if (fw) {
+        // two buckets: the second holds lightest weights >= bw, which pull
+        // only if st + bw, rounded, is below ub
+        static_assert(kUBuckets == 2, "binary32 pull-list end assumes two buckets");
+        j = dadd<true>(stn, (uint32_t)bw) < (uint32_t)ubn ? (unsigned long long)kUBuckets : 1ull;
+      } else {
+        const unsigned long long reach = ubn - stn;
+        j = (reach + bw - 1) / bw;
+      }
       const int32_t e = gbl(g.ufirst)[j < (unsigned long long)kUBuckets ? j : kUBuckets];
       I.u_end = e > I.u_done ? e : I.u_done;
       I.c.pull_unsettled += unsettled;
@@ -1102,11 +1224,15 @@ __device__ __noinline__ void block_settle(GInst& I, int kind, int item0, int nit
   GDevGraph& g = *gbl(I.g);
   const int tid = threadIdx.x;
   const uint32_t lb = I.lb, ub = I.ub, M = I.M;
-  // the per-distance ring feeds computeST, which needs integer distances:
-  // nothing to record with binary32 weights
+  // the ring feeds computeST: per distance, or with binary32 weights per bin
+  // of the ST_NUM grid (bins klb..kub hold this step's settled vertices)
   const bool fw = g.float_w != 0;
-  const uint32_t band = ub - lb;
-  const uint32_t nb = fw ? 0u : (band < (uint32_t)kLdsRing ? band : (uint32_t)kLdsRing);
+  const double inv = fw ? grid_inv(M) : 0.0;
+  const uint32_t klb = fw ? fbin(lb, inv) : lb;
+  const uint32_t kub = fw ? (ub >= 0x7f800000u ? kNoBin : fbin(ub, inv)) : ub;
+  const bool frec = fw && klb != kNoBin && kub != kNoBin;
+  const uint32_t band = fw ? (frec ? kub - klb + 1u : 0u) : ub - lb;
+  const uint32_t nb = band < (uint32_t)kLdsRing ? band : (uint32_t)kLdsRing;
   const int nh = g.num_deg < kLdsHist ? g.num_deg : kLdsHist;
   auto dinfo = gbl(g.dinfo);
   auto state = gbl(I.state);
@@ -1155,16 +1281,23 @@ __device__ __noinline__ void block_settle(GInst& I, int kind, int item0, int nit
     if (pend && d < pmin) pmin = d;
     if (!settle) continue;
     const int deg = (int)(uint32_t)di[k];
-    const uint32_t off = d - lb;
     // only the window [ub - M, ub) is read by the next computeST; the first
     // step's band may be wider, and older values would alias ring slots
-    if (!fw && (unsigned long long)d + M >= ub) {
+    // (binary32: only the last ring-size bins up to bin(ub) are kept)
+    uint32_t key = d;
+    bool rec = (unsigned long long)d + M >= ub;
+    if (fw) {
+      key = frec ? fbin(d, inv) : 0u;
+      rec = frec && (unsigned long long)key + ring_mask + 1ull > kub;
+    }
+    if (rec) {
+      const uint32_t off = key - klb;
       if (off < nb) {
         atomicAdd(&L.mass[off], (uint32_t)deg);
         atomicAdd(&L.cnt[off], 1u);
       } else {
-        atomicAdd(&ring_mass[d & ring_mask], (unsigned long long)deg);
-        atomicAdd(&ring_cnt[d & ring_mask], 1u);
+        atomicAdd(&ring_mass[key & ring_mask], (unsigned long long)deg);
+        atomicAdd(&ring_cnt[key & ring_mask], 1u);
       }
     }
     const int r = (int)(di[k] >> 32);
@@ -1217,7 +1350,7 @@ __device__ __noinline__ void block_settle(GInst& I, int kind, int item0, int nit
   for (uint32_t k = tid; k < nb; k += kBlock) {
     uint32_t c = L.cnt[k];
     if (c) {
-      uint32_t slot = (lb + k) & ring_mask;
+      uint32_t slot = (klb + k) & ring_mask;
       atomicAdd(&ring_mass[slot], (unsigned long long)L.mass[k]);
       atomicAdd(&ring_cnt[slot], c);
     }

@@ -839,7 +839,15 @@ int prep_graph(int32_t n, const int32_t* rowptr_in, const int32_t* col_in, const
   PREP_CHECK(hipGetLastError());
   // ...then ordered by (weight bucket of the smallest weight, id): 4096-key
   // chunks sorted in LDS, then merge passes over the whole list
-  const uint32_t ub_width = (uint32_t)(((unsigned long long)maxw + kUBucketDiv) / kUBucketDiv);
+  uint32_t ub_width = (uint32_t)(((unsigned long long)maxw + kUBucketDiv) / kUBucketDiv);
+  if (flags & 2) {
+    // binary32: bucket 0 = lightest edge below maxW / kUBucketDiv in value
+    float f;
+    std::memcpy(&f, &maxw, sizeof f);
+    f /= (float)kUBucketDiv;
+    std::memcpy(&ub_width, &f, sizeof f);
+    if (ub_width == 0) ub_width = 1;
+  }
   int32_t* ufirst = A.get<int32_t>(kUBuckets + 1);
   if (!A.ok) {
     *msg = "device allocation failed";

@@ -7,7 +7,7 @@ import pytest
 
 import graphgen
 from graphgen import small
-from oracle import native
+from oracle import eic, native
 
 pytestmark = pytest.mark.gpu
 
@@ -64,16 +64,42 @@ def test_rounding_of_the_path_sum():
     assert d.tolist() == [0.0, 16777216.0, 16777216.0, 16777216.0]
 
 
+@pytest.mark.parametrize("topt", [True, False])
 @pytest.mark.parametrize("name", ["rmat14f", "rmat14c1", "rmat14c5", "rmat14c9", "rmat16f"])
-def test_real_weight_workloads(name):
+def test_real_weight_workloads(name, topt):
     wl = graphgen.workload(name)
     adj = native.Adjacency(wl.edges.n, wl.edges.src, wl.edges.dst, wl.edges.w)
     g = sssp.Graph.from_csr(wl.csr, float_weights=True)
+    pulls = 0
     for s in wl.sources(3):
-        d = g.solve(int(s)).cpu().numpy()
-        assert sssp.counters()["flags"] == 0
+        d = g.solve(int(s), traversal_opt=topt).cpu().numpy()
+        c = sssp.counters()
+        assert c["flags"] == 0
+        pulls += c["pulls"]
         assert_bits(d, adj.dijkstra_f32(int(s)), "%s s=%d" % (name, s))
+    # the ST_NUM grid gives the traversal optimisation a threshold below lb
+    assert (pulls > 0) == topt
     adj.close()
+
+
+@pytest.mark.parametrize("name", ["rmat12f", "rmat12c5", "rmat14f", "rmat14c9"])
+def test_schedule_matches_the_f32_model(name):
+    """<lb, ub, st> per step and the statistics taken at each step's end
+    (sumD, highD, gap, the grid computeST) are functions of the settled set,
+    so the GPU must reproduce the binary32 model step for step."""
+    wl = graphgen.workload(name)
+    c = wl.csr
+    g = sssp.Graph.from_csr(c, float_weights=True)
+    for s in wl.sources(3):
+        ref = eic.eic_sssp_f32(c.n, c.rowptr, c.col, c.w, int(s))
+        g.solve(int(s))
+        got = sssp.schedule()
+        assert len(got) == len(ref.steps), (len(got), len(ref.steps))
+        for a, b in zip(got, ref.steps):
+            assert (a["lb"], a["ub"], a["st"]) == (b.lb, b.ub, b.st), (a, b)
+            if b.ub != INF or b.lb != 0:
+                assert (a["L"], a["S"], a["h"], a["gap"], a["st_next"]) == \
+                    (b.L, b.S, b.h, b.gap, b.st_next), (a, b)
 
 
 def test_tree_and_point_to_point_with_real_weights():

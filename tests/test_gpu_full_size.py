@@ -2,7 +2,8 @@
 configuration bench.py times: RMAT-24 (every distance checked by the
 oracle's invariant checker, which characterises them completely for weights
 >= 1; bench.py compares one source with the oracle's Dijkstra; a
-shortest-path tree checked by the oracle's tree checker), ER-22 and the
+shortest-path tree checked by the oracle's tree checker), RMAT-24 with real
+binary32 weights against the oracle's binary32 Dijkstra, ER-22 and the
 2048 x 2048 grid against the oracle's Dijkstra, and the 64-source RMAT-22
 plan (sampled rows)."""
 import numpy as np
@@ -62,6 +63,26 @@ def test_rmat24_tree():
     assert invariant_ok(c, s, d)
     assert native.check_tree(c.n, c.rowptr, c.col, c.w, s, d, p.cpu().numpy()) == [0, 0, 0, 0]
     g.close()
+
+
+def test_rmat24_real_weights():
+    # weights uniform on (0, 1]: one source against the oracle's binary32
+    # Dijkstra, with the traversal optimisation on (the ST_NUM grid) and off
+    wl = graphgen.workload("rmat24f")
+    c = wl.csr
+    g = sssp.Graph.from_csr(c, float_weights=True)
+    s = int(wl.sources(1)[0])
+    on = g.solve(s).cpu().numpy()
+    cnt = sssp.counters()
+    assert cnt["flags"] == 0 and cnt["pulls"] > 0
+    off = g.solve(s, traversal_opt=False).cpu().numpy()
+    assert sssp.counters()["flags"] == 0
+    g.close()
+    adj = native.Adjacency(wl.edges.n, wl.edges.src, wl.edges.dst, wl.edges.w)
+    ref = adj.dijkstra_f32(s)
+    adj.close()
+    assert_same(on, ref, "rmat24f")
+    assert_same(off, ref, "rmat24f filter off")
 
 
 def test_er22_against_oracle():

@@ -109,3 +109,106 @@ def test_real_weight_generators(pivot):
         # in any other window of that width
         hist, _ = np.histogram(w, bins=20, range=(0.0, 1.0))
         assert abs((np.argmax(hist) + 0.5) / 20 - pivot) <= 0.05 + 1e-9, hist
+
+
+# ------------------------------------------------ the binary32 schedule model
+
+from oracle import eic  # noqa: E402
+from oracle import heuristic as H  # noqa: E402
+
+
+def _bits(x):
+    return int(np.array([x], np.float32).view(np.uint32)[0])
+
+
+@pytest.mark.parametrize("topt", [True, False])
+def test_f32_model_reaches_the_f32_dijkstra_tiny_fuzz(topt):
+    for vname, vals in sorted(VALUE_SETS.items()):
+        vals = np.asarray(vals, np.float32)
+        for n in range(1, 9):
+            for m in (0, n, 3 * n):
+                el = small.tiny_random(n, m, [1], seed=5000 + 10 * n + m)
+                rng = np.random.default_rng(5100 + 10 * n + m)
+                wb = rng.choice(vals, size=el.src.shape[0]).view(np.uint32)
+                el = graphgen.from_arrays(n, el.src, el.dst, wb)
+                c = graphgen.to_csr(el)
+                adj = native.Adjacency(n, el.src, el.dst, el.w)
+                for s in range(n):
+                    r = eic.eic_sssp_f32(c.n, c.rowptr, c.col, c.w, s, traversal_opt=topt)
+                    assert np.array_equal(r.dist, adj.dijkstra_f32(s)), (vname, n, m, s)
+                adj.close()
+
+
+@pytest.mark.parametrize("name", ["rmat12f", "rmat12c1", "rmat12c5", "rmat12c9"])
+def test_f32_model_workloads_pull_and_stay_exact(name):
+    """With the ST_NUM grid the model pulls, scans far fewer entries than with
+    the traversal optimisation off, and still reaches the binary32 Dijkstra."""
+    wl = graphgen.workload(name)
+    c = wl.csr
+    adj = native.Adjacency(wl.edges.n, wl.edges.src, wl.edges.dst, wl.edges.w)
+    for s in wl.sources(2):
+        ref = adj.dijkstra_f32(int(s))
+        on = eic.eic_sssp_f32(c.n, c.rowptr, c.col, c.w, int(s))
+        off = eic.eic_sssp_f32(c.n, c.rowptr, c.col, c.w, int(s), traversal_opt=False)
+        assert np.array_equal(on.dist, ref) and np.array_equal(off.dist, ref)
+        assert on.pulls > 0 and off.pulls == 0
+        deg = c.degrees()
+        assert eic.normalised(on, c.n, deg)["nTrav"] < 0.5 * eic.normalised(off, c.n, deg)["nTrav"]
+        for st in on.steps:
+            assert st.st <= st.lb
+    adj.close()
+
+
+def test_grid_compute_st_equals_the_exact_window_on_dyadic_distances():
+    """With maxW = 1 and every distance a multiple of 1/ST_NUM, the grid's bins
+    are exactly the distinct distances, and Eq. 4-6 scale by a power of two:
+    the grid computeST must return the exact-window computeST of the
+    distances times ST_NUM, divided by ST_NUM."""
+    rng = np.random.default_rng(31337)
+    Mi = H.ST_NUM
+    Mb = _bits(1.0)
+    hits = 0
+    for trial in range(400):
+        Li = int(rng.integers(1, 6 * Mi))
+        gap_i = int(rng.integers(1, Mi))          # below M: the main branch
+        gap_lb_i = int(rng.integers(1, Mi))
+        nnz = int(rng.integers(1000, 100000))
+        S = int(rng.integers(0, nnz // 2)) if trial % 2 else int(rng.integers(0, 3000))
+        k = int(rng.integers(0, 200))
+        settled = rng.integers(max(0, Li - Mi - 8), Li, size=k) if Li > 0 else np.zeros(0, np.int64)
+        degs = rng.integers(1, 500, size=settled.shape[0])
+        wv, inv = np.unique(settled[settled >= max(0, Li - Mi)], return_inverse=True)
+        wm = np.zeros(wv.shape[0], np.int64)
+        np.add.at(wm, inv, degs[settled >= max(0, Li - Mi)])
+        want = H.compute_st(Li, gap_i, gap_lb_i, S, nnz, Mi, wv, wm)
+        Lb = _bits(Li / Mi)
+        Lf = np.float32(Li / Mi)
+        ulp = np.float32(H.f32(Lb + 1)) - Lf
+        lo = np.float32(np.float32(Lf - np.float32(1.0)) - np.float32(2.0) * ulp)
+        lb0 = _bits(lo) if lo > 0 else 0
+        Yb = _bits((Li + gap_i) / Mi)
+        sb = np.array([_bits(x / Mi) for x in settled.tolist()], np.uint32)
+        got = H.compute_st_f32(Lb, _bits(gap_i / Mi), _bits(gap_lb_i / Mi), S, nnz, Mb, lb0, Yb, sb, degs)
+        assert H.f32(got) * Mi == want, (trial, Li, want, H.f32(got) * Mi)
+        hits += want < Li
+    assert hits > 100
+
+
+def test_grid_threshold_is_the_first_value_of_its_bin():
+    rng = np.random.default_rng(99)
+    wl = graphgen.workload("rmat12f")
+    c = wl.csr
+    r = eic.eic_sssp_f32(c.n, c.rowptr, c.col, c.w, int(wl.sources(1)[0]))
+    M = int(c.w.max())
+    inv = float(H.ST_NUM) / H.f32(M)
+    seen = 0
+    for st in r.steps:
+        if st.st < st.lb and st.st > 0:
+            k = H.grid_bin(st.st, inv)
+            assert H.grid_bin(st.st - 1, inv) < k
+            seen += 1
+    assert seen > 0
+    # bins never decrease along the bit patterns
+    x = np.sort(rng.integers(0, 0x40000000, size=20000)).tolist()
+    b = [H.grid_bin(v, inv) for v in x]
+    assert all(b[i] <= b[i + 1] for i in range(len(b) - 1))
