@@ -244,6 +244,8 @@ def workload(name: str, scale: Optional[int] = None) -> Workload:
     ``rmat24``  R-MAT scale 24, edge factor 16, w in 1..255
     ``grid2048`` 2048 x 2048 grid, 5% of edges dropped, 1% diagonals, w in 1..1000
     ``rmat<k>`` / ``er<k>`` / ``grid<k>`` the same recipes at other sizes
+    ``grid<k>w<W>``  the grid recipe with w in 1..W (W above 65536: beyond the
+                 exact selection-threshold window)
     ``rmat<k>f``  the R-MAT graph rmat<k> with real weights uniform on (0, 1] (binary32 bits)
     ``rmat<k>c<d>``  the same with the float-pivot variant's weights (Eq. 8), pivot d / 10
     ``rmat<k>p<power>``  the R-MAT graph rmat<k> with its weights replaced by the
@@ -278,9 +280,12 @@ def workload(name: str, scale: Optional[int] = None) -> Workload:
         n = 1 << s
         el = gnm(n, 16 * n, 255, seed)
     elif name.startswith("grid"):
-        side = int(name[4:]) if scale is None else scale
+        # grid<side>, or grid<side>w<W>: the same recipe with w in 1..W
+        body = name[4:]
+        sk, wk = body.split("w") if "w" in body else (body, "1000")
+        side = int(sk) if scale is None else scale
         seed = SEED_BASE + {2048: 4}.get(side, 300 + side)
-        el = grid(side, side, 0.95, 0.01, 1000, seed)
+        el = grid(side, side, 0.95, 0.01, int(wk), seed)
     else:
         raise ValueError("unknown workload %r" % name)
     return Workload(name, el, to_csr(el), seed)

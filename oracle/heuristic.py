@@ -27,15 +27,18 @@ Readings where the text is silent or ambiguous:
   otherwise L.  Below L - M every candidate clamps to the same estimate.
 * Eq. (4)-(6) are evaluated in IEEE double with the operation order written
   here and no fused multiply-add.
-* When the largest weight exceeds ST_WINDOW_MAX the traversal optimisation is
-  off (st = L): the exact window of candidate distances is not kept.
+* When the largest weight exceeds ST_WINDOW_MAX the exact window of candidate
+  distances is not kept: computeST scores the points of the ST_NUM grid
+  instead, as for real weights (below).
 * A single sentinel INF = 2^32 - 1 stands for +infinity in dist, ub and every
   threshold; sums are clamped to it.
-* Real (binary32) weights: computeST scores the points of a grid of ST_NUM
-  (Section 4.1: 2^10) equal bins per maxW, bin(d) = floor(d * ST_NUM / maxW) in
-  double; a candidate is a grid point whose bin holds a settled vertex in the
-  window above lb0 = L - M (lowered by two units in the last place of L), and
-  the threshold returned is the smallest binary32 value of the winning bin.
+* The ST_NUM grid (real binary32 weights, and integer weights beyond the
+  exact window): ST_NUM (Section 4.1: 2^10) equal bins per maxW, bin(d) =
+  floor(d * ST_NUM / maxW) in double; a candidate is a grid point whose bin
+  holds a settled vertex and has no distance below lb0 = L - M (for binary32,
+  lowered by two units in the last place of L), scored by Eq. 4-6 at the grid
+  point, and the threshold returned is the smallest distance (bit pattern, or
+  integer) of the winning bin.
 """
 from __future__ import annotations
 
@@ -137,7 +140,11 @@ def compute_st(L: int, gap_L: int, gap_lb: int, S: int, nnz: int, M: int,
     win_vals: distinct settled distances in [max(0, L - M), L), ascending;
     win_mass: total degree of the settled vertices at each of those distances.
     """
-    if not traversal_opt or M > ST_WINDOW_MAX:
+    if traversal_opt and M > ST_WINDOW_MAX:
+        # beyond the exact window: the ST_NUM grid
+        return compute_st_grid(L, gap_L, gap_lb, S, nnz, M, max(0, L - M), min(L + gap_L, INF),
+                               win_vals, win_mass, False)
+    if not traversal_opt:
         return L
     if 2 * S >= nnz or gap_lb == M:
         return L
@@ -158,19 +165,31 @@ def compute_st(L: int, gap_L: int, gap_lb: int, S: int, nnz: int, M: int,
     return best
 
 
-# --------------------------------------------------------------- binary32 --
+# ------------------------------------------ the selection-threshold grid --
 
 def f32(bits: int) -> float:
     """The value of a binary32 bit pattern, as a Python (double) float."""
     return float(np.asarray(bits, dtype=np.uint32).view(np.float32))
 
 
-def grid_bin(bits: int, inv: float):
-    """bin(d) = floor(d * inv) for inv = ST_NUM / maxW, in double; None past
-    2^31 bins, for +inf and for the sentinel."""
-    if bits >= F32_INF_BITS:
+def _value(key: int, is_f32: bool) -> float:
+    return f32(key) if is_f32 else float(key)
+
+
+def _values(keys: np.ndarray, is_f32: bool) -> np.ndarray:
+    k = np.asarray(keys)
+    if is_f32:
+        return k.astype(np.uint32).view(np.float32).astype(np.float64)
+    return k.astype(np.float64)
+
+
+def grid_bin(key: int, inv: float, is_f32: bool = True):
+    """bin(d) = floor(value(d) * inv) for inv = ST_NUM / maxW, in double; None
+    past 2^31 bins, for +inf and for the sentinel.  value() is the binary32
+    value of a bit pattern, or the integer itself."""
+    if key >= (F32_INF_BITS if is_f32 else INF):
         return None
-    x = f32(bits) * inv
+    x = _value(key, is_f32) * inv
     return int(math.floor(x)) if x < 2147483648.0 else None
 
 
@@ -185,32 +204,34 @@ def profit_f(x: float, L: float, Y: float, S: int, Sx: int, M: float, nnz: int) 
     return (pushed - long_) - pulled
 
 
-def compute_st_f32(L: int, gap_L: int, gap_lb: int, S: int, nnz: int, M: int, lb0: int, Y: int,
-                   settled_dist: np.ndarray, settled_deg: np.ndarray,
-                   traversal_opt: bool = True) -> int:
-    """Function 2 (computeST) with binary32 distances (bit patterns), over the
-    ST_NUM grid.  settled_dist / settled_deg: the settled vertices (dist < L)."""
-    if not traversal_opt or M == 0 or L >= F32_INF_BITS:
+def compute_st_grid(L: int, gap_L: int, gap_lb: int, S: int, nnz: int, M: int, lb0: int, Y: int,
+                    settled_keys: np.ndarray, settled_deg: np.ndarray, is_f32: bool,
+                    traversal_opt: bool = True) -> int:
+    """Function 2 (computeST) over the ST_NUM grid (Section 4.1).  Keys are
+    binary32 bit patterns (is_f32) or integers; settled_keys / settled_deg:
+    settled vertices (dist < L), any of them, or one entry per distinct
+    distance with its total degree."""
+    inf_key = F32_INF_BITS if is_f32 else INF
+    if not traversal_opt or M == 0 or L >= inf_key:
         return L
     if 2 * S >= nnz or gap_lb == M:
         return L
     if gap_L == M:
         return lb0
-    inv = float(ST_NUM) / f32(M)
-    kL = grid_bin(L, inv)
+    inv = float(ST_NUM) / _value(M, is_f32)
+    kL = grid_bin(L, inv, is_f32)
     if kL is None:
         return L
-    klo = 0 if lb0 == 0 else grid_bin(lb0, inv) + 1
+    klo = 0 if lb0 == 0 else grid_bin(lb0 - 1, inv, is_f32) + 1   # first bin with no key below lb0
     if klo > kL:
         return L
-    d = np.asarray(settled_dist, dtype=np.uint32).view(np.float32).astype(np.float64)
-    b = np.floor(d * inv).astype(np.int64)
+    b = np.floor(_values(settled_keys, is_f32) * inv).astype(np.int64)
     sel = (b >= klo) & (b <= kL)
     mass = {}
     for k, m in zip(b[sel].tolist(), np.asarray(settled_deg, dtype=np.int64)[sel].tolist()):
         mass[k] = mass.get(k, 0) + m
-    Mf, Lf = f32(M), f32(L)
-    Yf = math.inf if Y >= F32_INF_BITS else f32(Y)
+    Mf, Lf = _value(M, is_f32), _value(L, is_f32)
+    Yf = math.inf if Y >= inf_key else _value(Y, is_f32)
     delta = Mf / float(ST_NUM)
     keys = sorted(mass)
     suffix, acc = {}, 0
@@ -224,11 +245,20 @@ def compute_st_f32(L: int, gap_L: int, gap_lb: int, S: int, nnz: int, M: int, lb
             best, max_p = k, p
     if best is None:
         return L
-    lo, hi = 0, L   # smallest bit pattern whose bin is at least best
+    lo, hi = 0, L   # smallest key whose bin is at least best
     while lo < hi:
         mid = (lo + hi) // 2
-        if grid_bin(mid, inv) >= best:
+        if grid_bin(mid, inv, is_f32) >= best:
             hi = mid
         else:
             lo = mid + 1
     return lo
+
+
+def compute_st_f32(L: int, gap_L: int, gap_lb: int, S: int, nnz: int, M: int, lb0: int, Y: int,
+                   settled_dist: np.ndarray, settled_deg: np.ndarray,
+                   traversal_opt: bool = True) -> int:
+    """Function 2 (computeST) with binary32 distances (bit patterns), over the
+    ST_NUM grid.  settled_dist / settled_deg: the settled vertices (dist < L)."""
+    return compute_st_grid(L, gap_L, gap_lb, S, nnz, M, lb0, Y, settled_dist, settled_deg, True,
+                           traversal_opt)

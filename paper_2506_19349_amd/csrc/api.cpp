@@ -52,13 +52,13 @@ Needs needs_for(const DevGraph& g, int maxw) {
   r.trace = 1 << 16;
   if (g.float_w) {
     // binary32 weights: the selection-threshold grid (kStNum bins per maxW)
-    r.ring = kFloatRing;
+    r.ring = kGridRing;
     r.steprec = 1u << 17;
   } else if (g.max_w <= kRingMax) {
     r.ring = pow2_at_least(std::max<uint64_t>(64, 2ull * g.max_w + 2));
     r.steprec = pow2_at_least(std::max<uint64_t>(64, 2ull * g.max_w + 64));
   } else {
-    r.ring = 1024;
+    r.ring = kGridRing;  // the selection-threshold grid
     r.steprec = 1u << 17;
   }
   return r;

@@ -15,8 +15,8 @@ constexpr int kRatioNum = 4096;          // RATIO_NUM, Section 4.1
 constexpr uint32_t kRingMax = 65536;     // exact selection-threshold window up to this max weight
 constexpr int kLdsRing = 1024;           // settle: distance bins privatised in LDS
 constexpr int kStNum = 1024;             // ST_NUM, Section 4.1: selection-threshold grid per max weight
-constexpr uint32_t kFloatRing = 4096;    // grid bins kept with binary32 weights (>= 2 ST_NUM + 2)
-constexpr uint32_t kNoBin = 0xFFFFFFFFu; // a binary32 distance too large for the grid
+constexpr uint32_t kGridRing = 4096;     // grid bins kept (>= 2 ST_NUM + 2)
+constexpr uint32_t kNoBin = 0xFFFFFFFFu; // a distance too large for the grid
 constexpr int kLdsHist = 1024;           // settle: degree ranks privatised in LDS
 constexpr int kHeavyChunk = 256;         // edges per heavy chunk
 constexpr int kDefaultHeavy = 64;        // ranges longer than this are split

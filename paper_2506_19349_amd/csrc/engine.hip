@@ -268,16 +268,25 @@ __device__ uint32_t block_compute_st(const GInst& I, uint32_t L, uint32_t gapL, 
   return res;
 }
 
-// Binary32 distances on the selection-threshold grid (Section 4.1: ST_NUM
-// candidates per span): bin(d) = floor(d * kStNum / maxW), evaluated in double,
+// The selection-threshold grid (Section 4.1: ST_NUM candidates per span),
+// used for binary32 distances and for integer weights too large for the
+// exact window: bin(d) = floor(value(d) * kStNum / maxW), evaluated in double,
 // so it never decreases as d grows; kNoBin past 2^31 bins, for +inf and for
-// the sentinel.
-__device__ __forceinline__ double grid_inv(uint32_t M) {
-  return (double)kStNum / (double)__uint_as_float(M);
+// the sentinel. value() is the binary32 value of the bit pattern, or the
+// integer itself.
+__device__ __forceinline__ double dval(uint32_t d, bool fw) {
+  return fw ? (double)__uint_as_float(d) : (double)d;
 }
 
-__device__ __forceinline__ uint32_t fbin(uint32_t d, double inv) {
-  const double x = (double)__uint_as_float(d) * inv;
+__device__ __forceinline__ uint32_t dinf(bool fw) { return fw ? 0x7f800000u : kInf; }
+
+__device__ __forceinline__ double grid_inv(uint32_t M, bool fw) {
+  return (double)kStNum / dval(M, fw);
+}
+
+__device__ __forceinline__ uint32_t gbin(uint32_t d, double inv, bool fw) {
+  if (d >= dinf(fw)) return kNoBin;
+  const double x = dval(d, fw) * inv;
   return x < 2147483648.0 ? (uint32_t)x : kNoBin;
 }
 
@@ -296,29 +305,30 @@ __device__ __forceinline__ double profit_of_f(double x, double L, double Y, unsi
   return (pushed - lng) - pulled;
 }
 
-// Function 2 (computeST) with binary32 distances. The candidates are the
-// grid points (kStNum per maxW, Section 4.1) whose bin holds a settled vertex
-// and lies inside the window above lb0 = L - M; each is scored by Eq. 4-6 at
-// the grid point with the settled mass of its bin and the bins above it. The
-// threshold returned for the winning bin is the smallest binary32 value in
-// it, so that dist >= st holds exactly for the vertices of that bin and
-// above. Whole workgroup.
-__device__ uint32_t block_compute_st_f(const GInst& I, uint32_t L, uint32_t gapL, uint32_t lb0,
-                                       uint32_t ubn, int32_t nnz, HeurLds& lds) {
+// Function 2 (computeST) over the grid. The candidates are the grid points
+// (kStNum per maxW) whose bin holds a settled vertex and has no key below
+// lb0 = L - M; each is scored by Eq. 4-6 at the
+// grid point with the settled mass of its bin and the bins above it. The
+// threshold returned for the winning bin is the smallest key (binary32 bit
+// pattern, or integer) in it, so that dist >= st holds exactly for the
+// vertices of that bin and above. Whole workgroup.
+__device__ uint32_t block_compute_st_grid(const GInst& I, uint32_t L, uint32_t gapL, uint32_t lb0,
+                                          uint32_t ubn, int32_t nnz, bool fw, HeurLds& lds) {
   const uint32_t M = I.M;
   const unsigned long long S = I.S.v;
-  if (!I.traversal_opt || M == 0u || L >= 0x7f800000u) return L;
+  if (!I.traversal_opt || M == 0u || L >= dinf(fw)) return L;
   if (2ull * S >= (unsigned long long)nnz || I.gap_cur == M) return L;
   if (gapL == M) return lb0;
-  const double inv = grid_inv(M);
-  const uint32_t kL = fbin(L, inv);
+  const double inv = grid_inv(M, fw);
+  const uint32_t kL = gbin(L, inv, fw);
   if (kL == kNoBin) return L;
-  const uint32_t klo = lb0 == 0u ? 0u : fbin(lb0, inv) + 1u;
+  // the first bin whose smallest key is at least lb0
+  const uint32_t klo = lb0 == 0u ? 0u : gbin(lb0 - 1u, inv, fw) + 1u;
   if (klo > kL) return L;
   const uint32_t W = kL - klo + 1u;
-  const double Mf = (double)__uint_as_float(M);
-  const double Lf = (double)__uint_as_float(L);
-  const double Y = ubn >= 0x7f800000u ? __builtin_huge_val() : (double)__uint_as_float(ubn);
+  const double Mf = dval(M, fw);
+  const double Lf = dval(L, fw);
+  const double Y = ubn >= dinf(fw) ? __builtin_huge_val() : dval(ubn, fw);
   const double delta = Mf / (double)kStNum;
   const int tid = threadIdx.x;
   const uint32_t chunk = (W + kBlock - 1) / kBlock;
@@ -359,12 +369,12 @@ __device__ uint32_t block_compute_st_f(const GInst& I, uint32_t L, uint32_t gapL
   }
   uint32_t res = L;
   if (lds.pbest[0] > 0.0) {
-    // smallest binary32 value in bin kb (bin(L) = kL >= kb, so within [0, L])
+    // smallest key in bin kb (bin(L) = kL >= kb, so within [0, L])
     const uint32_t kb = lds.xbest[0];
     uint32_t lo = 0u, hi = L;
     while (lo < hi) {
       const uint32_t mid = lo + ((hi - lo) >> 1);
-      if (fbin(mid, inv) >= kb) hi = mid; else lo = mid + 1u;
+      if (gbin(mid, inv, fw) >= kb) hi = mid; else lo = mid + 1u;
     }
     res = lo;
   }
@@ -410,9 +420,11 @@ __device__ __noinline__ void run_heuristic(GInst& I, HeurLds& lds) {
     if (ubn > kInf) ubn = kInf;
     lb0 = L > I.M ? L - I.M : 0u;
   }
-  // binary32 weights: computeST scores the points of the ST_NUM grid
-  uint32_t stn = fw ? block_compute_st_f(I, L, gapL, lb0, (uint32_t)ubn, g.nnz, lds)
-                    : block_compute_st(I, L, gapL, g.nnz, lds);
+  // binary32 weights, or integer weights beyond the exact window: computeST
+  // scores the points of the ST_NUM grid
+  const bool grid = fw || I.M > kRingMax;
+  uint32_t stn = grid ? block_compute_st_grid(I, L, gapL, lb0, (uint32_t)ubn, g.nnz, fw, lds)
+                      : block_compute_st(I, L, gapL, g.nnz, lds);
   if (tid == 0) {
     if (mass != S) I.flags.v |= FLAG_MASS;
     StepRec rec;
@@ -443,12 +455,12 @@ __device__ __noinline__ void run_heuristic(GInst& I, HeurLds& lds) {
     return;
   }
   // clear the ring slots of the next band [L, ubn) before its settle pass;
-  // binary32 weights: the grid bins after bin(L) up to bin(ubn) (bin(L) may
-  // already hold settled vertices below L)
+  // on the grid: the bins after bin(L) up to bin(ubn) (bin(L) may already
+  // hold settled vertices below L)
   uint32_t width, key0;
-  if (fw) {
-    const double inv = grid_inv(I.M);
-    const uint32_t kl = fbin(L, inv), ku = ubn >= 0x7f800000u ? kNoBin : fbin((uint32_t)ubn, inv);
+  if (grid) {
+    const double inv = grid_inv(I.M, fw);
+    const uint32_t kl = gbin(L, inv, fw), ku = gbin((uint32_t)ubn, inv, fw);
     const bool ok = kl != kNoBin && ku != kNoBin;
     width = ok ? ku - kl : 0u;
     key0 = kl + 1u;
@@ -1224,14 +1236,16 @@ __device__ __noinline__ void block_settle(GInst& I, int kind, int item0, int nit
   GDevGraph& g = *gbl(I.g);
   const int tid = threadIdx.x;
   const uint32_t lb = I.lb, ub = I.ub, M = I.M;
-  // the ring feeds computeST: per distance, or with binary32 weights per bin
-  // of the ST_NUM grid (bins klb..kub hold this step's settled vertices)
+  // the ring feeds computeST: per distance, or per bin of the ST_NUM grid
+  // (binary32 weights, or integer weights beyond the exact window; bins
+  // klb..kub hold this step's settled vertices)
   const bool fw = g.float_w != 0;
-  const double inv = fw ? grid_inv(M) : 0.0;
-  const uint32_t klb = fw ? fbin(lb, inv) : lb;
-  const uint32_t kub = fw ? (ub >= 0x7f800000u ? kNoBin : fbin(ub, inv)) : ub;
-  const bool frec = fw && klb != kNoBin && kub != kNoBin;
-  const uint32_t band = fw ? (frec ? kub - klb + 1u : 0u) : ub - lb;
+  const bool grid = fw || M > kRingMax;
+  const double inv = grid ? grid_inv(M, fw) : 0.0;
+  const uint32_t klb = grid ? gbin(lb, inv, fw) : lb;
+  const uint32_t kub = grid ? gbin(ub, inv, fw) : ub;
+  const bool frec = grid && klb != kNoBin && kub != kNoBin;
+  const uint32_t band = grid ? (frec ? kub - klb + 1u : 0u) : ub - lb;
   const uint32_t nb = band < (uint32_t)kLdsRing ? band : (uint32_t)kLdsRing;
   const int nh = g.num_deg < kLdsHist ? g.num_deg : kLdsHist;
   auto dinfo = gbl(g.dinfo);
@@ -1283,11 +1297,11 @@ __device__ __noinline__ void block_settle(GInst& I, int kind, int item0, int nit
     const int deg = (int)(uint32_t)di[k];
     // only the window [ub - M, ub) is read by the next computeST; the first
     // step's band may be wider, and older values would alias ring slots
-    // (binary32: only the last ring-size bins up to bin(ub) are kept)
+    // (grid: only the last ring-size bins up to bin(ub) are kept)
     uint32_t key = d;
     bool rec = (unsigned long long)d + M >= ub;
-    if (fw) {
-      key = frec ? fbin(d, inv) : 0u;
+    if (grid) {
+      key = frec ? gbin(d, inv, fw) : 0u;
       rec = frec && (unsigned long long)key + ring_mask + 1ull > kub;
     }
     if (rec) {

@@ -81,7 +81,8 @@ def test_rmat14_host_driven_mode():
         assert_same(gpu_dist(g, s, host_driven=True), oracle_dist(wl.edges, s), "host-driven")
 
 
-@pytest.mark.parametrize("name", ["rmat14", "er12", "grid64", "rmat12", "rmat12p1", "rmat12p4"])
+@pytest.mark.parametrize("name", ["rmat14", "er12", "grid64", "rmat12", "rmat12p1", "rmat12p4",
+                                  "rmat12p17", "rmat14p20", "grid64w1000000"])
 def test_schedule_matches_model(name):
     """The per-step <lb, ub, st> and the statistics taken at each step's end
     are determined by the settled set, so the GPU must reproduce the
@@ -136,7 +137,7 @@ def test_prep_long_rows_sorted():
     assert np.array_equal(g.rtow(), H.rtow_table(c.w))
 
 
-@pytest.mark.parametrize("name", ["er16", "grid256", "rmat16"])
+@pytest.mark.parametrize("name", ["er16", "grid256", "rmat16", "grid256w1000000"])
 def test_medium_graphs_bit_exact(name):
     wl = graphgen.workload(name)
     g = sssp.Graph.from_csr(wl.csr)
@@ -145,10 +146,12 @@ def test_medium_graphs_bit_exact(name):
         assert sssp.counters()["flags"] == 0
 
 
-@pytest.mark.parametrize("power", [1, 2, 3, 4, 6, 8, 10])
+@pytest.mark.parametrize("power", [1, 2, 3, 4, 6, 8, 10, 17, 20])
 def test_integer_power_variants_bit_exact(power):
     """The paper's integer-power variant graphs (Eq. 7; power 1 is unit weights,
-    every shortest path tied), with and without the traversal filter."""
+    every shortest path tied), with and without the traversal filter; powers
+    17 and 20 put the largest weight beyond the exact selection-threshold
+    window (the ST_NUM grid)."""
     wl = graphgen.workload("rmat14p%d" % power)
     g = sssp.Graph.from_csr(wl.csr)
     for s in wl.sources(3):

@@ -157,3 +157,21 @@ def test_model_on_integer_power_variants():
     assert ntrav[1] > ntrav[4] > ntrav[8] * 0.9, ntrav
     for p in (8, 10):
         assert 2.5 <= ntrav[p] <= 5.5, ntrav
+
+
+@pytest.mark.parametrize("name", ["rmat12p17", "rmat12p20"])
+def test_weights_beyond_the_exact_window_use_the_grid(name):
+    """Weights above 65536 (Eq. 7 with power 17 and 20): computeST runs on the
+    ST_NUM grid, the model pulls and scans far fewer entries than with the
+    traversal optimisation off, and stays exact."""
+    wl = graphgen.workload(name)
+    c = wl.csr
+    assert int(c.w.max()) > 65536
+    deg = c.degrees()
+    for s in wl.sources(2):
+        ref = native.dijkstra(wl.edges.n, wl.edges.src, wl.edges.dst, wl.edges.w, int(s))
+        on = eic.eic_sssp(c.n, c.rowptr, c.col, c.w, int(s))
+        off = eic.eic_sssp(c.n, c.rowptr, c.col, c.w, int(s), traversal_opt=False)
+        assert np.array_equal(on.dist, ref) and np.array_equal(off.dist, ref)
+        assert on.pulls > 0
+        assert eic.normalised(on, c.n, deg)["nTrav"] < 0.5 * eic.normalised(off, c.n, deg)["nTrav"]

@@ -223,3 +223,54 @@ def test_profit_nondecreasing_between_distances():
         xs = range(L - M, L)
         ps = [H.profit(x, L, Y, S, Sx, M, nnz) for x in xs]
         assert all(b >= a for a, b in zip(ps, ps[1:]))
+
+
+# ------------------------------------------ the grid beyond the exact window
+
+def test_integer_grid_equals_the_exact_window_on_multiples_of_the_bin_width():
+    """With maxW = ST_NUM * c (beyond the exact window) and every distance,
+    gap and L a multiple of c, the grid's bins are exactly the distinct
+    distances, and every term of Eq. 4-6 is a ratio of exact integers, each
+    scaled by c: the grid computeST returns c times the exact-window
+    computeST of the problem divided by c."""
+    from oracle import heuristic as Hm
+    rng = np.random.default_rng(4242)
+    c = 100
+    Mi = Hm.ST_NUM          # the scaled-down problem (exact window)
+    M = Mi * c              # 102400 > ST_WINDOW_MAX
+    assert M > Hm.ST_WINDOW_MAX
+    hits = 0
+    for trial in range(400):
+        Li = int(rng.integers(1, 6 * Mi))
+        gap_i = int(rng.integers(1, Mi))
+        gap_lb_i = int(rng.integers(1, Mi))
+        nnz = int(rng.integers(1000, 100000))
+        S = int(rng.integers(0, nnz // 2)) if trial % 2 else int(rng.integers(0, 3000))
+        k = int(rng.integers(0, 200))
+        settled = rng.integers(max(0, Li - Mi), Li, size=k)
+        degs = rng.integers(1, 500, size=k)
+        wv, inv = np.unique(settled, return_inverse=True)
+        wm = np.zeros(wv.shape[0], np.int64)
+        np.add.at(wm, inv, degs)
+        want = Hm.compute_st(Li, gap_i, gap_lb_i, S, nnz, Mi, wv, wm)
+        got = Hm.compute_st(Li * c, gap_i * c, gap_lb_i * c, S, nnz, M, wv * c, wm)
+        assert got == want * c, (trial, Li, want, got)
+        hits += want < Li
+    assert hits > 100
+
+
+def test_integer_grid_threshold_is_the_first_value_of_its_bin():
+    from oracle import heuristic as Hm
+    M = 3 * 65536 + 7
+    inv = float(Hm.ST_NUM) / float(M)
+    rng = np.random.default_rng(7)
+    for _ in range(200):
+        L = int(rng.integers(M // 2, 4 * M))
+        settled = np.unique(rng.integers(max(0, L - M), L, size=300))
+        degs = rng.integers(1, 400, size=settled.shape[0])
+        st = Hm.compute_st(L, M // 50, M // 40, 2000, 10 ** 6, M, settled, degs)
+        assert max(0, L - M) <= st <= L
+        if st < L:
+            k = Hm.grid_bin(st, inv, False)
+            assert st == 0 or Hm.grid_bin(st - 1, inv, False) < k
+            assert np.any((settled >= st) & (np.floor(settled * inv) == k))
