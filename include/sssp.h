@@ -135,9 +135,9 @@ sssp_graph* sssp_graph_create(int32_t n, const int32_t* rowptr, const int32_t* c
  * and NaN are rejected). Distances are then binary32 bit patterns too: each
  * is the smallest, over all paths, of the path's weights summed in order in
  * binary32 (round to nearest), the value the textbook Dijkstra computes in
- * binary32; UINT32_MAX still marks unreachable vertices. Such graphs run the
- * dynamic stepping (Eq. 1-3) with the selection threshold at lb: computeST's
- * window (Eq. 4-6) is kept for integer distances only. */
+ * binary32; UINT32_MAX still marks unreachable vertices. computeST (Eq. 4-6)
+ * then scores the points of a grid of 1024 bins per largest weight (ST_NUM,
+ * Section 4.1), as it does for integer weights above 65536. */
 #define SSSP_CREATE_FLOAT_WEIGHTS 2
 /* As sssp_graph_create, with flags (SSSP_CREATE_*). Skipping the symmetry
  * check leaves correctness to the caller: the pull (Section 3.2) relies on it. */
