@@ -208,6 +208,21 @@ sssp_status sssp_solve_multi(const sssp_graph* const* gs, const int32_t* sources
                              uint32_t* const* dist_outs, const sssp_options* opt,
                              hipStream_t stream);
 
+/* As sssp_solve_multi, each pair optionally a point-to-point query and
+ * optionally with its shortest-path tree (the outputs of sssp_solve_p2p and
+ * sssp_solve_tree, Sections 2.1 and 5). targets: NULL, or a host array of k
+ * entries, -1 for a full solve, else the target vertex of pair i (that
+ * solve stops once its target is settled; its entries not above the
+ * target's distance are exact, the others upper bounds). parent_outs: NULL,
+ * or a host array of k entries, each NULL or device memory of gs[i]'s n
+ * int32 (parent[s] = s, -1 where the distance is UINT32_MAX; the parent
+ * edge of every other vertex is tight for its returned distance). Argument
+ * errors as for sssp_solve_multi, plus a target outside [-1, n). */
+sssp_status sssp_solve_multi_ex(const sssp_graph* const* gs, const int32_t* sources,
+                                const int32_t* targets, int32_t k, uint32_t* const* dist_outs,
+                                int32_t* const* parent_outs, const sssp_options* opt,
+                                hipStream_t stream);
+
 /* Counters of the last solve enqueued on `stream` (for a batch: summed over
  * its instances). Synchronises the stream. */
 sssp_status sssp_get_counters(hipStream_t stream, sssp_counters* out);
@@ -241,6 +256,18 @@ sssp_plan* sssp_plan_create(const sssp_graph* const* gs, int32_t k, uint32_t* co
  * gs[i]) on `stream`. Waits for the plan's previous run to finish first (its
  * instance images are re-staged). Asynchronous otherwise. */
 sssp_status sssp_plan_run(sssp_plan* p, const int32_t* sources, hipStream_t stream);
+
+/* As sssp_plan_create, with a shortest-path tree per instance: parent_outs
+ * NULL, or k entries, each NULL or device memory of gs[i]'s n int32 written
+ * at every run (as in sssp_solve_multi_ex). */
+sssp_plan* sssp_plan_create_ex(const sssp_graph* const* gs, int32_t k, uint32_t* const* dist_outs,
+                               int32_t* const* parent_outs, const sssp_options* opt, hipStream_t stream);
+
+/* As sssp_plan_run, each instance optionally a point-to-point query:
+ * targets NULL, or k entries, -1 for a full solve (as in
+ * sssp_solve_multi_ex). */
+sssp_status sssp_plan_run_ex(sssp_plan* p, const int32_t* sources, const int32_t* targets,
+                             hipStream_t stream);
 
 /* Counters of the plan's last run, summed over its instances (waits for it). */
 sssp_status sssp_plan_counters(sssp_plan* p, sssp_counters* out);
@@ -326,6 +353,14 @@ int64_t sssp_server_query_bytes(sssp_server* s, int32_t graph_id);
  * exceeds the budget; SSSP_E_BUSY if the queue is full. Thread-safe. */
 sssp_status sssp_server_submit(sssp_server* s, int32_t graph_id, int32_t source, uint32_t* dist_out,
                                int64_t* ticket);
+
+/* As sssp_server_submit, optionally a point-to-point query (target >= 0;
+ * -1 for a full solve) and optionally with its shortest-path tree into
+ * parent_out (device, n int32, caller-owned, or NULL); outputs as in
+ * sssp_solve_multi_ex. A tree query counts 12 more bytes per vertex against
+ * the budget (its output and the solve's tree words). */
+sssp_status sssp_server_submit_ex(sssp_server* s, int32_t graph_id, int32_t source, int32_t target,
+                                  uint32_t* dist_out, int32_t* parent_out, int64_t* ticket);
 
 /* *done = 1 once the query is finished (its distances are then complete in
  * device memory and visible to any stream). */

@@ -175,8 +175,17 @@ class Graph:
         return out
 
 
-def solve_multi(graphs: Sequence[Graph], sources: Sequence[int], outs=None, stream=None, **opts):
-    """Independent (graph, source) pairs in one launch; returns the list of distance tensors."""
+def _parent_array(parents, k):
+    """ctypes array of k int32 output pointers (None entries stay NULL)."""
+    return (ctypes.c_void_p * k)(*[(_ptr(p) if p is not None else None) for p in parents])
+
+
+def solve_multi(graphs: Sequence[Graph], sources: Sequence[int], outs=None, stream=None,
+                targets: Optional[Sequence[int]] = None, trees: bool = False, **opts):
+    """Independent (graph, source) pairs in one launch; returns the list of
+    distance tensors. targets: None, or one per pair (-1: full solve, else a
+    point-to-point query that stops once that vertex is settled). trees: also
+    return a shortest-path tree per pair, as (outs, parents)."""
     k = len(graphs)
     if outs is None:
         outs = [_empty_dist(g.n) for g in graphs]
@@ -184,10 +193,24 @@ def solve_multi(graphs: Sequence[Graph], sources: Sequence[int], outs=None, stre
     srcs = np.ascontiguousarray(np.asarray(sources, dtype=np.int32))
     ptrs = (ctypes.c_void_p * k)(*[_ptr(o) for o in outs])
     o = _options(**opts)
-    _lib.check(_lib.sssp_solve_multi(ctypes.cast(hs, ctypes.c_void_p), srcs.ctypes.data, k,
-                                     ctypes.cast(ptrs, ctypes.c_void_p), ctypes.byref(o),
-                                     _stream_handle(stream)))
-    return outs
+    if targets is None and not trees:
+        _lib.check(_lib.sssp_solve_multi(ctypes.cast(hs, ctypes.c_void_p), srcs.ctypes.data, k,
+                                         ctypes.cast(ptrs, ctypes.c_void_p), ctypes.byref(o),
+                                         _stream_handle(stream)))
+        return outs
+    tg = None if targets is None else np.ascontiguousarray(np.asarray(targets, dtype=np.int32))
+    parents = None
+    par = None
+    if trees:
+        torch = _torch()
+        parents = [torch.empty(g.n, dtype=torch.int32, device="cuda") for g in graphs]
+        par = _parent_array(parents, k)
+    _lib.check(_lib.sssp_solve_multi_ex(ctypes.cast(hs, ctypes.c_void_p), srcs.ctypes.data,
+                                        None if tg is None else tg.ctypes.data, k,
+                                        ctypes.cast(ptrs, ctypes.c_void_p),
+                                        None if par is None else ctypes.cast(par, ctypes.c_void_p),
+                                        ctypes.byref(o), _stream_handle(stream)))
+    return (outs, parents) if trees else outs
 
 
 def _counters_dict(c) -> dict:
@@ -199,25 +222,41 @@ class Plan:
     replayed with new sources: k sources on one graph, or one source on each
     of k graphs. `outs` are the device tensors every run writes."""
 
-    def __init__(self, graphs: Sequence[Graph], outs, stream=None, **opts):
+    def __init__(self, graphs: Sequence[Graph], outs, stream=None, parents=None, **opts):
         self.k = len(graphs)
         self.graphs = list(graphs)
         self.outs = list(outs)
+        self.parents = None if parents is None else list(parents)
         hs = (ctypes.c_void_p * self.k)(*[g._h for g in graphs])
         ptrs = (ctypes.c_void_p * self.k)(*[_ptr(o) for o in self.outs])
         o = _options(**opts)
-        h = _lib.sssp_plan_create(ctypes.cast(hs, ctypes.c_void_p), self.k,
-                                  ctypes.cast(ptrs, ctypes.c_void_p), ctypes.byref(o),
-                                  _stream_handle(stream))
+        if self.parents is None:
+            h = _lib.sssp_plan_create(ctypes.cast(hs, ctypes.c_void_p), self.k,
+                                      ctypes.cast(ptrs, ctypes.c_void_p), ctypes.byref(o),
+                                      _stream_handle(stream))
+        else:
+            par = _parent_array(self.parents, self.k)
+            h = _lib.sssp_plan_create_ex(ctypes.cast(hs, ctypes.c_void_p), self.k,
+                                         ctypes.cast(ptrs, ctypes.c_void_p), ctypes.cast(par, ctypes.c_void_p),
+                                         ctypes.byref(o), _stream_handle(stream))
         if not h:
             _lib.check(_lib.sssp_last_error() or -6)
         self._h = h
 
-    def run(self, sources: Sequence[int], stream=None):
+    def run(self, sources: Sequence[int], stream=None, targets: Optional[Sequence[int]] = None):
+        """Replay for new sources (and, optionally, point-to-point targets,
+        -1 for a full solve); returns the distance tensors."""
         srcs = np.ascontiguousarray(np.asarray(sources, dtype=np.int32))
         if srcs.shape[0] != self.k:
             raise ValueError("need %d sources" % self.k)
-        _lib.check(_lib.sssp_plan_run(self._h, srcs.ctypes.data, _stream_handle(stream)))
+        if targets is None:
+            _lib.check(_lib.sssp_plan_run(self._h, srcs.ctypes.data, _stream_handle(stream)))
+        else:
+            tg = np.ascontiguousarray(np.asarray(targets, dtype=np.int32))
+            if tg.shape[0] != self.k:
+                raise ValueError("need %d targets" % self.k)
+            _lib.check(_lib.sssp_plan_run_ex(self._h, srcs.ctypes.data, tg.ctypes.data,
+                                             _stream_handle(stream)))
         return self.outs
 
     def counters(self) -> dict:
@@ -288,10 +327,16 @@ class Server:
             _lib.check(int(b))
         return int(b)
 
-    def submit(self, graph_id: int, source: int, out) -> int:
+    def submit(self, graph_id: int, source: int, out, target: int = -1, parent=None) -> int:
+        """Queue a query; target >= 0 makes it point-to-point, parent (an int32
+        cuda tensor of n entries) asks for its shortest-path tree."""
         t = ctypes.c_int64(0)
-        _lib.check(_lib.sssp_server_submit(self._h, int(graph_id), int(source), _ptr(out),
-                                           ctypes.byref(t)))
+        if target == -1 and parent is None:
+            _lib.check(_lib.sssp_server_submit(self._h, int(graph_id), int(source), _ptr(out),
+                                               ctypes.byref(t)))
+        else:
+            _lib.check(_lib.sssp_server_submit_ex(self._h, int(graph_id), int(source), int(target), _ptr(out),
+                                                  None if parent is None else _ptr(parent), ctypes.byref(t)))
         return t.value
 
     def poll(self, ticket: int) -> bool:

@@ -96,6 +96,7 @@ sssp_solve_tree = _sig("sssp_solve_tree", i32, vp, i32, vp, vp, ctypes.POINTER(O
 sssp_solve_p2p = _sig("sssp_solve_p2p", i32, vp, i32, i32, vp, ctypes.POINTER(Options), vp)
 sssp_solve_batch = _sig("sssp_solve_batch", i32, vp, vp, i32, vp, vp)
 sssp_solve_multi = _sig("sssp_solve_multi", i32, vp, vp, i32, vp, ctypes.POINTER(Options), vp)
+sssp_solve_multi_ex = _sig("sssp_solve_multi_ex", i32, vp, vp, vp, i32, vp, vp, ctypes.POINTER(Options), vp)
 sssp_get_counters = _sig("sssp_get_counters", i32, vp, ctypes.POINTER(Counters))
 sssp_get_schedule = _sig("sssp_get_schedule", i32, vp, ctypes.POINTER(Step), i32, i32p)
 sssp_engine_times = _sig("sssp_engine_times", i32, vp, ctypes.POINTER(ctypes.c_float), i32, i32p)
@@ -104,6 +105,8 @@ sssp_debug_get_tick_log = _sig("sssp_debug_get_tick_log", i32, vp, vp, i32, i32p
                                ctypes.POINTER(ctypes.c_uint64))
 sssp_plan_create = _sig("sssp_plan_create", vp, vp, i32, vp, ctypes.POINTER(Options), vp)
 sssp_plan_run = _sig("sssp_plan_run", i32, vp, vp, vp)
+sssp_plan_create_ex = _sig("sssp_plan_create_ex", vp, vp, i32, vp, vp, ctypes.POINTER(Options), vp)
+sssp_plan_run_ex = _sig("sssp_plan_run_ex", i32, vp, vp, vp, vp)
 sssp_plan_counters = _sig("sssp_plan_counters", i32, vp, ctypes.POINTER(Counters))
 sssp_plan_destroy = _sig("sssp_plan_destroy", i32, vp)
 sssp_autotune = _sig("sssp_autotune", i32, vp, vp, i32, i32, i32, ctypes.POINTER(Options),
@@ -112,6 +115,8 @@ sssp_server_create = _sig("sssp_server_create", vp, ctypes.POINTER(ServerConfig)
 sssp_server_add_graph = _sig("sssp_server_add_graph", i32, vp, vp)
 sssp_server_query_bytes = _sig("sssp_server_query_bytes", ctypes.c_int64, vp, i32)
 sssp_server_submit = _sig("sssp_server_submit", i32, vp, i32, i32, vp, ctypes.POINTER(ctypes.c_int64))
+sssp_server_submit_ex = _sig("sssp_server_submit_ex", i32, vp, i32, i32, i32, vp, vp,
+                             ctypes.POINTER(ctypes.c_int64))
 sssp_server_poll = _sig("sssp_server_poll", i32, vp, ctypes.c_int64, i32p)
 sssp_server_wait = _sig("sssp_server_wait", i32, vp, ctypes.c_int64)
 sssp_server_request_info = _sig("sssp_server_request_info", i32, vp, ctypes.c_int64,

@@ -503,7 +503,7 @@ sssp_status collect_counters(Workspace& w, int i0, int k, sssp_counters* out) {
   flags |= hg.error;
   out->flags = flags;
   if (flags & FLAG_OVERFLOW) return fail(SSSP_E_DIST_OVERFLOW, "a distance does not fit below UINT32_MAX");
-  if (flags & (FLAG_CAPACITY | FLAG_MASS | FLAG_TIMEOUT | FLAG_TICKS))
+  if (flags & (FLAG_CAPACITY | FLAG_MASS | FLAG_TIMEOUT | FLAG_TICKS | FLAG_TREE))
     return fail(SSSP_E_DEVICE, "internal engine condition, flags = " + std::to_string(flags));
   return ok();
 }
@@ -678,6 +678,23 @@ sssp_status sssp_solve_multi(const sssp_graph* const* gs, const int32_t* sources
   Opts o;
   if (!parse_opts(opt, &o, &err)) return fail(SSSP_E_INVAL, err);
   return run_instances(gs, sources, k, dist_outs, o, stream);
+}
+
+sssp_status sssp_solve_multi_ex(const sssp_graph* const* gs, const int32_t* sources, const int32_t* targets,
+                                int32_t k, uint32_t* const* dist_outs, int32_t* const* parent_outs,
+                                const sssp_options* opt, hipStream_t stream) {
+  std::string err;
+  if (k < 1 || !gs || !sources || !dist_outs) return fail(SSSP_E_INVAL, "k >= 1 and arrays required");
+  for (int i = 0; i < k; ++i) {
+    if (!check_graph(gs[i], &err)) return fail(SSSP_E_INVAL, err);
+    if (sources[i] < 0 || sources[i] >= gs[i]->gh.h.n) return fail(SSSP_E_INVAL, "source out of range");
+    if (targets && (targets[i] < -1 || targets[i] >= gs[i]->gh.h.n))
+      return fail(SSSP_E_INVAL, "target out of range (-1: none)");
+    if (!dist_outs[i]) return fail(SSSP_E_INVAL, "dist_outs entry is NULL");
+  }
+  Opts o;
+  if (!parse_opts(opt, &o, &err)) return fail(SSSP_E_INVAL, err);
+  return run_instances(gs, sources, k, dist_outs, o, stream, parent_outs, targets);
 }
 
 sssp_status sssp_get_counters(hipStream_t stream, sssp_counters* out) {

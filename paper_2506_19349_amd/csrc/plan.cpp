@@ -41,7 +41,8 @@ void plan_free(sssp_plan* p) {
   delete p;
 }
 
-sssp_status plan_build(sssp_plan* p, uint32_t* const* dist_outs, hipStream_t stream) {
+sssp_status plan_build(sssp_plan* p, uint32_t* const* dist_outs, int32_t* const* parent_outs,
+                       hipStream_t stream) {
   Workspace& w = p->w;
   std::string err;
   if (!ws_setup(w, stream, &err)) return fail(SSSP_E_DEVICE, err);
@@ -52,6 +53,7 @@ sssp_status plan_build(sssp_plan* p, uint32_t* const* dist_outs, hipStream_t str
     const DevGraph& g = p->gs[(size_t)i]->gh.h;
     max_n = std::max<long long>(max_n, g.n);
     hipError_t e = ensure_slot(w.slots[(size_t)i], needs_for(g, w.cus * w.occ * (kBlock / kWave)));
+    if (e == hipSuccess && parent_outs && parent_outs[i]) e = ensure_best(w.slots[(size_t)i], g.n);
     if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
       return fail(SSSP_E_NOMEM, "workspace allocation failed");
     HIP_TRY(e);
@@ -73,7 +75,9 @@ sssp_status plan_build(sssp_plan* p, uint32_t* const* dist_outs, hipStream_t str
   hG->insts = w.dInst;
   hG->sel_list = nullptr;
   hG->n_sel = -1;
-  for (int i = 0; i < k; ++i) fill_inst(p->hI[i], w.slots[(size_t)i], p->gs[(size_t)i], 0, dist_outs[i], p->o);
+  for (int i = 0; i < k; ++i)
+    fill_inst(p->hI[i], w.slots[(size_t)i], p->gs[(size_t)i], 0, dist_outs[i], p->o,
+              parent_outs ? parent_outs[i] : nullptr);
 
   long long total_n = 0;
   for (int i = 0; i < k; ++i) total_n += p->gs[(size_t)i]->gh.h.n;
@@ -97,6 +101,11 @@ extern "C" {
 
 sssp_plan* sssp_plan_create(const sssp_graph* const* gs, int32_t k, uint32_t* const* dist_outs,
                             const sssp_options* opt, hipStream_t stream) {
+  return sssp_plan_create_ex(gs, k, dist_outs, nullptr, opt, stream);
+}
+
+sssp_plan* sssp_plan_create_ex(const sssp_graph* const* gs, int32_t k, uint32_t* const* dist_outs,
+                               int32_t* const* parent_outs, const sssp_options* opt, hipStream_t stream) {
   std::string err;
   if (k < 1 || !gs || !dist_outs) {
     fail(SSSP_E_INVAL, "k >= 1, graphs and dist_outs required");
@@ -130,7 +139,7 @@ sssp_plan* sssp_plan_create(const sssp_graph* const* gs, int32_t k, uint32_t* co
   p->gs.assign(gs, gs + k);
   p->o = o;
   (void)hipGetDevice(&p->device);
-  sssp_status st = plan_build(p, dist_outs, stream);
+  sssp_status st = plan_build(p, dist_outs, parent_outs, stream);
   if (st != SSSP_OK) {
     std::string m = sssp_last_error_message();
     plan_free(p);
@@ -143,15 +152,25 @@ sssp_plan* sssp_plan_create(const sssp_graph* const* gs, int32_t k, uint32_t* co
 }
 
 sssp_status sssp_plan_run(sssp_plan* p, const int32_t* sources, hipStream_t stream) {
+  return sssp_plan_run_ex(p, sources, nullptr, stream);
+}
+
+sssp_status sssp_plan_run_ex(sssp_plan* p, const int32_t* sources, const int32_t* targets, hipStream_t stream) {
   if (!p || !sources) return fail(SSSP_E_INVAL, "plan and sources required");
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev != p->device)
     return fail(SSSP_E_INVAL, "the plan lives on another device than the current one");
-  for (int i = 0; i < p->k; ++i)
-    if (sources[i] < 0 || sources[i] >= p->gs[(size_t)i]->gh.h.n) return fail(SSSP_E_INVAL, "source out of range");
+  for (int i = 0; i < p->k; ++i) {
+    const int32_t n = p->gs[(size_t)i]->gh.h.n;
+    if (sources[i] < 0 || sources[i] >= n) return fail(SSSP_E_INVAL, "source out of range");
+    if (targets && (targets[i] < -1 || targets[i] >= n)) return fail(SSSP_E_INVAL, "target out of range (-1: none)");
+  }
   // the previous replay's copy nodes read the pinned images: wait for it
   if (p->pending) HIP_TRY(hipEventSynchronize(p->done));
-  for (int i = 0; i < p->k; ++i) p->hI[i].source = sources[i];
+  for (int i = 0; i < p->k; ++i) {
+    p->hI[i].source = sources[i];
+    p->hI[i].target = targets ? targets[i] : -1;
+  }
   HIP_TRY(hipGraphLaunch(p->exec, stream));
   HIP_TRY(hipEventRecord(p->done, stream));
   p->pending = true;

@@ -35,7 +35,9 @@ enum ReqState : int32_t { RS_DONE = 0, RS_QUEUED = 1, RS_RUNNING = 2 };
 
 struct Request {
   int32_t graph = 0, source = 0;
+  int32_t target = -1;          // point-to-point target, -1 for a full solve
   uint32_t* dist = nullptr;
+  int32_t* parent = nullptr;    // shortest-path tree output, or NULL
   int32_t state = RS_QUEUED;
   int32_t status = SSSP_OK;
   int32_t slot = -1;
@@ -64,7 +66,10 @@ struct sssp_server {
   std::vector<size_t> slot_bytes;   // device bytes of the slot's buffers
   std::vector<const sssp_graph*> slot_graph;
   std::vector<int32_t> slot_source;
+  std::vector<int32_t> slot_target;
   std::vector<uint32_t*> slot_dist;
+  std::vector<int32_t*> slot_parent;
+  std::vector<uint64_t> slot_out;   // bytes of the running query's outputs
   uint64_t allocated = 0, peak_allocated = 0, out_active = 0, peak_in_use = 0;
   int active = 0, peak_active = 0;
   int64_t next_ticket = 1;
@@ -104,7 +109,8 @@ void admit(sssp_server* S, std::vector<int>* fresh) {
     Request& r = S->reqs[t];
     const DevGraph& g = S->graphs[(size_t)r.graph]->gh.h;
     const Needs nd = needs_for(g, maxw_of(w));
-    const uint64_t out_b = sizeof(uint32_t) * (uint64_t)g.n;
+    // the caller's outputs count against the budget while the query runs
+    const uint64_t out_b = (r.parent ? 2 : 1) * sizeof(uint32_t) * (uint64_t)g.n;
     int pick = -1;
     size_t pick_bytes = 0;
     for (int i = 0; i < S->max_batch; ++i) {
@@ -172,10 +178,38 @@ void admit(sssp_server* S, std::vector<int>* fresh) {
       S->allocated += want;
       S->peak_allocated = std::max(S->peak_allocated, S->allocated);
     }
+    if (r.parent && w.slots[(size_t)pick].best_cap < g.n) {
+      // a tree query also needs the slot's (distance, source) words
+      const uint64_t extra = sizeof(uint64_t) * (uint64_t)g.n;
+      if (S->allocated + extra + S->out_active + out_b > S->budget) {
+        for (int i = 0; i < S->max_batch; ++i) {
+          if (i == pick || S->slot_req[(size_t)i] >= 0 || S->slot_bytes[(size_t)i] == 0) continue;
+          w.slots[(size_t)i].release();
+          S->allocated -= S->slot_bytes[(size_t)i];
+          S->slot_bytes[(size_t)i] = 0;
+        }
+        if (S->allocated + extra + S->out_active + out_b > S->budget) break;
+      }
+      if (ensure_best(w.slots[(size_t)pick], g.n) != hipSuccess) {
+        (void)hipGetLastError();
+        r.state = RS_DONE;
+        r.status = SSSP_E_NOMEM;
+        r.t_done = S->now_us();
+        S->queue.pop_front();
+        S->completed += 1;
+        continue;
+      }
+      S->slot_bytes[(size_t)pick] += extra;
+      S->allocated += extra;
+      S->peak_allocated = std::max(S->peak_allocated, S->allocated);
+    }
     S->slot_req[(size_t)pick] = t;
     S->slot_graph[(size_t)pick] = S->graphs[(size_t)r.graph];
     S->slot_source[(size_t)pick] = r.source;
+    S->slot_target[(size_t)pick] = r.target;
     S->slot_dist[(size_t)pick] = r.dist;
+    S->slot_parent[(size_t)pick] = r.parent;
+    S->slot_out[(size_t)pick] = out_b;
     r.slot = pick;
     r.state = RS_RUNNING;
     r.t_admit = S->now_us();
@@ -198,7 +232,9 @@ sssp_status cycle(sssp_server* S, const std::vector<int>& fresh, std::vector<int
   for (size_t j = 0; j < fresh.size(); ++j) {
     const int i = fresh[j];
     const sssp_graph* g = S->slot_graph[(size_t)i];
-    fill_inst(S->hI[i], w.slots[(size_t)i], g, S->slot_source[(size_t)i], S->slot_dist[(size_t)i], S->o);
+    fill_inst(S->hI[i], w.slots[(size_t)i], g, S->slot_source[(size_t)i], S->slot_dist[(size_t)i], S->o,
+              S->slot_parent[(size_t)i]);
+    S->hI[i].target = S->slot_target[(size_t)i];
     max_n = std::max<long long>(max_n, g->gh.h.n);
     HIP_TRY(hipMemcpyAsync(w.dInst + i, S->hI + i, sizeof(Inst), hipMemcpyHostToDevice, st));
     S->h_sel[j] = i;
@@ -306,12 +342,12 @@ void pump_main(sssp_server* S) {
         uint32_t flags = S->h_status[2 * i + 1];
         if (st != SSSP_OK) r.status = st;
         else if (flags & FLAG_OVERFLOW) r.status = SSSP_E_DIST_OVERFLOW;
-        else if (flags & (FLAG_CAPACITY | FLAG_MASS | FLAG_TIMEOUT | FLAG_TICKS)) r.status = SSSP_E_DEVICE;
+        else if (flags & (FLAG_CAPACITY | FLAG_MASS | FLAG_TIMEOUT | FLAG_TICKS | FLAG_TREE)) r.status = SSSP_E_DEVICE;
         else r.status = SSSP_OK;
         r.state = RS_DONE;
         r.t_done = t;
         S->slot_req[(size_t)i] = -1;
-        S->out_active -= sizeof(uint32_t) * (uint64_t)S->slot_graph[(size_t)i]->gh.h.n;
+        S->out_active -= S->slot_out[(size_t)i];
         S->active -= 1;
         S->completed += 1;
       }
@@ -342,7 +378,10 @@ sssp_status server_setup(sssp_server* S) {
   S->slot_bytes.assign((size_t)S->max_batch, 0);
   S->slot_graph.assign((size_t)S->max_batch, nullptr);
   S->slot_source.assign((size_t)S->max_batch, 0);
+  S->slot_target.assign((size_t)S->max_batch, -1);
   S->slot_dist.assign((size_t)S->max_batch, nullptr);
+  S->slot_parent.assign((size_t)S->max_batch, nullptr);
+  S->slot_out.assign((size_t)S->max_batch, 0);
   HIP_TRY(hipMalloc(&S->d_sel, sizeof(int32_t) * (size_t)S->max_batch));
   HIP_TRY(hipMalloc(&S->d_status, sizeof(uint32_t) * 2 * (size_t)S->max_batch));
   const size_t bytes = sizeof(Globals) + sizeof(Inst) * (size_t)S->max_batch +
@@ -451,6 +490,11 @@ int64_t sssp_server_query_bytes(sssp_server* S, int32_t graph_id) {
 
 sssp_status sssp_server_submit(sssp_server* S, int32_t graph_id, int32_t source, uint32_t* dist_out,
                                int64_t* ticket) {
+  return sssp_server_submit_ex(S, graph_id, source, -1, dist_out, nullptr, ticket);
+}
+
+sssp_status sssp_server_submit_ex(sssp_server* S, int32_t graph_id, int32_t source, int32_t target,
+                                  uint32_t* dist_out, int32_t* parent_out, int64_t* ticket) {
   if (!S || !dist_out || !ticket) return fail(SSSP_E_INVAL, "server, dist_out and ticket required");
   std::unique_lock<std::mutex> lk(S->mu);
   if (S->dead != SSSP_OK) return fail(S->dead, "server stopped after a device failure: " + S->dead_msg);
@@ -458,13 +502,18 @@ sssp_status sssp_server_submit(sssp_server* S, int32_t graph_id, int32_t source,
   if (graph_id < 0 || graph_id >= (int32_t)S->graphs.size()) return fail(SSSP_E_INVAL, "unknown graph id");
   const DevGraph& g = S->graphs[(size_t)graph_id]->gh.h;
   if (source < 0 || source >= g.n) return fail(SSSP_E_INVAL, "source out of range");
-  const uint64_t need = needs_bytes(needs_for(g, maxw_of(S->w))) + sizeof(uint32_t) * (uint64_t)g.n;
+  if (target < -1 || target >= g.n) return fail(SSSP_E_INVAL, "target out of range (-1: none)");
+  // workspace, the distance output and, for a tree, its output and 8-byte words
+  const uint64_t need = needs_bytes(needs_for(g, maxw_of(S->w))) +
+                        (parent_out ? 16 : 4) * (uint64_t)g.n;
   if (need > S->budget) return fail(SSSP_E_RANGE, "the query needs more device memory than the server's budget");
   if ((int)S->queue.size() >= S->max_pending) return fail(SSSP_E_BUSY, "admission queue is full");
   Request r;
   r.graph = graph_id;
   r.source = source;
+  r.target = target;
   r.dist = dist_out;
+  r.parent = parent_out;
   r.t_submit = S->now_us();
   const int64_t t = S->next_ticket++;
   S->reqs[t] = r;
