@@ -47,6 +47,22 @@ ENGINE_SOURCES = [os.path.join(ROOT, "paper_2506_19349_amd", "csrc", f)
                   for f in ("engine.hip", "engine.h")]
 
 
+def host_info(torch) -> dict:
+    """The machine the numbers come from: host CPU model and thread count (the
+    oracle's baselines run there) and the GPU's name."""
+    cpu = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    cpu = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": cpu, "nproc": os.cpu_count(),
+            "gpu": torch.cuda.get_device_name(0) if torch.cuda.is_available() else ""}
+
+
 def engine_source_hash() -> str:
     import hashlib
     h = hashlib.sha256()
@@ -565,6 +581,7 @@ def main():
         "weight_variants": variants,
         "prep_s": round(prep_s, 4),
         "counters": counters,
+        "host": host_info(torch),
     }
     print(json.dumps(line), flush=True)
 
