@@ -43,6 +43,8 @@ VALUE_SETS = {
     "decimal": [0.1, 0.2, 0.7, 1e-3],
     "with_zero": [0.0, 0.3, 0.33333334],
     "wide": [16777216.0, 1.0, 3.0, 0.5],
+    "tiny": [1e-30, 3e-30, 1e-29],
+    "extreme": [1e30, 1.0, 1e-30],
 }
 
 
