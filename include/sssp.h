@@ -1,8 +1,8 @@
 /*
  * sssp.h -- C ABI of an MI355X (gfx950) engine for single-source shortest
- * paths on undirected graphs with non-negative integer weights, following
- * Yu, Wang and Luo, "A Heuristic Algorithm for Shortest Path Search"
- * (arXiv 2506.19349).
+ * paths on undirected graphs with non-negative integer (or, on request,
+ * binary32) weights, following Yu, Wang and Luo, "A Heuristic Algorithm for
+ * Shortest Path Search" (arXiv 2506.19349).
  *
  * What is computed (the paper's problem statement, Section 2): for a source s,
  * dist[v] is the length of the shortest s-v path, dist[s] = 0, and a vertex
@@ -10,7 +10,8 @@
  * exactly these values; its heuristics (dynamic stepping, Section 3.1, and
  * traversal optimisation, Section 3.2, driving the Algorithm of Section 3.3)
  * only decide which relaxations run together. The predecessor array of
- * Section 2 is not produced.
+ * Section 2 comes with the tree entry points (sssp_solve_tree and the _ex
+ * forms of the batched, replayed and served solves).
  *
  * Conventions for every call:
  *  - Graphs are symmetric CSR: rowptr[n+1] (int32, rowptr[0] = 0,

@@ -45,6 +45,7 @@ VALUE_SETS = {
     "wide": [16777216.0, 1.0, 3.0, 0.5],
     "tiny": [1e-30, 3e-30, 1e-29],
     "extreme": [1e30, 1.0, 1e-30],
+    "all_zero": [0.0],
 }
 
 
