@@ -36,7 +36,8 @@ def assert_bits(got, ref, what):
 
 def test_tiny_fuzz_every_source():
     cases = 0
-    sets = ([0.5, 0.25, 1.0], [0.1, 0.2, 0.7, 1e-3], [0.0, 0.3, 0.3333333], [16777216.0, 1.0, 3.0])
+    sets = ([0.5, 0.25, 1.0], [0.1, 0.2, 0.7, 1e-3], [0.0, 0.3, 0.3333333], [16777216.0, 1.0, 3.0],
+            [1e-30, 3e-30, 1e-29], [1e30, 1.0, 1e-30], [0.0])
     for n in range(1, 10):
         for m in (0, n, 3 * n):
             for k, vals in enumerate(sets):
@@ -134,3 +135,25 @@ def test_invalid_real_weights_are_rejected(bad):
     el = graphgen.from_arrays(2, [0], [1], np.array([bad], np.float32).view(np.uint32))
     with pytest.raises(sssp.SSSPError):
         sssp.Graph.from_csr(graphgen.to_csr(el), float_weights=True)
+
+
+def test_schedule_matches_the_f32_model_tiny_fuzz():
+    sets = ([0.5, 0.25, 1.0], [0.1, 0.2, 0.7, 1e-3], [1e-30, 3e-30, 1e-29], [1e30, 1.0, 1e-30], [0.0])
+    cases = 0
+    for n in range(2, 10):
+        for m in (n, 3 * n):
+            for k, vals in enumerate(sets):
+                el = f32_edges(small.tiny_random(n, m, [1], seed=71 * n + m + k), vals, seed=n * 31 + m + k)
+                c = graphgen.to_csr(el)
+                g = sssp.Graph.from_csr(c, float_weights=True)
+                for s in range(n):
+                    ref = eic.eic_sssp_f32(c.n, c.rowptr, c.col, c.w, s)
+                    steps = [b for b in ref.steps if not (b.lb == 0 and b.ub == INF)]
+                    g.solve(s)
+                    got = sssp.schedule()
+                    assert len(got) == len(steps), (n, m, k, s)
+                    for a, b in zip(got, steps):
+                        assert (a["lb"], a["ub"], a["st"]) == (b.lb, b.ub, b.st), (n, m, k, s, a, b)
+                    cases += 1
+                g.close()
+    assert cases > 150

@@ -151,3 +151,57 @@ def test_server_tree_and_point_to_point_queries():
     srv.close()
     for g in gs:
         g.close()
+
+
+def test_one_launch_mixing_weight_kinds_trees_and_targets():
+    """Instances of one launch differ in weight kind (integer with the exact
+    window, integer beyond it on the grid, binary32), in tree output and in
+    point-to-point target; each must equal its own oracle."""
+    names = ["rmat12", "rmat12f", "rmat12p20", "rmat12c5", "grid64w1000000", "er12"]
+    wls = [graphgen.workload(n) for n in names]
+    fl = [n.endswith("f") or "c" in n[4:] for n in names]
+    gs = [sssp.Graph.from_csr(w.csr, float_weights=f) for w, f in zip(wls, fl)]
+    srcs = [int(w.sources(1)[0]) for w in wls]
+    adjs = [native.Adjacency(w.edges.n, w.edges.src, w.edges.dst, w.edges.w) for w in wls]
+    refs = [a.dijkstra_f32(s) if f else a.dijkstra(s) for a, s, f in zip(adjs, srcs, fl)]
+    tg = [-1, -1, pick_target(refs[2], 0.5), pick_target(refs[3], 0.3), -1, -1]
+    outs, pars = sssp.solve_multi(gs, srcs, targets=tg, trees=True)
+    torch.cuda.synchronize()
+    assert sssp.counters()["flags"] == 0
+    for i, w in enumerate(wls):
+        d = outs[i].cpu().numpy()
+        p = pars[i].cpu().numpy()
+        ref = refs[i]
+        if tg[i] < 0:
+            assert np.array_equal(d, ref), names[i]
+        else:
+            dt = int(ref[tg[i]])
+            assert int(d[tg[i]]) == dt, names[i]
+            low = d <= dt
+            assert np.array_equal(d[low], ref[low]), names[i]
+        # the parent of every exact, reachable vertex is joined to it by an edge
+        # that is tight for the returned distances (binary32: in binary32)
+        c = w.csr
+        exact = (d == ref) & (ref != INF)
+        if tg[i] >= 0:
+            exact &= d <= int(ref[tg[i]])
+        for v in np.nonzero(exact)[0][:1500]:
+            v = int(v)
+            u = int(p[v])
+            if v == srcs[i]:
+                assert u == v
+                continue
+            lo, hi = c.rowptr[v], c.rowptr[v + 1]
+            ws = c.w[lo:hi][c.col[lo:hi] == u]
+            assert ws.shape[0], (names[i], v, u)
+            if fl[i]:
+                du = np.array([ref[u]], np.uint32).view(np.float32)[0]
+                ok = any(np.float32(du + np.array([x], np.uint32).view(np.float32)[0])
+                         == np.array([ref[v]], np.uint32).view(np.float32)[0] for x in ws)
+            else:
+                ok = any(int(ref[u]) + int(x) == int(ref[v]) for x in ws)
+            assert ok, (names[i], v, u)
+    for a in adjs:
+        a.close()
+    for g in gs:
+        g.close()

@@ -256,3 +256,29 @@ def test_fused_rounds_on_off(name):
             [(a["lb"], a["ub"], a["st"]) for a in sched_off]
         if name == "grid256":
             assert c_on["fused_rounds"] > 0 and c_on["ticks"] < c_off["ticks"]
+
+
+def test_grid_beyond_the_window_tiny_fuzz():
+    """Integer weights above 65536 (the ST_NUM grid): every source of tiny
+    random graphs, distances against the oracle and the schedule against the
+    model."""
+    cases = 0
+    for n in range(2, 10):
+        for m in (n, 3 * n):
+            for weights in ([70000, 1, 300000], [65537, 65538, 2], [1 << 20, 70000, 1 << 19]):
+                el = small.tiny_random(n, m, weights, seed=613 * n + m + weights[0] % 97)
+                c = graphgen.to_csr(el)
+                g = sssp.Graph.from_csr(c)
+                for s in range(n):
+                    assert_same(gpu_dist(g, s), oracle_dist(el, s), "n=%d m=%d s=%d" % (n, m, s))
+                    ref = eic.eic_sssp(c.n, c.rowptr, c.col, c.w, s)
+                    steps = [b for b in ref.steps if not (b.lb == 0 and b.ub == INF)]
+                    got = sssp.schedule()
+                    # the engine keeps the first 2^16 steps (weights {1, 70000, ...}
+                    # give gap-1 steps up to 70000)
+                    assert len(got) == min(len(steps), 1 << 16)
+                    for a, b in zip(got, steps):
+                        assert (a["lb"], a["ub"], a["st"]) == (b.lb, b.ub, b.st), (n, m, s, a, b)
+                    cases += 1
+                g.close()
+    assert cases > 150
