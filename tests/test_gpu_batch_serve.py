@@ -142,3 +142,49 @@ def test_server_admission_by_budget():
     with pytest.raises(sssp.SSSPError):
         small.submit(gid, wl.csr.n, outs[0])
     small.close()
+
+
+def test_server_tree_queries_within_the_budget():
+    """A tree query counts its parent output and the solve's 8-byte tree words
+    against the budget: with room for a little more than one tree query, tree
+    and plain queries still all complete, correct, and the memory in use never
+    exceeds the budget; a budget too small for a tree query (but large enough
+    for a plain one) rejects it at submission."""
+    from oracle import native
+    wl = graphgen.workload("rmat14")
+    c = wl.csr
+    g = sssp.Graph.from_csr(c)
+    srv = sssp.Server(budget_bytes=1 << 40, max_batch=8, ticks_per_launch=2)
+    gid = srv.add_graph(g)
+    qb = srv.query_bytes(gid)
+    srv.close()
+    tree_b = qb + 12 * c.n
+    budget = int(1.3 * tree_b)
+    srv = sssp.Server(budget_bytes=budget, max_batch=8, ticks_per_launch=2)
+    gid = srv.add_graph(g)
+    srcs = [int(s) for s in wl.sources(6)]
+    outs = [torch.empty(c.n, dtype=torch.uint32, device="cuda") for _ in srcs]
+    pars = [torch.empty(c.n, dtype=torch.int32, device="cuda") if i % 2 == 0 else None for i in range(len(srcs))]
+    tickets = [srv.submit(gid, s, o, parent=p) for s, o, p in zip(srcs, outs, pars)]
+    for t in tickets:
+        srv.wait(t)
+        assert srv.info(t)["status"] == 0
+    st = srv.stats()
+    assert st["completed"] == len(srcs)
+    assert st["peak_in_use_bytes"] <= budget, st
+    for s, o, p in zip(srcs, outs, pars):
+        d = o.cpu().numpy()
+        same(d, oracle_dist(wl.edges, s), "tree-budget s=%d" % s)
+        if p is not None:
+            assert native.check_tree(c.n, c.rowptr, c.col, c.w, s, d, p.cpu().numpy()) == [0, 0, 0, 0]
+    srv.close()
+    tight = sssp.Server(budget_bytes=qb + 4 * c.n, max_batch=2)
+    gid = tight.add_graph(g)
+    with pytest.raises(sssp.SSSPError) as ei:
+        tight.submit(gid, srcs[0], outs[0], parent=pars[0])
+    assert ei.value.status == -3
+    t = tight.submit(gid, srcs[1], outs[1])
+    tight.wait(t)
+    same(outs[1].cpu().numpy(), oracle_dist(wl.edges, srcs[1]), "plain in a tight budget")
+    tight.close()
+    g.close()
