@@ -22,8 +22,8 @@ constexpr int kHeavyChunk = 256;         // edges per heavy chunk
 constexpr int kDefaultHeavy = 64;        // ranges longer than this are split
 constexpr int kStageCap = 1280;          // LDS staging of list appends per workgroup batch
 constexpr int kItemsPerThread = 2;       // round batches: items per thread
-constexpr int kRoundBatch = kBlock * kItemsPerThread;
-constexpr int kEdgesPerThread = 2;   // edges a thread relaxes per pass of a round batch  // items per workgroup batch
+constexpr int kRoundBatch = kBlock * kItemsPerThread;  // items per workgroup batch
+constexpr int kEdgesPerThread = 2;       // edges a thread relaxes per pass of a round batch
 constexpr int kHeavyPerBatch = 16;       // heavy chunks per workgroup batch
 constexpr int kSettlePer = 4;            // settle batches: items per thread
 constexpr int kSettleBatch = kBlock * kSettlePer;
