@@ -232,15 +232,14 @@ def variants_section(args, sssp, torch, np, graphgen):
     # with power 20 on the RMAT-24 topology (the ST_NUM grid), checked by the
     # oracle's invariant checker.
     for name in ("rmat22f", "rmat22c5", "rmat24f", "rmat24p20"):
-        fw = not name.endswith("p20")
+        fw = graphgen.binary32_weights(name)
         wl = graphgen.workload(name)
         csr = wl.csr
         deg = csr.degrees()
         g = sssp.Graph.from_csr(csr, float_weights=fw)
         srcs = [int(s) for s in wl.sources(5)]
         o = torch.empty(csr.n, dtype=torch.uint32, device="cuda")
-        rec = {"weights": ("binary32, " + ("uniform on (0, 1]" if name.endswith("f") else "converge(x, 0.5) (Eq. 8)"))
-               if fw else "integers 1..2^20 - 1 (Eq. 7, power 20)"}
+        rec = {"weights": graphgen.weight_label(name)}
         for topt in (True, False):
             g.solve(srcs[0], out=o, traversal_opt=topt)
             torch.cuda.synchronize()
@@ -402,9 +401,10 @@ def main():
     log("generated %s: n=%d nnz=%d in %.1fs" % (wl.name, csr.n, csr.nnz, time.time() - t))
     deg = csr.degrees()
 
+    fw = graphgen.binary32_weights(wl.name)
     torch.cuda.synchronize()
     t = time.perf_counter()
-    g = sssp.Graph.from_csr(csr)
+    g = sssp.Graph.from_csr(csr, float_weights=fw)
     torch.cuda.synchronize()
     prep_s = time.perf_counter() - t
     info = g.info()
@@ -511,13 +511,14 @@ def main():
         adj = native.Adjacency(wl.edges.n, wl.edges.src, wl.edges.dst, wl.edges.w)
         s = timed[-1]  # outs[0] holds this source's distances from the counters pass
         t = time.perf_counter()
-        ref = adj.dijkstra(s)
+        ref = adj.dijkstra_f32(s) if fw else adj.dijkstra(s)
         dt = time.perf_counter() - t
         adj.close()
         parity = bool(np.array_equal(ref, outs[0].cpu().numpy()))
         cpu = {"value": round(m_cc[-1] / dt / 1e9, 6), "unit": "GTEPS", "cores": 1, "kind": "oracle",
-               "sample": "binary-heap Dijkstra (the oracle), 1 thread, one source of the same "
-                         "%s graph, %.1f s; GPU result for it bit-exact: %s" % (wl.name, dt, parity)}
+               "sample": "binary-heap Dijkstra (the oracle%s), 1 thread, one source of the same "
+                         "%s graph, %.1f s; GPU result for it bit-exact: %s"
+                         % (", binary32" if fw else "", wl.name, dt, parity)}
         log("oracle: %.2f s for one source -> %.4f GTEPS; GPU bit-exact: %s" % (dt, cpu["value"], parity))
 
     if args.calibrate_copy:
@@ -549,11 +550,12 @@ def main():
               "n": csr.n, "nnz": csr.nnz, "sources": K, "seed": wl.seed,
               "m_cc_mean": int(sum(m_cc) / len(m_cc)), "parallelism": "1 GPU"}
     if wl.name.startswith("rmat"):
-        config.update({"edge_factor": 16, "weights": "U{1..255}", "rmat_abc": [0.57, 0.19, 0.19]})
+        config.update({"edge_factor": 16, "weights": graphgen.weight_label(wl.name),
+                       "rmat_abc": [0.57, 0.19, 0.19]})
     elif wl.name.startswith("er"):
-        config.update({"mean_degree": 32, "weights": "U{1..255}"})
+        config.update({"mean_degree": 32, "weights": graphgen.weight_label(wl.name)})
     elif wl.name.startswith("grid"):
-        config.update({"edges_kept": 0.95, "diagonals": 0.01, "weights": "U{1..1000}"})
+        config.update({"edges_kept": 0.95, "diagonals": 0.01, "weights": graphgen.weight_label(wl.name)})
     line = {
         "metric": METRIC,
         "value": round(gteps, 3),
@@ -565,7 +567,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u32",
+        "dtype": "f32" if fw else "u32",
         "data": "synthetic",
         "config": config,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,

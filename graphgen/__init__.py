@@ -236,6 +236,27 @@ class Workload:
         return pick_sources(self.csr, k, self.seed + 7919)
 
 
+def binary32_weights(name: str) -> bool:
+    """True for the workloads whose weights are binary32 bit patterns
+    (rmat<k>f, rmat<k>c<d>)."""
+    return name.startswith("rmat") and (name.endswith("f") or "c" in name[4:])
+
+
+def weight_label(name: str) -> str:
+    """The weight distribution of a named workload, as reported."""
+    if binary32_weights(name):
+        if name.endswith("f"):
+            return "binary32, uniform on (0, 1]"
+        return "binary32, converge(x, %s) (Eq. 8)" % (int(name.split("c")[1]) / 10.0)
+    if name.startswith("rmat") and "p" in name[4:]:
+        p = int(name[4:].split("p")[1])
+        return "Eq. 7, power %d: 1..%d" % (p, (1 << p) - 1)
+    if name.startswith("grid"):
+        body = name[4:]
+        return "U{1..%s}" % (body.split("w")[1] if "w" in body else "1000")
+    return "U{1..255}"
+
+
 def workload(name: str, scale: Optional[int] = None) -> Workload:
     """Named synthetic workloads.
 
@@ -251,7 +272,7 @@ def workload(name: str, scale: Optional[int] = None) -> Workload:
     ``rmat<k>p<power>``  the R-MAT graph rmat<k> with its weights replaced by the
                  integer-power variant's (Eq. 7): 2^power - 1 distinct weights
     """
-    if name.startswith("rmat") and (name.endswith("f") or "c" in name[4:]):
+    if binary32_weights(name):
         # rmat<k>f: real weights uniform on (0, 1]; rmat<k>c<d>: the float-pivot
         # variant (Eq. 8) with pivot d / 10 -- binary32 bit patterns
         body = name[4:]
