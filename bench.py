@@ -357,6 +357,35 @@ def served_section(args, sssp, torch, np, graphgen):
     log("served: %.2f q/s p50 %.1f ms p99 %.1f ms (plain FIFO %.2f q/s p50 %.1f p99 %.1f); equal: %s"
         % (N / span, res["p50_ms"], res["p99_ms"], N / fifo_span, res["plain_fifo"]["p50_ms"],
            res["plain_fifo"]["p99_ms"], same))
+    if not args.no_cpu_baseline:
+        # the oracle on a bounded sample of the same stream: the first 8 queries
+        # of each graph, each graph's on a thread pool; every result is also
+        # compared with what the server returned for that query
+        from oracle import native  # CPU baseline leg only
+        threads = max(1, min(16, os.cpu_count() or 1))
+        per = 8
+        picked = {}
+        for q, (gi, s) in enumerate(queries):
+            lst = picked.setdefault(gi, [])
+            if len(lst) < per:
+                lst.append(q)
+        dtc, nq, agree = 0.0, 0, True
+        for gi, qs in sorted(picked.items()):
+            w = wls[gi]
+            adj = native.Adjacency(w.edges.n, w.edges.src, w.edges.dst, w.edges.w)
+            t0c = time.perf_counter()
+            ref = adj.dijkstra_many([queries[q][1] for q in qs], threads)
+            dtc += time.perf_counter() - t0c
+            adj.close()
+            nq += len(qs)
+            agree = agree and all(np.array_equal(ref[j], outs[q].cpu().numpy()) for j, q in enumerate(qs))
+        res["cpu_baseline"] = {
+            "value": round(nq / dtc, 3), "unit": "queries/s", "cores": threads, "kind": "oracle",
+            "sample": "binary-heap Dijkstra (the oracle), the first %d queries of each graph in the stream "
+                      "(%d in all), each graph's on a %d-thread pool, %.1f s; all equal the served results: %s"
+                      % (per, nq, threads, dtc, agree)}
+        log("served mix on the oracle: %.2f queries/s on %d threads (%d queries, %.1f s); equal: %s"
+            % (nq / dtc, threads, nq, dtc, agree))
     for gg in gs:
         gg.close()
     return res
