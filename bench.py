@@ -477,7 +477,10 @@ def main():
     achieved = (sum(B) / len(B)) / (eng_mean_us * 1e-6) / 1e9
     n_reach = int((outs[1 if K > 1 else 0].cpu().numpy() != INF).sum())
     c0 = ctr[1 if K > 1 else 0]
+    trav = sum(c["push_scanned"] + c["pull_scanned"] for c in ctr) / len(ctr)
     counters = {
+        # CSR entries the solves scan (pushed and pulled), per second of the timed run
+        "traversed_edges_per_s": round(trav / (total_s / K), 1),
         "nTrav": round((c0["push_scanned"] + c0["pull_scanned"]) / max(n_reach, 1), 3),
         "nSync": round((c0["rounds"] + c0["pulls"]) / math.log2(csr.n), 3),
         "steps": c0["steps"], "rounds": c0["rounds"], "ticks": c0["ticks"],
