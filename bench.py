@@ -413,7 +413,7 @@ def main():
                          "scaling the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build runs a single-GPU solver "
+        print("bench.py measures one GPU only: the solver runs on a single GPU "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
