@@ -108,3 +108,23 @@ def test_power_variant_keeps_the_topology():
     b = graphgen.workload("rmat12p3")
     assert np.array_equal(a.edges.src, b.edges.src) and np.array_equal(a.edges.dst, b.edges.dst)
     assert set(np.unique(b.edges.w).tolist()) <= set(range(1, 8))
+
+
+def test_workload_weight_kinds_and_labels():
+    """binary32_weights / weight_label agree with the weights each named
+    workload actually carries."""
+    import numpy as np
+    cases = {"rmat12": (False, "U{1..255}"), "rmat12f": (True, "binary32, uniform on (0, 1]"),
+             "rmat12c5": (True, "binary32, converge(x, 0.5) (Eq. 8)"),
+             "rmat12p20": (False, "Eq. 7, power 20: 1..1048575"), "grid64": (False, "U{1..1000}"),
+             "grid64w1000000": (False, "U{1..1000000}"), "er12": (False, "U{1..255}")}
+    for name, (fw, label) in cases.items():
+        assert graphgen.binary32_weights(name) == fw, name
+        assert graphgen.weight_label(name) == label, name
+        w = graphgen.workload(name).csr.w
+        if fw:
+            v = w.view(np.float32)
+            assert np.all(v > 0) and np.all(v <= 1.0), name
+        else:
+            hi = {"rmat12p20": (1 << 20) - 1, "grid64w1000000": 1000000, "grid64": 1000}.get(name, 255)
+            assert w.min() >= 1 and w.max() <= hi, name
