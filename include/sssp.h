@@ -119,14 +119,17 @@ typedef struct {
 
 /* ---- graphs ------------------------------------------------------------- */
 
-/* Build the device graph: validate the CSR, check symmetry, sort each row by
- * (weight, column), and precompute the statistics inputs -- degrees, the
- * degree histogram and highD(0), the weight quantiles RtoW[4096] (Section 4.1:
- * RtoW[x] = maxW(G, x/4095)). This is the paper's preprocessing (Section 4.1,
- * Section 4.6). rowptr/colidx/weight may be host or device pointers; they are
- * copied, and the caller keeps ownership. Synchronous. Returns NULL on error
- * (see sssp_last_error: SSSP_E_INVAL, SSSP_E_NOT_SYMMETRIC, SSSP_E_RANGE,
- * SSSP_E_NOMEM, SSSP_E_DEVICE). */
+/* Build the device graph of the Section 2 problem (an undirected graph
+ * G = <V, E, w> with non-negative weights): validate the CSR, check symmetry,
+ * sort each row by (weight, column), and precompute the statistics inputs --
+ * degrees, the degree histogram and highD(0), the weight quantiles RtoW[4096]
+ * (Section 4.1: RtoW[x] = maxW(G, x/4095)). This is the paper's preprocessing
+ * (Section 4.1, Section 4.6). n >= 1 vertices; rowptr/colidx/weight (layout
+ * above) may be host or device pointers; they are copied, and the caller
+ * keeps ownership. Synchronous. Returns NULL on error (see sssp_last_error:
+ * SSSP_E_INVAL for n < 1, NULL arrays or an invalid CSR, SSSP_E_NOT_SYMMETRIC,
+ * SSSP_E_RANGE, SSSP_E_NOMEM, SSSP_E_DEVICE). The graph lives on the device
+ * current at creation; sssp_graph_destroy frees it. */
 sssp_graph* sssp_graph_create(int32_t n, const int32_t* rowptr, const int32_t* colidx,
                               const uint32_t* weight);
 
@@ -160,11 +163,18 @@ sssp_status sssp_graph_rtow(const sssp_graph* g, uint32_t* rtow_out);
 
 /* ---- solves ------------------------------------------------------------- */
 
-/* Distances from `source` into dist_out (device, n uint32), enqueued on
- * `stream`. dist_out[source] = 0; unreachable vertices get UINT32_MAX.
- * Asynchronous: a reachable vertex whose distance is >= UINT32_MAX (the
- * distances are then incomplete) is reported by sssp_get_counters returning
- * SSSP_E_DIST_OVERFLOW. */
+/* The single-source problem of Section 2 (its problem statement: the length
+ * of a shortest path from the source to every vertex, +infinity for vertices
+ * the source does not reach), solved by the Algorithm of Section 3.3.
+ * source: a vertex in [0, n). dist_out: caller-owned device memory of n uint32,
+ * written in `stream` order; dist_out[source] = 0, unreachable vertices get
+ * UINT32_MAX. The graph stays read-only, so solves on different streams may
+ * run at once; each stream has its own workspace, allocated on first use.
+ * Errors: SSSP_E_INVAL (NULL graph or dist_out, a source out of range, a graph
+ * of another device), returned before anything is enqueued; SSSP_E_NOMEM,
+ * SSSP_E_DEVICE. Asynchronous: a reachable vertex whose distance is >=
+ * UINT32_MAX (the distances are then incomplete) is reported by
+ * sssp_get_counters returning SSSP_E_DIST_OVERFLOW. */
 sssp_status sssp_solve(const sssp_graph* g, int32_t source, uint32_t* dist_out,
                        hipStream_t stream);
 
@@ -189,22 +199,32 @@ sssp_status sssp_solve_tree(const sssp_graph* g, int32_t source, uint32_t* dist_
 /* Point-to-point query (Section 5 names it among the method's uses): the
  * solve stops at the end of the first step after which `target` is settled.
  * dist_out (device, n uint32, caller-owned) then holds the exact distance of
- * target, and of every vertex whose entry is <= that distance; the other
+ * target, and of every vertex whose distance is not above the target's (all
+ * of them lie below the band's lower end when the solve stops); the other
  * entries are upper bounds of their distances (UINT32_MAX where no path has
- * been found yet). An unreachable target runs the whole solve and reads
+ * been found yet), all of them above the target's distance. An unreachable target runs the whole solve and reads
  * UINT32_MAX. Options as sssp_solve_ex (NULL = defaults); enqueued on
  * `stream`; sssp_get_counters and sssp_get_schedule describe the steps run. */
 sssp_status sssp_solve_p2p(const sssp_graph* g, int32_t source, int32_t target, uint32_t* dist_out,
                            const sssp_options* opt, hipStream_t stream);
 
-/* k sources on one graph in one persistent launch. sources: host array of k
- * vertex ids; dist_out: device, k * n uint32, row i for sources[i]. */
+/* k sources on one graph in one persistent launch: the paper's trial
+ * protocol (Section 4: 64 sources per graph, drawn among the vertices of
+ * degree >= 1, run one after another there) as one batch of k independent
+ * solves of the Section 2 problem. sources: host array of k vertex ids (k >=
+ * 1; repeats allowed); dist_out: caller-owned device memory of k * n uint32,
+ * row i (n entries from dist_out + i * n) for sources[i], written in `stream`
+ * order as sssp_solve writes one row. The batch keeps one solver workspace per
+ * source on the stream. Errors as sssp_solve, plus k < 1 or NULL sources. */
 sssp_status sssp_solve_batch(const sssp_graph* g, const int32_t* sources, int32_t k,
                              uint32_t* dist_out, hipStream_t stream);
 
-/* k independent (graph, source) pairs in one persistent launch; graphs may
- * differ in size. gs, sources, dist_outs: host arrays of k entries;
- * dist_outs[i] is device memory of gs[i]'s n uint32. */
+/* k independent (graph, source) pairs in one persistent launch (the Section 2
+ * problem for each pair; Section 4's trial protocol over many graphs); graphs
+ * may differ in size. gs, sources, dist_outs: host arrays of k entries;
+ * dist_outs[i] is caller-owned device memory of gs[i]'s n uint32, written in
+ * `stream` order. Errors as sssp_solve for any pair, plus k < 1 or NULL
+ * arrays, all before anything is enqueued. */
 sssp_status sssp_solve_multi(const sssp_graph* const* gs, const int32_t* sources, int32_t k,
                              uint32_t* const* dist_outs, const sssp_options* opt,
                              hipStream_t stream);
@@ -213,8 +233,8 @@ sssp_status sssp_solve_multi(const sssp_graph* const* gs, const int32_t* sources
  * optionally with its shortest-path tree (the outputs of sssp_solve_p2p and
  * sssp_solve_tree, Sections 2.1 and 5). targets: NULL, or a host array of k
  * entries, -1 for a full solve, else the target vertex of pair i (that
- * solve stops once its target is settled; its entries not above the
- * target's distance are exact, the others upper bounds). parent_outs: NULL,
+ * solve stops once its target is settled; the entries of the vertices whose
+ * distance is not above the target's are exact, the others upper bounds). parent_outs: NULL,
  * or a host array of k entries, each NULL or device memory of gs[i]'s n
  * int32 (parent[s] = s, -1 where the distance is UINT32_MAX; the parent
  * edge of every other vertex is tight for its returned distance). Argument
@@ -395,6 +415,19 @@ sssp_status sssp_debug_tick_log(hipStream_t stream, int32_t cap);
  * into out); *len receives the tick count, *t_start the engine's start time. */
 sssp_status sssp_debug_get_tick_log(hipStream_t stream, uint64_t* out, int32_t cap, int32_t* len,
                                     uint64_t* t_start);
+
+/* ---- teardown ----------------------------------------------------------- */
+
+/* Free what the library holds on its own behalf: the per-stream solver
+ * workspaces of the plain, tree, point-to-point and batched solves (device
+ * buffers, pinned staging buffers, HIP events) on every device. Graphs, plans
+ * and servers belong to the caller and are not touched. Waits for each device
+ * that held a workspace to finish its work first. A later solve sets its
+ * workspace up again. For a process about to exit, so that no HIP object of
+ * the library outlives the runtime's own teardown (the Python package calls it
+ * from an exit hook after closing its graphs, plans and servers); no solve may
+ * be enqueued concurrently. */
+sssp_status sssp_release_workspaces(void);
 
 /* ---- errors ------------------------------------------------------------- */
 

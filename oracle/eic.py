@@ -61,6 +61,7 @@ class Result:
     pulls: int = 0
     high_d0: int = 0
     gap0: int = 0
+    complete: bool = True   # False: max_steps ended the model before its stopping test
 
 
 def _row_edges(rowptr: np.ndarray, rows: np.ndarray) -> tuple:
@@ -164,6 +165,8 @@ def eic_sssp(n: int, rowptr: np.ndarray, col: np.ndarray, w: np.ndarray, s: int,
         finite = dist[dist < INF]
         if int(finite.max()) + M < lb:
             break
+    else:
+        res.complete = False
     res.dist = dist.astype(np.uint32)
     return res
 
@@ -182,10 +185,16 @@ def eic_sssp_f32(n: int, rowptr: np.ndarray, col: np.ndarray, wbits: np.ndarray,
     bit patterns (finite, non-negative, so they order like their values) and
     every path sum is one binary32 addition, rounded to nearest.  The readings
     that differ from the integer model: the next band ends at fl(L + gap)
-    with the gap at least the smallest positive weight and the band reaching
-    past the smallest pending distance (one unit in the last place when the
-    sum does not move); lb0 = fl(fl(L - M) - 2 ulp(L)); the pull takes an edge
-    while fl(st + w) < ub; computeST works on the ST_NUM grid."""
+    with the gap at least the smallest positive weight, and one unit in the
+    last place above L when that sum rounds back to L (ub > lb, Section 3);
+    lb0 = fl(fl(L - M) - 2 ulp(L)); the pull takes an edge while
+    fl(st + w) < ub; computeST works on the ST_NUM grid.
+
+    A band narrower than the spacing of the remaining distances settles
+    nothing and the next one starts where it ended, as in the integer model:
+    weights that span many orders of magnitude (say 1e-30 and 1e30 in one
+    graph) can need a step per unit in the last place. `complete` is False
+    when max_steps ran out first."""
     rowptr = np.asarray(rowptr, dtype=np.int64)
     col = np.asarray(col, dtype=np.int64)
     w = np.asarray(wbits, dtype=np.uint32).astype(np.int64)
@@ -260,14 +269,13 @@ def eic_sssp_f32(n: int, rowptr: np.ndarray, col: np.ndarray, wbits: np.ndarray,
         if L == INF:
             res.steps.append(Step(lb, ub, st, rounds, pulled, L, S, h, gap_L, L))
             break
+        # ub = L + gap(L) (Section 3.3), rounded; the gap is positive (Section
+        # 3.1: gap in (0, maxW]), so a zero quantile takes the smallest positive
+        # weight, and ub > lb holds even where the sum rounds back to L
         gf = gap_L if (gap_L > minpos or minpos == INF) else minpos
         e = int(_fadd(L, gf))
         if e <= L:
             e = L + 1
-        pend = dist[(dist >= L) & (dist < INF)]
-        pm = int(pend.min()) if pend.shape[0] else INF
-        if pm != INF and e <= pm:
-            e = pm + 1
         ub_next = INF if e >= H.F32_INF_BITS else e
         Lf = np.float32(H.f32(L))
         ulp = np.float32(H.f32(L + 1)) - Lf
@@ -283,6 +291,8 @@ def eic_sssp_f32(n: int, rowptr: np.ndarray, col: np.ndarray, wbits: np.ndarray,
         finite = dist[dist < INF]
         if int(_fadd(int(finite.max()), M)) < lb:
             break
+    else:
+        res.complete = False
     res.dist = dist.astype(np.uint32)
     return res
 

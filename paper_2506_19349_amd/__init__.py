@@ -7,7 +7,9 @@ uint32 distances (UINT32_MAX = unreachable) into torch device tensors.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
+import weakref
 from typing import Iterable, Optional, Sequence
 
 import numpy as np
@@ -18,11 +20,39 @@ from ._lib import SSSPError
 INF = 0xFFFFFFFF
 
 __all__ = ["Graph", "solve_multi", "counters", "schedule", "engine_times", "Plan", "autotune",
-           "Server", "SSSPError", "INF", "version"]
+           "Server", "SSSPError", "INF", "version", "release_workspaces"]
 
 
 def version() -> str:
     return _lib.sssp_version().decode()
+
+
+# Library objects still open at interpreter exit, closed by the exit hook in
+# dependency order (servers and plans hold graphs) before the library frees its
+# own workspaces: nothing of the library is left for the HIP runtime's teardown.
+_open_servers = weakref.WeakSet()
+_open_plans = weakref.WeakSet()
+_open_graphs = weakref.WeakSet()
+
+
+def release_workspaces() -> None:
+    """Free the library's own per-stream workspaces (sssp_release_workspaces);
+    graphs, plans and servers stay. Later solves allocate them again."""
+    _lib.check(_lib.sssp_release_workspaces())
+
+
+@atexit.register
+def _close_at_exit():
+    for group in (_open_servers, _open_plans, _open_graphs):
+        for obj in list(group):
+            try:
+                obj.close()
+            except Exception:
+                pass
+    try:
+        _lib.sssp_release_workspaces()
+    except Exception:
+        pass
 
 
 def _torch():
@@ -73,6 +103,27 @@ def _options(traversal_opt=True, alpha=None, beta=None, host_driven=False, block
     return o
 
 
+def _check_out(t, count: int, parent: bool = False, what: str = "out"):
+    """An output the kernels write: a contiguous cuda tensor on the current
+    device of at least `count` entries, uint32 (distances) or int32 (parents)."""
+    torch = _torch()
+    want = torch.int32 if parent else torch.uint32
+    if not isinstance(t, torch.Tensor):
+        raise ValueError("%s must be a torch cuda tensor" % what)
+    if t.device.type != "cuda":
+        raise ValueError("%s must be a cuda tensor, not on %s" % (what, t.device))
+    if t.device.index != torch.cuda.current_device():
+        raise ValueError("%s must be on the current cuda device (cuda:%d), not %s"
+                         % (what, torch.cuda.current_device(), t.device))
+    if t.dtype != want:
+        raise ValueError("%s must be %s, not %s" % (what, want, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % what)
+    if t.numel() < count:
+        raise ValueError("%s holds %d entries, %d needed" % (what, t.numel(), count))
+    return t
+
+
 def _empty_dist(n: int, k: Optional[int] = None):
     torch = _torch()
     shape = (n,) if k is None else (k, n)
@@ -97,6 +148,7 @@ class Graph:
         self.n = n
         info = self.info()
         self.nnz = info["nnz"]
+        _open_graphs.add(self)
 
     @classmethod
     def from_csr(cls, csr, check_symmetry: bool = True, float_weights: bool = False) -> "Graph":
@@ -131,8 +183,7 @@ class Graph:
 
     def solve(self, source: int, out=None, stream=None, **opts):
         """Distances from `source` as a uint32 cuda tensor of n entries."""
-        if out is None:
-            out = _empty_dist(self.n)
+        out = _empty_dist(self.n) if out is None else _check_out(out, self.n)
         o = _options(**opts)
         _lib.check(_lib.sssp_solve_ex(self._h, int(source), _ptr(out), ctypes.byref(o),
                                       _stream_handle(stream)))
@@ -142,11 +193,12 @@ class Graph:
         """Distances and a shortest-path tree from `source`: (dist, parent), a uint32
         and an int32 cuda tensor of n entries; parent[source] = source, -1 where
         unreachable."""
-        if out is None:
-            out = _empty_dist(self.n)
+        out = _empty_dist(self.n) if out is None else _check_out(out, self.n)
         if parent is None:
             torch = _torch()
             parent = torch.empty(self.n, dtype=torch.int32, device="cuda")
+        else:
+            _check_out(parent, self.n, parent=True, what="parent")
         o = _options(**opts)
         _lib.check(_lib.sssp_solve_tree(self._h, int(source), _ptr(out), _ptr(parent), ctypes.byref(o),
                                         _stream_handle(stream)))
@@ -155,10 +207,9 @@ class Graph:
     def solve_p2p(self, source: int, target: int, out=None, stream=None, **opts):
         """Point-to-point query: the solve stops once `target` is settled. Returns
         (distance of target, the uint32 distance tensor): exact for target and
-        for every entry not above its distance, upper bounds elsewhere. Waits
+        for every vertex whose distance is not above it, upper bounds elsewhere. Waits
         for the stream."""
-        if out is None:
-            out = _empty_dist(self.n)
+        out = _empty_dist(self.n) if out is None else _check_out(out, self.n)
         o = _options(**opts)
         _lib.check(_lib.sssp_solve_p2p(self._h, int(source), int(target), _ptr(out), ctypes.byref(o),
                                        _stream_handle(stream)))
@@ -168,8 +219,7 @@ class Graph:
         """k sources in one launch: a (k, n) uint32 cuda tensor, row i for sources[i]."""
         srcs = np.ascontiguousarray(np.asarray(sources, dtype=np.int32))
         k = int(srcs.shape[0])
-        if out is None:
-            out = _empty_dist(self.n, k)
+        out = _empty_dist(self.n, k) if out is None else _check_out(out, k * self.n)
         _lib.check(_lib.sssp_solve_batch(self._h, srcs.ctypes.data, k, _ptr(out),
                                          _stream_handle(stream)))
         return out
@@ -189,6 +239,10 @@ def solve_multi(graphs: Sequence[Graph], sources: Sequence[int], outs=None, stre
     k = len(graphs)
     if outs is None:
         outs = [_empty_dist(g.n) for g in graphs]
+    if len(outs) != k:
+        raise ValueError("need %d outputs" % k)
+    for g, o in zip(graphs, outs):
+        _check_out(o, g.n)
     hs = (ctypes.c_void_p * k)(*[g._h for g in graphs])
     srcs = np.ascontiguousarray(np.asarray(sources, dtype=np.int32))
     ptrs = (ctypes.c_void_p * k)(*[_ptr(o) for o in outs])
@@ -227,6 +281,12 @@ class Plan:
         self.graphs = list(graphs)
         self.outs = list(outs)
         self.parents = None if parents is None else list(parents)
+        if len(self.outs) != self.k or (self.parents is not None and len(self.parents) != self.k):
+            raise ValueError("need %d outputs" % self.k)
+        for i, g in enumerate(self.graphs):
+            _check_out(self.outs[i], g.n)
+            if self.parents is not None and self.parents[i] is not None:
+                _check_out(self.parents[i], g.n, parent=True, what="parent")
         hs = (ctypes.c_void_p * self.k)(*[g._h for g in graphs])
         ptrs = (ctypes.c_void_p * self.k)(*[_ptr(o) for o in self.outs])
         o = _options(**opts)
@@ -242,6 +302,7 @@ class Plan:
         if not h:
             _lib.check(_lib.sssp_last_error() or -6)
         self._h = h
+        _open_plans.add(self)
 
     def run(self, sources: Sequence[int], stream=None, targets: Optional[Sequence[int]] = None):
         """Replay for new sources (and, optionally, point-to-point targets,
@@ -312,7 +373,11 @@ class Server:
         if not h:
             _lib.check(_lib.sssp_last_error() or -6)
         self._h = h
+        _open_servers.add(self)
         self._graphs = []
+        # outputs of queries not yet released: the pump writes them
+        # asynchronously, so they must outlive the caller's own references
+        self._outputs = {}
 
     def add_graph(self, g: Graph) -> int:
         gid = _lib.sssp_server_add_graph(self._h, g._h)
@@ -329,7 +394,13 @@ class Server:
 
     def submit(self, graph_id: int, source: int, out, target: int = -1, parent=None) -> int:
         """Queue a query; target >= 0 makes it point-to-point, parent (an int32
-        cuda tensor of n entries) asks for its shortest-path tree."""
+        cuda tensor of n entries) asks for its shortest-path tree. The server
+        keeps references to out and parent until release() or close()."""
+        if 0 <= int(graph_id) < len(self._graphs):  # an unknown id is the library's to reject
+            n = self._graphs[int(graph_id)].n
+            _check_out(out, n)
+            if parent is not None:
+                _check_out(parent, n, parent=True, what="parent")
         t = ctypes.c_int64(0)
         if target == -1 and parent is None:
             _lib.check(_lib.sssp_server_submit(self._h, int(graph_id), int(source), _ptr(out),
@@ -337,6 +408,7 @@ class Server:
         else:
             _lib.check(_lib.sssp_server_submit_ex(self._h, int(graph_id), int(source), int(target), _ptr(out),
                                                   None if parent is None else _ptr(parent), ctypes.byref(t)))
+        self._outputs[t.value] = (out, parent)
         return t.value
 
     def poll(self, ticket: int) -> bool:
@@ -354,6 +426,7 @@ class Server:
 
     def release(self, ticket: int) -> None:
         _lib.check(_lib.sssp_server_release(self._h, ctypes.c_int64(ticket)))
+        self._outputs.pop(int(ticket), None)
 
     def stats(self) -> dict:
         s = _lib.ServerStats()
@@ -362,8 +435,9 @@ class Server:
 
     def close(self):
         if getattr(self, "_h", None):
-            _lib.sssp_server_destroy(self._h)
+            _lib.sssp_server_destroy(self._h)  # finishes every submitted query first
             self._h = None
+        self._outputs = {}
 
     def __del__(self):
         try:

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "runtime.h"
+#include "sizing.h"
 
 namespace sssp {
 
@@ -47,7 +48,8 @@ Needs needs_for(const DevGraph& g, int maxw) {
   r.n = g.n;
   r.maxw = maxw;
   r.list = g.n;
-  r.heavy = g.nnz / 128 + 4096;
+  const int64_t hc = heavy_list_capacity(g.nnz, g.heavy_rows, kHeavyChunk);
+  r.heavy = (int32_t)std::min<int64_t>(hc, INT32_MAX);
   r.hist = std::max(g.num_deg, 1);
   r.trace = 1 << 16;
   if (g.float_w) {
@@ -291,7 +293,8 @@ bool parse_opts(const sssp_options* o, Opts* r, std::string* err) {
   if (o->blocks_per_cu < 0) { *err = "blocks_per_cu must be >= 0"; return false; }
   r->blocks_per_cu = o->blocks_per_cu;
   if (o->heavy_split < 0) { *err = "heavy_split must be >= 0"; return false; }
-  if (o->heavy_split > 0) r->heavy = std::max(o->heavy_split, kWave);
+  // the heavy-chunk lists are sized for the least split (sizing.h)
+  if (o->heavy_split > 0) r->heavy = std::max(o->heavy_split, kDefaultHeavy);
   if (o->fuse_rounds < 0) r->fuse = 0;
   else if (o->fuse_rounds > 0) r->fuse = o->fuse_rounds;
   return true;
@@ -790,6 +793,24 @@ sssp_status sssp_debug_get_tick_log(hipStream_t stream, uint64_t* out, int32_t c
   *t_start = hg.t_start;
   m = std::min(m, cap);
   if (m > 0) HIP_TRY(hipMemcpy(out, w->d_tick_log, sizeof(uint64_t) * 4 * (size_t)m, hipMemcpyDeviceToHost));
+  return ok();
+}
+
+sssp_status sssp_release_workspaces(void) {
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  int cur = 0;
+  const bool have_cur = hipGetDevice(&cur) == hipSuccess;
+  sssp_status st = SSSP_OK;
+  for (auto& kv : g_ws) {
+    Workspace* w = kv.second;
+    // the stream may already be gone: wait for the whole device instead
+    if (hipSetDevice(kv.first.first) != hipSuccess || hipDeviceSynchronize() != hipSuccess) st = SSSP_E_DEVICE;
+    ws_release(*w);
+    delete w;
+  }
+  g_ws.clear();
+  if (have_cur) (void)hipSetDevice(cur);
+  if (st != SSSP_OK) return fail(st, "a device did not finish its work before release");
   return ok();
 }
 

@@ -19,7 +19,7 @@ constexpr uint32_t kGridRing = 4096;     // grid bins kept (>= 2 ST_NUM + 2)
 constexpr uint32_t kNoBin = 0xFFFFFFFFu; // a distance too large for the grid
 constexpr int kLdsHist = 1024;           // settle: degree ranks privatised in LDS
 constexpr int kHeavyChunk = 256;         // edges per heavy chunk
-constexpr int kDefaultHeavy = 64;        // ranges longer than this are split
+constexpr int kDefaultHeavy = 64;        // ranges longer than this are split (also the least split allowed)
 constexpr int kStageCap = 1280;          // LDS staging of list appends per workgroup batch
 constexpr int kItemsPerThread = 2;       // round batches: items per thread
 constexpr int kRoundBatch = kBlock * kItemsPerThread;  // items per workgroup batch
@@ -72,7 +72,7 @@ struct DevGraph {
   // comparison stays an unsigned one; only sums are taken in fp32.
   uint32_t float_w;
   uint32_t min_pos_w;        // smallest positive weight (UINT32_MAX if none)
-  uint32_t pad_g2;
+  int32_t heavy_rows;        // vertices whose degree exceeds kDefaultHeavy (sizes the heavy-chunk lists)
   const uint32_t* rtow;      // 4096
   // per row, 16 int32: entry b - 1 (b = 1..15) is the first position of the
   // row whose weight is >= b * rwi_width (entry 15 unused). Written for rows
@@ -230,7 +230,6 @@ struct Inst : InstFixed, InstCtl {
   // 128-byte line so that they never share a line with the fields above ----
   HotI32 q_next_cnt, touched_cnt, p_next_cnt, u_next_cnt, settled_cnt, h_next_cnt, settle_done;
   HotU32 ub_next, max_settled, flags;
-  HotU32 pend_min;  // binary32 weights: smallest distance left pending by a settle pass
   HotU64 S;  // sumD(lb): degree mass of the unsettled set
 };
 

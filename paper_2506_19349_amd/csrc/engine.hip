@@ -398,17 +398,15 @@ __device__ __noinline__ void run_heuristic(GInst& I, HeurLds& lds) {
   unsigned long long ubn;
   uint32_t lb0;
   if (fw) {
-    // The next band ends at L + gap rounded, with two floors that play the
-    // role of the integer gap's floor of 1 (R5): the gap is at least the
-    // smallest positive weight (a zero weight quantile would otherwise give a
-    // gap of the least denormal), and the band reaches past the smallest
-    // pending distance, so that every step settles a vertex or fills the
-    // pending list. Infinity and beyond are the +inf sentinel.
+    // The next band ends at L + gap (Section 3.3), rounded. The gap is
+    // positive (Section 3.1 keeps it in (0, maxW]): a zero weight quantile
+    // takes the smallest positive weight, as the integer gap takes 1, and
+    // where L + gap rounds back to L the band still ends above L (the next
+    // threshold is greater than the current one, Section 3). Infinity and
+    // beyond are the +inf sentinel.
     const uint32_t gf = gapL > g.min_pos_w || g.min_pos_w == kInf ? gapL : g.min_pos_w;
     uint32_t e = dadd<true>(L, gf);
     if (e <= L) e = L + 1u;
-    const uint32_t pm = I.pend_min.v;
-    if (pm != kInf && pm >= L && e <= pm) e = pm + 1u;
     ubn = e >= 0x7f800000u ? (unsigned long long)kInf : (unsigned long long)e;
     // lb0 = L - M, lowered by two units in the last place of L: a settled
     // distance d whose rounded d + M still reaches L lies above it
@@ -1282,7 +1280,7 @@ __device__ __noinline__ void block_settle(GInst& I, int kind, int item0, int nit
     }
   }
   unsigned long long sdec = 0;
-  uint32_t maxd = 0, pmin = kInf;
+  uint32_t maxd = 0;
   int ns = 0, np = 0;
 #pragma unroll
   for (int k = 0; k < kSettlePer; ++k) {
@@ -1292,7 +1290,6 @@ __device__ __noinline__ void block_settle(GInst& I, int kind, int item0, int nit
     const bool pend = v >= 0 && d >= ub;
     ns += settle ? 1 : 0;
     np += pend ? 1 : 0;
-    if (pend && d < pmin) pmin = d;
     if (!settle) continue;
     const int deg = (int)(uint32_t)di[k];
     // only the window [ub - M, ub) is read by the next computeST; the first
@@ -1350,10 +1347,6 @@ __device__ __noinline__ void block_settle(GInst& I, int kind, int item0, int nit
     wm = y > wm ? y : wm;
   }
   unsigned long long qe = wave_sum((unsigned long long)(ns + np));
-  if (fw) {
-    const uint32_t pm = wave_min_u32(pmin);
-    if (lane_id() == 0 && pm != kInf) atomicMin(&I.pend_min.v, pm);
-  }
   if (lane_id() == 0) {
     L.sdec[tid / kWave] = ws;
     L.maxd[tid / kWave] = wm;
@@ -1551,7 +1544,6 @@ __device__ void transition(InstCtl& X, SegSpec& Sp, const HotIn& h, int32_t n, i
     X.nT = min(h.touched, n);
     X.settled_mark = min(h.settled, n);
     I.settle_done.v = 0;
-    I.pend_min.v = kInf;
     int bt = (X.nT + kSettleBatch - 1) / kSettleBatch;
     if (bt < 1) bt = 1;
     int bp = (X.nP + kSettleBatch - 1) / kSettleBatch;
@@ -2012,7 +2004,6 @@ __global__ void __launch_bounds__(kBlock) k_init_ctl(Globals* Gp) {
       I.max_settled.v = 0;
       I.S.v = (unsigned long long)g.nnz;
       I.settle_items = 0; I.settle_done.v = 0;
-      I.pend_min.v = kInf;
       I.flags.v = 0;
       I.pull_on = 0;
       I.init_round = 0;

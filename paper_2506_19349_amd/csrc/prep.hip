@@ -973,7 +973,12 @@ int prep_graph(int32_t n, const int32_t* rowptr_in, const int32_t* col_in, const
   h.ubucket_width = ub_width;
   h.float_w = (flags & 2) ? 1u : 0u;
   h.min_pos_w = minpos;
-  h.pad_g2 = 0;
+  {
+    int64_t hr = 0;
+    for (int32_t i = 0; i < D; ++i)
+      if (deg_vals[(size_t)i] > kDefaultHeavy) hr += deg_cnt[(size_t)i];
+    h.heavy_rows = (int32_t)hr;
+  }
   h.rtow = rtow;
   h.rwi = rwi;
   h.rwi_width = rwi_width;

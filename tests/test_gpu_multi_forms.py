@@ -2,8 +2,9 @@
 (sssp_solve_multi_ex), replayed plans (sssp_plan_create_ex / sssp_plan_run_ex)
 and the query server (sssp_server_submit_ex). Full solves are bit-exact with
 the Dijkstra oracle and their trees pass the oracle's tree checker; a
-point-to-point pair is exact at its target and at every entry not above it,
-an upper bound elsewhere, and its tree is tight on the exact entries."""
+point-to-point pair is exact at its target and at every vertex whose distance
+is not above the target's, an upper bound elsewhere, and its tree is tight on the
+exact entries."""
 import numpy as np
 import pytest
 
@@ -38,8 +39,9 @@ def check_p2p(wl, s, t, d, p=None):
     ref = oracle(wl, s)
     dt = int(ref[t])
     assert int(d[t]) == dt
-    low = d <= dt
+    low = ref <= dt
     assert np.array_equal(d[low], ref[low])
+    assert np.array_equal(d <= dt, low)
     assert np.all(d.astype(np.uint64) >= ref.astype(np.uint64))
     if p is not None:
         c = wl.csr
@@ -177,7 +179,7 @@ def test_one_launch_mixing_weight_kinds_trees_and_targets():
         else:
             dt = int(ref[tg[i]])
             assert int(d[tg[i]]) == dt, names[i]
-            low = d <= dt
+            low = ref <= dt
             assert np.array_equal(d[low], ref[low]), names[i]
         # the parent of every exact, reachable vertex is joined to it by an edge
         # that is tight for the returned distances (binary32: in binary32)

