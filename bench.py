@@ -25,6 +25,8 @@ if ROOT not in sys.path:
 METRIC = "SSSP GTEPS on RMAT-24 (1 GPU); batched queries/s + p99 latency vs plain"
 HBM_PEAK_GBS = 8000.0
 INF = 0xFFFFFFFF
+# how the oracle used for the CPU baselines was built (set in main)
+ORACLE_BUILD = "gcc -O3"
 
 
 def log(*a):
@@ -96,6 +98,80 @@ def measured_traffic(workload: str):
             + float(vals["engine_write_kib"]) * 1024.0 * f_write)
 
 
+def time_solves(sssp, torch, g, srcs, outs, warm, **opts):
+    """Solve each source once (outs[i] for srcs[i]) after solving warm[] untimed;
+    returns (wall seconds, engine microseconds per solve)."""
+    for s in warm:
+        g.solve(s, out=outs[0], **opts)
+    torch.cuda.synchronize()
+    sssp.engine_times()
+    t0 = time.perf_counter()
+    for i, s in enumerate(srcs):
+        g.solve(s, out=outs[i], **opts)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, sssp.engine_times()
+
+
+def config_section(args, sssp, torch, np, graphgen, name, nsrc, repeat, what):
+    """One plain configuration: GTEPS over its seeded sources (each solved
+    `repeat` times, after one untimed solve), the engine kernel's mean time
+    (HIP events), algorithmic bytes and their fraction of the HBM peak, every
+    source's distances against the oracle's Dijkstra (bit for bit), and the
+    oracle itself timed on one source, one thread."""
+    from oracle import native  # parity and the CPU baseline leg
+    t = time.time()
+    wl = graphgen.workload(name)
+    c = wl.csr
+    deg = c.degrees()
+    g = sssp.Graph.from_csr(c)
+    log("%s: n=%d nnz=%d generated and prepared in %.1fs" % (name, c.n, c.nnz, time.time() - t))
+    base = [int(s) for s in wl.sources(nsrc)]
+    srcs = [s for s in base for _ in range(repeat)]
+    outs = [torch.empty(c.n, dtype=torch.uint32, device="cuda") for _ in base]
+    wall, eng = 0.0, []
+    for r in range(repeat):
+        dt, e = time_solves(sssp, torch, g, base, outs, base[:1] if r == 0 else [])
+        wall += dt
+        eng += e
+    dists = [o.cpu().numpy() for o in outs]
+    m_cc = [int(deg[d != INF].sum()) // 2 for d in dists]
+    gteps = sum(m_cc) * repeat / wall / 1e9
+    ctr = []
+    for s in base:
+        g.solve(s, out=outs[0])
+        ctr.append(sssp.counters())
+    sssp.engine_times()
+    B = sum(alg_bytes(x) for x in ctr) / len(ctr)
+    eng_mean = sum(eng) / max(len(eng), 1)
+    del outs
+    g.close()
+    adj = native.Adjacency(wl.edges.n, wl.edges.src, wl.edges.dst, wl.edges.w)
+    threads = max(1, min(16, os.cpu_count() or 1))
+    refs = adj.dijkstra_many(base, threads)
+    exact = [bool(np.array_equal(refs[i], dists[i])) for i in range(len(base))]
+    rec = {"workload": what, "n": c.n, "nnz": c.nnz, "seed": wl.seed, "sources": len(base),
+           "solves_timed": len(srcs), "gteps": round(gteps, 4), "ms_per_solve": round(wall * 1e3 / len(srcs), 4),
+           "engine_us_mean": round(eng_mean, 2), "alg_bytes_per_solve": int(B),
+           "roofline_frac_alg": round(B / (eng_mean * 1e-6) / 1e9 / HBM_PEAK_GBS, 6),
+           "parity_vs_oracle": {"sources_checked": len(base), "bit_exact": all(exact)},
+           "counters": {"steps": ctr[0]["steps"], "rounds": ctr[0]["rounds"], "ticks": ctr[0]["ticks"],
+                        "fused_rounds": ctr[0]["fused_rounds"],
+                        "nTrav": round((ctr[0]["push_scanned"] + ctr[0]["pull_scanned"])
+                                       / max(int((dists[0] != INF).sum()), 1), 3)}}
+    if not args.no_cpu_baseline:
+        t0 = time.perf_counter()
+        adj.dijkstra(base[0])
+        dtc = time.perf_counter() - t0
+        rec["cpu_baseline"] = {
+            "value": round(m_cc[0] / dtc / 1e9, 6), "unit": "GTEPS", "cores": 1, "kind": "oracle",
+            "sample": "binary-heap Dijkstra (the oracle, %s), 1 thread, source %d of the same graph, %.2f s"
+                      % (ORACLE_BUILD, base[0], dtc)}
+    adj.close()
+    log("%s: %.3f GTEPS, %.3f ms/solve, engine %.1f us, %d steps, %d ticks; bit-exact on %d sources: %s"
+        % (name, gteps, rec["ms_per_solve"], eng_mean, ctr[0]["steps"], ctr[0]["ticks"], len(base), all(exact)))
+    return rec
+
+
 def batched_section(args, sssp, torch, np, graphgen):
     """64 sources on RMAT-22 in one graph-captured persistent launch, and 256
     small R-MAT graphs (scales 10..16) in another; knobs picked by the
@@ -146,8 +222,8 @@ def batched_section(args, sssp, torch, np, graphgen):
         ok_c = bool(np.array_equal(ref[0], outs[0].cpu().numpy()))
         res["rmat22_64_sources"]["cpu_baseline"] = {
             "value": round(len(sample) / dtc, 3), "unit": "queries/s", "cores": threads, "kind": "oracle",
-            "sample": "binary-heap Dijkstra (the oracle), %d sources of the same graph on a %d-thread "
-                      "pool, %.1f s; first row equals the GPU's: %s" % (len(sample), threads, dtc, ok_c)}
+            "sample": "binary-heap Dijkstra (the oracle, %s), %d sources of the same graph on a %d-thread "
+                      "pool, %.1f s; first row equals the GPU's: %s" % (ORACLE_BUILD, len(sample), threads, dtc, ok_c)}
     del outs, plan, one
     g.close()
 
@@ -283,80 +359,139 @@ def variants_section(args, sssp, torch, np, graphgen):
 
 
 def served_section(args, sssp, torch, np, graphgen):
-    """Poisson stream of single-source queries over resident graphs (RMAT-20,
-    RMAT-22, RMAT-23 and the 2048 x 2048 road-like grid), graph uniform per
-    query, served with continuous batching; against plain one-at-a-time FIFO
-    solves of the same trace (service times measured solo, queueing applied)."""
+    """Served SSSP over resident graphs (RMAT-20, RMAT-22, RMAT-23 and the
+    2048 x 2048 road-like grid): N single-source queries, graph uniform per
+    query, sources among each graph's vertices of degree >= 1.
+
+    * Plain FIFO: one solve at a time in arrival order, run for real at the
+      arrival rate of the FIFO capacity (lambda = 1.0); its per-query service
+      times give FIFO's capacity and its latencies at the other rates (one
+      server, one query at a time: finish = max(finish, arrival) + service).
+    * Served: the continuous-batching server at saturation (every query
+      submitted at once: its capacity), then a Poisson stream at lambda =
+      {0.5, 0.8, 1.0, 1.25} x FIFO capacity: throughput, p50 and p99 latency
+      from submission to completion.
+    Every served result is compared with the same query solved alone."""
     names = ["rmat20", "rmat22", "rmat23", "grid2048"]
     wls = [graphgen.workload(nm) for nm in names]
     gs = [sssp.Graph.from_csr(w.csr) for w in wls]
     N = args.serve_queries
+    loads = [float(x) for x in args.serve_loads.split(",")]
+    rng = np.random.default_rng(graphgen.SEED_BASE + 7)
+    which = rng.integers(0, len(gs), size=N)
+    unit_gaps = rng.exponential(1.0, size=N)  # a unit-rate Poisson stream, scaled per load
     pools = [[int(x) for x in w.sources(N)] for w in wls]
-    # capacity of one-at-a-time solves on this mix
-    one = [torch.empty(w.csr.n, dtype=torch.uint32, device="cuda") for w in wls]
-    cal = []
-    for gi, gg in enumerate(gs):
-        for s in pools[gi][-2:]:
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            gg.solve(s, out=one[gi])
-            torch.cuda.synchronize()
-            cal.append(time.perf_counter() - t0)
-    mean_service = sum(cal) / len(cal)
-    rate = args.serve_load / mean_service
-    arrivals, which = graphgen.poisson_trace(N, rate, len(gs))
     queries = [(int(which[q]), pools[int(which[q])][q]) for q in range(N)]
-    # plain: each query alone, in arrival order, one at a time
-    solo = []
-    service = []
-    for gi, s in queries:
-        o = torch.empty(wls[gi].csr.n, dtype=torch.uint32, device="cuda")
+    pct = lambda xs, p: float(np.percentile(np.asarray(xs), p) * 1e3)
+    # FIFO capacity, calibrated on 8 queries of each graph
+    one = [torch.empty(w.csr.n, dtype=torch.uint32, device="cuda") for w in wls]
+    per_graph = []
+    for gi, gg in enumerate(gs):
+        gg.solve(pools[gi][-1], out=one[gi])
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        gs[gi].solve(s, out=o)
+        for s in pools[gi][-9:-1]:
+            gg.solve(s, out=one[gi])
         torch.cuda.synchronize()
-        service.append(time.perf_counter() - t0)
-        solo.append(o)
-    fin = 0.0
-    fifo_lat = []
-    for a, sv in zip(arrivals, service):
-        fin = max(fin, a) + sv
-        fifo_lat.append(fin - a)
-    fifo_span = fin - arrivals[0]
-    # served
-    srv = sssp.Server(budget_bytes=args.serve_budget_gib << 30, max_batch=args.serve_slots,
-                      ticks_per_launch=args.serve_ticks)
-    ids = [srv.add_graph(gg) for gg in gs]
-    outs = [torch.empty(wls[gi].csr.n, dtype=torch.uint32, device="cuda") for gi, _ in queries]
-    tickets = []
-    t0 = time.perf_counter()
+        per_graph.append((time.perf_counter() - t0) / 8)
+    cap0 = 1.0 / (sum(per_graph) / len(per_graph))
+    log("served mix: one-at-a-time service %s ms -> FIFO capacity %.2f q/s"
+        % ([round(x * 1e3, 2) for x in per_graph], cap0))
+    # plain FIFO for real at lambda = 1.0: the solo results are kept for the
+    # comparison with the served ones
+    arrivals = np.cumsum(unit_gaps) / cap0
+    arrivals -= arrivals[0]
+    solo = [torch.empty(wls[gi].csr.n, dtype=torch.uint32, device="cuda") for gi, _ in queries]
+    service, fifo_lat = [], []
+    t_start = time.perf_counter()
     for q, (gi, s) in enumerate(queries):
-        delay = arrivals[q] - (time.perf_counter() - t0)
-        if delay > 0:
-            time.sleep(delay)
-        tickets.append(srv.submit(ids[gi], s, outs[q]))
-    for t in tickets:
-        srv.wait(t)
-    infos = [srv.info(t) for t in tickets]
-    st = srv.stats()
-    srv.close()
-    lat = [(i["done_us"] - i["submit_us"]) * 1e-6 for i in infos]
-    span = (max(i["done_us"] for i in infos) - min(i["submit_us"] for i in infos)) * 1e-6
-    same = all(bool(torch.equal(a, b)) for a, b in zip(outs, solo))
-    pct = lambda xs, p: float(np.percentile(np.asarray(xs), p) * 1e3)
+        now = time.perf_counter() - t_start
+        if arrivals[q] > now:
+            time.sleep(arrivals[q] - now)
+        t0 = time.perf_counter()
+        gs[gi].solve(s, out=solo[q])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        service.append(t1 - t0)
+        fifo_lat.append(t1 - t_start - arrivals[q])
+    fifo_cap = N / sum(service)
+    log("plain FIFO at %.2f q/s (run): p50 %.1f ms p99 %.1f ms; capacity over all %d queries %.2f q/s"
+        % (cap0, pct(fifo_lat, 50), pct(fifo_lat, 99), N, fifo_cap))
+
+    def fifo_at(rate):
+        arr = np.cumsum(unit_gaps) / rate
+        arr -= arr[0]
+        fin, lat = 0.0, []
+        for a, sv in zip(arr, service):
+            fin = max(fin, a) + sv
+            lat.append(fin - a)
+        return {"queries_per_s": round(N / fin, 3), "p50_ms": round(pct(lat, 50), 2),
+                "p99_ms": round(pct(lat, 99), 2)}
+
+    outs = [torch.empty(wls[gi].csr.n, dtype=torch.uint32, device="cuda") for gi, _ in queries]
+
+    def serve(rate):
+        srv = sssp.Server(budget_bytes=args.serve_budget_gib << 30, max_batch=args.serve_slots,
+                          ticks_per_launch=args.serve_ticks)
+        ids = [srv.add_graph(gg) for gg in gs]
+        for o in outs:
+            o.fill_(0)
+        torch.cuda.synchronize()
+        tickets = []
+        t0 = time.perf_counter()
+        if rate is None:
+            arr = np.zeros(N)
+        else:
+            arr = np.cumsum(unit_gaps) / rate
+            arr -= arr[0]
+        for q, (gi, s) in enumerate(queries):
+            delay = arr[q] - (time.perf_counter() - t0)
+            if delay > 0:
+                time.sleep(delay)
+            tickets.append(srv.submit(ids[gi], s, outs[q]))
+        for t in tickets:
+            srv.wait(t)
+        infos = [srv.info(t) for t in tickets]
+        st = srv.stats()
+        srv.close()
+        lat = [(i["done_us"] - i["submit_us"]) * 1e-6 for i in infos]
+        span = (max(i["done_us"] for i in infos) - min(i["submit_us"] for i in infos)) * 1e-6
+        same = all(bool(torch.equal(a, b)) for a, b in zip(outs, solo))
+        ok = all(i["status"] == 0 for i in infos)
+        return {"queries_per_s": round(N / span, 3), "p50_ms": round(pct(lat, 50), 2),
+                "p99_ms": round(pct(lat, 99), 2), "peak_in_flight": st["peak_active"],
+                "engine_launches": st["launches"], "peak_in_use_bytes": st["peak_in_use_bytes"],
+                "all_ok": ok, "equal_to_alone": same}
+
+    sat = serve(None)
+    log("served at saturation (all %d submitted at once): %.2f q/s; equal to alone: %s"
+        % (N, sat["queries_per_s"], sat["equal_to_alone"]))
+    sweep = []
+    for f in loads:
+        rate = f * cap0
+        r = serve(rate)
+        r.update({"load": f, "arrival_rate_per_s": round(rate, 3)})
+        r["plain_fifo"] = fifo_at(rate)
+        if f == 1.0:
+            r["plain_fifo_run"] = {"queries_per_s": round(N / (t1 - t_start), 3),
+                                   "p50_ms": round(pct(fifo_lat, 50), 2), "p99_ms": round(pct(fifo_lat, 99), 2)}
+        sweep.append(r)
+        log("served at %.2f x FIFO capacity (%.2f q/s): %.2f q/s p50 %.1f ms p99 %.1f ms | FIFO %.2f q/s "
+            "p50 %.1f p99 %.1f; equal: %s" % (f, rate, r["queries_per_s"], r["p50_ms"], r["p99_ms"],
+                                                 r["plain_fifo"]["queries_per_s"], r["plain_fifo"]["p50_ms"],
+                                                 r["plain_fifo"]["p99_ms"], r["equal_to_alone"]))
     res = {
-        "queries": N, "graphs": names, "arrival_rate_per_s": round(rate, 2),
-        "load_vs_one_at_a_time_capacity": args.serve_load,
-        "queries_per_s": round(N / span, 2), "p50_ms": round(pct(lat, 50), 2),
-        "p99_ms": round(pct(lat, 99), 2),
-        "plain_fifo": {"queries_per_s": round(N / fifo_span, 2), "p50_ms": round(pct(fifo_lat, 50), 2),
-                       "p99_ms": round(pct(fifo_lat, 99), 2)},
-        "peak_in_flight": st["peak_active"], "engine_launches": st["launches"],
-        "budget_bytes": st["budget_bytes"], "peak_in_use_bytes": st["peak_in_use_bytes"],
-        "results_equal_alone_and_in_mix": same}
-    log("served: %.2f q/s p50 %.1f ms p99 %.1f ms (plain FIFO %.2f q/s p50 %.1f p99 %.1f); equal: %s"
-        % (N / span, res["p50_ms"], res["p99_ms"], N / fifo_span, res["plain_fifo"]["p50_ms"],
-           res["plain_fifo"]["p99_ms"], same))
+        "queries": N, "graphs": names, "slots": args.serve_slots, "ticks_per_launch": args.serve_ticks,
+        "budget_bytes": args.serve_budget_gib << 30,
+        "one_at_a_time_ms_per_graph": [round(x * 1e3, 3) for x in per_graph],
+        "fifo_capacity_per_s": round(cap0, 3), "fifo_capacity_all_queries_per_s": round(fifo_cap, 3),
+        "saturation": {"served_queries_per_s": sat["queries_per_s"],
+                       "plain_fifo_queries_per_s": round(fifo_cap, 3),
+                       "speedup": round(sat["queries_per_s"] / fifo_cap, 2),
+                       "equal_to_alone": sat["equal_to_alone"], "all_ok": sat["all_ok"]},
+        "sweep": sweep,
+        "fifo_note": "plain FIFO was run at load 1.0 (plain_fifo_run); plain_fifo at each load applies "
+                     "one-server FIFO queueing to the service times measured in that run"}
     if not args.no_cpu_baseline:
         # the oracle on a bounded sample of the same stream: the first 8 queries
         # of each graph, each graph's on a thread pool; every result is also
@@ -381,11 +516,12 @@ def served_section(args, sssp, torch, np, graphgen):
             agree = agree and all(np.array_equal(ref[j], outs[q].cpu().numpy()) for j, q in enumerate(qs))
         res["cpu_baseline"] = {
             "value": round(nq / dtc, 3), "unit": "queries/s", "cores": threads, "kind": "oracle",
-            "sample": "binary-heap Dijkstra (the oracle), the first %d queries of each graph in the stream "
-                      "(%d in all), each graph's on a %d-thread pool, %.1f s; all equal the served results: %s"
-                      % (per, nq, threads, dtc, agree)}
+            "sample": "binary-heap Dijkstra (the oracle, %s), the first %d queries of each graph in the "
+                      "stream (%d in all), each graph's on a %d-thread pool, %.1f s; all equal the served "
+                      "results: %s" % (ORACLE_BUILD, per, nq, threads, dtc, agree)}
         log("served mix on the oracle: %.2f queries/s on %d threads (%d queries, %.1f s); equal: %s"
             % (nq / dtc, threads, nq, dtc, agree))
+    del outs, solo, one
     for gg in gs:
         gg.close()
     return res
@@ -402,9 +538,11 @@ def main():
     ap.add_argument("--no-served", action="store_true", help="skip the served measurements")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the integer-power weight variants of RMAT-22")
-    ap.add_argument("--serve-queries", type=int, default=128)
-    ap.add_argument("--serve-load", type=float, default=0.8,
-                    help="arrival rate as a fraction of the one-at-a-time capacity of the mix")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the other plain configurations (RMAT-14, ER-22, the 2048^2 grid)")
+    ap.add_argument("--serve-queries", type=int, default=1024)
+    ap.add_argument("--serve-loads", default="0.5,0.8,1.0,1.25",
+                    help="arrival rates as fractions of the one-at-a-time (FIFO) capacity of the mix")
     ap.add_argument("--serve-slots", type=int, default=64)
     ap.add_argument("--serve-ticks", type=int, default=64)
     ap.add_argument("--serve-budget-gib", type=int, default=64)
@@ -422,6 +560,19 @@ def main():
 
     import graphgen
     import paper_2506_19349_amd as sssp
+
+    global ORACLE_BUILD
+    if not args.no_cpu_baseline:
+        # the oracle timed as a CPU baseline is built for the host that runs it
+        import tempfile
+        from oracle import build as obuild, native
+        try:
+            native.use_build(obuild.build_for_this_host(tempfile.mkdtemp(prefix="oracle_")))
+            ORACLE_BUILD = "gcc -O3 -march=native -ffp-contract=off"
+        except Exception as e:  # the portable in-tree build stays in use
+            log("oracle: host-tuned build failed (%s); timing the in-tree -O3 build" % e)
+            ORACLE_BUILD = "gcc -O3 -ffp-contract=off (in-tree)"
+        log("oracle for the CPU baselines: %s" % ORACLE_BUILD)
 
     torch.cuda.set_device(0)
     t = time.time()
@@ -548,9 +699,9 @@ def main():
         adj.close()
         parity = bool(np.array_equal(ref, outs[0].cpu().numpy()))
         cpu = {"value": round(m_cc[-1] / dt / 1e9, 6), "unit": "GTEPS", "cores": 1, "kind": "oracle",
-               "sample": "binary-heap Dijkstra (the oracle%s), 1 thread, one source of the same "
+               "sample": "binary-heap Dijkstra (the oracle%s, %s), 1 thread, one source of the same "
                          "%s graph, %.1f s; GPU result for it bit-exact: %s"
-                         % (", binary32" if fw else "", wl.name, dt, parity)}
+                         % (", binary32" if fw else "", ORACLE_BUILD, wl.name, dt, parity)}
         log("oracle: %.2f s for one source -> %.4f GTEPS; GPU bit-exact: %s" % (dt, cpu["value"], parity))
 
     if args.calibrate_copy:
@@ -567,9 +718,20 @@ def main():
     batched = None
     served = None
     variants = None
+    configs = None
     if wl.name == "rmat24":
         del outs
         g.close()
+        if not args.no_configs:
+            configs = {
+                "rmat14": config_section(args, sssp, torch, np, graphgen, "rmat14", 1, 16,
+                                         "R-MAT scale 14, edge factor 16, one seeded source (solved 16 times)"),
+                "er22": config_section(args, sssp, torch, np, graphgen, "er22", 8, 2,
+                                       "G(n, m), n = 2^22, mean degree 32, 8 seeded sources one at a time"),
+                "grid2048": config_section(args, sssp, torch, np, graphgen, "grid2048", 4, 1,
+                                           "2048 x 2048 grid, 5% of edges dropped, 1% diagonals, "
+                                           "w in 1..1000, 4 seeded sources"),
+            }
         if not args.no_batched:
             batched = batched_section(args, sssp, torch, np, graphgen)
         if not args.no_served:
@@ -608,6 +770,7 @@ def main():
                      "kernel": "k_engine", "kernel_us_mean": round(eng_mean_us, 2),
                      "alg_bytes_per_launch": int(sum(B) / len(B))},
         "cpu_baseline": cpu,
+        "configs": configs,
         "ablation_filter_off": ablation,
         "batched": batched,
         "served": served,

@@ -15,14 +15,24 @@ OK, BAD_ARGS, NOMEM, OVERFLOW = 0, -1, -2, 1
 INF = 0xFFFFFFFF
 
 
-def _load():
+def use_build(path: str) -> None:
+    """Load another build of the same source (say one tuned for this host)
+    in place of the in-tree library, for every later call."""
+    global _lib
+    _lib = None
+    _load(path)
+
+
+def _load(path: str = None):
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB_PATH):
-        from . import build as _b
-        _b.build()
-    lib = ctypes.CDLL(_LIB_PATH)
+    if path is None:
+        path = _LIB_PATH
+        if not os.path.exists(path):
+            from . import build as _b
+            _b.build()
+    lib = ctypes.CDLL(path)
     i32p = ctypes.POINTER(ctypes.c_int32)
     u32p = ctypes.POINTER(ctypes.c_uint32)
     i64 = ctypes.c_int64
