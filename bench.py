@@ -549,6 +549,9 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with three 1 GiB device-to-device copies (reference kernel for "
                          "scaling the FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--calibrate-gather", action="store_true",
+                    help="end with three random gathers of 2^22 distinct 64-byte rows of a 4 GiB "
+                         "table (reference kernel of known bytes for random 64-byte reads)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the solver runs on a single GPU "
@@ -714,6 +717,22 @@ def main():
         torch.cuda.synchronize()
         del a, b
         log("calibration copies done (3 x 1 GiB)")
+    if args.calibrate_gather:
+        # 2^22 distinct rows of 64 bytes (8 int64) at random positions of a
+        # 2^26-row table (4 GiB, beyond the last-level cache): 256 MiB read by
+        # 64-byte random gathers, 256 MiB written contiguously
+        rows = 1 << 26
+        tab = torch.empty((rows, 8), dtype=torch.int64, device="cuda")
+        tab.fill_(1)
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(wl.seed)
+        idx = torch.randperm(rows, device="cuda", generator=gen)[: 1 << 22].contiguous()
+        torch.cuda.synchronize()
+        for _ in range(3):
+            out = torch.index_select(tab, 0, idx)
+        torch.cuda.synchronize()
+        del tab, idx, out
+        log("calibration gathers done (3 x 2^22 random 64-byte rows)")
 
     batched = None
     served = None

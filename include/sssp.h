@@ -66,7 +66,11 @@ typedef struct {
   int32_t fuse_rounds;   /* bucket fusion (Section 4.1's FUSED): rounds one workgroup may chain
                             without a grid-wide synchronisation while the frontier fits one
                             batch; 0 -> 256, -1 -> off */
-  int32_t reserved[8];
+  int32_t tile_shape;    /* engine tile shape (one kernel instantiation each): 0 -> default (1);
+                            1: 512-item round batches, 1024-item settle batches; 2: 1024-item
+                            round batches (longer rounds within one workgroup, 3 workgroups per
+                            CU); 3: 256-item round batches; 4: 2048-item settle batches */
+  int32_t reserved[7];
 } sssp_options;
 
 /* Work counters of one solve (the paper's Section 4 measures). */
@@ -113,7 +117,9 @@ typedef struct {
   int32_t distinct_degrees;
   uint32_t max_weight;  /* maxW(G, 1) */
   uint32_t high_d0;     /* highD(0) over the whole vertex set */
-  uint32_t reserved;
+  uint32_t hub_first;   /* vertices the preparation moved to the front of its internal order
+                           (rows of at least 4x the mean degree, at most 2^19; 0: the caller's
+                           order is kept). Ids in and out of every call stay the caller's. */
   uint64_t device_bytes; /* device memory held by the graph */
 } sssp_graph_info;
 
@@ -307,14 +313,18 @@ typedef struct {
 
 /* Time the workload -- k (graph, source) pairs, solved one at a time
  * (batched = 0) or as one k-instance launch (batched = 1) -- under candidate
- * launch knobs and return the fastest in *inout: workgroups per CU (grid
- * size), the heavy-row split threshold (rows above it are spread over the
- * grid in 256-entry chunks), bucket fusion on/off, and, when tune_beta is
- * nonzero, beta of Eq. (1) (the step width; 0.9 is the paper's value). Knobs
- * are tuned one at a time from the values passed in (coordinate descent), each
- * candidate measured by HIP events around the engine launch after one untimed
- * pass. No knob changes a distance. Synchronous; allocates scratch distance
- * buffers for the trials. report may be NULL. */
+ * launch knobs and return the fastest in *inout. The knobs, in this order:
+ * the tile shape (tile_shape 1..4: round batches of 512, 1024 or 256 items,
+ * settle batches of 1024 or 2048), workgroups per CU (1, 2, or all the
+ * shape's kernel allows), the heavy-row split threshold (64, 256, 1024, 4096:
+ * ranges above it are spread over the grid in 256-entry chunks), bucket
+ * fusion on/off, and, when tune_beta is nonzero, beta of Eq. (1) in {0.85,
+ * 0.9, 0.95} (Section 4.3 finds the method insensitive there; 0.9 is the
+ * paper's value). Knobs are tuned one at a time from the values passed in
+ * (coordinate descent), each candidate measured by HIP events around the
+ * engine launch after one untimed pass. No knob changes a distance; beta
+ * changes the schedule. Synchronous; allocates scratch distance buffers for
+ * the trials. report may be NULL. */
 sssp_status sssp_autotune(const sssp_graph* const* gs, const int32_t* sources, int32_t k, int32_t batched,
                           int32_t tune_beta, sssp_options* inout, sssp_tune_report* report,
                           hipStream_t stream);
@@ -404,14 +414,17 @@ sssp_status sssp_server_destroy(sssp_server* s);
 /* ---- debugging ---------------------------------------------------------- */
 
 /* Enable (cap > 0) or disable (cap = 0) a per-tick log of the engine for the
- * solves that follow on `stream`: for each device-wide tick, four uint64 --
- * the 100 MHz wall clock when the tick's last workgroup arrived, the tick's
- * work batches, bits of instance 0's state (tick kind | init round << 8 |
- * pull << 9 | step << 16), and the wall clock when the next tick was released.
- * Synchronises the stream. */
+ * solves that follow on `stream`: for each device-wide tick, eight uint64 on
+ * the 100 MHz wall clock unless stated -- [0] when the tick's last workgroup
+ * arrived at the barrier, [1] the tick's work batches, [2] bits of instance
+ * 0's state (tick kind | init round << 8 | pull << 9 | step << 16), [3] when
+ * the next tick was released, [4] when the tick's first batch started, [5]
+ * when its last workgroup finished its batches, [6] and [7] when the step's
+ * heuristic started and ended (0 if none ran in the tick). Synchronises the
+ * stream. */
 sssp_status sssp_debug_tick_log(hipStream_t stream, int32_t cap);
 
-/* Copy the tick log of the last solve on `stream` (cap entries of four uint64
+/* Copy the tick log of the last solve on `stream` (cap entries of eight uint64
  * into out); *len receives the tick count, *t_start the engine's start time. */
 sssp_status sssp_debug_get_tick_log(hipStream_t stream, uint64_t* out, int32_t cap, int32_t* len,
                                     uint64_t* t_start);

@@ -91,7 +91,7 @@ def _as_u32(a):
 
 
 def _options(traversal_opt=True, alpha=None, beta=None, host_driven=False, blocks_per_cu=0,
-             heavy_split=0, fuse_rounds=0):
+             heavy_split=0, fuse_rounds=0, tile_shape=0):
     o = _lib.Options()
     o.traversal_opt = 1 if traversal_opt else -1
     o.alpha = int(alpha or 0)
@@ -100,6 +100,7 @@ def _options(traversal_opt=True, alpha=None, beta=None, host_driven=False, block
     o.blocks_per_cu = int(blocks_per_cu)
     o.heavy_split = int(heavy_split)
     o.fuse_rounds = int(fuse_rounds)
+    o.tile_shape = int(tile_shape)
     return o
 
 
@@ -353,7 +354,7 @@ def autotune(graphs: Sequence[Graph], sources: Sequence[int], batched: bool = Fa
                                   ctypes.byref(rep), _stream_handle(stream)))
     tuned = {"traversal_opt": o.traversal_opt >= 0, "alpha": o.alpha, "beta": o.beta,
              "blocks_per_cu": o.blocks_per_cu, "heavy_split": o.heavy_split,
-             "fuse_rounds": o.fuse_rounds}
+             "fuse_rounds": o.fuse_rounds, "tile_shape": o.tile_shape}
     report = {"default_us": rep.default_us, "best_us": rep.best_us, "evaluations": rep.evaluations}
     return tuned, report
 
@@ -469,19 +470,27 @@ def debug_tick_log(enable_cap: int, stream=None) -> None:
 
 
 def debug_get_tick_log(stream=None, cap: int = 1 << 16):
-    """Per-tick log of the last solve: list of (t_end_us, batches, kind_bits, epilogue_us),
-    times in microseconds from the engine start (100 MHz clock)."""
-    buf = np.empty((cap, 4), np.uint64)
+    """Per-tick log of the last solve: one dict per tick with times in
+    microseconds from the engine start (100 MHz clock): `arrive` (last
+    workgroup at the barrier), `release` (next tick released), `first`
+    and `last` (earliest batch start, latest batch end), `heur` and
+    `heur_end` (the step's heuristic, None if none ran), and `batches`, `kind`
+    (tick kind | init round << 8 | pull << 9 | step << 16)."""
+    buf = np.empty((cap, 8), np.uint64)
     n = ctypes.c_int32(0)
     t0 = ctypes.c_uint64(0)
     _lib.check(_lib.sssp_debug_get_tick_log(_stream_handle(stream), buf.ctypes.data, cap,
                                             ctypes.byref(n), ctypes.byref(t0)))
     m = min(cap, n.value)
+    base = t0.value
+    us = lambda x: (int(x) - base) / 100.0
     out = []
     for i in range(m):
         e = buf[i]
-        out.append(((int(e[0]) - t0.value) / 100.0, int(e[1]), int(e[2]),
-                    (int(e[3]) - int(e[0])) / 100.0))
+        out.append({"arrive": us(e[0]), "batches": int(e[1]), "kind": int(e[2]), "release": us(e[3]),
+                    "first": us(e[4]) if int(e[4]) != 0xFFFFFFFFFFFFFFFF else None,
+                    "last": us(e[5]) if int(e[5]) else None,
+                    "heur": us(e[6]) if int(e[6]) else None, "heur_end": us(e[7]) if int(e[7]) else None})
     return out
 
 

@@ -29,7 +29,7 @@ u32p = ctypes.POINTER(ctypes.c_uint32)
 class Options(ctypes.Structure):
     _fields_ = [("traversal_opt", i32), ("alpha", i32), ("beta", ctypes.c_double),
                 ("host_driven", i32), ("blocks_per_cu", i32), ("heavy_split", i32),
-                ("fuse_rounds", i32), ("reserved", i32 * 8)]
+                ("fuse_rounds", i32), ("tile_shape", i32), ("reserved", i32 * 7)]
 
 
 class Counters(ctypes.Structure):
@@ -49,7 +49,7 @@ class Step(ctypes.Structure):
 class GraphInfo(ctypes.Structure):
     _fields_ = [("n", i32), ("nnz", i32), ("nonisolated", i32), ("max_degree", i32),
                 ("distinct_degrees", i32), ("max_weight", u32), ("high_d0", u32),
-                ("reserved", u32), ("device_bytes", ctypes.c_uint64)]
+                ("hub_first", u32), ("device_bytes", ctypes.c_uint64)]
 
 
 class TuneReport(ctypes.Structure):

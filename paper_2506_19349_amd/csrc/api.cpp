@@ -197,8 +197,12 @@ bool ws_setup(Workspace& w, hipStream_t stream, std::string* err) {
     return false;
   }
   w.cus = prop.multiProcessorCount;
-  w.occ = engine_blocks_per_cu();
-  w.grid = w.cus * w.occ;
+  w.occ = 1;
+  for (int sh = 0; sh < kNumShapes; ++sh) {
+    w.occ_s[sh] = engine_blocks_per_cu(sh);
+    w.occ = std::max(w.occ, w.occ_s[sh]);
+  }
+  w.grid = w.cus * w.occ_s[SHAPE_STD];
   for (int i = 0; i < Workspace::kStages; ++i) {
     if (hipEventCreateWithFlags(&w.stage_ev[i], hipEventDisableTiming) != hipSuccess) {
       *err = "hipEventCreate failed";
@@ -297,6 +301,11 @@ bool parse_opts(const sssp_options* o, Opts* r, std::string* err) {
   if (o->heavy_split > 0) r->heavy = std::max(o->heavy_split, kDefaultHeavy);
   if (o->fuse_rounds < 0) r->fuse = 0;
   else if (o->fuse_rounds > 0) r->fuse = o->fuse_rounds;
+  if (o->tile_shape < 0 || o->tile_shape > kNumShapes) {
+    *err = "tile_shape must be in 0.." + std::to_string(kNumShapes);
+    return false;
+  }
+  if (o->tile_shape > 0) r->shape = o->tile_shape - 1;
   return true;
 }
 
@@ -398,6 +407,8 @@ sssp_status run_instances_ws(Workspace& w, const sssp_graph* const* gs, const in
   hG->insts = w.dInst;
   hG->sel_list = nullptr;
   hG->n_sel = -1;
+  hG->round_batch = round_batch_of(o.shape);
+  hG->settle_batch = settle_batch_of(o.shape);
   for (int i = 0; i < k; ++i) {
     fill_inst(hI[i], w.slots[(size_t)i], gs[i], sources[i], dists[i], o, parents ? parents[i] : nullptr);
     if (targets) hI[i].target = targets[i];
@@ -413,7 +424,7 @@ sssp_status run_instances_ws(Workspace& w, const sssp_graph* const* gs, const in
   if (!host_driven) {
     long long total_n = 0;
     for (int i = 0; i < k; ++i) total_n += gs[i]->gh.h.n;
-    hipError_t e = launch_engine(w.dG, engine_grid(w, o, total_n), true, 0, stream);
+    hipError_t e = launch_engine(w.dG, engine_grid(w, o, total_n), true, 0, stream, o.shape);
     if (e != hipSuccess) {
       (void)hipGetLastError();
       w.persistent_failed = true;
@@ -422,9 +433,9 @@ sssp_status run_instances_ws(Workspace& w, const sssp_graph* const* gs, const in
   }
   if (host_driven) {
     // one tick per launch; the host polls the completion flag
-    const int grid = w.cus * std::max(1, std::min(w.occ, 8));
+    const int grid = w.cus * std::max(1, std::min(w.occ_s[o.shape], 8));
     for (long long t = 0;; ++t) {
-      HIP_TRY(launch_engine(w.dG, grid, false, 0, stream));
+      HIP_TRY(launch_engine(w.dG, grid, false, 0, stream, o.shape));
       HIP_TRY(hipMemcpyAsync(w.pinned_flag, &w.dG->all_done, sizeof(unsigned int) * 2,
                              hipMemcpyDeviceToHost, stream));
       HIP_TRY(hipStreamSynchronize(stream));
@@ -441,12 +452,14 @@ sssp_status run_instances_ws(Workspace& w, const sssp_graph* const* gs, const in
 }
 
 int engine_grid(const Workspace& w, const Opts& o, long long total_n) {
-  const int bpc = o.blocks_per_cu > 0 ? std::min(o.blocks_per_cu, w.occ) : w.occ;
+  const int occ = w.occ_s[o.shape];
+  const int bpc = o.blocks_per_cu > 0 ? std::min(o.blocks_per_cu, occ) : occ;
   const int full = w.cus * bpc;
   if (o.blocks_per_cu > 0) return full;  // an explicit choice is honoured
   // no tick has more batches than the vertices fill: small graphs take a
   // smaller grid (cheaper barriers), a multiple of the XCD count
-  long long need = (total_n + kRoundBatch - 1) / kRoundBatch;
+  const int rb = round_batch_of(o.shape);
+  long long need = (total_n + rb - 1) / rb;
   need = ((need + kMaxXcd - 1) / kMaxXcd) * kMaxXcd;
   if (need < kMaxXcd) need = kMaxXcd;
   return (int)std::min<long long>(full, need);
@@ -580,6 +593,7 @@ sssp_status sssp_graph_info_get(const sssp_graph* g, sssp_graph_info* out) {
   out->distinct_degrees = g->gh.distinct_degrees;
   out->max_weight = h.max_w;
   out->high_d0 = h.high_d0;
+  out->hub_first = (uint32_t)h.relabelled;
   out->device_bytes = g->gh.bytes;
   return ok();
 }
@@ -591,9 +605,35 @@ sssp_status sssp_graph_sorted_rows(const sssp_graph* g, int32_t* col_out, uint32
   if (h.nnz > 0 && (!col_out || !w_out)) return fail(SSSP_E_INVAL, "NULL output");
   std::vector<uint64_t> tmp((size_t)h.nnz);
   if (h.nnz > 0) HIP_TRY(hipMemcpy(tmp.data(), h.adj, sizeof(uint64_t) * (size_t)h.nnz, hipMemcpyDeviceToHost));
-  for (size_t e = 0; e < tmp.size(); ++e) {
-    col_out[e] = (int32_t)(uint32_t)(tmp[e] & 0xffffffffull);
-    w_out[e] = (uint32_t)(tmp[e] >> 32);
+  if (!h.new_of_old) {
+    for (size_t e = 0; e < tmp.size(); ++e) {
+      col_out[e] = (int32_t)(uint32_t)(tmp[e] & 0xffffffffull);
+      w_out[e] = (uint32_t)(tmp[e] >> 32);
+    }
+    return ok();
+  }
+  // hub-first internal order: rows and columns back to the caller's ids, each
+  // row re-sorted by (weight, caller's column)
+  const size_t n = (size_t)h.n;
+  std::vector<int32_t> rp(n + 1), ren(n), back(n);
+  HIP_TRY(hipMemcpy(rp.data(), h.rowptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(ren.data(), h.new_of_old, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(back.data(), h.old_of_new, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+  size_t pos = 0;
+  std::vector<uint64_t> row;
+  for (size_t u = 0; u < n; ++u) {
+    const int32_t r = ren[u];
+    row.clear();
+    for (int32_t e = rp[(size_t)r]; e < rp[(size_t)r + 1]; ++e) {
+      const uint64_t k = tmp[(size_t)e];
+      row.push_back((k & 0xffffffff00000000ull) | (uint32_t)back[(size_t)(uint32_t)(k & 0xffffffffull)]);
+    }
+    std::sort(row.begin(), row.end());
+    for (uint64_t k : row) {
+      col_out[pos] = (int32_t)(uint32_t)(k & 0xffffffffull);
+      w_out[pos] = (uint32_t)(k >> 32);
+      ++pos;
+    }
   }
   return ok();
 }
@@ -772,7 +812,7 @@ sssp_status sssp_debug_tick_log(hipStream_t stream, int32_t cap) {
   w->d_tick_log = nullptr;
   w->tick_log_cap = 0;
   if (cap > 0) {
-    HIP_TRY(hipMalloc(&w->d_tick_log, sizeof(unsigned long long) * 4 * (size_t)cap));
+    HIP_TRY(hipMalloc(&w->d_tick_log, sizeof(unsigned long long) * kTickLogWords * (size_t)cap));
     w->tick_log_cap = cap;
   }
   return ok();
@@ -792,7 +832,7 @@ sssp_status sssp_debug_get_tick_log(hipStream_t stream, uint64_t* out, int32_t c
   *len = (int32_t)hg.ticks;
   *t_start = hg.t_start;
   m = std::min(m, cap);
-  if (m > 0) HIP_TRY(hipMemcpy(out, w->d_tick_log, sizeof(uint64_t) * 4 * (size_t)m, hipMemcpyDeviceToHost));
+  if (m > 0) HIP_TRY(hipMemcpy(out, w->d_tick_log, sizeof(uint64_t) * kTickLogWords * (size_t)m, hipMemcpyDeviceToHost));
   return ok();
 }
 

@@ -20,14 +20,33 @@ constexpr uint32_t kNoBin = 0xFFFFFFFFu; // a distance too large for the grid
 constexpr int kLdsHist = 1024;           // settle: degree ranks privatised in LDS
 constexpr int kHeavyChunk = 256;         // edges per heavy chunk
 constexpr int kDefaultHeavy = 64;        // ranges longer than this are split (also the least split allowed)
-constexpr int kStageCap = 1280;          // LDS staging of list appends per workgroup batch
-constexpr int kItemsPerThread = 2;       // round batches: items per thread
-constexpr int kRoundBatch = kBlock * kItemsPerThread;  // items per workgroup batch
-constexpr int kEdgesPerThread = 2;       // edges a thread relaxes per pass of a round batch
 constexpr int kHeavyPerBatch = 16;       // heavy chunks per workgroup batch
-constexpr int kSettlePer = 4;            // settle batches: items per thread
-constexpr int kSettleBatch = kBlock * kSettlePer;
 constexpr int kDefaultFuse = 256;        // rounds a workgroup may chain on a small frontier
+
+// Tile shapes of the engine: each is its own instantiation of the engine
+// kernel (a launch picks one; none changes a distance or the schedule).
+template <int kIt, int kEd, int kSe, int kOcc>
+struct TileShape {
+  static constexpr int kItems = kIt;                     // round batches: items per thread
+  static constexpr int kBatch = kBlock * kIt;            // items per round batch
+  static constexpr int kEdges = kEd;                     // edges a thread relaxes per pass
+  static constexpr int kSettle = kSe;                    // settle batches: items per thread
+  static constexpr int kSettleBatch = kBlock * kSe;      // items per settle batch
+  static constexpr int kStage = kBatch + kBlock * kEd + 256;  // LDS staging of list appends
+  static constexpr int kMinBlocks = kOcc;                // workgroups per CU budgeted for
+};
+using ShapeStd = TileShape<2, 2, 4, 5>;     // 512-item round batches
+using ShapeWide = TileShape<4, 2, 4, 3>;    // 1024-item round batches: longer single-workgroup rounds
+using ShapeNarrow = TileShape<1, 2, 4, 5>;  // 256-item round batches: more batches per frontier
+using ShapeSettle8 = TileShape<2, 2, 8, 5>; // 2048-item settle batches
+enum ShapeId : int { SHAPE_STD = 0, SHAPE_WIDE = 1, SHAPE_NARROW = 2, SHAPE_SETTLE8 = 3, kNumShapes = 4 };
+constexpr int round_batch_of(int shape) {
+  return shape == SHAPE_WIDE ? ShapeWide::kBatch : shape == SHAPE_NARROW ? ShapeNarrow::kBatch
+                                                                           : ShapeStd::kBatch;
+}
+constexpr int settle_batch_of(int shape) {
+  return shape == SHAPE_SETTLE8 ? ShapeSettle8::kSettleBatch : ShapeStd::kSettleBatch;
+}
 
 // ------------------------------------------------------------------ graph --
 // An unsettled-list (pull-list) entry: the vertex, the smallest weight of its
@@ -78,7 +97,19 @@ struct DevGraph {
   // row whose weight is >= b * rwi_width (entry 15 unused). Written for rows
   // longer than kRowIndexMin only.
   const int32_t* rwi;
+  // Internal vertex order: every array above is indexed by internal ids. With
+  // a hub-first order (relabelled > 0 vertices moved to the front) these map
+  // the caller's ids to internal ones and back; null when the order is the
+  // caller's.
+  const int32_t* new_of_old;
+  const int32_t* old_of_new;
+  int32_t relabelled;
+  int32_t pad_g3;
 };
+// hub-first order: the least degree of a front vertex, and at most this many
+// front vertices (their 8-byte state words fill 4 MiB, an XCD's L2)
+constexpr int kHubMinDegree = 64;
+constexpr int kHubPrefixMax = 1 << 19;
 constexpr int kRowIndexMin = 8;
 // Two pull-list buckets: smallest weight below 1/16 of the weight range (the
 // first pull of a step sequence usually needs only these), and the rest. More
@@ -176,6 +207,8 @@ struct InstFixed {
   int32_t trace_cap;
   int32_t source;
   int32_t target;          // point-to-point query: stop once this vertex is settled; -1: none
+  // source and target as internal ids (set by the per-solve initialisation)
+  int32_t src_in, tgt_in;
   // which round-batch instantiation runs this instance: bit 0 a tree is
   // recorded (best != null), bit 1 the graph has binary32 weights
   uint32_t mode;
@@ -245,6 +278,7 @@ constexpr uint32_t FLAG_TREE = 64u;           // a tree entry disagrees with its
 // ------------------------------------------------------------- tick table --
 
 constexpr int kMaxXcd = 8;  // XCDs (each with its own L2) on an MI355X
+constexpr int kTickLogWords = 8;  // words per tick of the debug tick log
 
 struct Globals {
   // grid barrier: arrival counter and release generation on lines of their own
@@ -264,9 +298,13 @@ struct Globals {
   int32_t total_batches;
   int32_t ninst;
   int32_t max_ticks_hit;
+  // items per round batch and per settle batch of the launch's tile shape
+  int32_t round_batch, settle_batch;
   unsigned long long ticks;
   unsigned long long tick_limit;  // safety stop for a schedule that fails to end
-  unsigned long long* tick_log;   // optional: per tick {end time, batches, kind bits, epilogue end}
+  // optional: per tick kTickLogWords words {last arrival, batches, kind bits, release, earliest
+  // batch start, latest batch end, heuristic start, heuristic end}
+  unsigned long long* tick_log;
   unsigned long long tick_log_cap;
   unsigned long long t_start;     // wall clock when the engine started
   // per segment: instance, kind, item count, items per batch, first batch
@@ -341,8 +379,10 @@ using GDevGraph = SSSP_GBL const DevGraph;
 
 // host launch wrappers (engine.hip)
 hipError_t launch_init(Globals* dG, long long max_n, hipStream_t stream);
-int engine_blocks_per_cu();
-hipError_t launch_engine(Globals* dG, int grid, bool persistent, int max_ticks, hipStream_t stream);
+// workgroups per CU of the engine kernel of a tile shape
+int engine_blocks_per_cu(int shape);
+hipError_t launch_engine(Globals* dG, int grid, bool persistent, int max_ticks, hipStream_t stream,
+                         int shape);
 hipError_t launch_overflow_check(Globals* dG, long long max_n, hipStream_t stream);
 // distances of the selected instances from their state into the outputs
 hipError_t launch_finish(Globals* dG, long long max_n, hipStream_t stream);
@@ -351,6 +391,6 @@ hipError_t launch_status(Globals* dG, int ninst, uint32_t* status, hipStream_t s
 // the set-up + engine + overflow-check sequence of one solve as graph nodes
 // after `dep` (may be null); the engine node is cooperative
 hipError_t add_solve_nodes(hipGraph_t graph, hipGraphNode_t dep, Globals* dG, long long max_n, int grid,
-                           hipGraphNode_t* last);
+                           int shape, hipGraphNode_t* last);
 
 }  // namespace sssp

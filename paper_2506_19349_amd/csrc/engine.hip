@@ -446,7 +446,7 @@ __device__ __noinline__ void run_heuristic(GInst& I, HeurLds& lds) {
   const bool beyond = fw ? dadd<true>(I.max_settled.v, I.M) < L
                         : (unsigned long long)I.max_settled.v + I.M < L;
   const bool done = (L == kInf) || (I.p_next_cnt.v == 0 && beyond) ||
-                    (I.target >= 0 && (uint32_t)(gbl(I.state)[I.target] >> 32) < L);
+                    (I.tgt_in >= 0 && (uint32_t)(gbl(I.state)[I.tgt_in] >> 32) < L);
   if (done) {
     if (tid == 0) I.phase = PH_DONE;
     __syncthreads();
@@ -638,9 +638,11 @@ __device__ __forceinline__ bool hub_bit(const SSSP_GBL uint32_t* bits, int v) {
 // Appends of a workgroup batch are staged in LDS and written out with one
 // device atomic per list and flush: thousands of waves claiming list slots
 // on the same counter would otherwise queue behind each other.
+template <int kCap>
 struct StageLds {
-  int32_t q[kStageCap];  // next frontier
-  int32_t t[kStageCap];  // touched list (and the surviving pull list in phase 1)
+  static constexpr int kSize = kCap;
+  int32_t q[kCap];  // next frontier
+  int32_t t[kCap];  // touched list (and the surviving pull list in phase 1)
   int32_t nq, nt;
   int32_t base_q, base_t;
 };
@@ -659,7 +661,8 @@ __device__ __forceinline__ void stage_append(int32_t* buf, int32_t* cnt, bool wa
 // Whole workgroup: copy the pull-list entries whose positions were staged in
 // q to `dst`. Position p is entry p of `cur` for p < ncur, else entry p - ncur
 // of `fresh`.
-__device__ void stage_flush_entries(StageLds& S, const SSSP_GBL UEntry* cur, int ncur,
+template <class St>
+__device__ void stage_flush_entries(St& S, const SSSP_GBL UEntry* cur, int ncur,
                                     const SSSP_GBL UEntry* fresh, SSSP_GBL UEntry* dst,
                                     SSSP_GBL int32_t* cnt, int cap, SSSP_GBL uint32_t* flags) {
   __syncthreads();
@@ -680,7 +683,8 @@ __device__ void stage_flush_entries(StageLds& S, const SSSP_GBL UEntry* cur, int
 }
 
 // Whole workgroup: copy the staged entries to their lists.
-__device__ void stage_flush(StageLds& S, SSSP_GBL int32_t* qlist, SSSP_GBL int32_t* qcnt, SSSP_GBL int32_t* tlist,
+template <class St>
+__device__ void stage_flush(St& S, SSSP_GBL int32_t* qlist, SSSP_GBL int32_t* qcnt, SSSP_GBL int32_t* tlist,
                             SSSP_GBL int32_t* tcnt,
                             int cap, SSSP_GBL uint32_t* flags) {
   __syncthreads();
@@ -707,9 +711,9 @@ __device__ void stage_flush(StageLds& S, SSSP_GBL int32_t* qlist, SSSP_GBL int32
 // A successful decrease of dist[t] to c by vertex src during round `rid`,
 // whose previous decrease was in round `prev`: t joins the next frontier once per round
 // (SAP) and the step's touched list once per step. Convergent within a wave.
-template <bool kTree>
+template <bool kTree, class St>
 __device__ __forceinline__ void on_success(const View& V, bool ok, int t, uint32_t c, uint32_t prev, int src,
-                                           WaveAcc& acc, StageLds& S) {
+                                           WaveAcc& acc, St& S) {
   bool wq = false, wt = false;
   if (ok) {
     wq = prev != V.rid;
@@ -754,25 +758,27 @@ __device__ void emit_heavy(GInst& I, int u, uint32_t d, int lo, int hi, bool pul
 // Phase 2 finds each compacted item's edge range -- the band filter
 // [lb - d, ub - d) on the weight-sorted row, or the pull prefix w < ub - st --
 // and relaxes all of the batch's edges with a workgroup-wide merge path.
+template <class Sh>
 struct RoundLds {
-  int32_t u[kRoundBatch];
-  uint32_t d[kRoundBatch];
+  int32_t u[Sh::kBatch];
+  uint32_t d[Sh::kBatch];
   // pull items: best candidate for dist[u] found in this batch; with a tree
   // (candidate << 32) | the settled neighbour it comes from
   union {
-    uint32_t pmin32[kRoundBatch];
-    unsigned long long pmin64[kRoundBatch];
+    uint32_t pmin32[Sh::kBatch];
+    unsigned long long pmin64[Sh::kBatch];
   };
-  int32_t lo[kRoundBatch];
-  int32_t re[kRoundBatch];  // row end when the row is known (pull-list items), else -1
-  int32_t sz[kRoundBatch];  // size, -1 = range still to find; then exclusive offsets
-  uint8_t pull[kRoundBatch];
+  int32_t lo[Sh::kBatch];
+  int32_t re[Sh::kBatch];  // row end when the row is known (pull-list items), else -1
+  int32_t sz[Sh::kBatch];  // size, -1 = range still to find; then exclusive offsets
+  uint8_t pull[Sh::kBatch];
   int32_t count;
   int32_t iscan[kBlock / kWave + 1];
-  StageLds stage;
+  StageLds<Sh::kStage> stage;
 };
 
-__device__ __forceinline__ void lds_push_item(RoundLds& L, bool want, int u, uint32_t d, int lo,
+template <class RL>
+__device__ __forceinline__ void lds_push_item(RL& L, bool want, int u, uint32_t d, int lo,
                                               int sz, bool pull, int re = -1) {
   uint64_t m = __ballot(want);
   if (m == 0) return;
@@ -795,13 +801,16 @@ __device__ __forceinline__ void lds_push_item(RoundLds& L, bool want, int u, uin
 // instantiation, so that solves without one pay nothing for it).
 // kFloat: binary32 weights; the band searches then test dist + w itself
 // against the band ends, rounded as the relaxation rounds it.
-template <bool kTree, bool kFloat>
-__device__ __noinline__ void block_round(GInst& I, int kind, int item0, int nitems, RoundLds& L) {
+template <bool kTree, bool kFloat, class Sh>
+__device__ __noinline__ void block_round(GInst& I, int kind, int item0, int nitems, RoundLds<Sh>& L) {
+  constexpr int kItemsPerThread = Sh::kItems;
+  constexpr int kEdgesPerThread = Sh::kEdges;
+  constexpr int kStageCap = Sh::kStage;
   const View V = make_view(I);
   const int tid = threadIdx.x;
   const uint32_t lb = V.lb, ub = V.ub, st = V.st;
   WaveAcc acc = {0, 0, 0, 0, 0, 0, 0, kInf};
-  StageLds& S = L.stage;
+  auto& S = L.stage;
   if (tid == 0) {
     L.count = 0;
     S.nq = 0;
@@ -1008,6 +1017,7 @@ __device__ __noinline__ void block_round(GInst& I, int kind, int item0, int nite
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
         const int k = k0 + j;
+        if (k >= kItemsPerThread) break;  // an odd count: the last pair is single
         const bool small = need[k] && re[k] - rs[k] <= kRowIndexMin;
 #pragma unroll
         for (int i = 0; i < kRowIndexMin; ++i)
@@ -1016,6 +1026,7 @@ __device__ __noinline__ void block_round(GInst& I, int kind, int item0, int nite
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
         const int k = k0 + j;
+        if (k >= kItemsPerThread) break;
         if (!(need[k] && re[k] - rs[k] <= kRowIndexMin) || leaf[k]) continue;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
@@ -1220,17 +1231,20 @@ struct SettleLds {
   int base[2];
 };
 
+template <class Sh>
 union BlockLds {
   SettleLds s;
   HeurLds h;
-  RoundLds r;
+  RoundLds<Sh> r;
 };
 
 // One workgroup settles up to kSettleBatch items (kSettlePer per thread): the
 // step's touched vertices (with dist < ub they are final; in the first step
 // the rest stay pending) and the pending list's compaction. Degree mass moves from the unsettled histogram
 // to the per-distance ring; settled vertices are appended to the settled list.
+template <class Sh>
 __device__ __noinline__ void block_settle(GInst& I, int kind, int item0, int nitems, SettleLds& L) {
+  constexpr int kSettlePer = Sh::kSettle;
   GDevGraph& g = *gbl(I.g);
   const int tid = threadIdx.x;
   const uint32_t lb = I.lb, ub = I.ub, M = I.M;
@@ -1398,8 +1412,8 @@ __device__ int find_segment(const GGlobals& G, int b) {
 // any grouping of rounds reaches the same settled set. When the frontier
 // empties or grows past one batch, the epilogue takes over with its usual
 // transition of the last round.
-template <bool kTree, bool kFloat>
-__device__ __noinline__ void fused_rounds(GInst& I, RoundLds& L) {
+template <bool kTree, bool kFloat, class Sh>
+__device__ __noinline__ void fused_rounds(GInst& I, RoundLds<Sh>& L) {
   __shared__ int s_go, s_nq;
   const int cap = I.fuse_cap;
   for (int r = 0; r < cap; ++r) {
@@ -1412,7 +1426,7 @@ __device__ __noinline__ void fused_rounds(GInst& I, RoundLds& L) {
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       const int nq = __hip_atomic_load(&I.q_next_cnt.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       const int nh = __hip_atomic_load(&I.h_next_cnt.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      const bool go = nh == 0 && nq > 0 && nq <= kRoundBatch;
+      const bool go = nh == 0 && nq > 0 && nq <= Sh::kBatch;
       if (go) {
         const uint32_t ubn = __hip_atomic_load(&I.ub_next.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (I.first && ubn < I.ub) I.ub = ubn;
@@ -1431,15 +1445,34 @@ __device__ __noinline__ void fused_rounds(GInst& I, RoundLds& L) {
     }
     __syncthreads();
     if (!s_go) break;
-    block_round<kTree, kFloat>(I, SEG_Q, 0, s_nq, L);
+    block_round<kTree, kFloat, Sh>(I, SEG_Q, 0, s_nq, L);
   }
+}
+
+// Debug tick log: words 4..7 of a tick's entry (earliest batch start, latest
+// batch end, heuristic start and end) are opened before the tick runs.
+__device__ void tick_log_open(GGlobals& G, unsigned long long t) {
+  auto e = gbl(G.tick_log) + kTickLogWords * t;
+  e[4] = ~0ull;
+  e[5] = 0;
+  e[6] = 0;
+  e[7] = 0;
+}
+
+__device__ __forceinline__ SSSP_GBL unsigned long long* tick_log_entry(GGlobals& G) {
+  if (!G.tick_log) return nullptr;
+  const unsigned long long t = G.ticks;
+  return t < G.tick_log_cap ? gbl(G.tick_log) + kTickLogWords * t : nullptr;
 }
 
 // One tick's batches, taken round-robin by the P participating workgroups
 // (this one is number pid).
-__device__ void run_tick(GGlobals& G, BlockLds& lds, int pid, int P) {
+template <class Sh>
+__device__ void run_tick(GGlobals& G, BlockLds<Sh>& lds, int pid, int P) {
   __shared__ int s_last;
   const int total_batches = G.total_batches;
+  SSSP_GBL unsigned long long* tl = tick_log_entry(G);
+  if (tl && threadIdx.x == 0 && pid < total_batches) atomicMin((unsigned long long*)(tl + 4), wall_clock64());
   for (int b = pid; b < total_batches; b += P) {
     const int sgi = find_segment(G, b);
     GInst& I = gbl(G.insts)[gbl(G.seg_inst)[sgi]];
@@ -1448,7 +1481,7 @@ __device__ void run_tick(GGlobals& G, BlockLds& lds, int pid, int P) {
     const int item0 = (b - gbl(G.seg_first_batch)[sgi]) * pb;
     const int cnt = gbl(G.seg_count)[sgi];
     if (kind == SEG_ST || kind == SEG_SP) {
-      block_settle(I, kind, item0, cnt, lds.s);
+      block_settle<Sh>(I, kind, item0, cnt, lds.s);
       // the heuristic only reads words updated by device atomics: waiting for
       // this batch's atomics to complete is enough before counting it done
       __builtin_amdgcn_s_waitcnt(0);
@@ -1459,9 +1492,13 @@ __device__ void run_tick(GGlobals& G, BlockLds& lds, int pid, int P) {
       }
       __syncthreads();
       if (s_last) {
-        if (threadIdx.x == 0) __threadfence();
+        if (threadIdx.x == 0) {
+          __threadfence();
+          if (tl) tl[6] = wall_clock64();
+        }
         __syncthreads();
         run_heuristic(I, lds.h);
+        if (tl && threadIdx.x == 0) tl[7] = wall_clock64();
         // its plain stores (next step's control words, ring clears) must be
         // out of this XCD's L2 before other XCDs use them: done at the barrier
       }
@@ -1471,25 +1508,26 @@ __device__ void run_tick(GGlobals& G, BlockLds& lds, int pid, int P) {
       const bool tree = (mode & 1u) != 0;
       const bool fw = (mode & 2u) != 0;
       if (fw) {
-        if (tree) block_round<true, true>(I, kind, item0, cnt, lds.r);
-        else block_round<false, true>(I, kind, item0, cnt, lds.r);
+        if (tree) block_round<true, true, Sh>(I, kind, item0, cnt, lds.r);
+        else block_round<false, true, Sh>(I, kind, item0, cnt, lds.r);
       } else {
-        if (tree) block_round<true, false>(I, kind, item0, cnt, lds.r);
-        else block_round<false, false>(I, kind, item0, cnt, lds.r);
+        if (tree) block_round<true, false, Sh>(I, kind, item0, cnt, lds.r);
+        else block_round<false, false, Sh>(I, kind, item0, cnt, lds.r);
       }
       // a frontier that fits one batch, with no heavy chunks, belongs to this
       // workgroup alone for the whole tick: chain its next rounds here
       if (kind == SEG_Q && cnt <= pb && I.nH == 0 && I.fuse_cap > 0) {
         if (fw) {
-          if (tree) fused_rounds<true, true>(I, lds.r);
-          else fused_rounds<false, true>(I, lds.r);
+          if (tree) fused_rounds<true, true, Sh>(I, lds.r);
+          else fused_rounds<false, true, Sh>(I, lds.r);
         } else {
-          if (tree) fused_rounds<true, false>(I, lds.r);
-          else fused_rounds<false, false>(I, lds.r);
+          if (tree) fused_rounds<true, false, Sh>(I, lds.r);
+          else fused_rounds<false, false, Sh>(I, lds.r);
         }
       }
     }
   }
+  if (tl && threadIdx.x == 0 && pid < total_batches) atomicMax((unsigned long long*)(tl + 5), wall_clock64());
 }
 
 // Words updated by device atomics during a tick that the transition reads.
@@ -1503,7 +1541,7 @@ struct HotIn {
 // the next tick go to Sp. Resets the hot words it consumed in I.
 // Serial per instance; called by one thread per instance.
 __device__ void transition(InstCtl& X, SegSpec& Sp, const HotIn& h, int32_t n, int32_t heavy_cap,
-                           unsigned long long& rounds, GInst& I) {
+                           int32_t rb, int32_t sb, unsigned long long& rounds, GInst& I) {
 #pragma unroll
   for (int s = 0; s < kMaxSegPerInst; ++s) {
     Sp.cnt[s] = 0;
@@ -1531,7 +1569,7 @@ __device__ void transition(InstCtl& X, SegSpec& Sp, const HotIn& h, int32_t n, i
       X.nF = nq;
       X.nH = nh;
       X.rid += 1;
-      Sp.cnt[0] = nq; Sp.kind[0] = SEG_Q; Sp.pb[0] = kRoundBatch;
+      Sp.cnt[0] = nq; Sp.kind[0] = SEG_Q; Sp.pb[0] = rb;
       Sp.cnt[1] = nh; Sp.kind[1] = SEG_H; Sp.pb[1] = kHeavyPerBatch;
       return;
     }
@@ -1544,14 +1582,14 @@ __device__ void transition(InstCtl& X, SegSpec& Sp, const HotIn& h, int32_t n, i
     X.nT = min(h.touched, n);
     X.settled_mark = min(h.settled, n);
     I.settle_done.v = 0;
-    int bt = (X.nT + kSettleBatch - 1) / kSettleBatch;
+    int bt = (X.nT + sb - 1) / sb;
     if (bt < 1) bt = 1;
-    int bp = (X.nP + kSettleBatch - 1) / kSettleBatch;
+    int bp = (X.nP + sb - 1) / sb;
     X.settle_items = bt + bp;
     // a settle tick always has at least one batch so that the heuristic runs:
     // -1 marks one empty batch
-    Sp.cnt[0] = X.nT == 0 ? -1 : X.nT; Sp.kind[0] = SEG_ST; Sp.pb[0] = kSettleBatch;
-    Sp.cnt[1] = X.nP; Sp.kind[1] = SEG_SP; Sp.pb[1] = kSettleBatch;
+    Sp.cnt[0] = X.nT == 0 ? -1 : X.nT; Sp.kind[0] = SEG_ST; Sp.pb[0] = sb;
+    Sp.cnt[1] = X.nP; Sp.kind[1] = SEG_SP; Sp.pb[1] = sb;
     return;
   }
   // a settle tick ran; the heuristic has set phase to ROUND or DONE
@@ -1563,10 +1601,10 @@ __device__ void transition(InstCtl& X, SegSpec& Sp, const HotIn& h, int32_t n, i
   X.tick_kind = PH_ROUND;
   X.init_round = 1;
   X.nF = 0;
-  Sp.cnt[0] = X.wEnd - X.wBegin; Sp.kind[0] = SEG_W; Sp.pb[0] = kRoundBatch;
-  Sp.cnt[1] = X.nP; Sp.kind[1] = SEG_P; Sp.pb[1] = kRoundBatch;
+  Sp.cnt[0] = X.wEnd - X.wBegin; Sp.kind[0] = SEG_W; Sp.pb[0] = rb;
+  Sp.cnt[1] = X.nP; Sp.kind[1] = SEG_P; Sp.pb[1] = rb;
   Sp.cnt[2] = X.pull_on ? X.nU + (X.u_end - X.u_done) : 0; Sp.kind[2] = SEG_U;
-  Sp.pb[2] = kRoundBatch;
+  Sp.pb[2] = rb;
 }
 
 // Build the tick table. With do_transition, every instance first takes its
@@ -1601,7 +1639,7 @@ __device__ void build_table(GGlobals& G, bool do_transition, bool count) {
       const int32_t n = I.n, heavy_cap = I.heavy_cap;
       unsigned long long rounds = I.c.rounds, ticks = I.c.ticks;
       if (count && X.phase != PH_DONE) ticks += 1;
-      transition(X, Sp, h, n, heavy_cap, rounds, I);
+      transition(X, Sp, h, n, heavy_cap, G.round_batch, G.settle_batch, rounds, I);
       gstore(ctl, X);
       gstore(&I.spec, Sp);
       I.c.rounds = rounds;
@@ -1721,7 +1759,7 @@ __device__ __forceinline__ void epilogue(GGlobals& G, unsigned int gen, unsigned
                                      unsigned int min_members) {
   if (threadIdx.x == 0) {
     if (gbl(G.tick_log) && G.ticks < G.tick_log_cap) {
-      auto e = gbl(G.tick_log) + 4 * G.ticks;
+      auto e = gbl(G.tick_log) + kTickLogWords * G.ticks;
       e[0] = wall_clock64();
       e[1] = (unsigned long long)G.total_batches;
       const GInst& I0 = gbl(G.insts)[0];
@@ -1735,8 +1773,9 @@ __device__ __forceinline__ void epilogue(GGlobals& G, unsigned int gen, unsigned
     // the next tick starts at generation gen + 1
     __hip_atomic_store(&G.quota[(gen + 1u) & 7u], quota_for(G.total_batches, nxcd, min_members),
                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (gbl(G.tick_log) && G.ticks < G.tick_log_cap) gbl(G.tick_log)[4 * G.ticks + 3] = wall_clock64();
+    if (gbl(G.tick_log) && G.ticks < G.tick_log_cap) gbl(G.tick_log)[kTickLogWords * G.ticks + 3] = wall_clock64();
     G.ticks += 1;
+    if (gbl(G.tick_log) && G.ticks < G.tick_log_cap) tick_log_open(G, G.ticks);
     if (G.ticks >= G.tick_limit) {
       G.error |= FLAG_TICKS;
       G.all_done = 1u;
@@ -1864,8 +1903,9 @@ __device__ bool barrier_tick(GGlobals& G, BarrierState& B, unsigned int quota) {
   return s_ok != 0;
 }
 
-__global__ void __launch_bounds__(kBlock, 5) k_engine(Globals* Gp, int persistent, int max_ticks) {
-  __shared__ BlockLds lds;
+template <class Sh>
+__global__ void __launch_bounds__(kBlock, Sh::kMinBlocks) k_engine(Globals* Gp, int persistent, int max_ticks) {
+  __shared__ BlockLds<Sh> lds;
   __shared__ BarrierState s_b;
   GGlobals& G = *gbl(Gp);
   if (threadIdx.x == 0) {
@@ -1876,7 +1916,7 @@ __global__ void __launch_bounds__(kBlock, 5) k_engine(Globals* Gp, int persisten
   if (!persistent) {
     // one tick; the kernel boundary is the barrier
     if (__hip_atomic_load(&G.all_done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
-    run_tick(G, lds, blockIdx.x, gridDim.x);
+    run_tick<Sh>(G, lds, blockIdx.x, gridDim.x);
     unsigned int gen = s_b.gen;
     barrier_flat(G, gen, false, true);
     return;
@@ -1929,7 +1969,7 @@ __global__ void __launch_bounds__(kBlock, 5) k_engine(Globals* Gp, int persisten
         __syncthreads();
         stale = false;
       }
-      run_tick(G, lds, (int)(B.rank * B.nxcd + B.xidx), (int)(q * B.nxcd));
+      run_tick<Sh>(G, lds, (int)(B.rank * B.nxcd + B.xidx), (int)(q * B.nxcd));
       if (!barrier_tick(G, B, q)) break;
       t += 1;
     } else {
@@ -1985,7 +2025,11 @@ __global__ void __launch_bounds__(kBlock) k_init_ctl(Globals* Gp) {
     GInst& I = gbl(G.insts)[G.n_sel < 0 ? j : gbl(G.sel_list)[j]];
     GDevGraph& g = *gbl(I.g);
     if (threadIdx.x == 0) {
-      const int s = I.source;
+      // the caller's ids to internal ones
+      const SSSP_GBL int32_t* ren = g.new_of_old ? gbl(g.new_of_old) : nullptr;
+      const int s = ren ? ren[I.source] : I.source;
+      I.src_in = s;
+      I.tgt_in = I.target < 0 ? -1 : (ren ? ren[I.target] : I.target);
       const int deg_s = gbl(g.rowptr)[s + 1] - gbl(g.rowptr)[s];
       I.M = g.max_w;
       I.lb = 0; I.ub = kInf; I.st = 0; I.lb0 = 0;
@@ -2026,7 +2070,7 @@ __global__ void __launch_bounds__(kBlock) k_init_ctl(Globals* Gp) {
       for (int sg = 0; sg < kMaxSegPerInst; ++sg) {
         I.spec.cnt[sg] = 0;
         I.spec.kind[sg] = SEG_Q;
-        I.spec.pb[sg] = kRoundBatch;
+        I.spec.pb[sg] = G.round_batch;
       }
       I.spec.cnt[0] = I.nF;
     }
@@ -2048,6 +2092,7 @@ __global__ void __launch_bounds__(kBlock) k_init_ctl(Globals* Gp) {
     G.error = 0;
     G.max_ticks_hit = 0;
     G.ticks = 0;
+    if (gbl(G.tick_log) && G.tick_log_cap > 0) tick_log_open(G, 0);
   }
   __syncthreads();
   build_table(G, false, false);
@@ -2087,16 +2132,22 @@ __global__ void k_finish(Globals* Gp) {
   const int nsel = G.n_sel < 0 ? G.ninst : G.n_sel;
   for (int j = 0; j < nsel; ++j) {
     GInst& I = gbl(G.insts)[G.n_sel < 0 ? j : gbl(G.sel_list)[j]];
+    GDevGraph& g = *gbl(I.g);
     auto state = gbl(I.state);
     auto dist = gbl(I.dist);
-    for (long long v = tid; v < I.n; v += stride) dist[v] = (uint32_t)(state[v] >> 32);
+    // outputs are indexed by the caller's ids: v is the caller's, ren[v] internal
+    const SSSP_GBL int32_t* ren = g.new_of_old ? gbl(g.new_of_old) : nullptr;
+    const SSSP_GBL int32_t* back = g.old_of_new ? gbl(g.old_of_new) : nullptr;
+    for (long long v = tid; v < I.n; v += stride) dist[v] = (uint32_t)(state[ren ? ren[v] : v] >> 32);
     if (I.parent && I.best) {
       auto parent = gbl(I.parent);
       auto best = gbl(I.best);
       for (long long v = tid; v < I.n; v += stride) {
-        const uint32_t d = (uint32_t)(state[v] >> 32);
-        const unsigned long long b = best[v];
-        parent[v] = d == kInf ? -1 : (int32_t)(uint32_t)b;
+        const long long vi = ren ? ren[v] : v;
+        const uint32_t d = (uint32_t)(state[vi] >> 32);
+        const unsigned long long b = best[vi];
+        const int32_t p = (int32_t)(uint32_t)b;
+        parent[v] = d == kInf ? -1 : (back ? back[p] : p);
         if (d != kInf && (uint32_t)(b >> 32) != d) atomicOr(&I.flags.v, FLAG_TREE);
       }
     }
@@ -2146,23 +2197,31 @@ hipError_t launch_init(Globals* dG, long long max_n, hipStream_t stream) {
   return hipGetLastError();
 }
 
-int engine_blocks_per_cu() {
+// The engine kernel of a tile shape.
+const void* engine_fn(int shape) {
+  switch (shape) {
+    case SHAPE_WIDE: return reinterpret_cast<const void*>(k_engine<ShapeWide>);
+    case SHAPE_NARROW: return reinterpret_cast<const void*>(k_engine<ShapeNarrow>);
+    case SHAPE_SETTLE8: return reinterpret_cast<const void*>(k_engine<ShapeSettle8>);
+    default: return reinterpret_cast<const void*>(k_engine<ShapeStd>);
+  }
+}
+
+int engine_blocks_per_cu(int shape) {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(k_engine), kBlock,
-                                                   0) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, engine_fn(shape), kBlock, 0) != hipSuccess)
     return 1;
   return nb < 1 ? 1 : nb;
 }
 
-hipError_t launch_engine(Globals* dG, int grid, bool persistent, int max_ticks, hipStream_t stream) {
-  if (!persistent) {
-    k_engine<<<grid, kBlock, 0, stream>>>(dG, 0, 0);
-    return hipGetLastError();
-  }
-  int pers = 1;
-  void* args[] = {(void*)&dG, (void*)&pers, (void*)&max_ticks};
-  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_engine), dim3(grid), dim3(kBlock),
-                                    args, 0, stream);
+hipError_t launch_engine(Globals* dG, int grid, bool persistent, int max_ticks, hipStream_t stream,
+                         int shape) {
+  int pers = persistent ? 1 : 0;
+  int mt = persistent ? max_ticks : 0;
+  void* args[] = {(void*)&dG, (void*)&pers, (void*)&mt};
+  if (!persistent)
+    return hipLaunchKernel(engine_fn(shape), dim3(grid), dim3(kBlock), args, 0, stream);
+  return hipLaunchCooperativeKernel(engine_fn(shape), dim3(grid), dim3(kBlock), args, 0, stream);
 }
 
 hipError_t launch_status(Globals* dG, int ninst, uint32_t* status, hipStream_t stream) {
@@ -2173,7 +2232,7 @@ hipError_t launch_status(Globals* dG, int ninst, uint32_t* status, hipStream_t s
 }
 
 hipError_t add_solve_nodes(hipGraph_t graph, hipGraphNode_t dep, Globals* dG, long long max_n, int grid,
-                           hipGraphNode_t* last) {
+                           int shape, hipGraphNode_t* last) {
   long long ib = (max_n + kBlock - 1) / kBlock;
   ib = ib < 1 ? 1 : (ib > 16384 ? 16384 : ib);
   long long ob = (max_n + kBlock - 1) / kBlock;
@@ -2195,7 +2254,7 @@ hipError_t add_solve_nodes(hipGraph_t graph, hipGraphNode_t dep, Globals* dG, lo
   p.gridDim = dim3(1);
   e = hipGraphAddKernelNode(&n_ctl, graph, &n_arr, 1, &p);
   if (e != hipSuccess) return e;
-  p.func = reinterpret_cast<void*>(k_engine);
+  p.func = const_cast<void*>(engine_fn(shape));
   p.gridDim = dim3((unsigned)grid);
   p.kernelParams = a_e;
   e = hipGraphAddKernelNode(&n_eng, graph, &n_ctl, 1, &p);

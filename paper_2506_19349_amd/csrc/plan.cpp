@@ -75,6 +75,8 @@ sssp_status plan_build(sssp_plan* p, uint32_t* const* dist_outs, int32_t* const*
   hG->insts = w.dInst;
   hG->sel_list = nullptr;
   hG->n_sel = -1;
+  hG->round_batch = round_batch_of(p->o.shape);
+  hG->settle_batch = settle_batch_of(p->o.shape);
   for (int i = 0; i < k; ++i)
     fill_inst(p->hI[i], w.slots[(size_t)i], p->gs[(size_t)i], 0, dist_outs[i], p->o,
               parent_outs ? parent_outs[i] : nullptr);
@@ -88,7 +90,7 @@ sssp_status plan_build(sssp_plan* p, uint32_t* const* dist_outs, int32_t* const*
                                   hipMemcpyHostToDevice));
   HIP_TRY(hipGraphAddMemcpyNode1D(&n_i, p->graph, &n_g, 1, w.dInst, p->hI, sizeof(Inst) * (size_t)k,
                                   hipMemcpyHostToDevice));
-  HIP_TRY(add_solve_nodes(p->graph, n_i, w.dG, max_n, grid, &last));
+  HIP_TRY(add_solve_nodes(p->graph, n_i, w.dG, max_n, grid, p->o.shape, &last));
   HIP_TRY(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
   HIP_TRY(hipEventCreateWithFlags(&p->done, hipEventDisableTiming));
   w.last_k = k;
@@ -268,19 +270,28 @@ sssp_status sssp_autotune(const sssp_graph* const* gs, const int32_t* sources, i
   st = measure(best, &best_us);
   base_us = best_us;
   // coordinate descent over the launch knobs; none of them changes a distance
-  std::vector<int> bpcs;
-  for (int b : {1, 2, w.occ})
-    if (b >= 1 && b <= w.occ && std::find(bpcs.begin(), bpcs.end(), b) == bpcs.end()) bpcs.push_back(b);
-  for (int knob = 0; knob < 4 && st == SSSP_OK; ++knob) {
+  // knobs in turn: the tile shape (engine instantiation: items per round
+  // batch 256 / 512 / 1024, settle batch 1024 / 2048), workgroups per CU (1,
+  // 2, all the shape allows), the heavy-range split, bucket fusion on / off,
+  // and beta within the range Section 4.3 finds insensitive
+  for (int knob = 0; knob < 5 && st == SSSP_OK; ++knob) {
     std::vector<Opts> cands;
     if (knob == 0) {
-      for (int b : bpcs) { Opts o = best; o.blocks_per_cu = b; cands.push_back(o); }
+      for (int sh = 0; sh < kNumShapes; ++sh) { Opts o = best; o.shape = sh; cands.push_back(o); }
     } else if (knob == 1) {
-      for (int h : {256, 1024, 4096}) { Opts o = best; o.heavy = h; cands.push_back(o); }
+      const int occ = w.occ_s[best.shape];
+      for (int b : {1, 2, 0}) {
+        if (b > occ) continue;
+        Opts o = best;
+        o.blocks_per_cu = b;  // 0: the default grid rule (all the shape allows, fewer for small graphs)
+        cands.push_back(o);
+      }
     } else if (knob == 2) {
+      for (int h : {kDefaultHeavy, 256, 1024, 4096}) { Opts o = best; o.heavy = h; cands.push_back(o); }
+    } else if (knob == 3) {
       for (int f : {kDefaultFuse, 0}) { Opts o = best; o.fuse = f; cands.push_back(o); }
     } else if (tune_beta) {
-      for (double b : {0.8, 0.9, 0.95}) { Opts o = best; o.beta = b; cands.push_back(o); }
+      for (double b : {0.85, 0.9, 0.95}) { Opts o = best; o.beta = b; cands.push_back(o); }
     }
     for (const Opts& o : cands) {
       double us = 0;
@@ -303,6 +314,7 @@ sssp_status sssp_autotune(const sssp_graph* const* gs, const int32_t* sources, i
   inout->blocks_per_cu = best.blocks_per_cu;  // 0: the default grid rule
   inout->heavy_split = best.heavy;
   inout->fuse_rounds = best.fuse > 0 ? best.fuse : -1;
+  inout->tile_shape = best.shape + 1;
   if (report) {
     std::memset(report, 0, sizeof(*report));
     report->default_us = base_us;

@@ -48,6 +48,21 @@ __global__ void k_pack(const int32_t* col, const uint32_t* w, int32_t nnz, uint6
     adj[e] = ((uint64_t)w[e] << 32) | (uint32_t)col[e];
 }
 
+// Relabelled packing: row u of the input becomes row new_of_old[u]; its
+// columns are renamed the same way. One wave per input row.
+__global__ void k_pack_relabel(const int32_t* rp_in, const int32_t* col, const uint32_t* w,
+                               const int32_t* new_of_old, const int32_t* rowptr, int32_t n, uint64_t* adj) {
+  const int lane = __lane_id();
+  const long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const long long nwaves = ((long long)gridDim.x * blockDim.x) / kWave;
+  for (long long u = wave; u < n; u += nwaves) {
+    const int a = rp_in[u], b = rp_in[u + 1];
+    const long long dst = rowptr[new_of_old[u]];
+    for (int e = a + lane; e < b; e += kWave)
+      adj[dst + (e - a)] = ((uint64_t)w[e] << 32) | (uint32_t)new_of_old[col[e]];
+  }
+}
+
 // ------------------------------------------------------- segmented sort --
 
 // rows by length: 2..64 -> small, 65..kMedMax -> medium, longer -> large
@@ -532,6 +547,24 @@ int grid_for(long long work, int per_block = kBlock, int cap = 8192) {
 
 }  // namespace
 
+// The vertices moved to the front of the internal order: degree at least
+// max(kHubMinDegree, 4 x the mean degree), at most kHubPrefixMax of them (the
+// highest degrees), by descending degree, ties by id. Empty when no vertex
+// qualifies (uniform-degree graphs such as grids and G(n, m) keep their order).
+std::vector<int32_t> hub_prefix(const std::vector<int32_t>& rp, int32_t n, int32_t nnz) {
+  std::vector<int32_t> out;
+  if (n < 2 || nnz == 0) return out;
+  const long long thr = std::max<long long>(kHubMinDegree, 4ll * nnz / n);
+  for (int32_t u = 0; u < n; ++u)
+    if (rp[(size_t)u + 1] - rp[(size_t)u] >= thr) out.push_back(u);
+  std::sort(out.begin(), out.end(), [&](int32_t a, int32_t b) {
+    const int32_t da = rp[(size_t)a + 1] - rp[(size_t)a], db = rp[(size_t)b + 1] - rp[(size_t)b];
+    return da != db ? da > db : a < b;
+  });
+  if (out.size() > (size_t)kHubPrefixMax) out.resize((size_t)kHubPrefixMax);
+  return out;
+}
+
 void free_graph(GraphHost* g) {
   for (void* p : g->allocs) (void)hipFree(p);
   g->allocs.clear();
@@ -584,6 +617,9 @@ int prep_graph(int32_t n, const int32_t* rowptr_in, const int32_t* col_in, const
   uint32_t maxw = 0;
   uint32_t minpos = 0xffffffffu;  // smallest positive weight
   int maxdeg = 0;
+  int32_t* new_of_old = nullptr;  // set when the vertices are renumbered hub-first
+  int32_t* old_of_new = nullptr;
+  int32_t relabelled = 0;
   if (nnz > 0) {
     int32_t* col = T.get<int32_t>((size_t)nnz);
     uint32_t* w = T.get<uint32_t>((size_t)nnz);
@@ -617,8 +653,50 @@ int prep_graph(int32_t n, const int32_t* rowptr_in, const int32_t* col_in, const
       *msg = "binary32 weights must be finite and non-negative";
       return -1;
     }
-    k_pack<<<grid_for(nnz), kBlock>>>(col, w, nnz, adj);
-    PREP_CHECK(hipGetLastError());
+    // Hub-first vertex order (internal ids): on a skewed graph the rows of at
+    // least 4x the mean degree (the vertices most relaxations land on) are
+    // moved to the front, by descending degree, so that their distance words
+    // share cache lines; the other vertices keep their order. Callers see
+    // their own ids: sources and targets are renamed on the way in, distances
+    // and parents on the way out.
+    std::vector<int32_t> prefix = hub_prefix(rp, n, nnz);
+    if (!prefix.empty()) {
+      const int32_t H = (int32_t)prefix.size();
+      std::vector<int32_t> n_of_o((size_t)n), o_of_n((size_t)n);
+      std::vector<char> in_prefix((size_t)n, 0);
+      for (int32_t i = 0; i < H; ++i) {
+        n_of_o[(size_t)prefix[(size_t)i]] = i;
+        in_prefix[(size_t)prefix[(size_t)i]] = 1;
+      }
+      int32_t next = H;
+      for (int32_t u = 0; u < n; ++u)
+        if (!in_prefix[(size_t)u]) n_of_o[(size_t)u] = next++;
+      for (int32_t u = 0; u < n; ++u) o_of_n[(size_t)n_of_o[(size_t)u]] = u;
+      std::vector<int32_t> rp_new((size_t)n + 1);
+      rp_new[0] = 0;
+      for (int32_t r = 0; r < n; ++r) {
+        const int32_t u = o_of_n[(size_t)r];
+        rp_new[(size_t)r + 1] = rp_new[(size_t)r] + (rp[(size_t)u + 1] - rp[(size_t)u]);
+      }
+      int32_t* d_rp_in = T.get<int32_t>((size_t)n + 1);
+      new_of_old = A.get<int32_t>((size_t)n);
+      old_of_new = A.get<int32_t>((size_t)n);
+      if (!T.ok || !A.ok) {
+        *msg = "device allocation failed";
+        return -5;
+      }
+      PREP_CHECK(hipMemcpy(d_rp_in, rp.data(), sizeof(int32_t) * ((size_t)n + 1), hipMemcpyHostToDevice));
+      PREP_CHECK(hipMemcpy(new_of_old, n_of_o.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice));
+      PREP_CHECK(hipMemcpy(old_of_new, o_of_n.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice));
+      PREP_CHECK(hipMemcpy(rowptr, rp_new.data(), sizeof(int32_t) * ((size_t)n + 1), hipMemcpyHostToDevice));
+      k_pack_relabel<<<grid_for((long long)n * kWave), kBlock>>>(d_rp_in, col, w, new_of_old, rowptr, n, adj);
+      PREP_CHECK(hipGetLastError());
+      rp.swap(rp_new);
+      relabelled = H;
+    } else {
+      k_pack<<<grid_for(nnz), kBlock>>>(col, w, nnz, adj);
+      PREP_CHECK(hipGetLastError());
+    }
   } else {
     for (int32_t v = 0; v < n; ++v)
       if (rp[(size_t)v + 1] < rp[(size_t)v]) {
@@ -982,6 +1060,9 @@ int prep_graph(int32_t n, const int32_t* rowptr_in, const int32_t* col_in, const
   h.rtow = rtow;
   h.rwi = rwi;
   h.rwi_width = rwi_width;
+  h.new_of_old = new_of_old;
+  h.old_of_new = old_of_new;
+  h.relabelled = relabelled;
   out->d = A.get<DevGraph>(1);
   if (!A.ok) {
     *msg = "device allocation failed";

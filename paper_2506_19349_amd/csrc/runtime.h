@@ -97,7 +97,8 @@ struct Workspace {
   unsigned int* pinned_flag = nullptr;
   int grid = 0;
   int cus = 0;
-  int occ = 0;
+  int occ = 0;                  // the most workgroups per CU of any tile shape (sizes per-wave slots)
+  int occ_s[kNumShapes] = {};   // workgroups per CU of each tile shape's engine kernel
   // last solve
   int last_k = 0;
   bool persistent_failed = false;
@@ -127,6 +128,7 @@ struct Opts {
   int blocks_per_cu = 0;
   int heavy = kDefaultHeavy;
   int fuse = kDefaultFuse;
+  int shape = SHAPE_STD;  // tile shape (engine kernel instantiation)
   unsigned long long tick_limit = 1ull << 22;
 };
 

@@ -244,9 +244,10 @@ sssp_status cycle(sssp_server* S, const std::vector<int>& fresh, std::vector<int
     HIP_TRY(hipMemcpyAsync(S->d_sel, S->h_sel, sizeof(int32_t) * fresh.size(), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(&w.dG->n_sel, S->h_nsel, sizeof(int32_t), hipMemcpyHostToDevice, st));
   HIP_TRY(launch_init(w.dG, fresh.empty() ? 1 : max_n, st));
-  const int bpc = S->o.blocks_per_cu > 0 ? std::min(S->o.blocks_per_cu, w.occ) : w.occ;
+  const int occ = w.occ_s[S->o.shape];
+  const int bpc = S->o.blocks_per_cu > 0 ? std::min(S->o.blocks_per_cu, occ) : occ;
   HIP_TRY(hipEventRecord(w.tev[0][0], st));
-  HIP_TRY(launch_engine(w.dG, w.cus * bpc, true, S->ticks_per_launch, st));
+  HIP_TRY(launch_engine(w.dG, w.cus * bpc, true, S->ticks_per_launch, st, S->o.shape));
   HIP_TRY(hipEventRecord(w.tev[1][0], st));
   HIP_TRY(launch_status(w.dG, S->max_batch, S->d_status, st));
   HIP_TRY(hipMemcpyAsync(S->h_status, S->d_status, sizeof(uint32_t) * 2 * (size_t)S->max_batch,
@@ -412,6 +413,8 @@ sssp_status server_setup(sssp_server* S) {
   hG->insts = w.dInst;
   hG->sel_list = S->d_sel;
   hG->n_sel = 0;
+  hG->round_batch = round_batch_of(S->o.shape);
+  hG->settle_batch = settle_batch_of(S->o.shape);
   for (int i = 0; i < S->max_batch; ++i) S->hI[i].phase = PH_DONE;
   HIP_TRY(hipMemcpyAsync(w.dG, hG, sizeof(Globals), hipMemcpyHostToDevice, S->stream));
   HIP_TRY(hipMemcpyAsync(w.dInst, S->hI, sizeof(Inst) * (size_t)S->max_batch, hipMemcpyHostToDevice,

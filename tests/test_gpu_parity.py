@@ -117,6 +117,21 @@ def test_prep_matches_definitions():
     rows = np.repeat(np.arange(c.n), deg)
     order = np.lexsort((c.col, c.w, rows))
     assert np.array_equal(col, c.col[order]) and np.array_equal(w, c.w[order])
+    # the internal hub-first order: rows of at least 4x the mean degree (and
+    # 64) in front, at most 2^19; the rows above came back in the caller's ids
+    thr = max(64, 4 * c.nnz // c.n)
+    assert info["hub_first"] == min(int((deg >= thr).sum()), 1 << 19) > 0
+
+
+@pytest.mark.parametrize("name", ["er16", "grid256", "rmat16"])
+def test_hub_first_order_only_on_skewed_graphs(name):
+    wl = graphgen.workload(name)
+    c = wl.csr
+    g = sssp.Graph.from_csr(c)
+    deg = c.degrees()
+    thr = max(64, 4 * c.nnz // c.n)
+    assert g.info()["hub_first"] == min(int((deg >= thr).sum()), 1 << 19)
+    assert (g.info()["hub_first"] > 0) == name.startswith("rmat")
 
 
 def test_prep_long_rows_sorted():
@@ -256,6 +271,42 @@ def test_fused_rounds_on_off(name):
             [(a["lb"], a["ub"], a["st"]) for a in sched_off]
         if name == "grid256":
             assert c_on["fused_rounds"] > 0 and c_on["ticks"] < c_off["ticks"]
+
+
+@pytest.mark.parametrize("name", ["rmat14", "grid256", "er14", "rmat14f"])
+def test_tile_shapes_agree(name):
+    """Every tile shape (engine instantiation: round batches of 256, 512 or
+    1024 items, settle batches of 1024 or 2048) gives the oracle's distances
+    and the same schedule; trees and point-to-point queries too."""
+    wl = graphgen.workload(name)
+    c = wl.csr
+    fw = graphgen.binary32_weights(name)
+    g = sssp.Graph.from_csr(c, float_weights=fw)
+    adj = native.Adjacency(wl.edges.n, wl.edges.src, wl.edges.dst, wl.edges.w)
+    for s in wl.sources(2):
+        s = int(s)
+        ref = adj.dijkstra_f32(s) if fw else adj.dijkstra(s)
+        scheds = []
+        for shape in (1, 2, 3, 4):
+            d = g.solve(s, tile_shape=shape).cpu().numpy()
+            assert sssp.counters()["flags"] == 0
+            assert_same(d, ref, "%s shape %d s=%d" % (name, shape, s))
+            scheds.append([(a["lb"], a["ub"], a["st"]) for a in sssp.schedule()])
+            dt, p = g.solve_tree(s, tile_shape=shape)
+            assert_same(dt.cpu().numpy(), ref, "%s tree shape %d" % (name, shape))
+            if not fw:
+                assert native.check_tree(c.n, c.rowptr, c.col, c.w, s, ref, p.cpu().numpy()) == [0, 0, 0, 0]
+        assert all(x == scheds[0] for x in scheds)
+    # several instances of one launch, each shape
+    srcs = [int(x) for x in wl.sources(3)]
+    for shape in (2, 3):
+        outs = sssp.solve_multi([g] * 3, srcs, tile_shape=shape)
+        for s, o in zip(srcs, outs):
+            ref = adj.dijkstra_f32(s) if fw else adj.dijkstra(s)
+            assert_same(o.cpu().numpy(), ref, "%s multi shape %d" % (name, shape))
+    adj.close()
+    with pytest.raises(sssp.SSSPError):
+        g.solve(srcs[0], tile_shape=9)
 
 
 def test_grid_beyond_the_window_tiny_fuzz():
