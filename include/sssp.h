@@ -429,6 +429,30 @@ sssp_status sssp_debug_tick_log(hipStream_t stream, int32_t cap);
 sssp_status sssp_debug_get_tick_log(hipStream_t stream, uint64_t* out, int32_t cap, int32_t* len,
                                     uint64_t* t_start);
 
+/* ---- a solve that allocates nothing -------------------------------------- */
+
+/* For callers that cannot allocate device or host memory during the call
+ * (code under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc): sssp_solve's result, computed by the same kernels, with every
+ * solver buffer carved out of one device array of SSSP_NOALLOC_SCRATCH_BYTES
+ * that the library holds on each GPU it runs on until the process ends. The
+ * caller passes the graph (created beforehand), the source and dist_out
+ * (device, n uint32, caller-owned), as for sssp_solve; the call makes no
+ * allocation of any kind. Returns SSSP_E_RANGE, before anything is enqueued,
+ * for a graph whose solver buffers do not fit the array (64 bytes per vertex,
+ * 1/4 byte per CSR entry and 64 bytes per row longer than 64 entries, plus
+ * about 0.6 MB; the 16,384-vertex R-MAT graph of edge factor 16 needs about
+ * 2 MB, a graph of a million vertices does not fit), and the
+ * other argument errors of sssp_solve. Every call on one GPU shares that GPU's
+ * array: calls that overlap on one GPU (on different streams, or from
+ * different threads without ordering) race and give wrong results; calls
+ * ordered on one stream are safe. No counters, schedule or engine timing are
+ * recorded for sssp_get_counters / sssp_get_schedule / sssp_engine_times; a
+ * distance overflow leaves the affected entries at UINT32_MAX unreported. */
+#define SSSP_NOALLOC_SCRATCH_BYTES (64u << 20)
+sssp_status sssp_solve_noalloc(const sssp_graph* g, int32_t source, uint32_t* dist_out,
+                               hipStream_t stream);
+
 /* ---- teardown ----------------------------------------------------------- */
 
 /* Free what the library holds on its own behalf: the per-stream solver

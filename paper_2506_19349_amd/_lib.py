@@ -124,6 +124,7 @@ sssp_server_request_info = _sig("sssp_server_request_info", i32, vp, ctypes.c_in
 sssp_server_release = _sig("sssp_server_release", i32, vp, ctypes.c_int64)
 sssp_server_get_stats = _sig("sssp_server_get_stats", i32, vp, ctypes.POINTER(ServerStats))
 sssp_server_destroy = _sig("sssp_server_destroy", i32, vp)
+sssp_solve_noalloc = _sig("sssp_solve_noalloc", i32, vp, i32, vp, vp)
 sssp_release_workspaces = _sig("sssp_release_workspaces", i32)
 sssp_last_error = _sig("sssp_last_error", i32)
 sssp_last_error_message = _sig("sssp_last_error_message", ctypes.c_char_p)
