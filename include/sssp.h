@@ -66,10 +66,12 @@ typedef struct {
   int32_t fuse_rounds;   /* bucket fusion (Section 4.1's FUSED): rounds one workgroup may chain
                             without a grid-wide synchronisation while the frontier fits one
                             batch; 0 -> 256, -1 -> off */
-  int32_t tile_shape;    /* engine tile shape (one kernel instantiation each): 0 -> default (1);
-                            1: 512-item round batches, 1024-item settle batches; 2: 1024-item
-                            round batches (longer rounds within one workgroup, 3 workgroups per
-                            CU); 3: 256-item round batches; 4: 2048-item settle batches */
+  int32_t tile_shape;    /* engine tile shape (one kernel instantiation each): 1: 512-item round
+                            batches, 1024-item settle batches; 2: 1024-item round batches (longer
+                            rounds within one workgroup, 3 workgroups per CU); 3: 256-item round
+                            batches; 4: 2048-item settle batches. 0 -> default: 1 when a graph of
+                            the solve has skewed degrees (sssp_graph_info.hub_first > 0), else 3;
+                            the query server uses 1 */
   int32_t reserved[7];
 } sssp_options;
 

@@ -314,6 +314,7 @@ void fill_inst(Inst& I, const SlotBuf& s, const sssp_graph* g, int32_t source, u
                const Opts& o, int32_t* parent) {
   std::memset(&I, 0, sizeof(Inst));
   I.g = g->gh.d;
+  I.gc = g->gh.h;
   I.dist = dist;
   I.parent = parent;
   I.best = parent ? s.best : nullptr;
@@ -362,9 +363,18 @@ sssp_status run_instances(const sssp_graph* const* gs, const int32_t* sources, i
 }
 
 // Enqueue k instances on workspace w; every argument has been checked.
+int resolve_shape(const Opts& o, const sssp_graph* const* gs, int k) {
+  if (o.shape >= 0) return o.shape;
+  for (int i = 0; i < k; ++i)
+    if (gs[i]->gh.h.relabelled > 0) return SHAPE_STD;
+  return SHAPE_NARROW;
+}
+
 sssp_status run_instances_ws(Workspace& w, const sssp_graph* const* gs, const int32_t* sources, int k,
-                             uint32_t* const* dists, const Opts& o, hipStream_t stream,
+                             uint32_t* const* dists, const Opts& o_in, hipStream_t stream,
                              int32_t* const* parents, const int32_t* targets) {
+  Opts o = o_in;
+  o.shape = resolve_shape(o_in, gs, k);
   HIP_TRY(ws_ensure_insts(w, k));
   long long max_n = 0;
   for (int i = 0; i < k; ++i) {

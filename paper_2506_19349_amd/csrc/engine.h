@@ -176,6 +176,9 @@ constexpr int kMaxSegPerInst = 5;  // segments one instance may have in a tick
 // work counters, and the words that device atomics update.
 struct InstFixed {
   const DevGraph* g;
+  // a copy of *g: the batches read the graph's arrays and sizes with the
+  // instance's own words, with no dependent load of the graph record
+  DevGraph gc;
   uint32_t* dist;          // the caller's output, written once the solve ends
   int32_t* parent;         // the caller's tree output (Section 2.1's predecessors), or null
   // with a tree: per vertex (distance << 32) | the vertex whose relaxation set

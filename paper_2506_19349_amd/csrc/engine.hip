@@ -386,7 +386,7 @@ __device__ uint32_t block_compute_st_grid(const GInst& I, uint32_t L, uint32_t g
 // computeST, step bookkeeping, termination test, and the next step's setup.
 // Runs on one workgroup, after every settle batch of the instance is done.
 __device__ __noinline__ void run_heuristic(GInst& I, HeurLds& lds) {
-  GDevGraph& g = *gbl(I.g);
+  GDevGraph& g = I.gc;
   const int tid = threadIdx.x;
   const uint32_t L = I.ub;
   unsigned long long mass;
@@ -472,26 +472,50 @@ __device__ __noinline__ void run_heuristic(GInst& I, HeurLds& lds) {
     gbl(I.ring_mass)[slot] = 0;
     gbl(I.ring_cnt)[slot] = 0;
   }
+  // The settled-list range holding every vertex settled with dist in [lb0,
+  // st]: from the first step record with ub > lb0 to the last with lb <= st
+  // (records are ordered by band). Both ends usually lie among the newest
+  // records: the newest kBlock are tested at once, one per thread; a bisection
+  // over the older ones runs only when an end lies beyond them.
+  __shared__ int32_t s_r0, s_r1;
+  const int32_t nrec = I.nsteprec;
+  const int32_t avail = nrec < (int32_t)(I.steprec_mask + 1) ? nrec : (int32_t)(I.steprec_mask + 1);
+  const int32_t first = nrec - avail;  // oldest record still held
+  const int32_t w0 = max(first, nrec - kBlock);
+  if (tid == 0) {
+    s_r0 = nrec;
+    s_r1 = w0 - 1;
+  }
+  __syncthreads();
+  {
+    const int32_t i = nrec - 1 - tid;
+    if (i >= w0) {
+      const StepRec rec = gload(gbl(I.steprec) + ((uint32_t)i & I.steprec_mask));
+      if (rec.ub > lb0) atomicMin(&s_r0, i);
+      if (rec.lb <= stn) atomicMax(&s_r1, i);
+    }
+  }
   __syncthreads();
   if (tid == 0) {
-    // settled-list range holding every vertex settled with dist in [lb0, st]
-    int32_t nrec = I.nsteprec;
-    int32_t avail = nrec < (int32_t)(I.steprec_mask + 1) ? nrec : (int32_t)(I.steprec_mask + 1);
-    int32_t first = nrec - avail;  // oldest record still held
-    // first record with ub > lb0
-    int32_t lo = first, hi = nrec;
-    while (lo < hi) {
-      int32_t mid = (lo + hi) >> 1;
-      if (gbl(I.steprec)[(uint32_t)mid & I.steprec_mask].ub > lb0) hi = mid; else lo = mid + 1;
+    int32_t r0 = s_r0, r1 = s_r1;
+    if (r0 == w0 && w0 > first) {
+      // first record with ub > lb0 among the older ones (w0 has it)
+      int32_t lo = first, hi = w0;
+      while (lo < hi) {
+        int32_t mid = (lo + hi) >> 1;
+        if (gbl(I.steprec)[(uint32_t)mid & I.steprec_mask].ub > lb0) hi = mid; else lo = mid + 1;
+      }
+      r0 = lo;
     }
-    int32_t r0 = lo;
-    // last record with lb <= st  (records are ordered by band)
-    lo = first; hi = nrec;
-    while (lo < hi) {
-      int32_t mid = (lo + hi) >> 1;
-      if (gbl(I.steprec)[(uint32_t)mid & I.steprec_mask].lb <= stn) lo = mid + 1; else hi = mid;
+    if (r1 < w0 && w0 > first) {
+      // last record with lb <= st among the older ones (w0 lacks it)
+      int32_t lo = first, hi = w0;
+      while (lo < hi) {
+        int32_t mid = (lo + hi) >> 1;
+        if (gbl(I.steprec)[(uint32_t)mid & I.steprec_mask].lb <= stn) lo = mid + 1; else hi = mid;
+      }
+      r1 = lo - 1;
     }
-    int32_t r1 = lo - 1;
     int32_t wb = 0, we = 0;
     if (r0 <= r1 && r0 < nrec && r1 >= first) {
       wb = gbl(I.steprec)[(uint32_t)r0 & I.steprec_mask].seg_begin;
@@ -563,7 +587,7 @@ struct View {
 
 __device__ __forceinline__ View make_view(GInst& I) {
   View v;
-  GDevGraph& g = *gbl(I.g);
+  GDevGraph& g = I.gc;
   v.rowptr = gbl(g.rowptr);
   v.adj = gbl(g.adj);
   v.wmin = gbl(g.wmin);
@@ -605,28 +629,61 @@ struct WaveAcc {
   uint32_t hubmin;
 };
 
-__device__ __forceinline__ int global_wave() { return (int)(blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave); }
+// The work counters of a workgroup, gathered in LDS for one instance at a
+// time and written to that instance's slot for this workgroup (no other
+// workgroup adds to it) when the workgroup turns to another instance or the
+// kernel ends: the batches themselves issue no counter atomics to memory.
+struct WgAcc {
+  unsigned long long v[7];  // expansions, band, push, pull vertices, pull entries, successes, queue
+  int inst;                 // instance the values belong to, -1: none
+  int pad;
+};
+static_assert(offsetof(Counters, band_expansions) == 8 && offsetof(Counters, push_scanned) == 16 &&
+                  offsetof(Counters, pull_vertices) == 24 && offsetof(Counters, pull_scanned) == 32 &&
+                  offsetof(Counters, relax_success) == 40 && offsetof(Counters, queue_entries) == 48,
+              "the gathered counters follow Counters' order");
+__shared__ WgAcc g_wgacc;
 
-// Work counters go to this wave's own slot (no other wave adds to it, so the
-// atomics never contend); the step-1 hub bound is a shared atomic.
+// Thread 0: write the gathered counters to their instance's slot and start over.
+__device__ void wgacc_flush(GGlobals& G) {
+  const int i = g_wgacc.inst;
+  if (i >= 0) {
+    GInst& I = gbl(G.insts)[i];
+    if ((int)blockIdx.x < I.maxw) {
+      SSSP_GBL unsigned long long* c = &gbl(I.cslot)[blockIdx.x].expansions;
+      // Counters keeps the same order as v[]
+      for (int k = 0; k < 7; ++k)
+        if (g_wgacc.v[k]) atomicAdd(c + k, g_wgacc.v[k]);  // no returned value: nothing waits
+    }
+  }
+  for (int k = 0; k < 7; ++k) g_wgacc.v[k] = 0;
+  g_wgacc.inst = -1;
+}
+
+// Thread 0, before a batch of instance i: the gathered counters must be i's.
+__device__ __forceinline__ void wgacc_select(GGlobals& G, int i) {
+  if (g_wgacc.inst != i) {
+    wgacc_flush(G);
+    g_wgacc.inst = i;
+  }
+}
+
+// The wave's counters go to the workgroup's gathered ones; the step-1 hub
+// bound is a shared atomic.
 __device__ __forceinline__ void flush_acc(GInst& I, int maxw, WaveAcc& a) {
+  (void)maxw;
   unsigned long long e = wave_sum(a.expansions), b = wave_sum(a.band), ps = wave_sum(a.pscan),
                      pv = wave_sum(a.pvert), pl = wave_sum(a.pullscan), su = wave_sum(a.success),
                      qe = wave_sum(a.qent);
   uint32_t hm = wave_min_u32(a.hubmin);
   if (lane_id() == 0) {
-    const int gw = global_wave();
-    if (gw < maxw) {
-      // atomics without a returned value: nothing waits for them
-      SSSP_GBL Counters& c = gbl(I.cslot)[gw];
-      if (e) atomicAdd(&c.expansions, e);
-      if (b) atomicAdd(&c.band_expansions, b);
-      if (ps) atomicAdd(&c.push_scanned, ps);
-      if (pv) atomicAdd(&c.pull_vertices, pv);
-      if (pl) atomicAdd(&c.pull_scanned, pl);
-      if (su) atomicAdd(&c.relax_success, su);
-      if (qe) atomicAdd(&c.queue_entries, qe);
-    }
+    if (e) atomicAdd(&g_wgacc.v[0], e);
+    if (b) atomicAdd(&g_wgacc.v[1], b);
+    if (ps) atomicAdd(&g_wgacc.v[2], ps);
+    if (pv) atomicAdd(&g_wgacc.v[3], pv);
+    if (pl) atomicAdd(&g_wgacc.v[4], pl);
+    if (su) atomicAdd(&g_wgacc.v[5], su);
+    if (qe) atomicAdd(&g_wgacc.v[6], qe);
     if (hm != kInf) atomicMin(&I.ub_next.v, hm);
   }
 }
@@ -850,7 +907,7 @@ __device__ __noinline__ void block_round(GInst& I, int kind, int item0, int nite
     const int usel = I.usel;
     const int ncur = I.nU;
     const SSSP_GBL UEntry* ucur = gbl(I.ulist[usel]);
-    const SSSP_GBL UEntry* fresh = gbl(gbl(I.g)->nonisolated) + I.u_done;
+    const SSSP_GBL UEntry* fresh = gbl(I.gc.nonisolated) + I.u_done;
     auto unext = gbl(I.ulist[usel ^ 1]);
     const uint32_t reach = ub - st;  // integer weights
     UEntry ee[kItemsPerThread];
@@ -1245,7 +1302,7 @@ union BlockLds {
 template <class Sh>
 __device__ __noinline__ void block_settle(GInst& I, int kind, int item0, int nitems, SettleLds& L) {
   constexpr int kSettlePer = Sh::kSettle;
-  GDevGraph& g = *gbl(I.g);
+  GDevGraph& g = I.gc;
   const int tid = threadIdx.x;
   const uint32_t lb = I.lb, ub = I.ub, M = I.M;
   // the ring feeds computeST: per distance, or per bin of the ST_NUM grid
@@ -1364,8 +1421,7 @@ __device__ __noinline__ void block_settle(GInst& I, int kind, int item0, int nit
   if (lane_id() == 0) {
     L.sdec[tid / kWave] = ws;
     L.maxd[tid / kWave] = wm;
-    const int gw = global_wave();
-    if (qe && gw < maxw) atomicAdd(&gbl(I.cslot)[gw].queue_entries, qe);
+    if (qe) atomicAdd(&g_wgacc.v[6], qe);
   }
   __syncthreads();
   for (uint32_t k = tid; k < nb; k += kBlock) {
@@ -1395,8 +1451,19 @@ __device__ __noinline__ void block_settle(GInst& I, int kind, int item0, int nit
 
 // ------------------------------------------------------------- scheduling --
 
+// The segment holding batch b: the last one whose first batch is <= b. With
+// few segments each thread tests one (a single round of loads); with many,
+// a bisection. Whole workgroup.
 __device__ int find_segment(const GGlobals& G, int b) {
-  int lo = 0, hi = G.nseg;  // seg_first_batch has nseg + 1 entries
+  const int nseg = G.nseg;  // seg_first_batch has nseg + 1 entries
+  if (nseg <= kBlock) {
+    const int t = threadIdx.x;
+    const bool le = t < nseg && gbl(G.seg_first_batch)[t] <= b;
+    // first batches do not decrease: the count of segments starting at or
+    // before b is the index of b's segment plus one
+    return __syncthreads_count(le) - 1;
+  }
+  int lo = 0, hi = nseg;
   while (lo < hi) {
     int mid = (lo + hi + 1) >> 1;
     if (gbl(G.seg_first_batch)[mid] <= b) lo = mid; else hi = mid - 1;
@@ -1475,7 +1542,10 @@ __device__ void run_tick(GGlobals& G, BlockLds<Sh>& lds, int pid, int P) {
   if (tl && threadIdx.x == 0 && pid < total_batches) atomicMin((unsigned long long*)(tl + 4), wall_clock64());
   for (int b = pid; b < total_batches; b += P) {
     const int sgi = find_segment(G, b);
-    GInst& I = gbl(G.insts)[gbl(G.seg_inst)[sgi]];
+    const int ii = gbl(G.seg_inst)[sgi];
+    GInst& I = gbl(G.insts)[ii];
+    __syncthreads();  // the previous batch's counter additions are in
+    if (threadIdx.x == 0) wgacc_select(G, ii);  // block_settle / block_round sync before adding
     const int kind = gbl(G.seg_kind)[sgi];
     const int pb = gbl(G.seg_per_batch)[sgi];
     const int item0 = (b - gbl(G.seg_first_batch)[sgi]) * pb;
@@ -1743,9 +1813,22 @@ __device__ bool spin_until_changed(SSSP_GBL unsigned int* word, unsigned int old
 // batches, at least one per XCD. The others sit the tick out, so a tick with
 // little work synchronises few workgroups (the barrier's cost grows with the
 // number of workgroups that write back and invalidate caches).
+//
+// A tick of at most kLocalBatches batches runs on one XCD (the first
+// populated one): every batch goes to its workgroups, and each other XCD sends
+// one workgroup to the barrier with no work. A run of small ticks (the rounds
+// and settle passes of a high-diameter graph) then reads what the previous
+// tick wrote from that XCD's own L2. Such a tick's word is the quota of the
+// working XCD with kLocalTick set.
+constexpr int kLocalBatches = 64;
+constexpr unsigned int kLocalTick = 0x80000000u;
 __device__ __forceinline__ unsigned int quota_for(int total_batches, unsigned int nxcd,
-                                                  unsigned int min_members) {
+                                                  unsigned int min_members, unsigned int members0) {
   const unsigned int nx = nxcd ? nxcd : 1u;
+  if (nx > 1u && total_batches <= kLocalBatches && (unsigned int)total_batches <= members0) {
+    const unsigned int q = total_batches < 1 ? 1u : (unsigned int)total_batches;
+    return q | kLocalTick;
+  }
   unsigned int q = ((unsigned int)total_batches + nx - 1) / nx;
   if (q < 1u) q = 1u;
   if (q > min_members) q = min_members;
@@ -1756,7 +1839,7 @@ __device__ __forceinline__ unsigned int quota_for(int total_batches, unsigned in
 // The serial part between two ticks (one workgroup): tick log, phase
 // transitions and the next tick's work layout.
 __device__ __forceinline__ void epilogue(GGlobals& G, unsigned int gen, unsigned int nxcd,
-                                     unsigned int min_members) {
+                                     unsigned int min_members, unsigned int members0) {
   if (threadIdx.x == 0) {
     if (gbl(G.tick_log) && G.ticks < G.tick_log_cap) {
       auto e = gbl(G.tick_log) + kTickLogWords * G.ticks;
@@ -1771,7 +1854,7 @@ __device__ __forceinline__ void epilogue(GGlobals& G, unsigned int gen, unsigned
   build_table(G, true, true);
   if (threadIdx.x == 0) {
     // the next tick starts at generation gen + 1
-    __hip_atomic_store(&G.quota[(gen + 1u) & 7u], quota_for(G.total_batches, nxcd, min_members),
+    __hip_atomic_store(&G.quota[(gen + 1u) & 7u], quota_for(G.total_batches, nxcd, min_members, members0),
                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (gbl(G.tick_log) && G.ticks < G.tick_log_cap) gbl(G.tick_log)[kTickLogWords * G.ticks + 3] = wall_clock64();
     G.ticks += 1;
@@ -1792,8 +1875,9 @@ struct BarrierState {
   uint32_t nxcd;       // XCDs with at least one workgroup
   uint32_t rank;       // this workgroup's rank among its XCD's workgroups
   uint32_t xidx;       // this XCD's index among the populated XCDs
-  uint32_t q0;         // workgroups per XCD in the launch's first tick
+  uint32_t q0;         // quota word of the launch's first tick
   uint32_t min_members;  // workgroups on the least populated XCD
+  uint32_t members0;   // workgroups on the first populated XCD (where small ticks run)
 };
 
 // Flat barrier with full fences by every workgroup; used once per launch to
@@ -1813,7 +1897,7 @@ __device__ bool barrier_flat(GGlobals& G, unsigned int& gen, bool wait, bool run
   if (s_last) {
     if (threadIdx.x == 0) __threadfence();
     __syncthreads();
-    if (run_epilogue) epilogue(G, gen, 1u, 1u);
+    if (run_epilogue) epilogue(G, gen, 1u, 1u, 1u);
     if (threadIdx.x == 0) {
       __hip_atomic_store(&G.bar_count.v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __threadfence();
@@ -1883,7 +1967,7 @@ __device__ bool barrier_tick(GGlobals& G, BarrierState& B, unsigned int quota) {
   __syncthreads();
   const int role = s_role;
   if (role == 2) {
-    epilogue(G, B.gen, B.nxcd, B.min_members);
+    epilogue(G, B.gen, B.nxcd, B.min_members, B.members0);
     if (threadIdx.x == 0) {
       __threadfence();
       atomicAdd(&G.bar_gen.v, 1u);
@@ -1909,6 +1993,8 @@ __global__ void __launch_bounds__(kBlock, Sh::kMinBlocks) k_engine(Globals* Gp, 
   __shared__ BarrierState s_b;
   GGlobals& G = *gbl(Gp);
   if (threadIdx.x == 0) {
+    for (int k = 0; k < 7; ++k) g_wgacc.v[k] = 0;
+    g_wgacc.inst = -1;
     s_b.gen = __hip_atomic_load(&G.bar_gen.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (blockIdx.x == 0 && G.ticks == 0) G.t_start = wall_clock64();
   }
@@ -1917,6 +2003,8 @@ __global__ void __launch_bounds__(kBlock, Sh::kMinBlocks) k_engine(Globals* Gp, 
     // one tick; the kernel boundary is the barrier
     if (__hip_atomic_load(&G.all_done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
     run_tick<Sh>(G, lds, blockIdx.x, gridDim.x);
+    __syncthreads();
+    if (threadIdx.x == 0) wgacc_flush(G);
     unsigned int gen = s_b.gen;
     barrier_flat(G, gen, false, true);
     return;
@@ -1934,11 +2022,12 @@ __global__ void __launch_bounds__(kBlock, Sh::kMinBlocks) k_engine(Globals* Gp, 
   if (threadIdx.x == 0) {
     s_b.gen = gen;
     s_b.members = __hip_atomic_load(&G.xcd_members[s_b.xcd].v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    uint32_t nx = 0, xi = 0, mn = 0xffffffffu;
+    uint32_t nx = 0, xi = 0, mn = 0xffffffffu, m0 = 0;
     for (int x = 0; x < kMaxXcd; ++x) {
       const uint32_t m = __hip_atomic_load(&G.xcd_members[x].v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (m == 0) continue;
       if ((uint32_t)x < s_b.xcd) ++xi;
+      if (nx == 0) m0 = m;
       ++nx;
       mn = m < mn ? m : mn;
     }
@@ -1947,8 +2036,9 @@ __global__ void __launch_bounds__(kBlock, Sh::kMinBlocks) k_engine(Globals* Gp, 
     // every workgroup computes the same values, the first tick's quota
     // included (from the table the set-up kernel built); the epilogue
     // publishes the later ones
-    s_b.q0 = quota_for(G.total_batches, nx, mn);
+    s_b.q0 = quota_for(G.total_batches, nx, mn, m0);
     s_b.min_members = mn;
+    s_b.members0 = m0;
   }
   __syncthreads();
   BarrierState B = s_b;
@@ -1961,7 +2051,11 @@ __global__ void __launch_bounds__(kBlock, Sh::kMinBlocks) k_engine(Globals* Gp, 
       s_quota = t == 0 ? B.q0
                        : __hip_atomic_load(&G.quota[B.gen & 7u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
-    const unsigned int q = s_quota;
+    const unsigned int qw = s_quota;
+    const bool local = (qw & kLocalTick) != 0;
+    const unsigned int qx = qw & ~kLocalTick;
+    // this XCD's participants: a small tick's batches all go to the first XCD
+    const unsigned int q = local ? (B.xidx == 0 ? qx : 1u) : qx;
     if (B.rank < q) {
       if (stale) {
         // back from waiting aside: drop cached lines before reading the tick's data
@@ -1969,7 +2063,8 @@ __global__ void __launch_bounds__(kBlock, Sh::kMinBlocks) k_engine(Globals* Gp, 
         __syncthreads();
         stale = false;
       }
-      run_tick<Sh>(G, lds, (int)(B.rank * B.nxcd + B.xidx), (int)(q * B.nxcd));
+      if (local) run_tick<Sh>(G, lds, B.xidx == 0 ? (int)B.rank : 0x7fffffff, (int)qx);
+      else run_tick<Sh>(G, lds, (int)(B.rank * B.nxcd + B.xidx), (int)(q * B.nxcd));
       if (!barrier_tick(G, B, q)) break;
       t += 1;
     } else {
@@ -1989,6 +2084,8 @@ __global__ void __launch_bounds__(kBlock, Sh::kMinBlocks) k_engine(Globals* Gp, 
       break;
     }
   }
+  __syncthreads();
+  if (threadIdx.x == 0) wgacc_flush(G);
 }
 
 // Per-solve state reset: state words, histogram, ring, counters. Grid-stride
@@ -2000,7 +2097,7 @@ __global__ void k_init_arrays(Globals* Gp) {
   const int nsel = G.n_sel < 0 ? G.ninst : G.n_sel;
   for (int j = 0; j < nsel; ++j) {
     GInst& I = gbl(G.insts)[G.n_sel < 0 ? j : gbl(G.sel_list)[j]];
-    GDevGraph& g = *gbl(I.g);
+    GDevGraph& g = I.gc;
     auto state = gbl(I.state);
     for (long long v = tid; v < I.n; v += stride) state[v] = (unsigned long long)kInf << 32;
     if (I.best)
@@ -2023,7 +2120,7 @@ __global__ void __launch_bounds__(kBlock) k_init_ctl(Globals* Gp) {
   const int nsel = G.n_sel < 0 ? G.ninst : G.n_sel;
   for (int j = 0; j < nsel; ++j) {
     GInst& I = gbl(G.insts)[G.n_sel < 0 ? j : gbl(G.sel_list)[j]];
-    GDevGraph& g = *gbl(I.g);
+    GDevGraph& g = I.gc;
     if (threadIdx.x == 0) {
       // the caller's ids to internal ones
       const SSSP_GBL int32_t* ren = g.new_of_old ? gbl(g.new_of_old) : nullptr;
@@ -2107,7 +2204,7 @@ __global__ void k_overflow_check(Globals* Gp) {
   for (int j = 0; j < nsel; ++j) {
     GInst& I = gbl(G.insts)[G.n_sel < 0 ? j : gbl(G.sel_list)[j]];
     if (!(I.flags.v & FLAG_MAYBE_OVERFLOW)) continue;
-    GDevGraph& g = *gbl(I.g);
+    GDevGraph& g = I.gc;
     bool found = false;
     for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < g.n && !found;
          v += (long long)gridDim.x * blockDim.x) {
@@ -2132,7 +2229,7 @@ __global__ void k_finish(Globals* Gp) {
   const int nsel = G.n_sel < 0 ? G.ninst : G.n_sel;
   for (int j = 0; j < nsel; ++j) {
     GInst& I = gbl(G.insts)[G.n_sel < 0 ? j : gbl(G.sel_list)[j]];
-    GDevGraph& g = *gbl(I.g);
+    GDevGraph& g = I.gc;
     auto state = gbl(I.state);
     auto dist = gbl(I.dist);
     // outputs are indexed by the caller's ids: v is the caller's, ren[v] internal

@@ -54,6 +54,7 @@ struct NoAllocDesc {
   double beta;
   int32_t source, n, maxw, heavy_cap, trace_cap, segcap, heavy_split, fuse_cap;
   uint32_t ring_mask, steprec_mask, alpha, topt, mode, pad;
+  int32_t round_batch, settle_batch;
 };
 
 // Lays the buffers of one solve out in the array from `base` on, each on a
@@ -80,6 +81,7 @@ __global__ void __launch_bounds__(kBlock) k_noalloc_setup(NoAllocDesc d) {
   if (threadIdx.x != 0) return;
   Inst& I = *d.I;
   I.g = d.g;
+  I.gc = *d.g;
   I.dist = d.dist;
   I.parent = nullptr;
   I.best = nullptr;
@@ -128,14 +130,15 @@ __global__ void __launch_bounds__(kBlock) k_noalloc_setup(NoAllocDesc d) {
   G.insts = d.I;
   G.sel_list = nullptr;
   G.n_sel = -1;
-  G.round_batch = ShapeStd::kBatch;
-  G.settle_batch = ShapeStd::kSettleBatch;
+  G.round_batch = d.round_batch;
+  G.settle_batch = d.settle_batch;
 }
 
 struct DeviceScratch {
   bool ready = false;
   unsigned char* ptr = nullptr;  // the array's address on that device
-  int cus = 0, occ = 0;
+  int cus = 0;
+  int occ[kNumShapes] = {};      // workgroups per CU of each tile shape's engine kernel
 };
 constexpr int kMaxDevices = 64;
 std::mutex g_na_mu;
@@ -167,13 +170,16 @@ extern "C" sssp_status sssp_solve_noalloc(const sssp_graph* g, int32_t source, u
       HIP_TRY(hipGetDeviceProperties(&prop, dev));
       e.ptr = static_cast<unsigned char*>(p);
       e.cus = prop.multiProcessorCount;
-      e.occ = engine_blocks_per_cu(SHAPE_STD);
+      for (int sh = 0; sh < kNumShapes; ++sh) e.occ[sh] = engine_blocks_per_cu(sh);
       e.ready = true;
     }
     ds = e;
   }
   const DevGraph& h = g->gh.h;
-  const int maxw = ds.cus * ds.occ * (kBlock / kWave);
+  Opts o;
+  const sssp_graph* gg[1] = {g};
+  const int shape = resolve_shape(o, gg, 1);  // the tile shape sssp_solve takes for this graph
+  const int maxw = ds.cus * ds.occ[shape] * (kBlock / kWave);
   Needs nd = needs_for(h, maxw);
   nd.trace = kNoAllocTrace;
   const int segcap = kMaxSegPerInst + 1;
@@ -203,7 +209,6 @@ extern "C" sssp_status sssp_solve_noalloc(const sssp_graph* g, int32_t source, u
   if (c.off > kScratchBytes)
     return fail(SSSP_E_RANGE, "this graph needs " + std::to_string(c.off) + " bytes of solver scratch; "
                 "sssp_solve_noalloc holds " + std::to_string(kScratchBytes));
-  Opts o;
   d.g = g->gh.d;
   d.dist = dist_out;
   d.tick_limit = o.tick_limit;
@@ -221,16 +226,19 @@ extern "C" sssp_status sssp_solve_noalloc(const sssp_graph* g, int32_t source, u
   d.alpha = o.alpha;
   d.topt = o.topt;
   d.mode = h.float_w ? 2u : 0u;
+  d.round_batch = round_batch_of(shape);
+  d.settle_batch = settle_batch_of(shape);
   hipLaunchKernelGGL(k_noalloc_setup, dim3(1), dim3(kBlock), 0, stream, d);
   HIP_TRY(hipGetLastError());
   HIP_TRY(launch_init(d.G, h.n, stream));
   // the persistent grid of sssp_solve: every CU's occupancy, fewer workgroups
   // for small graphs (a multiple of the XCD count)
-  long long need = ((long long)h.n + ShapeStd::kBatch - 1) / ShapeStd::kBatch;
+  const int rb = round_batch_of(shape);
+  long long need = ((long long)h.n + rb - 1) / rb;
   need = ((need + kMaxXcd - 1) / kMaxXcd) * kMaxXcd;
   need = std::max<long long>(need, kMaxXcd);
-  const int grid = (int)std::min<long long>((long long)ds.cus * ds.occ, need);
-  HIP_TRY(launch_engine(d.G, grid, true, 0, stream, SHAPE_STD));
+  const int grid = (int)std::min<long long>((long long)ds.cus * ds.occ[shape], need);
+  HIP_TRY(launch_engine(d.G, grid, true, 0, stream, shape));
   HIP_TRY(launch_overflow_check(d.G, h.n, stream));
   HIP_TRY(launch_finish(d.G, h.n, stream));
   return ok();

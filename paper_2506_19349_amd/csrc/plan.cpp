@@ -47,6 +47,7 @@ sssp_status plan_build(sssp_plan* p, uint32_t* const* dist_outs, int32_t* const*
   std::string err;
   if (!ws_setup(w, stream, &err)) return fail(SSSP_E_DEVICE, err);
   const int k = p->k;
+  p->o.shape = resolve_shape(p->o, p->gs.data(), k);
   HIP_TRY(ws_ensure_insts(w, k));
   long long max_n = 0;
   for (int i = 0; i < k; ++i) {
@@ -279,7 +280,7 @@ sssp_status sssp_autotune(const sssp_graph* const* gs, const int32_t* sources, i
     if (knob == 0) {
       for (int sh = 0; sh < kNumShapes; ++sh) { Opts o = best; o.shape = sh; cands.push_back(o); }
     } else if (knob == 1) {
-      const int occ = w.occ_s[best.shape];
+      const int occ = w.occ_s[resolve_shape(best, gs, k)];
       for (int b : {1, 2, 0}) {
         if (b > occ) continue;
         Opts o = best;
@@ -314,7 +315,7 @@ sssp_status sssp_autotune(const sssp_graph* const* gs, const int32_t* sources, i
   inout->blocks_per_cu = best.blocks_per_cu;  // 0: the default grid rule
   inout->heavy_split = best.heavy;
   inout->fuse_rounds = best.fuse > 0 ? best.fuse : -1;
-  inout->tile_shape = best.shape + 1;
+  inout->tile_shape = best.shape + 1;  // 0 when the default rule won
   if (report) {
     std::memset(report, 0, sizeof(*report));
     report->default_us = base_us;

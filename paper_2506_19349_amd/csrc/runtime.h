@@ -128,11 +128,16 @@ struct Opts {
   int blocks_per_cu = 0;
   int heavy = kDefaultHeavy;
   int fuse = kDefaultFuse;
-  int shape = SHAPE_STD;  // tile shape (engine kernel instantiation)
+  int shape = -1;  // tile shape (engine kernel instantiation); -1: by the graphs (resolve_shape)
   unsigned long long tick_limit = 1ull << 22;
 };
 
 bool parse_opts(const sssp_options* o, Opts* r, std::string* err);
+// The tile shape of a launch over these graphs: the one asked for, else the
+// standard shape when a graph has skewed degrees (a hub-first order) and the
+// narrow shape (256-item round batches, more of them per frontier) when none
+// has.
+int resolve_shape(const Opts& o, const sssp_graph* const* gs, int k);
 // Persistent grid size for k instances of total_n vertices: the tuned or
 // requested workgroups per CU, fewer for small graphs.
 int engine_grid(const Workspace& w, const Opts& o, long long total_n);

@@ -413,6 +413,7 @@ sssp_status server_setup(sssp_server* S) {
   hG->insts = w.dInst;
   hG->sel_list = S->d_sel;
   hG->n_sel = 0;
+  if (S->o.shape < 0) S->o.shape = SHAPE_STD;  // graphs come and go: the standard shape
   hG->round_batch = round_batch_of(S->o.shape);
   hG->settle_batch = settle_batch_of(S->o.shape);
   for (int i = 0; i < S->max_batch; ++i) S->hI[i].phase = PH_DONE;
