@@ -75,10 +75,15 @@ def engine_source_hash() -> str:
 
 
 def measured_traffic(workload: str):
-    """HBM bytes per engine launch from the committed counter summary: the
-    FETCH_SIZE and WRITE_SIZE readings (KiB per dispatch) of the engine kernel,
-    each scaled by what the same counter reads for a copy of known size. None
-    when there is no summary for this workload or the engine has changed since."""
+    """HBM bytes per engine launch from the committed counter summary, or None
+    when there is no summary for this workload or the engine has changed since.
+
+    Returns (traffic, copy_scaled, unscaled). traffic: the engine kernel's
+    FETCH_SIZE reading (KiB per dispatch) scaled by what the same counter reads
+    for a reference gather of known bytes (random 64-byte rows, the engine's own
+    access pattern), plus its WRITE_SIZE reading scaled by a copy of known
+    size. copy_scaled: both counters scaled by the copy (a streaming read);
+    unscaled: the two readings as they stand."""
     if workload != "rmat24" or not os.path.exists(COUNTERS_FILE):
         return None
     vals = {}
@@ -88,14 +93,16 @@ def measured_traffic(workload: str):
             if m:
                 vals[m.group(1)] = m.group(2)
     need = ("engine_source_sha256", "engine_fetch_kib", "engine_write_kib", "copy_bytes",
-            "copy_fetch_kib", "copy_write_kib")
+            "copy_fetch_kib", "copy_write_kib", "gather_read_bytes", "gather_fetch_kib")
     if any(k not in vals for k in need) or vals["engine_source_sha256"] != engine_source_hash():
         return None
+    fetch = float(vals["engine_fetch_kib"]) * 1024.0
+    write = float(vals["engine_write_kib"]) * 1024.0
     cb = float(vals["copy_bytes"])
-    f_fetch = cb / (float(vals["copy_fetch_kib"]) * 1024.0)
+    f_copy = cb / (float(vals["copy_fetch_kib"]) * 1024.0)
     f_write = cb / (float(vals["copy_write_kib"]) * 1024.0)
-    return (float(vals["engine_fetch_kib"]) * 1024.0 * f_fetch
-            + float(vals["engine_write_kib"]) * 1024.0 * f_write)
+    f_gather = float(vals["gather_read_bytes"]) / (float(vals["gather_fetch_kib"]) * 1024.0)
+    return fetch * f_gather + write * f_write, fetch * f_copy + write * f_write, fetch + write
 
 
 def time_solves(sssp, torch, g, srcs, outs, warm, **opts):
@@ -785,7 +792,9 @@ def main():
         "config": config,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
-                     "traffic": None if traffic is None else int(traffic),
+                     "traffic": None if traffic is None else int(traffic[0]),
+                     "traffic_copy_scaled": None if traffic is None else int(traffic[1]),
+                     "traffic_unscaled": None if traffic is None else int(traffic[2]),
                      "kernel": "k_engine", "kernel_us_mean": round(eng_mean_us, 2),
                      "alg_bytes_per_launch": int(sum(B) / len(B))},
         "cpu_baseline": cpu,
