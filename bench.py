@@ -29,8 +29,11 @@ INF = 0xFFFFFFFF
 ORACLE_BUILD = "gcc -O3"
 
 
+T_START = time.time()
+
+
 def log(*a):
-    print("[bench]", *a, file=sys.stderr, flush=True)
+    print("[bench]", "%6.1fs" % (time.time() - T_START), *a, file=sys.stderr, flush=True)
 
 
 def alg_bytes(c: dict) -> int:
@@ -179,6 +182,18 @@ def config_section(args, sssp, torch, np, graphgen, name, nsrc, repeat, what):
     return rec
 
 
+# the autotuner's coordinate-descent search space (sssp_autotune), knob by knob
+TUNER_SPACE = {"tile_shape": [1, 2, 3, 4], "blocks_per_cu": [1, 2, "all the shape allows"],
+               "heavy_split": [64, 256, 1024, 4096], "fuse_rounds": ["on (256)", "off"],
+               "beta": "0.9 (not tuned here; {0.85, 0.9, 0.95} with tune_beta)"}
+
+
+def tuner_report(rep, tune_s):
+    return {"space": TUNER_SPACE, "evaluations": rep["evaluations"], "seconds": round(tune_s, 2),
+            "default_us": round(rep["default_us"], 1), "best_us": round(rep["best_us"], 1),
+            "gain": round(rep["default_us"] / rep["best_us"], 4) if rep["best_us"] > 0 else None}
+
+
 def batched_section(args, sssp, torch, np, graphgen):
     """64 sources on RMAT-22 in one graph-captured persistent launch, and 256
     small R-MAT graphs (scales 10..16) in another; knobs picked by the
@@ -215,8 +230,7 @@ def batched_section(args, sssp, torch, np, graphgen):
     res["rmat22_64_sources"] = {
         "queries_per_s": round(k / dt, 1), "ms_per_batch": round(dt * 1e3, 3),
         "one_at_a_time_queries_per_s": round(k / dt1, 1), "speedup": round(dt1 / dt, 2),
-        "tuned": tuned, "tune_s": round(tune_s, 2), "tune_default_us": round(rep["default_us"], 1),
-        "tune_best_us": round(rep["best_us"], 1), "checked_rows_exact": bool(ok)}
+        "tuned": tuned, "tuner": tuner_report(rep, tune_s), "checked_rows_exact": bool(ok)}
     log("batched RMAT-22 x64: %.1f q/s (one at a time %.1f q/s), tuned %s" % (k / dt, k / dt1, tuned))
     if not args.no_cpu_baseline:
         threads = max(1, min(16, os.cpu_count() or 1))
@@ -237,7 +251,9 @@ def batched_section(args, sssp, torch, np, graphgen):
     batch = graphgen.small_rmat_batch()
     gs = [sssp.Graph.from_csr(w.csr) for w in batch]
     ss = [[int(x) for x in w.sources(4)] for w in batch]
+    t = time.perf_counter()
     tuned2, rep2 = sssp.autotune(gs, [s[0] for s in ss], batched=True)
+    tune_s2 = time.perf_counter() - t
     outs = [torch.empty(w.csr.n, dtype=torch.uint32, device="cuda") for w in batch]
     plan = sssp.Plan(gs, outs, **tuned2)
     plan.run([s[0] for s in ss])
@@ -258,8 +274,9 @@ def batched_section(args, sssp, torch, np, graphgen):
     res["rmat10to16_256_graphs"] = {
         "queries_per_s": round(len(gs) / dt, 1), "ms_per_batch": round(dt * 1e3, 3),
         "one_at_a_time_queries_per_s": round(len(gs) / dt1, 1), "speedup": round(dt1 / dt, 2),
-        "tuned": tuned2, "checked_rows_exact": bool(ok)}
-    log("batched 256 small graphs: %.1f q/s (one at a time %.1f q/s)" % (len(gs) / dt, len(gs) / dt1))
+        "tuned": tuned2, "tuner": tuner_report(rep2, tune_s2), "checked_rows_exact": bool(ok)}
+    log("batched 256 small graphs: %.1f q/s (one at a time %.1f q/s), tuner %.1f -> %.1f us" % (
+        len(gs) / dt, len(gs) / dt1, rep2["default_us"], rep2["best_us"]))
     plan.close()
     for gg in gs:
         gg.close()
@@ -377,7 +394,9 @@ def served_section(args, sssp, torch, np, graphgen):
     * Served: the continuous-batching server at saturation (every query
       submitted at once: its capacity), then a Poisson stream at lambda =
       {0.5, 0.8, 1.0, 1.25} x FIFO capacity: throughput, p50 and p99 latency
-      from submission to completion.
+      from submission to completion. Loads below capacity take the stream's
+      first --serve-queries-light queries (a run lasts queries / rate
+      seconds); the others all N.
     Every served result is compared with the same query solved alone."""
     names = ["rmat20", "rmat22", "rmat23", "grid2048"]
     wls = [graphgen.workload(nm) for nm in names]
@@ -425,19 +444,19 @@ def served_section(args, sssp, torch, np, graphgen):
     log("plain FIFO at %.2f q/s (run): p50 %.1f ms p99 %.1f ms; capacity over all %d queries %.2f q/s"
         % (cap0, pct(fifo_lat, 50), pct(fifo_lat, 99), N, fifo_cap))
 
-    def fifo_at(rate):
-        arr = np.cumsum(unit_gaps) / rate
+    def fifo_at(rate, nq):
+        arr = np.cumsum(unit_gaps[:nq]) / rate
         arr -= arr[0]
         fin, lat = 0.0, []
-        for a, sv in zip(arr, service):
+        for a, sv in zip(arr, service[:nq]):
             fin = max(fin, a) + sv
             lat.append(fin - a)
-        return {"queries_per_s": round(N / fin, 3), "p50_ms": round(pct(lat, 50), 2),
+        return {"queries_per_s": round(nq / fin, 3), "p50_ms": round(pct(lat, 50), 2),
                 "p99_ms": round(pct(lat, 99), 2)}
 
     outs = [torch.empty(wls[gi].csr.n, dtype=torch.uint32, device="cuda") for gi, _ in queries]
 
-    def serve(rate):
+    def serve(rate, nq):
         srv = sssp.Server(budget_bytes=args.serve_budget_gib << 30, max_batch=args.serve_slots,
                           ticks_per_launch=args.serve_ticks)
         ids = [srv.add_graph(gg) for gg in gs]
@@ -447,11 +466,11 @@ def served_section(args, sssp, torch, np, graphgen):
         tickets = []
         t0 = time.perf_counter()
         if rate is None:
-            arr = np.zeros(N)
+            arr = np.zeros(nq)
         else:
-            arr = np.cumsum(unit_gaps) / rate
+            arr = np.cumsum(unit_gaps[:nq]) / rate
             arr -= arr[0]
-        for q, (gi, s) in enumerate(queries):
+        for q, (gi, s) in enumerate(queries[:nq]):
             delay = arr[q] - (time.perf_counter() - t0)
             if delay > 0:
                 time.sleep(delay)
@@ -463,28 +482,29 @@ def served_section(args, sssp, torch, np, graphgen):
         srv.close()
         lat = [(i["done_us"] - i["submit_us"]) * 1e-6 for i in infos]
         span = (max(i["done_us"] for i in infos) - min(i["submit_us"] for i in infos)) * 1e-6
-        same = all(bool(torch.equal(a, b)) for a, b in zip(outs, solo))
+        same = all(bool(torch.equal(a, b)) for a, b in zip(outs[:nq], solo[:nq]))
         ok = all(i["status"] == 0 for i in infos)
-        return {"queries_per_s": round(N / span, 3), "p50_ms": round(pct(lat, 50), 2),
+        return {"queries": nq, "queries_per_s": round(nq / span, 3), "p50_ms": round(pct(lat, 50), 2),
                 "p99_ms": round(pct(lat, 99), 2), "peak_in_flight": st["peak_active"],
                 "engine_launches": st["launches"], "peak_in_use_bytes": st["peak_in_use_bytes"],
                 "all_ok": ok, "equal_to_alone": same}
 
-    sat = serve(None)
+    sat = serve(None, N)
     log("served at saturation (all %d submitted at once): %.2f q/s; equal to alone: %s"
         % (N, sat["queries_per_s"], sat["equal_to_alone"]))
     sweep = []
     for f in loads:
         rate = f * cap0
-        r = serve(rate)
+        nq = N if f >= 1.0 else min(N, args.serve_queries_light)
+        r = serve(rate, nq)
         r.update({"load": f, "arrival_rate_per_s": round(rate, 3)})
-        r["plain_fifo"] = fifo_at(rate)
+        r["plain_fifo"] = fifo_at(rate, nq)
         if f == 1.0:
             r["plain_fifo_run"] = {"queries_per_s": round(N / (t1 - t_start), 3),
                                    "p50_ms": round(pct(fifo_lat, 50), 2), "p99_ms": round(pct(fifo_lat, 99), 2)}
         sweep.append(r)
-        log("served at %.2f x FIFO capacity (%.2f q/s): %.2f q/s p50 %.1f ms p99 %.1f ms | FIFO %.2f q/s "
-            "p50 %.1f p99 %.1f; equal: %s" % (f, rate, r["queries_per_s"], r["p50_ms"], r["p99_ms"],
+        log("served at %.2f x FIFO capacity (%.2f q/s), %d queries: %.2f q/s p50 %.1f ms p99 %.1f ms | FIFO "
+            "%.2f q/s p50 %.1f p99 %.1f; equal: %s" % (f, rate, nq, r["queries_per_s"], r["p50_ms"], r["p99_ms"],
                                                  r["plain_fifo"]["queries_per_s"], r["plain_fifo"]["p50_ms"],
                                                  r["plain_fifo"]["p99_ms"], r["equal_to_alone"]))
     res = {
@@ -497,8 +517,9 @@ def served_section(args, sssp, torch, np, graphgen):
                        "speedup": round(sat["queries_per_s"] / fifo_cap, 2),
                        "equal_to_alone": sat["equal_to_alone"], "all_ok": sat["all_ok"]},
         "sweep": sweep,
-        "fifo_note": "plain FIFO was run at load 1.0 (plain_fifo_run); plain_fifo at each load applies "
-                     "one-server FIFO queueing to the service times measured in that run"}
+        "fifo_note": "plain FIFO was run at load 1.0 over all queries (plain_fifo_run); plain_fifo at each "
+                     "load applies one-server FIFO queueing to the service times measured in that run, over "
+                     "the same queries as the served run at that load"}
     if not args.no_cpu_baseline:
         # the oracle on a bounded sample of the same stream: the first 8 queries
         # of each graph, each graph's on a thread pool; every result is also
@@ -550,6 +571,8 @@ def main():
     ap.add_argument("--serve-queries", type=int, default=1024)
     ap.add_argument("--serve-loads", default="0.5,0.8,1.0,1.25",
                     help="arrival rates as fractions of the one-at-a-time (FIFO) capacity of the mix")
+    ap.add_argument("--serve-queries-light", type=int, default=256,
+                    help="queries of the served runs at loads below FIFO capacity (the stream's first)")
     ap.add_argument("--serve-slots", type=int, default=64)
     ap.add_argument("--serve-ticks", type=int, default=64)
     ap.add_argument("--serve-budget-gib", type=int, default=64)

@@ -173,7 +173,9 @@ hipError_t ws_ensure_insts(Workspace& w, int k) {
   int cap = std::max(k, 1);
   hipError_t e = dev_alloc(&w.dG, 1, w.allocs);
   if (e == hipSuccess) e = dev_alloc(&w.dInst, (size_t)cap, w.allocs);
-  if (e == hipSuccess) e = dev_alloc(&w.seg, (size_t)5 * (kMaxSegPerInst * cap + 1), w.allocs);
+  // the tick table: one 16-byte record per segment, plus the end record
+  if (e == hipSuccess)
+    e = dev_alloc(&w.seg, (sizeof(SegRec) / sizeof(int32_t)) * (size_t)(kMaxSegPerInst * cap + 1), w.allocs);
   if (e != hipSuccess) {
     w.inst_cap = 0;
     return e;
@@ -404,16 +406,11 @@ sssp_status run_instances_ws(Workspace& w, const sssp_graph* const* gs, const in
   Globals* hG = static_cast<Globals*>(st);
   Inst* hI = reinterpret_cast<Inst*>(static_cast<char*>(st) + sizeof(Globals));
   std::memset(st, 0, bytes);
-  const int segcap = kMaxSegPerInst * w.inst_cap + 1;
   hG->ninst = k;
   hG->tick_limit = o.tick_limit;
   hG->tick_log = w.d_tick_log;
   hG->tick_log_cap = (unsigned long long)w.tick_log_cap;
-  hG->seg_inst = w.seg;
-  hG->seg_kind = w.seg + segcap;
-  hG->seg_count = w.seg + 2 * segcap;
-  hG->seg_per_batch = w.seg + 3 * segcap;
-  hG->seg_first_batch = w.seg + 4 * segcap;
+  hG->seg = reinterpret_cast<SegRec*>(w.seg);
   hG->insts = w.dInst;
   hG->sel_list = nullptr;
   hG->n_sel = -1;

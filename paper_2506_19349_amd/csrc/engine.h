@@ -283,19 +283,35 @@ constexpr uint32_t FLAG_TREE = 64u;           // a tree entry disagrees with its
 constexpr int kMaxXcd = 8;  // XCDs (each with its own L2) on an MI355X
 constexpr int kTickLogWords = 8;  // words per tick of the debug tick log
 
+// One segment of a tick's table: a run of batches of one kind of work of one
+// instance. A batch needs only this record to start (one 16-byte load).
+struct alignas(16) SegRec {
+  int32_t first;  // the segment's first batch in the tick
+  int32_t inst;   // instance
+  int32_t count;  // items
+  int32_t word;   // kind | instance mode (bit 0 tree, bit 1 binary32) << 4 | items per batch << 8
+};
+__host__ __device__ constexpr int32_t seg_word(int kind, uint32_t mode, int per_batch) {
+  return kind | (int32_t)((mode & 3u) << 4) | (per_batch << 8);
+}
+
 struct Globals {
   // grid barrier: arrival counter and release generation on lines of their own
   HotU32 bar_count;
   HotU32 bar_gen;
-  // per-XCD arrival counters, release generations and workgroup counts
+  // per-XCD arrival counters, release words and workgroup counts. A release
+  // word holds the XCD's release generation (low half) and the quota word of
+  // the tick that release starts (high half): one load gives a waiting
+  // workgroup both.
   HotU32 xcd_count[kMaxXcd];
-  HotU32 xcd_gen[kMaxXcd];
+  HotU64 xcd_gen[kMaxXcd];
   HotU32 xcd_members[kMaxXcd];
   unsigned int all_done;
   unsigned int error;
-  // workgroups per XCD that take part in a tick (the rest wait aside), for
-  // the tick that starts at release generation g in quota[g % 8]
-  unsigned int quota[8];
+  // the next tick's quota word (workgroups per XCD that take part in it, the
+  // rest wait aside; small- and stop-tick bits), set by the epilogue for the
+  // XCD leaders to publish
+  unsigned int quota_next;
   // current tick layout
   int32_t nseg;
   int32_t total_batches;
@@ -310,12 +326,9 @@ struct Globals {
   unsigned long long* tick_log;
   unsigned long long tick_log_cap;
   unsigned long long t_start;     // wall clock when the engine started
-  // per segment: instance, kind, item count, items per batch, first batch
-  int32_t* seg_inst;
-  int32_t* seg_kind;
-  int32_t* seg_count;
-  int32_t* seg_per_batch;
-  int32_t* seg_first_batch;  // nseg + 1 entries
+  // the tick's segments, nseg + 1 records (the last one's first batch is the
+  // tick's batch count)
+  SegRec* seg;
   Inst* insts;
   // instances the set-up kernels act on: sel_list[0 .. n_sel), or all when n_sel < 0
   const int32_t* sel_list;

@@ -1451,24 +1451,31 @@ __device__ __noinline__ void block_settle(GInst& I, int kind, int item0, int nit
 
 // ------------------------------------------------------------- scheduling --
 
-// The segment holding batch b: the last one whose first batch is <= b. With
-// few segments each thread tests one (a single round of loads); with many,
-// a bisection. Whole workgroup.
-__device__ int find_segment(const GGlobals& G, int b) {
-  const int nseg = G.nseg;  // seg_first_batch has nseg + 1 entries
+// The record of the segment holding batch b: the last one whose first batch
+// is <= b. With few segments each thread loads one record (a single round of
+// loads); with many, a bisection. Whole workgroup.
+__device__ SegRec find_segment(const GGlobals& G, int b) {
+  const int nseg = G.nseg;  // the table has nseg + 1 records
+  const SSSP_GBL SegRec* seg = gbl(G.seg);
   if (nseg <= kBlock) {
+    __shared__ SegRec s_rec;
     const int t = threadIdx.x;
-    const bool le = t < nseg && gbl(G.seg_first_batch)[t] <= b;
+    SegRec r = {0, 0, 0, 0};
+    if (t < nseg) r = gload(seg + t);
     // first batches do not decrease: the count of segments starting at or
-    // before b is the index of b's segment plus one
-    return __syncthreads_count(le) - 1;
+    // before b is the index of b's segment plus one, and the thread of that
+    // index hands its record over
+    const int idx = __syncthreads_count(t < nseg && r.first <= b) - 1;
+    if (t == idx) s_rec = r;
+    __syncthreads();
+    return s_rec;
   }
   int lo = 0, hi = nseg;
   while (lo < hi) {
     int mid = (lo + hi + 1) >> 1;
-    if (gbl(G.seg_first_batch)[mid] <= b) lo = mid; else hi = mid - 1;
+    if (seg[mid].first <= b) lo = mid; else hi = mid - 1;
   }
-  return lo;
+  return gload(seg + lo);
 }
 
 // Bucket fusion (Section 4.1: up to FUSED = 256 rounds on a local frontier
@@ -1541,15 +1548,15 @@ __device__ void run_tick(GGlobals& G, BlockLds<Sh>& lds, int pid, int P) {
   SSSP_GBL unsigned long long* tl = tick_log_entry(G);
   if (tl && threadIdx.x == 0 && pid < total_batches) atomicMin((unsigned long long*)(tl + 4), wall_clock64());
   for (int b = pid; b < total_batches; b += P) {
-    const int sgi = find_segment(G, b);
-    const int ii = gbl(G.seg_inst)[sgi];
+    const SegRec sr = find_segment(G, b);
+    const int ii = sr.inst;
     GInst& I = gbl(G.insts)[ii];
     __syncthreads();  // the previous batch's counter additions are in
     if (threadIdx.x == 0) wgacc_select(G, ii);  // block_settle / block_round sync before adding
-    const int kind = gbl(G.seg_kind)[sgi];
-    const int pb = gbl(G.seg_per_batch)[sgi];
-    const int item0 = (b - gbl(G.seg_first_batch)[sgi]) * pb;
-    const int cnt = gbl(G.seg_count)[sgi];
+    const int kind = sr.word & 15;
+    const int pb = sr.word >> 8;
+    const int item0 = (b - sr.first) * pb;
+    const int cnt = sr.count;
     if (kind == SEG_ST || kind == SEG_SP) {
       block_settle<Sh>(I, kind, item0, cnt, lds.s);
       // the heuristic only reads words updated by device atomics: waiting for
@@ -1574,7 +1581,7 @@ __device__ void run_tick(GGlobals& G, BlockLds<Sh>& lds, int pid, int P) {
       }
       __syncthreads();
     } else {
-      const uint32_t mode = I.mode;
+      const uint32_t mode = (uint32_t)(sr.word >> 4) & 3u;
       const bool tree = (mode & 1u) != 0;
       const bool fw = (mode & 2u) != 0;
       if (fw) {
@@ -1694,10 +1701,11 @@ __device__ void build_table(GGlobals& G, bool do_transition, bool count) {
   const int per = (k + kBlock - 1) / kBlock;
   const int i0 = min(k, tid * per), i1 = min(k, i0 + per);
   SSSP_GBL Inst* insts = gbl(G.insts);
+  SSSP_GBL SegRec* seg = gbl(G.seg);
   int local_batches = 0;
-  int nb_last[kMaxSegPerInst];
+  int nb_last[kMaxSegPerInst], cnt_last[kMaxSegPerInst], word_last[kMaxSegPerInst];
 #pragma unroll
-  for (int s = 0; s < kMaxSegPerInst; ++s) nb_last[s] = 0;
+  for (int s = 0; s < kMaxSegPerInst; ++s) nb_last[s] = cnt_last[s] = word_last[s] = 0;
   for (int i = i0; i < i1; ++i) {
     GInst& I = insts[i];
     SSSP_GBL InstCtl* ctl = (SSSP_GBL InstCtl*)&I;
@@ -1718,19 +1726,21 @@ __device__ void build_table(GGlobals& G, bool do_transition, bool count) {
       Sp = gload((const SSSP_GBL SegSpec*)&I.spec);
     }
     if (X.phase != PH_DONE) atomicAdd(&s_active, 1);
+    const uint32_t mode = I.mode;
 #pragma unroll
     for (int s = 0; s < kMaxSegPerInst; ++s) {
-      const int sg = i * kMaxSegPerInst + s;
       int c = X.phase == PH_DONE ? 0 : Sp.cnt[s];
       const int pb = Sp.pb[s] > 0 ? Sp.pb[s] : kBlock;
       int nb;
       if (c < 0) { nb = 1; c = 0; }
       else nb = (c + pb - 1) / pb;
-      gbl(G.seg_inst)[sg] = i;
-      gbl(G.seg_kind)[sg] = Sp.kind[s];
-      gbl(G.seg_count)[sg] = c;
-      gbl(G.seg_per_batch)[sg] = pb;
-      if (per > 1) gbl(G.seg_first_batch)[sg] = nb;  // temporarily the batch count
+      cnt_last[s] = c;
+      word_last[s] = seg_word(Sp.kind[s], mode, pb);
+      if (per > 1) {
+        // the first batch is known after the scan: the count for now
+        const SegRec r = {nb, i, c, word_last[s]};
+        gstore(seg + i * kMaxSegPerInst + s, r);
+      }
       nb_last[s] = nb;
       local_batches += nb;
     }
@@ -1742,16 +1752,17 @@ __device__ void build_table(GGlobals& G, bool do_transition, bool count) {
     if (i0 < i1) {
 #pragma unroll
       for (int s = 0; s < kMaxSegPerInst; ++s) {
-        gbl(G.seg_first_batch)[i0 * kMaxSegPerInst + s] = run;
+        const SegRec r = {run, i0, cnt_last[s], word_last[s]};
+        gstore(seg + i0 * kMaxSegPerInst + s, r);
         run += nb_last[s];
       }
     }
   } else {
     for (int i = i0; i < i1; ++i) {
       for (int s = 0; s < kMaxSegPerInst; ++s) {
-        const int sg = i * kMaxSegPerInst + s;
-        const int nb = gbl(G.seg_first_batch)[sg];
-        gbl(G.seg_first_batch)[sg] = run;
+        SSSP_GBL int32_t* first = &seg[i * kMaxSegPerInst + s].first;
+        const int nb = *first;
+        *first = run;
         run += nb;
       }
     }
@@ -1759,7 +1770,8 @@ __device__ void build_table(GGlobals& G, bool do_transition, bool count) {
   __syncthreads();
   if (tid == 0) {
     G.nseg = k * kMaxSegPerInst;
-    gbl(G.seg_first_batch)[G.nseg] = (int)total;
+    const SegRec end = {(int)total, 0, 0, 0};
+    gstore(seg + G.nseg, end);
     G.total_batches = (int)total;
     G.all_done = (s_active == 0) ? 1u : 0u;
   }
@@ -1822,6 +1834,9 @@ __device__ bool spin_until_changed(SSSP_GBL unsigned int* word, unsigned int old
 // working XCD with kLocalTick set.
 constexpr int kLocalBatches = 64;
 constexpr unsigned int kLocalTick = 0x80000000u;
+// A quota word with kStopTick set ends the launch: the solves are done or an
+// error was raised (the next tick would have nothing to do).
+constexpr unsigned int kStopTick = 0x40000000u;
 __device__ __forceinline__ unsigned int quota_for(int total_batches, unsigned int nxcd,
                                                   unsigned int min_members, unsigned int members0) {
   const unsigned int nx = nxcd ? nxcd : 1u;
@@ -1853,9 +1868,9 @@ __device__ __forceinline__ void epilogue(GGlobals& G, unsigned int gen, unsigned
   __syncthreads();
   build_table(G, true, true);
   if (threadIdx.x == 0) {
-    // the next tick starts at generation gen + 1
-    __hip_atomic_store(&G.quota[(gen + 1u) & 7u], quota_for(G.total_batches, nxcd, min_members, members0),
-                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // the next tick's quota word (published with the release; the stop bit
+    // is added below once the tick count is known)
+    G.quota_next = quota_for(G.total_batches, nxcd, min_members, members0);
     if (gbl(G.tick_log) && G.ticks < G.tick_log_cap) gbl(G.tick_log)[kTickLogWords * G.ticks + 3] = wall_clock64();
     G.ticks += 1;
     if (gbl(G.tick_log) && G.ticks < G.tick_log_cap) tick_log_open(G, G.ticks);
@@ -1863,6 +1878,8 @@ __device__ __forceinline__ void epilogue(GGlobals& G, unsigned int gen, unsigned
       G.error |= FLAG_TICKS;
       G.all_done = 1u;
     }
+    if (G.all_done || __hip_atomic_load(&G.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      G.quota_next |= kStopTick;
   }
   __syncthreads();
 }
@@ -1914,33 +1931,59 @@ __device__ bool barrier_flat(GGlobals& G, unsigned int& gen, bool wait, bool run
   return s_ok != 0;
 }
 
+// The release word of an XCD: generation in the low half, the quota word of
+// the tick it starts in the high half.
+__device__ __forceinline__ unsigned long long release_word(unsigned int gen, unsigned int quota) {
+  return ((unsigned long long)quota << 32) | gen;
+}
+
 // A workgroup outside the current tick waits for its XCD's release of the
 // tick: one line per XCD, polled with long sleeps (it is not on the tick's
 // critical path, and hundreds of parked workgroups polling one line would slow
-// the channel behind it). Returns how many ticks have passed, 0 if an error
-// stopped the engine or the wait gave up. (The end of the engine is released
-// like any tick, after the done flag is set.)
-__device__ unsigned int park_until_released(GGlobals& G, unsigned int xcd, unsigned int xgen) {
+// the channel behind it). Returns the release word that ended the wait (its
+// generation tells how many ticks have passed), 0 if an error stopped the
+// engine or the wait gave up. (The end of the engine is released like any
+// tick, with the stop bit in its quota word.)
+__device__ unsigned long long park_until_released(GGlobals& G, unsigned int xcd, unsigned int xgen) {
   unsigned long long spins = 0;
-  unsigned int g;
-  while ((g = __hip_atomic_load(&G.xcd_gen[xcd].v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == xgen) {
+  unsigned long long w;
+  while ((unsigned int)(w = __hip_atomic_load(&G.xcd_gen[xcd].v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ==
+         xgen) {
     __builtin_amdgcn_s_sleep(16);
     ++spins;
-    if ((spins & 63u) == 0 && __hip_atomic_load(&G.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return 0u;
+    if ((spins & 63u) == 0 && __hip_atomic_load(&G.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return 0ull;
     if (spins > (1ull << 23)) {
       atomicOr(&G.error, FLAG_TIMEOUT);
-      return 0u;
+      return 0ull;
     }
   }
-  return g - xgen;
+  return w;
+}
+
+// A member of the tick waits for its XCD leader's release: returns the
+// release word, 0 if the wait gave up.
+__device__ unsigned long long spin_until_released(GGlobals& G, unsigned int xcd, unsigned int xgen) {
+  unsigned long long spins = 0;
+  unsigned long long w;
+  while ((unsigned int)(w = __hip_atomic_load(&G.xcd_gen[xcd].v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ==
+         xgen) {
+    __builtin_amdgcn_s_sleep(4);
+    if (++spins > (1ull << 27)) {
+      atomicOr(&G.error, FLAG_TIMEOUT);
+      return 0ull;
+    }
+  }
+  return w;
 }
 
 // Two-level barrier of the persistent engine among the tick's participants
-// (quota per XCD); the grid-wide last arriver runs the epilogue. Returns false
-// if a wait gave up.
-__device__ bool barrier_tick(GGlobals& G, BarrierState& B, unsigned int quota) {
+// (quota per XCD); the grid-wide last arriver runs the epilogue. The next
+// tick's quota word comes back in *next (from the epilogue, through each XCD
+// leader's release word). Returns false if a wait gave up.
+__device__ bool barrier_tick(GGlobals& G, BarrierState& B, unsigned int quota, unsigned int* next) {
   __shared__ int s_role;  // 0 wait for the XCD leader, 1 XCD leader, 2 epilogue
   __shared__ int s_ok;
+  __shared__ unsigned int s_next;
   // every wave's stores and atomics of this tick are complete before arriving
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
@@ -1969,21 +2012,35 @@ __device__ bool barrier_tick(GGlobals& G, BarrierState& B, unsigned int quota) {
   if (role == 2) {
     epilogue(G, B.gen, B.nxcd, B.min_members, B.members0);
     if (threadIdx.x == 0) {
+      const unsigned int qn = G.quota_next;
       __threadfence();
       atomicAdd(&G.bar_gen.v, 1u);
-      atomicAdd(&G.xcd_gen[B.xcd].v, 1u);
+      __hip_atomic_store(&G.xcd_gen[B.xcd].v, release_word(B.xgen + 1u, qn), __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+      s_next = qn;
     }
   } else if (role == 1) {
-    if (threadIdx.x == 0) atomicAdd(&G.xcd_gen[B.xcd].v, 1u);
+    if (threadIdx.x == 0) {
+      // after the leader's fence the epilogue's word is current; a leader
+      // whose wait gave up releases its XCD into a stop
+      const unsigned int qn =
+          s_ok ? __hip_atomic_load(&G.quota_next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : kStopTick;
+      __hip_atomic_store(&G.xcd_gen[B.xcd].v, release_word(B.xgen + 1u, qn), __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+      s_next = qn;
+    }
   } else {
     if (threadIdx.x == 0) {
-      s_ok = spin_until_changed<4>(&G.xcd_gen[B.xcd].v, B.xgen, &G.error) ? 1 : 0;
+      const unsigned long long w = spin_until_released(G, B.xcd, B.xgen);
+      s_ok = w != 0ull ? 1 : 0;
+      s_next = (unsigned int)(w >> 32);
       acquire_after_release();
     }
   }
   __syncthreads();
   B.gen += 1;
   B.xgen += 1;
+  *next = s_next;
   return s_ok != 0;
 }
 
@@ -2013,7 +2070,7 @@ __global__ void __launch_bounds__(kBlock, Sh::kMinBlocks) k_engine(Globals* Gp, 
   // settle the counts grid-wide
   if (threadIdx.x == 0) {
     s_b.xcd = xcd_of_this_wg();
-    s_b.xgen = __hip_atomic_load(&G.xcd_gen[s_b.xcd].v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    s_b.xgen = (unsigned int)__hip_atomic_load(&G.xcd_gen[s_b.xcd].v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     s_b.rank = atomicAdd(&G.xcd_members[s_b.xcd].v, 1u);
   }
   __syncthreads();
@@ -2042,16 +2099,15 @@ __global__ void __launch_bounds__(kBlock, Sh::kMinBlocks) k_engine(Globals* Gp, 
   }
   __syncthreads();
   BarrierState B = s_b;
-  __shared__ unsigned int s_quota;
   bool stale = false;  // parked since the last acquire
+  // the quota word of the coming tick: computed for the first, then handed
+  // over by each release (no shared word is read between ticks)
+  unsigned int qw = B.q0;
+  if (__hip_atomic_load(&G.all_done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
+      __hip_atomic_load(&G.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+    qw |= kStopTick;
   for (int t = 0;;) {
-    if (__hip_atomic_load(&G.all_done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
-    if (__hip_atomic_load(&G.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
-    if (threadIdx.x == 0)
-      s_quota = t == 0 ? B.q0
-                       : __hip_atomic_load(&G.quota[B.gen & 7u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __syncthreads();
-    const unsigned int qw = s_quota;
+    if (qw & kStopTick) break;
     const bool local = (qw & kLocalTick) != 0;
     const unsigned int qx = qw & ~kLocalTick;
     // this XCD's participants: a small tick's batches all go to the first XCD
@@ -2065,15 +2121,17 @@ __global__ void __launch_bounds__(kBlock, Sh::kMinBlocks) k_engine(Globals* Gp, 
       }
       if (local) run_tick<Sh>(G, lds, B.xidx == 0 ? (int)B.rank : 0x7fffffff, (int)qx);
       else run_tick<Sh>(G, lds, (int)(B.rank * B.nxcd + B.xidx), (int)(q * B.nxcd));
-      if (!barrier_tick(G, B, q)) break;
+      if (!barrier_tick(G, B, q, &qw)) break;
       t += 1;
     } else {
       // not needed in this tick: wait for its release
-      __shared__ unsigned int s_gen;
-      if (threadIdx.x == 0) s_gen = park_until_released(G, B.xcd, B.xgen);
+      __shared__ unsigned long long s_rel;
+      if (threadIdx.x == 0) s_rel = park_until_released(G, B.xcd, B.xgen);
       __syncthreads();
-      const unsigned int d = s_gen;
-      if (d == 0u) break;  // error or timeout
+      const unsigned long long w = s_rel;
+      if (w == 0ull) break;  // error or timeout
+      const unsigned int d = (unsigned int)w - B.xgen;
+      qw = (unsigned int)(w >> 32);
       t += (int)d;
       B.xgen += d;
       B.gen += d;

@@ -30,7 +30,7 @@ namespace {
 struct NoAllocDesc {
   Globals* G;
   Inst* I;
-  int32_t* seg;
+  SegRec* seg;
   const DevGraph* g;
   uint32_t* dist;
   uint64_t* state;
@@ -52,7 +52,7 @@ struct NoAllocDesc {
   Counters* cslot;
   unsigned long long tick_limit;
   double beta;
-  int32_t source, n, maxw, heavy_cap, trace_cap, segcap, heavy_split, fuse_cap;
+  int32_t source, n, maxw, heavy_cap, trace_cap, heavy_split, fuse_cap, pad0;
   uint32_t ring_mask, steprec_mask, alpha, topt, mode, pad;
   int32_t round_batch, settle_batch;
 };
@@ -122,11 +122,7 @@ __global__ void __launch_bounds__(kBlock) k_noalloc_setup(NoAllocDesc d) {
   G.tick_limit = d.tick_limit;
   G.tick_log = nullptr;
   G.tick_log_cap = 0;
-  G.seg_inst = d.seg;
-  G.seg_kind = d.seg + d.segcap;
-  G.seg_count = d.seg + 2 * d.segcap;
-  G.seg_per_batch = d.seg + 3 * d.segcap;
-  G.seg_first_batch = d.seg + 4 * d.segcap;
+  G.seg = d.seg;
   G.insts = d.I;
   G.sel_list = nullptr;
   G.n_sel = -1;
@@ -182,13 +178,12 @@ extern "C" sssp_status sssp_solve_noalloc(const sssp_graph* g, int32_t source, u
   const int maxw = ds.cus * ds.occ[shape] * (kBlock / kWave);
   Needs nd = needs_for(h, maxw);
   nd.trace = kNoAllocTrace;
-  const int segcap = kMaxSegPerInst + 1;
   Carve c{ds.ptr};
   NoAllocDesc d;
   std::memset(&d, 0, sizeof(d));
   d.G = c.take<Globals>(1);
   d.I = c.take<Inst>(1);
-  d.seg = c.take<int32_t>((size_t)5 * segcap);
+  d.seg = c.take<SegRec>((size_t)kMaxSegPerInst + 1);
   d.state = c.take<uint64_t>((size_t)nd.n);
   d.q0 = c.take<int32_t>((size_t)nd.list);
   d.q1 = c.take<int32_t>((size_t)nd.list);
@@ -218,7 +213,6 @@ extern "C" sssp_status sssp_solve_noalloc(const sssp_graph* g, int32_t source, u
   d.maxw = maxw;
   d.heavy_cap = nd.heavy;
   d.trace_cap = nd.trace;
-  d.segcap = segcap;
   d.heavy_split = o.heavy;
   d.fuse_cap = o.fuse;
   d.ring_mask = nd.ring - 1;

@@ -64,15 +64,10 @@ sssp_status plan_build(sssp_plan* p, uint32_t* const* dist_outs, int32_t* const*
   std::memset(p->pinned, 0, bytes);
   p->hG = static_cast<Globals*>(p->pinned);
   p->hI = reinterpret_cast<Inst*>(static_cast<char*>(p->pinned) + sizeof(Globals));
-  const int segcap = kMaxSegPerInst * w.inst_cap + 1;
   Globals* hG = p->hG;
   hG->ninst = k;
   hG->tick_limit = p->o.tick_limit;
-  hG->seg_inst = w.seg;
-  hG->seg_kind = w.seg + segcap;
-  hG->seg_count = w.seg + 2 * segcap;
-  hG->seg_per_batch = w.seg + 3 * segcap;
-  hG->seg_first_batch = w.seg + 4 * segcap;
+  hG->seg = reinterpret_cast<SegRec*>(w.seg);
   hG->insts = w.dInst;
   hG->sel_list = nullptr;
   hG->n_sel = -1;

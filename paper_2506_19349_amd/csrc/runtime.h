@@ -85,7 +85,7 @@ struct Workspace {
   int inst_cap = 0;
   Globals* dG = nullptr;
   Inst* dInst = nullptr;
-  int32_t* seg = nullptr;  // 5 arrays of (kMaxSegPerInst * inst_cap + 1)
+  int32_t* seg = nullptr;  // the tick table: (kMaxSegPerInst * inst_cap + 1) 16-byte SegRec records
   std::vector<void*> allocs;
   // pinned staging ring
   static constexpr int kStages = 4;

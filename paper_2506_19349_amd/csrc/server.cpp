@@ -401,15 +401,10 @@ sssp_status server_setup(sssp_server* S) {
   S->h_status = reinterpret_cast<uint32_t*>(p);
   HIP_TRY(hipEventCreateWithFlags(&S->ev, hipEventDisableTiming));
   // the instance table starts with every slot idle
-  const int segcap = kMaxSegPerInst * w.inst_cap + 1;
   Globals* hG = S->hG;
   hG->ninst = S->max_batch;
   hG->tick_limit = S->o.tick_limit;
-  hG->seg_inst = w.seg;
-  hG->seg_kind = w.seg + segcap;
-  hG->seg_count = w.seg + 2 * segcap;
-  hG->seg_per_batch = w.seg + 3 * segcap;
-  hG->seg_first_batch = w.seg + 4 * segcap;
+  hG->seg = reinterpret_cast<SegRec*>(w.seg);
   hG->insts = w.dInst;
   hG->sel_list = S->d_sel;
   hG->n_sel = 0;
