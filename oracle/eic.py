@@ -1,25 +1,40 @@
 """ORACLE -- test infrastructure only; the product path never imports this.
 
-A sequential model of the paper's heuristic SSSP algorithm (Section 3.3: the
-Algorithm, Function 1 initFrontiers and Function 2 computeST), written in the
-paper's order and notation with numpy doing the per-round vector work.
-Rounds are synchronous: every relaxation of a round reads the distances the
-round started with, and the round's candidates are merged with a minimum.
+A sequential model of the paper's heuristic SSSP method (Section 3), used to
+pin the GPU engine's schedule. It is built from the method's definitions:
 
-It serves two purposes in the tests:
-* it must reach exactly the Dijkstra distances (the method is exact: the
-  heuristics only reorder relaxations), and
-* its per-step schedule -- the band <lb, ub>, the selection threshold st and
-  the statistics taken at each step's end -- is fully determined by the graph
-  and the source (every quantity it uses at a step boundary is a function of
-  the settled set, whose distances are final), so the GPU engine has to
-  produce the same schedule step for step.
+* the band <lb, ub> of a step is settled to a fixpoint by synchronous
+  relaxation rounds restricted to the band (Section 3.3); during the first
+  step ub follows the nearest vertex of degree >= highD(0);
+* before the rounds, vertices already settled in [lb0, st] relax the edges
+  they had to defer (their sums now fall in the band), and, when the
+  selection threshold st lies below lb, every unsettled vertex takes its best
+  neighbour settled in [st, lb) whose sum lands in the band (the pull of
+  Section 3.2);
+* after the band is settled, the statistics at L = ub (sumD, highD) give
+  gap(L) (Eq. 1-3), the next band is <L, L + gap(L)>, and st for it comes
+  from computeST (Eq. 4-6);
+* the search ends when no remaining distance can still fall below the band.
 
-Readings of the text it follows: the first step's
-hub update of ub runs only during the first step; the first step ends the
-search when no vertex of degree >= highD(0) was reached (ub stays +inf);
-+inf is the single sentinel 2^32 - 1; the v != parent[u] skip is omitted
-(no parent[] is produced).
+Every relaxation of a round reads the distances the round started with, and
+the round's candidates are merged with a minimum (any order reaches the same
+fixpoint). The model serves two purposes in the tests: it must reach exactly
+the Dijkstra distances (the heuristics only reorder relaxations), and its
+per-step schedule -- <lb, ub, st> and the statistics taken at each step's end
+-- is determined by the graph and the source alone (every quantity used at a
+step boundary is a function of the settled set, whose distances are final),
+so the GPU engine has to produce the same schedule step for step.
+
+Distances are integers (uint32 range, +inf = 2^32 - 1, sums exact in int64)
+or binary32 bit patterns (finite, non-negative, so they order like their
+values; every sum is one binary32 addition rounded to nearest). The two
+differ only in how distances add, how the band's ends and lb0 are formed and
+which computeST runs; `_Integers` and `_Binary32` hold those rules.
+
+Readings of the text it follows: the first step's hub update of ub runs only
+during the first step; the first step ends the search when no vertex of
+degree >= highD(0) was reached (ub stays +inf); the v != parent[u] skip is
+omitted (no parent[] is produced).
 """
 from __future__ import annotations
 
@@ -77,100 +92,6 @@ def _row_edges(rowptr: np.ndarray, rows: np.ndarray) -> tuple:
     return idx, rows[owner]
 
 
-def eic_sssp(n: int, rowptr: np.ndarray, col: np.ndarray, w: np.ndarray, s: int,
-             alpha: int = H.ALPHA, beta: float = H.BETA, traversal_opt: bool = True,
-             max_steps: int = 10_000_000) -> Result:
-    rowptr = np.asarray(rowptr, dtype=np.int64)
-    col = np.asarray(col, dtype=np.int64)
-    w = np.asarray(w, dtype=np.int64)
-    deg = np.diff(rowptr)
-    nnz = int(rowptr[-1])
-    M = int(w.max()) if nnz else 0
-    # Preprocess (Section 4.1): weight quantisation; highD(0) over VS(0) = V.
-    rtow = H.rtow_table(w)
-    hd0 = H.high_d(deg)
-    hub = (deg >= max(hd0, 1))
-
-    dist = np.full(n, INF, dtype=np.int64)
-    dist[s] = 0
-    res = Result(dist=dist, steps=[], high_d0=hd0)
-    if deg[s] == 0:
-        res.dist = dist.astype(np.uint32)
-        return res
-    res.gap0 = H.gap(nnz, hd0, nnz, M, rtow, alpha, beta)
-
-    st, lb, ub = 0, 0, INF
-    first = True
-    gap_lb = res.gap0
-    for _ in range(max_steps):
-        # ---- Function 1: initFrontiers(st, lb, ub) ----
-        lb0 = max(0, lb - M)
-        push_set = np.nonzero((dist >= lb0) & (dist <= st))[0]
-        pulled = False
-        if st < lb:
-            pulled = True
-            res.pulls += 1
-            U = np.nonzero((dist > lb) & (deg > 0))[0]
-            res.pull_vertices += int(U.shape[0])
-            idx, owner = _row_edges(rowptr, U)
-            sel = w[idx] < ub - st
-            idx, owner = idx[sel], owner[sel]
-            res.pull_scanned += int(idx.shape[0])
-            v = col[idx]
-            dv = dist[v]
-            cand = dv + w[idx]
-            ok = (dv >= st) & (dv < lb) & (cand < ub)
-            np.minimum.at(dist, owner[ok], cand[ok])
-        band = np.nonzero((dist >= lb) & (dist < ub))[0]
-        F = np.union1d(push_set, band)
-        rounds = 0
-        # ---- the Algorithm's round loop ----
-        while F.shape[0] > 0:
-            paths = F[~((dist[F] > 0) & (deg[F] == 1))]
-            res.expansions += int(paths.shape[0])
-            res.band_expansions += int(np.count_nonzero(dist[paths] >= lb))
-            idx, owner = _row_edges(rowptr, paths)
-            cand = dist[owner] + w[idx]
-            sel = (cand >= lb) & (cand < ub)
-            idx, cand = idx[sel], cand[sel]
-            res.push_scanned += int(idx.shape[0])
-            v = col[idx]
-            before = dist.copy()
-            np.minimum.at(dist, v, cand)
-            F = np.nonzero(dist < before)[0]
-            rounds += 1
-            if first:
-                hub_d = dist[hub]
-                ub = int(hub_d.min()) if hub_d.shape[0] else INF
-        res.rounds += rounds
-        if first and ub == INF:
-            res.steps.append(Step(lb, ub, st, rounds, pulled, ub, 0, 0, 0, ub))
-            break
-        # ---- statistics at L = ub, then <st, lb, ub> <- <computeST, ub, ub + gap(ub)> ----
-        L = ub
-        in_vs = dist >= L
-        S = int(deg[in_vs].sum())
-        h = H.high_d(deg[in_vs])
-        gap_L = H.gap(S, h, nnz, M, rtow, alpha, beta)
-        wlo = max(0, L - M)
-        win = (dist >= wlo) & (dist < L)
-        wv, inv = np.unique(dist[win], return_inverse=True)
-        wm = np.zeros(wv.shape[0], dtype=np.int64)
-        np.add.at(wm, inv, deg[win])
-        st_next = H.compute_st(L, gap_L, gap_lb, S, nnz, M, wv, wm, traversal_opt)
-        res.steps.append(Step(lb, ub, st, rounds, pulled, L, S, h, gap_L, st_next))
-        st, lb, ub = st_next, L, min(L + gap_L, INF)
-        gap_lb = gap_L
-        first = False
-        finite = dist[dist < INF]
-        if int(finite.max()) + M < lb:
-            break
-    else:
-        res.complete = False
-    res.dist = dist.astype(np.uint32)
-    return res
-
-
 def _fadd(a, b) -> np.ndarray:
     """fl(a + b) of binary32 bit patterns, elementwise, as bit patterns (int64)."""
     a = np.asarray(a, dtype=np.int64).astype(np.uint32).view(np.float32)
@@ -178,123 +99,234 @@ def _fadd(a, b) -> np.ndarray:
     return (a + b).astype(np.float32).view(np.uint32).astype(np.int64)
 
 
-def eic_sssp_f32(n: int, rowptr: np.ndarray, col: np.ndarray, wbits: np.ndarray, s: int,
-                 alpha: int = H.ALPHA, beta: float = H.BETA, traversal_opt: bool = True,
-                 max_steps: int = 10_000_000) -> Result:
-    """The same model with real weights: weights and distances are binary32
-    bit patterns (finite, non-negative, so they order like their values) and
-    every path sum is one binary32 addition, rounded to nearest.  The readings
-    that differ from the integer model: the next band ends at fl(L + gap)
-    with the gap at least the smallest positive weight, and one unit in the
-    last place above L when that sum rounds back to L (ub > lb, Section 3);
-    lb0 = fl(fl(L - M) - 2 ulp(L)); the pull takes an edge while
-    fl(st + w) < ub; computeST works on the ST_NUM grid.
+# ---------------------------------------------------------- distance rules --
 
-    A band narrower than the spacing of the remaining distances settles
-    nothing and the next one starts where it ended, as in the integer model:
-    weights that span many orders of magnitude (say 1e-30 and 1e30 in one
-    graph) can need a step per unit in the last place. `complete` is False
-    when max_steps ran out first."""
-    rowptr = np.asarray(rowptr, dtype=np.int64)
-    col = np.asarray(col, dtype=np.int64)
-    w = np.asarray(wbits, dtype=np.uint32).astype(np.int64)
-    deg = np.diff(rowptr)
-    nnz = int(rowptr[-1])
-    M = int(w.max()) if nnz else 0
-    pos = w[w > 0]
-    minpos = int(pos.min()) if pos.shape[0] else INF
-    rtow = H.rtow_table(w)
-    hd0 = H.high_d(deg)
-    hub = (deg >= max(hd0, 1))
+class _Integers:
+    """Integer weights: exact sums, the window of distinct distances for
+    computeST while maxW allows it (Section 4.1's ST_NUM grid beyond)."""
 
-    dist = np.full(n, INF, dtype=np.int64)
-    dist[s] = 0
-    res = Result(dist=dist, steps=[], high_d0=hd0)
-    if deg[s] == 0:
-        res.dist = dist.astype(np.uint32)
-        return res
-    res.gap0 = H.gap(nnz, hd0, nnz, M, rtow, alpha, beta)
+    inf = INF
 
-    st, lb, ub, lb0 = 0, 0, INF, 0
-    first = True
-    gap_lb = res.gap0
-    for _ in range(max_steps):
-        # ---- Function 1: initFrontiers(st, lb, ub) ----
-        push_set = np.nonzero((dist >= lb0) & (dist <= st))[0]
-        pulled = False
-        if st < lb:
-            pulled = True
-            res.pulls += 1
-            U = np.nonzero((dist > lb) & (deg > 0))[0]
-            res.pull_vertices += int(U.shape[0])
-            idx, owner = _row_edges(rowptr, U)
-            sel = _fadd(np.full(idx.shape[0], st), w[idx]) < ub
-            idx, owner = idx[sel], owner[sel]
-            res.pull_scanned += int(idx.shape[0])
-            dv = dist[col[idx]]
-            ok = (dv >= st) & (dv < lb)
-            cand = _fadd(np.where(ok, dv, 0), w[idx])
-            ok &= cand < ub
-            np.minimum.at(dist, owner[ok], cand[ok])
-        band = np.nonzero((dist >= lb) & (dist < ub))[0]
-        F = np.union1d(push_set, band)
-        rounds = 0
-        # ---- the Algorithm's round loop ----
-        while F.shape[0] > 0:
-            paths = F[~((dist[F] > 0) & (deg[F] == 1))]
-            res.expansions += int(paths.shape[0])
-            res.band_expansions += int(np.count_nonzero(dist[paths] >= lb))
-            idx, owner = _row_edges(rowptr, paths)
-            cand = _fadd(dist[owner], w[idx])
-            sel = (cand >= lb) & (cand < ub)
-            idx, cand = idx[sel], cand[sel]
-            res.push_scanned += int(idx.shape[0])
-            before = dist.copy()
-            np.minimum.at(dist, col[idx], cand)
-            F = np.nonzero(dist < before)[0]
-            rounds += 1
-            if first:
-                hub_d = dist[hub]
-                ub = int(hub_d.min()) if hub_d.shape[0] else INF
-        res.rounds += rounds
-        if first and ub == INF:
-            res.steps.append(Step(lb, ub, st, rounds, pulled, ub, 0, 0, 0, ub))
-            break
-        # ---- statistics at L = ub; the next band, lb0 and computeST ----
-        L = ub
-        in_vs = dist >= L
-        S = int(deg[in_vs].sum())
-        h = H.high_d(deg[in_vs])
-        gap_L = H.gap(S, h, nnz, M, rtow, alpha, beta)
-        if L == INF:
-            res.steps.append(Step(lb, ub, st, rounds, pulled, L, S, h, gap_L, L))
-            break
-        # ub = L + gap(L) (Section 3.3), rounded; the gap is positive (Section
-        # 3.1: gap in (0, maxW]), so a zero quantile takes the smallest positive
-        # weight, and ub > lb holds even where the sum rounds back to L
-        gf = gap_L if (gap_L > minpos or minpos == INF) else minpos
-        e = int(_fadd(L, gf))
+    def __init__(self, w: np.ndarray):
+        self.w = np.asarray(w, dtype=np.int64)
+
+    def add(self, d, w):
+        return d + w
+
+    def reaches_below(self, st: int, w: np.ndarray, ub: int) -> np.ndarray:
+        # the pull takes an edge of weight w while w < ub - st (Section 3.2)
+        return w < ub - st
+
+    def low_end(self, lb: int, M: int) -> int:
+        # lb0 = max(0, lb - M): the settled vertices whose deferred edges can
+        # land in the band
+        return max(0, lb - M)
+
+    def band_end(self, L: int, gap: int) -> int:
+        return min(L + gap, INF)
+
+    def threshold(self, dist, deg, L, gap_L, gap_lb, S, nnz, M, lb0, ub_next, traversal_opt) -> int:
+        win = (dist >= lb0) & (dist < L)
+        vals, inv = np.unique(dist[win], return_inverse=True)
+        mass = np.zeros(vals.shape[0], dtype=np.int64)
+        np.add.at(mass, inv, deg[win])
+        return H.compute_st(L, gap_L, gap_lb, S, nnz, M, vals, mass, traversal_opt)
+
+    def stop_at_infinite_band(self) -> bool:
+        return False
+
+    def beyond(self, dmax: int, M: int, lb: int) -> bool:
+        return dmax + M < lb
+
+
+class _Binary32:
+    """Binary32 weights and distances (bit patterns): each sum rounds once;
+    computeST always scores the ST_NUM grid."""
+
+    inf = INF   # the shared +inf sentinel; finite bit patterns stay below 0x7f800000
+
+    def __init__(self, w: np.ndarray):
+        self.w = np.asarray(w, dtype=np.uint32).astype(np.int64)
+        pos = self.w[self.w > 0]
+        self.minpos = int(pos.min()) if pos.shape[0] else INF
+
+    def add(self, d, w):
+        return _fadd(d, w)
+
+    def reaches_below(self, st: int, w: np.ndarray, ub: int) -> np.ndarray:
+        # w < ub - st, rounded: a settled distance d >= st reaches below ub
+        # only if fl(st + w) does (rounding is monotone)
+        return _fadd(np.full(w.shape[0], st), w) < ub
+
+    def low_end(self, lb: int, M: int) -> int:
+        # lb - M lowered by two units in the last place of lb, so that a settled
+        # distance whose rounded sum with M still reaches lb is included
+        if lb == 0:
+            return 0
+        Lf = np.float32(H.f32(lb))
+        ulp = np.float32(H.f32(lb + 1)) - Lf
+        lo = np.float32(np.float32(Lf - np.float32(H.f32(M))) - np.float32(np.float32(2.0) * ulp))
+        return int(np.asarray(lo, dtype=np.float32).view(np.uint32)) if lo > 0 else 0
+
+    def band_end(self, L: int, gap: int) -> int:
+        # ub = L + gap(L) (Section 3.3), rounded. The gap is positive (Section
+        # 3.1 keeps it in (0, maxW]): a zero quantile takes the smallest
+        # positive weight; and the next band ends above L even where the sum
+        # rounds back to L
+        g = gap if (gap > self.minpos or self.minpos == INF) else self.minpos
+        e = int(_fadd(L, g))
         if e <= L:
             e = L + 1
-        ub_next = INF if e >= H.F32_INF_BITS else e
-        Lf = np.float32(H.f32(L))
-        ulp = np.float32(H.f32(L + 1)) - Lf
-        lo = np.float32(np.float32(Lf - np.float32(H.f32(M))) - np.float32(np.float32(2.0) * ulp))
-        lb0_next = int(np.asarray(lo, dtype=np.float32).view(np.uint32)) if lo > 0 else 0
+        return INF if e >= H.F32_INF_BITS else e
+
+    def threshold(self, dist, deg, L, gap_L, gap_lb, S, nnz, M, lb0, ub_next, traversal_opt) -> int:
         settled = dist < L
-        st_next = H.compute_st_f32(L, gap_L, gap_lb, S, nnz, M, lb0_next, ub_next, dist[settled],
-                                   deg[settled], traversal_opt)
+        return H.compute_st_f32(L, gap_L, gap_lb, S, nnz, M, lb0, ub_next, dist[settled], deg[settled],
+                                traversal_opt)
+
+    def stop_at_infinite_band(self) -> bool:
+        return True
+
+    def beyond(self, dmax: int, M: int, lb: int) -> bool:
+        return int(_fadd(dmax, M)) < lb
+
+
+# ------------------------------------------------------------ step pieces --
+
+class _Search:
+    """One search: the graph, the distance rules and the running state."""
+
+    def __init__(self, n, rowptr, col, rules, s):
+        self.n = n
+        self.rowptr = np.asarray(rowptr, dtype=np.int64)
+        self.col = np.asarray(col, dtype=np.int64)
+        self.rules = rules
+        self.w = rules.w
+        self.deg = np.diff(self.rowptr)
+        self.nnz = int(self.rowptr[-1])
+        self.M = int(self.w.max()) if self.nnz else 0
+        # Section 4.1's preprocessing: the weight quantiles and highD over VS(0) = V
+        self.rtow = H.rtow_table(self.w)
+        self.hd0 = H.high_d(self.deg)
+        self.hub = self.deg >= max(self.hd0, 1)
+        self.dist = np.full(n, INF, dtype=np.int64)
+        self.dist[s] = 0
+        self.res = Result(dist=self.dist, steps=[], high_d0=self.hd0)
+
+    def deferred(self, lb0: int, st: int) -> np.ndarray:
+        """Settled vertices in [lb0, st]: their edges deferred past earlier bands."""
+        d = self.dist
+        return np.nonzero((d >= lb0) & (d <= st))[0]
+
+    def pull(self, st: int, lb: int, ub: int) -> None:
+        """Every unsettled vertex of degree >= 1 takes its best neighbour settled
+        in [st, lb) through an edge short enough to land in the band."""
+        d, res = self.dist, self.res
+        res.pulls += 1
+        unsettled = np.nonzero((d > lb) & (self.deg > 0))[0]
+        res.pull_vertices += int(unsettled.shape[0])
+        idx, owner = _row_edges(self.rowptr, unsettled)
+        keep = self.rules.reaches_below(st, self.w[idx], ub)
+        idx, owner = idx[keep], owner[keep]
+        res.pull_scanned += int(idx.shape[0])
+        dv = d[self.col[idx]]
+        ok = (dv >= st) & (dv < lb)
+        cand = self.rules.add(np.where(ok, dv, 0), self.w[idx])
+        ok &= cand < ub
+        np.minimum.at(d, owner[ok], cand[ok])
+
+    def settle_band(self, frontier: np.ndarray, lb: int, ub: int, first: bool) -> tuple:
+        """Synchronous relaxation rounds restricted to the band until no
+        distance changes; leaves (degree 1, not the source) are not expanded.
+        In the first step ub follows the nearest hub after every round.
+        Returns (rounds, ub)."""
+        d, res = self.dist, self.res
+        rounds = 0
+        while frontier.shape[0] > 0:
+            paths = frontier[~((d[frontier] > 0) & (self.deg[frontier] == 1))]
+            res.expansions += int(paths.shape[0])
+            res.band_expansions += int(np.count_nonzero(d[paths] >= lb))
+            idx, owner = _row_edges(self.rowptr, paths)
+            cand = self.rules.add(d[owner], self.w[idx])
+            inside = (cand >= lb) & (cand < ub)
+            idx, cand = idx[inside], cand[inside]
+            res.push_scanned += int(idx.shape[0])
+            before = d.copy()
+            np.minimum.at(d, self.col[idx], cand)
+            frontier = np.nonzero(d < before)[0]
+            rounds += 1
+            if first:
+                hub_d = d[self.hub]
+                ub = int(hub_d.min()) if hub_d.shape[0] else INF
+        res.rounds += rounds
+        return rounds, ub
+
+    def statistics(self, L: int, alpha: int, beta: float) -> tuple:
+        """sumD(L) and highD(L) over VS(L) = {v : dist[v] >= L}, and gap(L) (Eq. 1-3)."""
+        in_vs = self.dist >= L
+        S = int(self.deg[in_vs].sum())
+        h = H.high_d(self.deg[in_vs])
+        return S, h, H.gap(S, h, self.nnz, self.M, self.rtow, alpha, beta)
+
+
+def _model(n, rowptr, col, rules, s, alpha, beta, traversal_opt, max_steps) -> Result:
+    run = _Search(n, rowptr, col, rules, s)
+    res, dist, M = run.res, run.dist, run.M
+    if run.deg[s] == 0:
+        res.dist = dist.astype(np.uint32)
+        return res
+    res.gap0 = H.gap(run.nnz, run.hd0, run.nnz, M, run.rtow, alpha, beta)
+    st, lb, ub = 0, 0, INF
+    first = True
+    gap_lb = res.gap0   # gap of the band just settled (gap(0) before the first)
+    for _ in range(max_steps):
+        frontier = run.deferred(rules.low_end(lb, M), st)
+        pulled = st < lb
+        if pulled:
+            run.pull(st, lb, ub)
+        band = np.nonzero((dist >= lb) & (dist < ub))[0]
+        rounds, ub = run.settle_band(np.union1d(frontier, band), lb, ub, first)
+        if first and ub == INF:
+            # no hub reached: the first band was the whole reachable set
+            res.steps.append(Step(lb, ub, st, rounds, pulled, ub, 0, 0, 0, ub))
+            break
+        L = ub
+        S, h, gap_L = run.statistics(L, alpha, beta)
+        if L == INF and rules.stop_at_infinite_band():
+            res.steps.append(Step(lb, ub, st, rounds, pulled, L, S, h, gap_L, L))
+            break
+        ub_next = rules.band_end(L, gap_L)
+        st_next = rules.threshold(dist, run.deg, L, gap_L, gap_lb, S, run.nnz, M, rules.low_end(L, M),
+                                  ub_next, traversal_opt)
         res.steps.append(Step(lb, ub, st, rounds, pulled, L, S, h, gap_L, st_next))
-        st, lb, ub, lb0 = st_next, L, ub_next, lb0_next
+        st, lb, ub = st_next, L, ub_next
         gap_lb = gap_L
         first = False
-        finite = dist[dist < INF]
-        if int(_fadd(int(finite.max()), M)) < lb:
+        if rules.beyond(int(dist[dist < INF].max()), M, lb):
             break
     else:
         res.complete = False
     res.dist = dist.astype(np.uint32)
     return res
+
+
+def eic_sssp(n: int, rowptr: np.ndarray, col: np.ndarray, w: np.ndarray, s: int,
+             alpha: int = H.ALPHA, beta: float = H.BETA, traversal_opt: bool = True,
+             max_steps: int = 10_000_000) -> Result:
+    """The model with integer weights."""
+    return _model(n, rowptr, col, _Integers(w), s, alpha, beta, traversal_opt, max_steps)
+
+
+def eic_sssp_f32(n: int, rowptr: np.ndarray, col: np.ndarray, wbits: np.ndarray, s: int,
+                 alpha: int = H.ALPHA, beta: float = H.BETA, traversal_opt: bool = True,
+                 max_steps: int = 10_000_000) -> Result:
+    """The model with real weights: weights and distances are binary32 bit
+    patterns. A band narrower than the spacing of the remaining distances
+    settles nothing and the next one starts where it ended, as with integers
+    and gap 1: weights that span many orders of magnitude (say 1e-30 and 1e30
+    in one graph) can need a step per unit in the last place. `complete` is
+    False when max_steps ran out first."""
+    return _model(n, rowptr, col, _Binary32(wbits), s, alpha, beta, traversal_opt, max_steps)
 
 
 def normalised(res: Result, n: int, deg: np.ndarray) -> dict:
