@@ -47,6 +47,16 @@ def alg_bytes(c: dict) -> int:
             + 16 * c["pull_unsettled"] + 12 * c["pull_scanned"] + 8 * c["queue_entries"])
 
 
+def alg_accesses(c: dict) -> int:
+    """Random accesses the method itself makes in one solve (counted by the
+    engine): one per expansion (the vertex's record), per pushed edge
+    (dist[v]), per successful decrease (the atomic), per vertex the pull
+    examines and per pulled edge; queue entries are read and written in order
+    and are not counted."""
+    return (c["expansions"] + c["push_scanned"] + c["relax_success"] + c["pull_unsettled"]
+            + c["pull_scanned"])
+
+
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_engine_rmat24_counters.md")
 ENGINE_SOURCES = [os.path.join(ROOT, "paper_2506_19349_amd", "csrc", f)
                   for f in ("engine.hip", "engine.h")]
@@ -576,6 +586,8 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=64)
     ap.add_argument("--serve-ticks", type=int, default=64)
     ap.add_argument("--serve-budget-gib", type=int, default=64)
+    ap.add_argument("--no-random-rates", action="store_true",
+                    help="skip the device's random-access rates (the roofline of roofline.random_access)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with three 1 GiB device-to-device copies (reference kernel for "
                          "scaling the FETCH_SIZE / WRITE_SIZE counters)")
@@ -672,6 +684,23 @@ def main():
     }
     log("GTEPS %.2f, engine %.1f us/solve, alg bytes %.1f MB/solve -> %.1f GB/s"
         % (gteps, eng_mean_us, sum(B) / len(B) / 1e6, achieved))
+
+    # the random-access roofline: the method's random accesses per second
+    # against the rate the device serves independent random 8-byte reads
+    # (measured here, sssp_device_random_rates)
+    random_access = None
+    if not args.no_random_rates:
+        rates = sssp.device_random_rates()
+        A = sum(alg_accesses(c) for c in ctr) / len(ctr)
+        a_rate = A / (eng_mean_us * 1e-6)
+        peak = rates["words8_small_per_s"]
+        random_access = {
+            "achieved": round(a_rate / 1e9, 3), "peak": round(peak / 1e9, 3), "unit": "G accesses/s",
+            "frac": round(a_rate / peak, 4), "accesses_per_launch": int(A),
+            "peak_kind": "8-byte words read at random from a 128 MiB array (the per-vertex state's size)",
+            "device_rates_g_per_s": {k: round(v / 1e9, 3) for k, v in rates.items() if k.endswith("_per_s")}}
+        log("random accesses: %.1f M/solve -> %.2f G/s, %.3f of the device's %.2f G/s random 8-byte reads"
+            % (A / 1e6, a_rate / 1e9, a_rate / peak, peak / 1e9))
 
     # ablation: the traversal-optimisation filter off (st = lb in every step;
     # same distances, more edges traversed)
@@ -819,7 +848,8 @@ def main():
                      "traffic_copy_scaled": None if traffic is None else int(traffic[1]),
                      "traffic_unscaled": None if traffic is None else int(traffic[2]),
                      "kernel": "k_engine", "kernel_us_mean": round(eng_mean_us, 2),
-                     "alg_bytes_per_launch": int(sum(B) / len(B))},
+                     "alg_bytes_per_launch": int(sum(B) / len(B)),
+                     "random_access": random_access},
         "cpu_baseline": cpu,
         "configs": configs,
         "ablation_filter_off": ablation,

@@ -468,6 +468,31 @@ sssp_status sssp_solve_noalloc(const sssp_graph* g, int32_t source, uint32_t* di
  * be enqueued concurrently. */
 sssp_status sssp_release_workspaces(void);
 
+/* ---- the device's random-access rates ----------------------------------- */
+
+/* The rates at which the current device serves the random accesses the solve
+ * engine is made of: the reference for the engine's roofline. The method
+ * (Section 3: relaxations, the pull's reads, the settle's statistics) moves a
+ * few bytes per access at positions no cache predicts, so its ceiling is the
+ * rate of independent random accesses, not HBM bandwidth. */
+typedef struct {
+  double rows64_per_s;         /* 64-byte rows gathered at random from a 4 GiB table */
+  double words8_small_per_s;   /* 8-byte words read at random from a 128 MiB array (the size of a
+                                  2^24-vertex graph's per-vertex state, which the 256 MB last-level
+                                  cache holds) */
+  double words8_large_per_s;   /* 8-byte words read at random from a 4 GiB array */
+  double atomics8_small_per_s; /* 64-bit atomicMin at random words of the 128 MiB array */
+  int64_t accesses;            /* accesses per timed launch (2^24) */
+  int32_t reserved[6];
+} sssp_random_rates;
+
+/* Measure the rates on the current device (16 workgroups of 256 threads per
+ * CU; positions from a counter-based hash; each rate the best of 3 timed
+ * launches after an untimed one, timed with HIP events on `stream`).
+ * Synchronous. Allocates and frees about 8.4 GB of device memory; returns
+ * SSSP_E_NOMEM when it does not fit. */
+sssp_status sssp_device_random_rates(sssp_random_rates* out, hipStream_t stream);
+
 /* ---- errors ------------------------------------------------------------- */
 
 sssp_status sssp_last_error(void);

@@ -41,6 +41,15 @@ def release_workspaces() -> None:
     _lib.check(_lib.sssp_release_workspaces())
 
 
+def device_random_rates(stream=None) -> dict:
+    """Random accesses per second the current device serves, by kind
+    (sssp_device_random_rates): 64-byte rows from a 4 GiB table, 8-byte words
+    from a 128 MiB and from a 4 GiB array, 64-bit atomicMin on the 128 MiB one."""
+    r = _lib.RandomRates()
+    _lib.check(_lib.sssp_device_random_rates(ctypes.byref(r), _stream_handle(stream)))
+    return {f: getattr(r, f) for f, _ in r._fields_ if f != "reserved"}
+
+
 @atexit.register
 def _close_at_exit():
     for group in (_open_servers, _open_plans, _open_graphs):

@@ -17,6 +17,12 @@ if not os.path.exists(LIB_PATH):
         "libsssp.so is not built: run `python -c 'import __graft_entry__ as g; g.build()'` "
         "(or paper_2506_19349_amd/build.py) first")
 
+# torch's HIP runtime comes up before the library's first HIP call (the
+# library works on torch's device memory and streams)
+import torch as _torch_rt  # noqa: E402
+
+_torch_rt.cuda.is_available()
+
 lib = ctypes.CDLL(LIB_PATH)
 
 i32 = ctypes.c_int32
@@ -55,6 +61,12 @@ class GraphInfo(ctypes.Structure):
 class TuneReport(ctypes.Structure):
     _fields_ = [("default_us", ctypes.c_double), ("best_us", ctypes.c_double),
                 ("evaluations", i32), ("reserved", i32 * 7)]
+
+
+class RandomRates(ctypes.Structure):
+    _fields_ = [("rows64_per_s", ctypes.c_double), ("words8_small_per_s", ctypes.c_double),
+                ("words8_large_per_s", ctypes.c_double), ("atomics8_small_per_s", ctypes.c_double),
+                ("accesses", ctypes.c_int64), ("reserved", i32 * 6)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -126,6 +138,7 @@ sssp_server_get_stats = _sig("sssp_server_get_stats", i32, vp, ctypes.POINTER(Se
 sssp_server_destroy = _sig("sssp_server_destroy", i32, vp)
 sssp_solve_noalloc = _sig("sssp_solve_noalloc", i32, vp, i32, vp, vp)
 sssp_release_workspaces = _sig("sssp_release_workspaces", i32)
+sssp_device_random_rates = _sig("sssp_device_random_rates", i32, ctypes.POINTER(RandomRates), vp)
 sssp_last_error = _sig("sssp_last_error", i32)
 sssp_last_error_message = _sig("sssp_last_error_message", ctypes.c_char_p)
 sssp_status_str = _sig("sssp_status_str", ctypes.c_char_p, i32)

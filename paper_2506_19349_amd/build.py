@@ -6,8 +6,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libsssp.so")
-SOURCES = ["csrc/engine.hip", "csrc/prep.hip", "csrc/noalloc.hip", "csrc/api.cpp", "csrc/plan.cpp",
-           "csrc/server.cpp"]
+SOURCES = ["csrc/engine.hip", "csrc/prep.hip", "csrc/noalloc.hip", "csrc/probe.hip", "csrc/api.cpp",
+           "csrc/plan.cpp", "csrc/server.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
