@@ -333,6 +333,49 @@ def variants_section(args, sssp, torch, np, graphgen):
             % (p, out["power%d" % p]["gteps"], out["power%d" % p]["nTrav"], c["steps"], ok))
         del o
         g.close()
+    # computeST's candidate set: Section 4.1's ST_NUM grid against the exact
+    # window of distinct settled distances, for integer weights the window
+    # covers (maxW 255: bins narrower than one unit, the window by default;
+    # maxW 65535: 64 units, the grid by default)
+    for name in ("rmat22p8", "rmat22p16"):
+        wl = graphgen.workload(name)
+        csr = wl.csr
+        deg = csr.degrees()
+        g = sssp.Graph.from_csr(csr)
+        srcs = [int(s) for s in wl.sources(5)]
+        o = torch.empty(csr.n, dtype=torch.uint32, device="cuda")
+        rec = {"max_weight": int(csr.w.max()),
+               "default": "st_grid" if int(csr.w.max()) > 1024 else "window"}
+        sched = {}
+        for grid in (False, True):
+            g.solve(srcs[0], out=o, st_grid=grid)
+            torch.cuda.synchronize()
+            sched[grid] = [(x["lb"], x["ub"], x["st"]) for x in sssp.schedule()]
+            sssp.engine_times()
+            m_cc, dt, ntrav = 0, 0.0, []
+            for s in srcs[1:]:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                g.solve(s, out=o, st_grid=grid)
+                torch.cuda.synchronize()
+                dt += time.perf_counter() - t0
+                c = sssp.counters()
+                reach = o.cpu().numpy() != INF
+                m_cc += int(deg[reach].sum()) // 2
+                ntrav.append((c["push_scanned"] + c["pull_scanned"]) / max(int(reach.sum()), 1))
+            eng = sssp.engine_times()
+            d = o.cpu().numpy()
+            rec["st_grid" if grid else "window"] = {
+                "gteps": round(m_cc / dt / 1e9, 3), "engine_us_mean": round(sum(eng) / max(len(eng), 1), 1),
+                "nTrav": round(sum(ntrav) / len(ntrav), 3), "steps": c["steps"],
+                "invariants_ok": sum(native.check_sssp(csr.n, csr.rowptr, csr.col, csr.w, srcs[-1], d)) == 0}
+        rec["same_schedule_first_source"] = sched[False] == sched[True]
+        out["computest_" + name] = rec
+        log("computeST on %s (maxW %d): window %.2f GTEPS nTrav %.2f | ST_NUM grid %.2f GTEPS nTrav %.2f; "
+            "same schedule: %s" % (name, rec["max_weight"], rec["window"]["gteps"], rec["window"]["nTrav"],
+                                   rec["st_grid"]["gteps"], rec["st_grid"]["nTrav"], rec["same_schedule_first_source"]))
+        del o
+        g.close()
     # real weights (binary32): the gr26 graphs' (0, 1] weights and a float-pivot
     # variant (Eq. 8) on the RMAT-22 topology, and the (0, 1] weights on the
     # RMAT-24 topology; 4 solves each with the traversal optimisation (the

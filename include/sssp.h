@@ -72,7 +72,13 @@ typedef struct {
                             batches; 4: 2048-item settle batches. 0 -> default: 1 when a graph of
                             the solve has skewed degrees (sssp_graph_info.hub_first > 0), else 3;
                             the query server uses 1 */
-  int32_t reserved[7];
+  int32_t st_grid;       /* computeST's candidates for integer weights (Section 4.1): 0 -> the exact window of
+                            distinct settled distances while maxW <= 1024 (= ST_NUM: a grid bin is then at
+                            most one unit wide) and the ST_NUM grid of 1024 bins per maxW above; 1 -> the grid
+                            always; -1 -> the window while maxW <= 65536. Binary32 weights and integer
+                            weights above 65536 always use the grid. Changes the schedule, never a
+                            distance */
+  int32_t reserved[6];
 } sssp_options;
 
 /* Work counters of one solve (the paper's Section 4 measures). */
@@ -149,7 +155,7 @@ sssp_graph* sssp_graph_create(int32_t n, const int32_t* rowptr, const int32_t* c
  * binary32 (round to nearest), the value the textbook Dijkstra computes in
  * binary32; UINT32_MAX still marks unreachable vertices. computeST (Eq. 4-6)
  * then scores the points of a grid of 1024 bins per largest weight (ST_NUM,
- * Section 4.1), as it does for integer weights above 65536. */
+ * Section 4.1), as it does for integer weights above 1024 (sssp_options.st_grid). */
 #define SSSP_CREATE_FLOAT_WEIGHTS 2
 /* As sssp_graph_create, with flags (SSSP_CREATE_*). Skipping the symmetry
  * check leaves correctness to the caller: the pull (Section 3.2) relies on it. */

@@ -102,13 +102,23 @@ def _fadd(a, b) -> np.ndarray:
 # ---------------------------------------------------------- distance rules --
 
 class _Integers:
-    """Integer weights: exact sums, the window of distinct distances for
-    computeST while maxW allows it (Section 4.1's ST_NUM grid beyond)."""
+    """Integer weights: exact sums. computeST scores the exact window of
+    distinct settled distances while maxW <= ST_NUM, where a bin of Section
+    4.1's grid (ST_NUM per maxW) is at most one distance unit wide, and the
+    grid above (st_grid None); st_grid True asks for the grid always, False
+    for the window while it fits (maxW <= ST_WINDOW_MAX)."""
 
     inf = INF
 
-    def __init__(self, w: np.ndarray):
+    def __init__(self, w: np.ndarray, st_grid=None):
         self.w = np.asarray(w, dtype=np.int64)
+        M = int(self.w.max()) if self.w.shape[0] else 0
+        if M > H.ST_WINDOW_MAX:
+            self.grid = True
+        elif st_grid is None:
+            self.grid = M > H.ST_NUM
+        else:
+            self.grid = bool(st_grid)
 
     def add(self, d, w):
         return d + w
@@ -130,6 +140,9 @@ class _Integers:
         vals, inv = np.unique(dist[win], return_inverse=True)
         mass = np.zeros(vals.shape[0], dtype=np.int64)
         np.add.at(mass, inv, deg[win])
+        if self.grid:
+            return H.compute_st_grid(L, gap_L, gap_lb, S, nnz, M, lb0, ub_next, vals, mass, False,
+                                     traversal_opt)
         return H.compute_st(L, gap_L, gap_lb, S, nnz, M, vals, mass, traversal_opt)
 
     def stop_at_infinite_band(self) -> bool:
@@ -312,9 +325,11 @@ def _model(n, rowptr, col, rules, s, alpha, beta, traversal_opt, max_steps) -> R
 
 def eic_sssp(n: int, rowptr: np.ndarray, col: np.ndarray, w: np.ndarray, s: int,
              alpha: int = H.ALPHA, beta: float = H.BETA, traversal_opt: bool = True,
-             max_steps: int = 10_000_000) -> Result:
-    """The model with integer weights."""
-    return _model(n, rowptr, col, _Integers(w), s, alpha, beta, traversal_opt, max_steps)
+             max_steps: int = 10_000_000, st_grid=None) -> Result:
+    """The model with integer weights; st_grid: computeST's candidates (None:
+    the exact window while maxW <= ST_NUM, the ST_NUM grid above; True: the
+    grid; False: the window while maxW <= 65536)."""
+    return _model(n, rowptr, col, _Integers(w, st_grid), s, alpha, beta, traversal_opt, max_steps)
 
 
 def eic_sssp_f32(n: int, rowptr: np.ndarray, col: np.ndarray, wbits: np.ndarray, s: int,

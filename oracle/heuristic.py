@@ -29,7 +29,9 @@ Readings where the text is silent or ambiguous:
   here and no fused multiply-add.
 * When the largest weight exceeds ST_WINDOW_MAX the exact window of candidate
   distances is not kept: computeST scores the points of the ST_NUM grid
-  instead, as for real weights (below).
+  instead, as for real weights (below). (The schedule model scores the grid by
+  default once the largest weight exceeds ST_NUM, where the window would hold
+  more candidates than the grid.)
 * A single sentinel INF = 2^32 - 1 stands for +infinity in dist, ub and every
   threshold; sums are clamped to it.
 * The ST_NUM grid (real binary32 weights, and integer weights beyond the

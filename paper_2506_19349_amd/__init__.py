@@ -100,7 +100,7 @@ def _as_u32(a):
 
 
 def _options(traversal_opt=True, alpha=None, beta=None, host_driven=False, blocks_per_cu=0,
-             heavy_split=0, fuse_rounds=0, tile_shape=0):
+             heavy_split=0, fuse_rounds=0, tile_shape=0, st_grid=None):
     o = _lib.Options()
     o.traversal_opt = 1 if traversal_opt else -1
     o.alpha = int(alpha or 0)
@@ -110,6 +110,8 @@ def _options(traversal_opt=True, alpha=None, beta=None, host_driven=False, block
     o.heavy_split = int(heavy_split)
     o.fuse_rounds = int(fuse_rounds)
     o.tile_shape = int(tile_shape)
+    # None: by the weights; True: the ST_NUM grid; False: the exact window
+    o.st_grid = 0 if st_grid is None else (1 if st_grid else -1)
     return o
 
 

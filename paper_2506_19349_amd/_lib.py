@@ -35,7 +35,8 @@ u32p = ctypes.POINTER(ctypes.c_uint32)
 class Options(ctypes.Structure):
     _fields_ = [("traversal_opt", i32), ("alpha", i32), ("beta", ctypes.c_double),
                 ("host_driven", i32), ("blocks_per_cu", i32), ("heavy_split", i32),
-                ("fuse_rounds", i32), ("tile_shape", i32), ("reserved", i32 * 7)]
+                ("fuse_rounds", i32), ("tile_shape", i32), ("st_grid", i32),
+                ("reserved", i32 * 6)]
 
 
 class Counters(ctypes.Structure):

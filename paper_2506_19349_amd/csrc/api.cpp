@@ -57,7 +57,9 @@ Needs needs_for(const DevGraph& g, int maxw) {
     r.ring = kGridRing;
     r.steprec = 1u << 17;
   } else if (g.max_w <= kRingMax) {
-    r.ring = pow2_at_least(std::max<uint64_t>(64, 2ull * g.max_w + 2));
+    // per distance of the exact window (a solve may ask for it while max
+    // weight <= kRingMax), and at least the grid's bins
+    r.ring = pow2_at_least(std::max<uint64_t>(kGridRing, 2ull * g.max_w + 2));
     r.steprec = pow2_at_least(std::max<uint64_t>(64, 2ull * g.max_w + 64));
   } else {
     r.ring = kGridRing;  // the selection-threshold grid
@@ -308,6 +310,7 @@ bool parse_opts(const sssp_options* o, Opts* r, std::string* err) {
     return false;
   }
   if (o->tile_shape > 0) r->shape = o->tile_shape - 1;
+  r->st_grid = o->st_grid > 0 ? 1 : (o->st_grid < 0 ? -1 : 0);
   return true;
 }
 
@@ -349,6 +352,7 @@ void fill_inst(Inst& I, const SlotBuf& s, const sssp_graph* g, int32_t source, u
   I.n = g->gh.h.n;
   I.alpha = o.alpha;
   I.traversal_opt = o.topt;
+  I.st_grid = o.st_grid;
   I.beta = o.beta;
   I.heavy_split = o.heavy;
   I.fuse_cap = o.fuse;

@@ -12,7 +12,7 @@ constexpr uint32_t kInf = 0xFFFFFFFFu;   // +infinity: the single sentinel for d
 constexpr int kWave = 64;                // CDNA wavefront
 constexpr int kBlock = 256;              // threads per workgroup (4 waves)
 constexpr int kRatioNum = 4096;          // RATIO_NUM, Section 4.1
-constexpr uint32_t kRingMax = 65536;     // exact selection-threshold window up to this max weight
+constexpr uint32_t kRingMax = 65536;     // the longest exact selection-threshold window (max weight)
 constexpr int kLdsRing = 1024;           // settle: distance bins privatised in LDS
 constexpr int kStNum = 1024;             // ST_NUM, Section 4.1: selection-threshold grid per max weight
 constexpr uint32_t kGridRing = 4096;     // grid bins kept (>= 2 ST_NUM + 2)
@@ -215,7 +215,10 @@ struct InstFixed {
   // which round-batch instantiation runs this instance: bit 0 a tree is
   // recorded (best != null), bit 1 the graph has binary32 weights
   uint32_t mode;
-  uint32_t pad_mode;
+  // computeST's candidates for integer weights: 0 the exact window of
+  // distinct settled distances while max weight <= kStNum, the ST_NUM grid
+  // above; 1 the grid always; -1 the window while max weight <= kRingMax
+  int32_t st_grid;
   int32_t n;
   uint32_t alpha;
   uint32_t traversal_opt;

@@ -274,6 +274,18 @@ __device__ uint32_t block_compute_st(const GInst& I, uint32_t L, uint32_t gapL, 
 // so it never decreases as d grows; kNoBin past 2^31 bins, for +inf and for
 // the sentinel. value() is the binary32 value of the bit pattern, or the
 // integer itself.
+// Which candidate set computeST scores (Section 4.1): the ST_NUM grid for
+// binary32 weights and, by default, for integer weights above ST_NUM (where a
+// grid bin is wider than one distance unit and the grid has fewer candidates
+// than the exact window); below, each bin holds at most one integer distance
+// and the exact window of distinct settled distances is scored instead.
+// st_grid = 1 asks for the grid always, -1 for the window while it fits.
+__device__ __forceinline__ bool use_st_grid(bool fw, uint32_t M, int32_t st_grid) {
+  if (fw || M > kRingMax) return true;
+  if (st_grid != 0) return st_grid > 0;
+  return M > (uint32_t)kStNum;
+}
+
 __device__ __forceinline__ double dval(uint32_t d, bool fw) {
   return fw ? (double)__uint_as_float(d) : (double)d;
 }
@@ -420,7 +432,7 @@ __device__ __noinline__ void run_heuristic(GInst& I, HeurLds& lds) {
   }
   // binary32 weights, or integer weights beyond the exact window: computeST
   // scores the points of the ST_NUM grid
-  const bool grid = fw || I.M > kRingMax;
+  const bool grid = use_st_grid(fw, I.M, I.st_grid);
   uint32_t stn = grid ? block_compute_st_grid(I, L, gapL, lb0, (uint32_t)ubn, g.nnz, fw, lds)
                       : block_compute_st(I, L, gapL, g.nnz, lds);
   if (tid == 0) {
@@ -1309,7 +1321,7 @@ __device__ __noinline__ void block_settle(GInst& I, int kind, int item0, int nit
   // (binary32 weights, or integer weights beyond the exact window; bins
   // klb..kub hold this step's settled vertices)
   const bool fw = g.float_w != 0;
-  const bool grid = fw || M > kRingMax;
+  const bool grid = use_st_grid(fw, M, I.st_grid);
   const double inv = grid ? grid_inv(M, fw) : 0.0;
   const uint32_t klb = grid ? gbin(lb, inv, fw) : lb;
   const uint32_t kub = grid ? gbin(ub, inv, fw) : ub;

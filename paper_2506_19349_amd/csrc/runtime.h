@@ -129,6 +129,7 @@ struct Opts {
   int heavy = kDefaultHeavy;
   int fuse = kDefaultFuse;
   int shape = -1;  // tile shape (engine kernel instantiation); -1: by the graphs (resolve_shape)
+  int st_grid = 0;  // computeST's candidates for integer weights (Inst::st_grid)
   unsigned long long tick_limit = 1ull << 22;
 };
 

@@ -333,3 +333,26 @@ def test_grid_beyond_the_window_tiny_fuzz():
                     cases += 1
                 g.close()
     assert cases > 150
+
+
+@pytest.mark.parametrize("mode", [None, True, False])
+@pytest.mark.parametrize("name", ["rmat14", "rmat12p16", "er12", "grid64w10000"])
+def test_schedule_matches_model_for_each_st_candidate_set(name, mode):
+    """computeST's candidates for integer weights (sssp_options.st_grid): by
+    the weights (the exact window up to maxW 1024, the ST_NUM grid above), the
+    grid, or the window; the engine's schedule equals the model's in the same
+    mode, and the distances stay exact."""
+    wl = graphgen.workload(name)
+    c = wl.csr
+    g = sssp.Graph.from_csr(c)
+    for s in wl.sources(3):
+        ref = eic.eic_sssp(c.n, c.rowptr, c.col, c.w, int(s), st_grid=mode)
+        d = g.solve(int(s), st_grid=mode)
+        assert np.array_equal(d.cpu().numpy(), ref.dist)
+        got = sssp.schedule()
+        assert len(got) == len(ref.steps), (len(got), len(ref.steps))
+        for a, b in zip(got, ref.steps):
+            assert (a["lb"], a["ub"], a["st"]) == (b.lb, b.ub, b.st), (a, b)
+            if b.ub != INF or b.lb != 0:
+                assert (a["L"], a["S"], a["h"], a["gap"], a["st_next"]) == \
+                    (b.L, b.S, b.h, b.gap, b.st_next), (a, b)

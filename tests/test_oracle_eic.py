@@ -175,3 +175,52 @@ def test_weights_beyond_the_exact_window_use_the_grid(name):
         assert np.array_equal(on.dist, ref) and np.array_equal(off.dist, ref)
         assert on.pulls > 0
         assert eic.normalised(on, c.n, deg)["nTrav"] < 0.5 * eic.normalised(off, c.n, deg)["nTrav"]
+
+
+def test_st_grid_model_is_exact():
+    """computeST on the ST_NUM grid for integer weights within the exact
+    window's range (st_grid): another schedule, the same distances."""
+    for n in range(2, 11):
+        for weights in ([1, 2, 3], list(range(1, 256)), [0, 1, 2]):
+            el = small.tiny_random(n, 3 * n, weights, seed=31 * n + len(weights))
+            c = graphgen.to_csr(el)
+            for s in range(n):
+                ref = native.dijkstra(el.n, el.src, el.dst, el.w, s)
+                got = eic.eic_sssp(c.n, c.rowptr, c.col, c.w, s, st_grid=True).dist
+                assert np.array_equal(got, ref), (n, weights[:3], s)
+    wl = graphgen.workload("rmat12p16")
+    c = wl.csr
+    assert 1024 < int(c.w.max()) <= 65536
+    for s in wl.sources(2):
+        ref = native.dijkstra(wl.edges.n, wl.edges.src, wl.edges.dst, wl.edges.w, int(s))
+        assert np.array_equal(eic.eic_sssp(c.n, c.rowptr, c.col, c.w, int(s), st_grid=True).dist, ref)
+
+
+def test_st_grid_equals_the_window_when_bins_are_no_wider_than_one():
+    """With ST_NUM = 1024 bins per maxW and maxW <= 1024 a bin is at most one
+    distance unit wide, so each bin holds at most one integer distance: the
+    grid's candidates and their masses are the exact window's, scored at the
+    grid point at or just below each distance (at the distance itself when
+    maxW = 1024), and every step here picks the same threshold. Wider bins
+    (maxW up to 65536) give another schedule."""
+    rng = np.random.default_rng(3)
+    for t in range(40):
+        n = int(rng.integers(5, 160))
+        m = int(rng.integers(n, 5 * n))
+        top = int(rng.choice([255, 1000, 1024]))
+        el = small.tiny_random(n, m, list(range(1, top + 1)), seed=1000 + t)
+        c = graphgen.to_csr(el)
+        s = int(rng.integers(0, n))
+        a = eic.eic_sssp(c.n, c.rowptr, c.col, c.w, s)
+        b = eic.eic_sssp(c.n, c.rowptr, c.col, c.w, s, st_grid=True)
+        assert [(x.lb, x.ub, x.st, x.st_next) for x in a.steps] == \
+               [(x.lb, x.ub, x.st, x.st_next) for x in b.steps], (t, top)
+    wl = graphgen.workload("rmat12p16")
+    c = wl.csr
+    s = int(wl.sources(1)[0])
+    a = eic.eic_sssp(c.n, c.rowptr, c.col, c.w, s, st_grid=False)
+    b = eic.eic_sssp(c.n, c.rowptr, c.col, c.w, s, st_grid=True)
+    assert [x.st_next for x in a.steps] != [x.st_next for x in b.steps]
+    # above ST_NUM the grid is the default
+    d = eic.eic_sssp(c.n, c.rowptr, c.col, c.w, s)
+    assert [x.st_next for x in d.steps] == [x.st_next for x in b.steps]
