@@ -1714,7 +1714,7 @@ __device__ void build_table(GGlobals& G, bool do_transition, bool count) {
   const int i0 = min(k, tid * per), i1 = min(k, i0 + per);
   SSSP_GBL Inst* insts = gbl(G.insts);
   SSSP_GBL SegRec* seg = gbl(G.seg);
-  int local_batches = 0;
+  int local_batches = 0, local_segs = 0;
   int nb_last[kMaxSegPerInst], cnt_last[kMaxSegPerInst], word_last[kMaxSegPerInst];
 #pragma unroll
   for (int s = 0; s < kMaxSegPerInst; ++s) nb_last[s] = cnt_last[s] = word_last[s] = 0;
@@ -1755,17 +1755,30 @@ __device__ void build_table(GGlobals& G, bool do_transition, bool count) {
       }
       nb_last[s] = nb;
       local_batches += nb;
+      local_segs += nb > 0 ? 1 : 0;
     }
   }
+  // With at most kBlock instances the table lists only segments that have
+  // batches (inactive instances and empty lists take no record), so that a
+  // launch of many instances, most of them idle or with one or two kinds of
+  // work, keeps a table short enough for the one-load segment search. One scan
+  // gives both offsets: batches in the low half (a tick has fewer than 2^31),
+  // records in the high half.
+  const unsigned long long mine =
+      per == 1 ? ((unsigned long long)local_segs << 32) | (unsigned long long)local_batches
+               : (unsigned long long)local_batches;
   unsigned long long total;
-  unsigned long long before = block_excl_scan<unsigned long long>((unsigned long long)local_batches, sh, &total);
-  int run = (int)before;
+  const unsigned long long before = block_excl_scan<unsigned long long>(mine, sh, &total);
+  int run = per == 1 ? (int)(uint32_t)before : (int)before;
   if (per == 1) {
     if (i0 < i1) {
+      int pos = (int)(before >> 32);
 #pragma unroll
       for (int s = 0; s < kMaxSegPerInst; ++s) {
+        if (nb_last[s] == 0) continue;
         const SegRec r = {run, i0, cnt_last[s], word_last[s]};
-        gstore(seg + i0 * kMaxSegPerInst + s, r);
+        gstore(seg + pos, r);
+        ++pos;
         run += nb_last[s];
       }
     }
@@ -1781,10 +1794,12 @@ __device__ void build_table(GGlobals& G, bool do_transition, bool count) {
   }
   __syncthreads();
   if (tid == 0) {
-    G.nseg = k * kMaxSegPerInst;
-    const SegRec end = {(int)total, 0, 0, 0};
-    gstore(seg + G.nseg, end);
-    G.total_batches = (int)total;
+    const int nseg = per == 1 ? (int)(total >> 32) : k * kMaxSegPerInst;
+    const int batches = per == 1 ? (int)(uint32_t)total : (int)total;
+    G.nseg = nseg;
+    const SegRec end = {batches, 0, 0, 0};
+    gstore(seg + nseg, end);
+    G.total_batches = batches;
     G.all_done = (s_active == 0) ? 1u : 0u;
   }
   __syncthreads();
