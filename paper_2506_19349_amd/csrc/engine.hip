@@ -1924,8 +1924,7 @@ struct BarrierState {
   uint32_t members0;   // workgroups on the first populated XCD (where small ticks run)
 };
 
-// Flat barrier with full fences by every workgroup; used once per launch to
-// register the workgroups of each XCD, and as the whole barrier of the
+// Flat barrier with full fences by every workgroup: the whole barrier of the
 // one-launch-per-tick mode (where the kernel boundary does the waiting).
 __device__ bool barrier_flat(GGlobals& G, unsigned int& gen, bool wait, bool run_epilogue) {
   __shared__ int s_last;
@@ -2071,6 +2070,40 @@ __device__ bool barrier_tick(GGlobals& G, BarrierState& B, unsigned int quota, u
   return s_ok != 0;
 }
 
+// Registration of a persistent launch (thread 0 of each workgroup, after it
+// took its rank on its XCD): the last workgroup of the grid to arrive reads
+// the final member counts and releases every populated XCD with the launch's
+// layout in the high half of the release word: the populated-XCD mask (bits
+// 0-7), the fewest workgroups on one XCD (bits 8-19) and the workgroups of the
+// first populated XCD (bits 20-31); at most 8 workgroups of 256 threads fit a
+// CU, so a count stays below 4096. The others wait on their own XCD's line.
+// Nothing but the counts is exchanged (the launch's data was written by
+// earlier kernels), so no cache is written back or invalidated. Returns the
+// layout, 0 if the wait gave up.
+__device__ uint32_t register_launch(GGlobals& G, uint32_t xcd, unsigned int xgen) {
+  // the rank's atomic is complete before this workgroup counts as arrived
+  __builtin_amdgcn_s_waitcnt(0);
+  const unsigned int a = atomicAdd(&G.bar_count.v, 1u);
+  if (a != gridDim.x - 1u) return (uint32_t)(spin_until_released(G, xcd, xgen) >> 32);
+  uint32_t mask = 0, mn = 0xffffffffu, m0 = 0;
+  for (int x = 0; x < kMaxXcd; ++x) {
+    const uint32_t m = __hip_atomic_load(&G.xcd_members[x].v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (m == 0) continue;
+    if (mask == 0) m0 = m;
+    mask |= 1u << x;
+    mn = m < mn ? m : mn;
+  }
+  const uint32_t lay = mask | (mn << 8) | (m0 << 20);
+  __hip_atomic_store(&G.bar_count.v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (int x = 0; x < kMaxXcd; ++x) {
+    if (!(mask >> x & 1u)) continue;
+    const unsigned int g = (uint32_t)x == xcd ? xgen
+        : (unsigned int)__hip_atomic_load(&G.xcd_gen[x].v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&G.xcd_gen[x].v, release_word(g + 1u, lay), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  return lay;
+}
+
 template <class Sh>
 __global__ void __launch_bounds__(kBlock, Sh::kMinBlocks) k_engine(Globals* Gp, int persistent, int max_ticks) {
   __shared__ BlockLds<Sh> lds;
@@ -2093,37 +2126,30 @@ __global__ void __launch_bounds__(kBlock, Sh::kMinBlocks) k_engine(Globals* Gp, 
     barrier_flat(G, gen, false, true);
     return;
   }
-  // register this workgroup with its XCD (and take a rank there), then
-  // settle the counts grid-wide
+  // register this workgroup with its XCD (and take a rank there); the last
+  // of the grid to register releases every XCD with the final layout
   if (threadIdx.x == 0) {
     s_b.xcd = xcd_of_this_wg();
     s_b.xgen = (unsigned int)__hip_atomic_load(&G.xcd_gen[s_b.xcd].v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     s_b.rank = atomicAdd(&G.xcd_members[s_b.xcd].v, 1u);
+    const uint32_t lay = register_launch(G, s_b.xcd, s_b.xgen);
+    s_b.nxcd = 0;  // no layout: the wait gave up
+    if (lay != 0u) {
+      const uint32_t mask = lay & 0xffu;
+      const uint32_t mn = (lay >> 8) & 0xfffu, m0 = lay >> 20;
+      s_b.nxcd = (uint32_t)__builtin_popcount(mask);
+      s_b.xidx = (uint32_t)__builtin_popcount(mask & ((1u << s_b.xcd) - 1u));
+      s_b.xgen += 1u;
+      // every workgroup computes the same values, the first tick's quota
+      // included (from the table the set-up kernel built); the epilogue
+      // publishes the later ones
+      s_b.q0 = quota_for(G.total_batches, s_b.nxcd, mn, m0);
+      s_b.min_members = mn;
+      s_b.members0 = m0;
+    }
   }
   __syncthreads();
-  unsigned int gen = s_b.gen;
-  if (!barrier_flat(G, gen, true, false)) return;
-  if (threadIdx.x == 0) {
-    s_b.gen = gen;
-    s_b.members = __hip_atomic_load(&G.xcd_members[s_b.xcd].v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    uint32_t nx = 0, xi = 0, mn = 0xffffffffu, m0 = 0;
-    for (int x = 0; x < kMaxXcd; ++x) {
-      const uint32_t m = __hip_atomic_load(&G.xcd_members[x].v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (m == 0) continue;
-      if ((uint32_t)x < s_b.xcd) ++xi;
-      if (nx == 0) m0 = m;
-      ++nx;
-      mn = m < mn ? m : mn;
-    }
-    s_b.nxcd = nx;
-    s_b.xidx = xi;
-    // every workgroup computes the same values, the first tick's quota
-    // included (from the table the set-up kernel built); the epilogue
-    // publishes the later ones
-    s_b.q0 = quota_for(G.total_batches, nx, mn, m0);
-    s_b.min_members = mn;
-    s_b.members0 = m0;
-  }
+  if (s_b.nxcd == 0u) return;
   __syncthreads();
   BarrierState B = s_b;
   bool stale = false;  // parked since the last acquire
